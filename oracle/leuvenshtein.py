@@ -1,0 +1,158 @@
+"""Oracle, encrypted Leuvenshtein -- TEST INFRASTRUCTURE ONLY.
+
+The encrypted algorithm of arXiv 2508.14568 written out step by step on top
+of the schoolbook TFHE oracle (``tfhe.py``):
+  * Algorithm 3 / Algorithm 4 equality: z1 = x1 - y1, eq1 = PBS(z1; LUT_eq),
+    z2 = 2 (x2 - y2) + (1 - eq1), eq9 = PBS(z2; LUT_eq9) for 7-bit characters
+    split into a 4-bit and a 3-bit symbol (Section 4.3); one PBS on x - y for
+    2-bit DNA bases (Section 6.4 uses a single equality PBS for DNA).
+  * Algorithm 4 main loop (j outer, i inner): key = (1 - v[i,j-1]) +
+    3 (1 + h[i-1,j]) + eq9[i,j] (Eq. eq_keyeq2), M = PBS(key; LUT_min),
+    v[i,j] = M - h[i-1,j], h[i,j] = M - v[i,j-1], boundary v[i,0] = h[0,j] = 1.
+  * Result: D = m + sum_j h[m,j] (the return of Algorithm 4 with the boundary
+    term h[m,0] left out; Fig. fig_myers shows the bold bottom-row arrows
+    summing to the distance).
+  * Section 5 preprocessing: T[c][i] = Enc(9 [a_i = c]) for c in an alphabet
+    S; the main loop then reads eq9[i,j] = T[b_j][i] with no bootstrap.
+  * Section 6.2 (parallelism over cells): cells on one anti-diagonal are
+    independent; ``dp(..., order="diagonal")`` evaluates them as one batch.
+"""
+import numpy as np
+
+from . import plaintext as P
+from . import tfhe as T
+
+ENC_ASCII7 = 0
+ENC_DNA2 = 1
+
+LUT_IDS = {"eq": 0, "eq9": 1, "min": 2}
+
+
+def lut_polys(N: int) -> np.ndarray:
+    """Test polynomials in the order of LUT_IDS."""
+    return np.stack([T.test_polynomial(P.LUT_EQ, N), T.test_polynomial(P.LUT_EQ9, N),
+                     T.test_polynomial(P.lut_min_negated(), N)])
+
+
+def symbols(s, encoding):
+    """Per-character symbol lists: ASCII -> (c & 15, c >> 4); DNA -> (code,)."""
+    if encoding == ENC_ASCII7:
+        return [P.ascii_symbols(c) for c in s]
+    return [(P.dna_code(c),) for c in s]
+
+
+def encrypt_string(keys: T.Keys, s, encoding: int, seed: int) -> np.ndarray:
+    """Array (m, nsym, N+1): symbol r of character i is ciphertext number
+    i * nsym + r under the encryption seed."""
+    syms = symbols(s, encoding)
+    nsym = 2 if encoding == ENC_ASCII7 else 1
+    out = np.zeros((len(syms), nsym, keys.N + 1), dtype=T.U64)
+    for i, sy in enumerate(syms):
+        for r in range(nsym):
+            out[i, r] = keys.encrypt(sy[r], seed, i * nsym + r)
+    return out
+
+
+def _pbs(keys, cts, lut_name, nthreads):
+    polys = lut_polys(keys.N)
+    return keys.pbs_batch(cts, polys, LUT_IDS[lut_name], nthreads)
+
+
+def equality(keys: T.Keys, A: np.ndarray, B: np.ndarray, encoding: int, nthreads=None):
+    """eq9[i,j] for every pair (all m*n pairs are independent of the DP).
+    Returns (eq1, eq9) with eq1 None for DNA; arrays are (m, n, N+1)."""
+    m, n, W = A.shape[0], B.shape[0], keys.N + 1
+    if encoding == ENC_DNA2:
+        z = (A[:, None, 0, :] - B[None, :, 0, :]).astype(T.U64).reshape(m * n, W)
+        return None, _pbs(keys, z, "eq9", nthreads).reshape(m, n, W)
+    z1 = (A[:, None, 0, :] - B[None, :, 0, :]).astype(T.U64).reshape(m * n, W)
+    eq1 = _pbs(keys, z1, "eq", nthreads)
+    one = T.trivial(1, keys.N)
+    z2 = (T.scale(A[:, None, 1, :], 2) - T.scale(B[None, :, 1, :], 2)).reshape(m * n, W)
+    z2 = (z2 + one[None, :] - eq1).astype(T.U64)
+    eq9 = _pbs(keys, z2, "eq9", nthreads)
+    return eq1.reshape(m, n, W), eq9.reshape(m, n, W)
+
+
+def preprocess(keys: T.Keys, A: np.ndarray, alphabet, encoding: int, nthreads=None):
+    """Section 5 table T[c][i] = Enc(9 [a_i = alphabet[c]]), shape (|S|, m, N+1):
+    the equality pipeline with the cleartext symbol as a noise-free ciphertext."""
+    m, W = A.shape[0], keys.N + 1
+    Bc = np.stack([np.stack([T.trivial(s, keys.N) for s in sy]) for sy in symbols(alphabet, encoding)])
+    _, eq9 = equality(keys, A, Bc, encoding, nthreads)        # (m, |S|, W)
+    return np.ascontiguousarray(eq9.transpose(1, 0, 2))
+
+
+def dp(keys: T.Keys, m: int, n: int, eq9_at, order: str = "alg4", nthreads=None, record: bool = False):
+    """Main loop of Algorithm 4 over an m x n grid; eq9_at(i, j) returns the
+    ciphertext of 9 [a_i = b_j] (1-based indices).  Returns the last-row
+    vector h[m, 1..n] (n ciphertexts) and, when record is set, a dict with
+    every key and M ciphertext."""
+    N, W = keys.N, keys.N + 1
+    polys = lut_polys(N)
+    one = T.trivial(1, N)
+    four = T.trivial(4, N)
+    V = np.tile(one, (m + 1, 1))      # V[i] = v[i, last j]   (v[i,0] = 1)
+    H = np.tile(one, (n + 1, 1))      # H[j] = h[last i, j]   (h[0,j] = 1)
+    rec = {"key": {}, "M": {}} if record else None
+
+    def key_of(i, j):
+        return (four - V[i] + T.scale(H[j], 3) + eq9_at(i, j)).astype(T.U64)
+
+    def update(i, j, M):
+        v_new = (M - H[j]).astype(T.U64)
+        h_new = (M - V[i]).astype(T.U64)
+        V[i], H[j] = v_new, h_new
+
+    if order == "alg4":
+        for j in range(1, n + 1):
+            for i in range(1, m + 1):
+                key = key_of(i, j)
+                M = keys.pbs(key, polys[LUT_IDS["min"]])
+                if record:
+                    rec["key"][(i, j)], rec["M"][(i, j)] = key, M
+                update(i, j, M)
+    elif order == "diagonal":
+        for s in range(2, m + n + 1):
+            cells = [(i, s - i) for i in range(max(1, s - n), min(m, s - 1) + 1)]
+            keys_b = np.stack([key_of(i, j) for i, j in cells])
+            Ms = keys.pbs_batch(keys_b, polys, LUT_IDS["min"], nthreads)
+            for (i, j), key, M in zip(cells, keys_b, Ms):
+                if record:
+                    rec["key"][(i, j)], rec["M"][(i, j)] = key, M
+                update(i, j, M)
+    else:
+        raise ValueError(order)
+    h_last = H[1:].copy()
+    return (h_last, rec) if record else h_last
+
+
+def edit_distance(keys: T.Keys, A: np.ndarray, B: np.ndarray, encoding: int, order="diagonal",
+                  nthreads=None, record=False):
+    """Algorithm 4 on two encrypted strings; returns h[m,1..n] (and records)."""
+    m, n = A.shape[0], B.shape[0]
+    if m == 0 or n == 0:
+        h_last = np.tile(T.trivial(1, keys.N), (n, 1))
+        return (h_last, {"eq9": None}) if record else h_last
+    eq1, eq9 = equality(keys, A, B, encoding, nthreads)
+    out = dp(keys, m, n, lambda i, j: eq9[i - 1, j - 1], order, nthreads, record)
+    if record:
+        out[1]["eq1"], out[1]["eq9"] = eq1, eq9
+    return out
+
+
+def edit_distance_clear(keys: T.Keys, table: np.ndarray, alphabet, b, encoding: int, order="diagonal",
+                        nthreads=None, record=False):
+    """Main loop with eq9[i,j] = T[b_j][i] read from the preprocessing table."""
+    m, n = table.shape[1], len(b)
+    index = {c: k for k, c in enumerate(alphabet)}
+    cols = [index[c] for c in b]
+    if m == 0 or n == 0:
+        return np.tile(T.trivial(1, keys.N), (n, 1))
+    return dp(keys, m, n, lambda i, j: table[cols[j - 1], i - 1], order, nthreads, record)
+
+
+def decrypt_distance(keys: T.Keys, m: int, h_last: np.ndarray) -> int:
+    """D = m + sum_j dec(h[m,j]) with dec in {-1, 0, 1}; the sum is taken in
+    the clear since D can exceed the 5-bit plaintext space."""
+    return P.distance_from_last_row(m, [keys.decrypt_signed(ct) for ct in h_last])

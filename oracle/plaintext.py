@@ -1,0 +1,145 @@
+"""Oracle, plaintext layer -- TEST INFRASTRUCTURE ONLY.
+
+The cleartext definitions that the encrypted method must reproduce exactly
+(arXiv 2508.14568):
+  * Wagner-Fischer distance matrix, Eq. (eq_wf) in Section 2.3.
+  * Difference encoding of the distance matrix, Eq. (eq:delta) (Myers).
+  * The shared non-linearity M = 1 + min(-eq, dv_in, dh_in) with
+    dv_out = M - dh_in and dh_out = M - dv_in, Eq. (mye_eq_2), Section 3.1.
+  * The single-lookup cell tables: the key (dv+1) + 3(1+dh) + 9eq of
+    Eq. (eq_keyeq) with Table LUTmin, and the noise-reduced key
+    (1-dv) + 3(1+dh) + 9eq of Eq. (eq_keyeq2) that Algorithms 1 and 4 use.
+  * Equality tables LUT_eq and LUT_eq9, Eqs. (eq_eqlut) and (eq_eqlut9).
+  * The 7-bit character split into a 4-bit and a 3-bit symbol (Section 4.3).
+"""
+import itertools
+
+import numpy as np
+
+
+def wagner_fischer(a, b) -> np.ndarray:
+    """Full (m+1) x (n+1) distance matrix: D[i,0] = i, D[0,j] = j and
+    D[i,j] = D[i-1,j-1] if a_i = b_j else 1 + min of the three neighbours."""
+    m, n = len(a), len(b)
+    D = np.zeros((m + 1, n + 1), dtype=np.int64)
+    D[:, 0] = np.arange(m + 1)
+    D[0, :] = np.arange(n + 1)
+    for i in range(1, m + 1):
+        for j in range(1, n + 1):
+            if a[i - 1] == b[j - 1]:
+                D[i, j] = D[i - 1, j - 1]
+            else:
+                D[i, j] = 1 + min(D[i - 1, j], D[i, j - 1], D[i - 1, j - 1])
+    return D
+
+
+def edit_distance(a, b) -> int:
+    return int(wagner_fischer(a, b)[len(a), len(b)])
+
+
+def deltas_from_matrix(D: np.ndarray):
+    """dv[i,j] = D[i,j] - D[i-1,j] (i >= 1) and dh[i,j] = D[i,j] - D[i,j-1]
+    (j >= 1); entries that the definition does not cover are left at 0."""
+    dv = np.zeros_like(D)
+    dh = np.zeros_like(D)
+    dv[1:, :] = D[1:, :] - D[:-1, :]
+    dh[:, 1:] = D[:, 1:] - D[:, :-1]
+    return dv, dh
+
+
+def cell_M(eq: int, dv_in: int, dh_in: int) -> int:
+    """M = 1 + min(-eq, dv_in, dh_in), Eq. (mye_eq_2)."""
+    return 1 + min(-eq, dv_in, dh_in)
+
+
+def cell(eq: int, dv_in: int, dh_in: int):
+    """(dv_out, dh_out) of one cell through the shared non-linearity."""
+    M = cell_M(eq, dv_in, dh_in)
+    return M - dh_in, M - dv_in
+
+
+def delta_dp(a, b):
+    """The difference-encoded dynamic programme with boundary v[i,0] = 1 and
+    h[0,j] = 1 (Algorithms 1/4 set-up); returns (v, h, M) as (m+1)x(n+1)
+    integer arrays in the loop order of the algorithms (j outer, i inner)."""
+    m, n = len(a), len(b)
+    v = np.ones((m + 1, n + 1), dtype=np.int64)
+    h = np.ones((m + 1, n + 1), dtype=np.int64)
+    M = np.zeros((m + 1, n + 1), dtype=np.int64)
+    for j in range(1, n + 1):
+        for i in range(1, m + 1):
+            eq = 1 if a[i - 1] == b[j - 1] else 0
+            M[i, j] = cell_M(eq, v[i, j - 1], h[i - 1, j])
+            v[i, j] = M[i, j] - h[i - 1, j]
+            h[i, j] = M[i, j] - v[i, j - 1]
+    return v, h, M
+
+
+def distance_from_last_row(m: int, h_last) -> int:
+    """D[m,n] = D[m,0] + sum_j dh[m,j] = m + sum_{j=1..n} h[m,j]."""
+    return int(m + sum(int(x) for x in h_last))
+
+
+# --------------------------------------------------------------- tables
+
+def lut_from_function(f, key_of):
+    """Build the 16-entry table of a function f over all inputs (dv, dh, eq)
+    keyed by key_of(dv, dh, eq) in [0, 18).  Keys 16 and 17 land on the
+    negated entries 0 and 1 (Section 2.2), so both must be 0 there; the
+    assertion enforces it."""
+    table = {}
+    for dv, dh, eq in itertools.product((-1, 0, 1), (-1, 0, 1), (0, 1)):
+        k = key_of(dv, dh, eq)
+        val = f(eq, dv, dh)
+        assert table.get(k, val) == val, "key collision with different values"
+        table[k] = val
+    assert set(table) == set(range(18))
+    lut = [table[x] for x in range(16)]
+    for x in (16, 17):
+        assert (-lut[x - 16]) % 32 == table[x] % 32, "negacyclic extension violated"
+    return lut
+
+
+def key_plain(dv, dh, eq):
+    """Eq. (eq_keyeq): (dv + 1) + 3 (1 + dh) + 9 eq."""
+    return (dv + 1) + 3 * (1 + dh) + 9 * eq
+
+
+def key_negated(dv, dh, eq):
+    """Eq. (eq_keyeq2): (1 - dv) + 3 (1 + dh) + 9 eq."""
+    return (1 - dv) + 3 * (1 + dh) + 9 * eq
+
+
+def lut_min_plain():
+    """Table LUTmin of Section 3.1 (key of Eq. eq_keyeq)."""
+    return lut_from_function(cell_M, key_plain)
+
+
+def lut_min_negated():
+    """Table for the key of Eq. (eq_keyeq2), which Algorithms 1 and 4 use; the
+    paper states that the table changes but does not print it."""
+    return lut_from_function(cell_M, key_negated)
+
+
+LUT_EQ = [1] + [0] * 15          # Eq. (eq_eqlut)
+LUT_EQ9 = [9] + [0] * 15         # Eq. (eq_eqlut9)
+LUT_X_MINUS_4 = [(x - 4) % 16 for x in range(16)]   # Table table_lutrelu
+
+
+def negacyclic_read(lut16, x: int, modulus: int = 32) -> int:
+    """Value a bootstrap returns for plaintext x in Z_32 (Section 2.2): the
+    entry itself below 16, its negation for 16 <= x < 32."""
+    x %= 32
+    return lut16[x] % modulus if x < 16 else (-lut16[x - 16]) % modulus
+
+
+# ------------------------------------------------------------- symbols
+
+def ascii_symbols(c: int):
+    """7-bit character -> (4-bit symbol, 3-bit symbol) = (c & 15, c >> 4)."""
+    assert 0 <= c < 128
+    return c & 15, c >> 4
+
+
+def dna_code(base) -> int:
+    return "ACGT".index(base) if isinstance(base, str) else int(base)

@@ -1,0 +1,119 @@
+"""Pins of the encrypted Leuvenshtein oracle (Algorithms 3 and 4, Section 5
+preprocessing of arXiv 2508.14568) against the plaintext definitions."""
+import itertools
+
+import numpy as np
+
+from conftest import golden
+from oracle import leuvenshtein as L
+from oracle import plaintext as P
+from oracle import tfhe as T
+
+
+def test_dna_equality_all_pairs(oracle_toy_keys):
+    k = oracle_toy_keys
+    A = L.encrypt_string(k, "ACGT", L.ENC_DNA2, 1)
+    B = L.encrypt_string(k, "ACGT", L.ENC_DNA2, 2)
+    _, eq9 = L.equality(k, A, B, L.ENC_DNA2)
+    for i, j in itertools.product(range(4), range(4)):
+        assert k.decrypt(eq9[i, j]) == (9 if i == j else 0)
+
+
+def test_ascii_equality_algorithm3(oracle_toy_keys):
+    """Pairs equal in both symbols, only the 4-bit one, only the 3-bit one, or
+    neither (Section 4.3); eq1 decrypts to the 4-bit equality."""
+    k = oracle_toy_keys
+    xs = b"aAqQ0p~ "
+    ys = b"aQqA1` ~"
+    A = L.encrypt_string(k, xs, L.ENC_ASCII7, 3)
+    B = L.encrypt_string(k, ys, L.ENC_ASCII7, 4)
+    eq1, eq9 = L.equality(k, A, B, L.ENC_ASCII7)
+    for i, j in itertools.product(range(len(xs)), range(len(ys))):
+        assert k.decrypt(eq1[i, j]) == (1 if (xs[i] & 15) == (ys[j] & 15) else 0)
+        assert k.decrypt(eq9[i, j]) == (9 if xs[i] == ys[j] else 0)
+
+
+def test_fig3_encrypted(oracle_toy_keys):
+    """KID / SIT: every M decrypts to the plaintext diagonal difference and the
+    returned bottom row gives the distance 2 (Fig. fig_myers)."""
+    k = oracle_toy_keys
+    g = golden("fig3_kid_sit.json")
+    A = L.encrypt_string(k, g["a"].encode(), L.ENC_ASCII7, 5)
+    B = L.encrypt_string(k, g["b"].encode(), L.ENC_ASCII7, 6)
+    h_last, rec = L.edit_distance(k, A, B, L.ENC_ASCII7, record=True)
+    _, h, M = P.delta_dp(g["a"], g["b"])
+    for (i, j), ct in rec["M"].items():
+        assert k.decrypt_signed(ct) == M[i, j]
+    assert [k.decrypt_signed(c) for c in h_last] == g["dh_rows"][3]
+    assert L.decrypt_distance(k, 3, h_last) == g["distance"]
+
+
+def test_alg4_order_equals_diagonal_order(oracle_toy_keys):
+    """Section 6.2: cells of one anti-diagonal are independent, so evaluating
+    them as a batch yields bit-identical ciphertexts."""
+    k = oracle_toy_keys
+    A = L.encrypt_string(k, b"ACGTTG", L.ENC_DNA2, 7)
+    B = L.encrypt_string(k, b"CGTAA", L.ENC_DNA2, 8)
+    _, eq9 = L.equality(k, A, B, L.ENC_DNA2)
+    h1, r1 = L.dp(k, 6, 5, lambda i, j: eq9[i - 1, j - 1], order="alg4", record=True)
+    h2, r2 = L.dp(k, 6, 5, lambda i, j: eq9[i - 1, j - 1], order="diagonal", record=True)
+    assert (h1 == h2).all()
+    for key in r1["M"]:
+        assert (r1["M"][key] == r2["M"][key]).all()
+
+
+def test_random_pairs_distance(oracle_toy_keys):
+    k = oracle_toy_keys
+    rng = np.random.default_rng(9)
+    for t in range(4):
+        a = bytes(rng.choice(list(b"ACGT"), size=int(rng.integers(1, 7))))
+        b = bytes(rng.choice(list(b"ACGT"), size=int(rng.integers(1, 7))))
+        A = L.encrypt_string(k, a, L.ENC_DNA2, 100 + t)
+        B = L.encrypt_string(k, b, L.ENC_DNA2, 200 + t)
+        h_last = L.edit_distance(k, A, B, L.ENC_DNA2)
+        assert L.decrypt_distance(k, len(a), h_last) == P.edit_distance(a, b)
+
+
+def test_empty_strings(oracle_toy_keys):
+    k = oracle_toy_keys
+    A = L.encrypt_string(k, b"ACG", L.ENC_DNA2, 1)
+    E = L.encrypt_string(k, b"", L.ENC_DNA2, 2)
+    assert L.decrypt_distance(k, 3, L.edit_distance(k, A, E, L.ENC_DNA2)) == 3
+    assert L.decrypt_distance(k, 0, L.edit_distance(k, E, A, L.ENC_DNA2)) == 3
+    assert L.decrypt_distance(k, 0, L.edit_distance(k, E, E, L.ENC_DNA2)) == 0
+
+
+def test_preprocessing_table_abbey(oracle_toy_keys):
+    """Table tab_pre: one enc(9) per column at the row of the character, zeros
+    elsewhere (stored as eq9, as Section 5 allows)."""
+    k = oracle_toy_keys
+    g = golden("tab_pre_abbey.json")
+    A = L.encrypt_string(k, g["word"].encode(), L.ENC_ASCII7, 12)
+    alpha = g["alphabet"].encode()
+    Tab = L.preprocess(k, A, alpha, L.ENC_ASCII7)
+    dec = [[k.decrypt(Tab[c, i]) // 9 for i in range(5)] for c in range(len(alpha))]
+    for ch, row in g["printed_rows"].items():
+        assert dec[alpha.index(ch.encode())] == row
+    assert all(sum(dec[c][i] for c in range(len(alpha))) == 1 for i in range(5))
+
+
+def test_preprocessed_main_pass_matches(oracle_toy_keys):
+    k = oracle_toy_keys
+    a, b = b"kitten", b"sitting"
+    alpha = bytes(sorted(set(b)))
+    A = L.encrypt_string(k, a, L.ENC_ASCII7, 31)
+    Tab = L.preprocess(k, A, alpha, L.ENC_ASCII7)
+    h_last = L.edit_distance_clear(k, Tab, alpha, b, L.ENC_ASCII7)
+    assert L.decrypt_distance(k, len(a), h_last) == P.edit_distance(a, b) == 3
+
+
+def test_small_dna_full_parameters(oracle_keys):
+    k = oracle_keys
+    a, b = b"GAT", b"GT"
+    A = L.encrypt_string(k, a, L.ENC_DNA2, 41)
+    B = L.encrypt_string(k, b, L.ENC_DNA2, 42)
+    h_last, rec = L.edit_distance(k, A, B, L.ENC_DNA2, record=True)
+    assert L.decrypt_distance(k, 3, h_last) == P.edit_distance(a, b) == 1
+    _, _, M = P.delta_dp(a, b)
+    for (i, j), ct in rec["M"].items():
+        assert k.decrypt_signed(ct) == M[i, j]
