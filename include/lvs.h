@@ -1,0 +1,210 @@
+/*
+ * lvs.h -- C ABI of liblvs, an MI355X (gfx950) implementation of the
+ * Leuvenshtein encrypted edit distance (Legiest, D'Anvers, Spasic, Tran,
+ * Verbauwhede, arXiv 2508.14568).
+ *
+ * Conventions common to every call:
+ *   - Return value: LVS_OK (0) on success, a negative LVS_E_* code on failure;
+ *     lvs_last_error() returns a text for the calling thread's last failure.
+ *   - A ciphertext is a big-key LWE vector of N+1 = 2049 little-endian 64-bit
+ *     words (a_0..a_{N-1}, b) over the torus Z/2^64 with a 5-bit plaintext
+ *     space: value x in Z_32 sits at x * 2^59 (Section 2.2 of the paper).
+ *   - An encrypted string of length L is an array [L][nsym][N+1] words,
+ *     nsym = 2 for 7-bit ASCII (symbols c & 15 and c >> 4, Section 4.3) and 1
+ *     for 2-bit DNA bases (codes 0..3).
+ *   - Pointers named d_* are device pointers on the context's device, h_* and
+ *     other pointers are host pointers.  The library never allocates device
+ *     memory: the caller passes the context arena and per-call workspaces
+ *     whose sizes the *_bytes queries return.  Input buffers are borrowed for
+ *     the duration of the call; device work is enqueued on the context's
+ *     stream and the call returns without waiting for it unless stated.
+ *   - Handles are opaque and released with lvs_free (NULL is ignored).
+ *   - Calls on one context must not overlap (one context per device).
+ */
+#ifndef LVS_H
+#define LVS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LVS_OK = 0,
+    LVS_E_INVAL = -1,        /* bad argument (NULL, size, alignment)           */
+    LVS_E_ALPHABET = -2,     /* symbol outside the alphabet of the encoding   */
+    LVS_E_NOISE_BUDGET = -3, /* strings longer than the no-refresh bound      */
+    LVS_E_NOMEM_HOST = -4,   /* host allocation failed                        */
+    LVS_E_NOMEM_DEVICE = -5, /* caller-provided device memory too small       */
+    LVS_E_DEVICE = -6,       /* HIP runtime error                             */
+    LVS_E_PARAMS = -7        /* parameter set not supported by the kernels    */
+};
+
+typedef enum { LVS_ENC_ASCII7 = 0, LVS_ENC_DNA2 = 1 } lvs_encoding;
+
+/* Lookup-table slots of a context.  EQ = [1,0,..] (Eq. eq_eqlut), EQ9 =
+ * [9,0,..] (Eq. eq_eqlut9), MIN = 1 + min(-eq, dv, dh) under the key
+ * (1 - dv) + 3 (1 + dh) + 9 eq (Eq. eq_keyeq2, Algorithms 1 and 4).  Slots
+ * from LVS_LUT_USER are free for lvs_context_set_lut. */
+enum { LVS_LUT_EQ = 0, LVS_LUT_EQ9 = 1, LVS_LUT_MIN = 2, LVS_LUT_USER = 3, LVS_LUT_SLOTS = 8 };
+
+/* TFHE parameter set; noise standard deviations are given as sigma * 2^64. */
+typedef struct {
+    uint32_t n_lwe, glwe_k, poly_N, pbs_base_log, pbs_level, ks_base_log, ks_level;
+    uint64_t lwe_noise_q64, glwe_noise_q64;
+} lvs_params;
+
+typedef struct lvs_client_key lvs_client_key;
+typedef struct lvs_server_key lvs_server_key;
+typedef struct lvs_context lvs_context;
+
+/* Text of the calling thread's last error (never NULL). */
+const char* lvs_last_error(void);
+
+/* The parameter set the kernels implement: n = 742, k = 1, N = 2048,
+ * bootstrap gadget 2^23 x 1, key switch 2^3 x 5, noise 7.0698e-6 / 2.9404e-16
+ * of q (the TFHE "4-bit message" set the paper's Section 6.1 runs on). */
+int lvs_params_default(lvs_params* out);
+
+/* Words per ciphertext (N + 1). */
+size_t lvs_ct_words(void);
+
+/* ----------------------------------------------------------- host crypto */
+
+/* Key generation from one seed (the client draws the small LWE key, the GLWE
+ * key, the bootstrapping key GGSW(s_i) and the key-switching key with a
+ * counter-based SplitMix64 stream per object).  Both handles are owned by the
+ * caller.  Cost: about a second of host time. */
+int lvs_keygen(const lvs_params* params, uint64_t seed, lvs_client_key** ck, lvs_server_key** sk);
+
+/* Encrypts symbol value mu (0..31) as ciphertext number `index` of the
+ * encryption seed `seed` into h_ct (N+1 words). */
+int lvs_lwe_encrypt(const lvs_client_key* ck, uint32_t mu, uint64_t seed, uint64_t index, uint64_t* h_ct);
+
+/* Decrypts h_ct: *mu in 0..31 and, if phase_err is not NULL, the signed
+ * distance of the phase from mu * 2^59. */
+int lvs_lwe_decrypt(const lvs_client_key* ck, const uint64_t* h_ct, uint32_t* mu, int64_t* phase_err);
+
+/* Encrypts a string (Section 2.1 notation a_1..a_m, split into symbols
+ * a_i^(r)).  Symbol r of character i is ciphertext number i * nsym + r of
+ * `seed`.  h_out holds len * nsym * (N+1) words.  LVS_E_ALPHABET if a
+ * character is >= 128 (ASCII) or >= 4 (DNA codes 0..3). */
+int lvs_encrypt_string(const lvs_client_key* ck, const uint8_t* s, size_t len, int encoding, uint64_t seed,
+                       uint64_t* h_out);
+
+/* Decrypts the result of an edit distance: h_last holds the n bottom-row
+ * difference ciphertexts h[m, 1..n]; *out = m + sum_j dec(h[m, j]) with dec
+ * in {-1, 0, 1} (Fig. fig_myers: the bottom-row differences sum to the
+ * distance; Algorithm 4 returns m plus that row). */
+int lvs_decrypt_distance(const lvs_client_key* ck, const uint64_t* h_last, size_t m, size_t n, int64_t* out);
+
+/* Copies key material out for inspection by tests: kind 0 = small key
+ * (n bytes), 1 = GLWE key (N bytes), 2 = bootstrapping key (n*2*2*N words,
+ * [i][row][mask|body][N]), 3 = key-switching key (N*5*(n+1) words).  With
+ * buf == NULL only *len (bytes) is set. */
+int lvs_key_export(const lvs_client_key* ck, const lvs_server_key* sk, int kind, void* buf, size_t* len);
+
+/* --------------------------------------------------------- device context */
+
+/* Bytes of device memory lvs_context_create needs (bootstrapping key in NTT
+ * form, key-switching key, twiddles, lookup tables). */
+int lvs_context_bytes(const lvs_params* params, size_t* bytes);
+
+/* Uploads the server key into d_arena (at least lvs_context_bytes, 256-byte
+ * aligned, owned by the caller and kept alive while the context lives),
+ * converts the bootstrapping key to the NTT domain, and binds hip_stream (a
+ * hipStream_t; NULL = default stream) on device `device`.  Synchronous. */
+int lvs_context_create(const lvs_server_key* sk, int device, void* hip_stream, void* d_arena, size_t arena_bytes,
+                       lvs_context** out);
+
+/* Replaces the stream work is enqueued on. */
+int lvs_context_set_stream(lvs_context* ctx, void* hip_stream);
+
+/* Installs a 16-entry lookup table f: Z_16 -> Z_32 in slot >= LVS_LUT_USER
+ * (inputs 16..31 read -f(x-16), Section 2.2).  Synchronous. */
+int lvs_context_set_lut(lvs_context* ctx, int slot, const int32_t f16[16]);
+
+/* Waits for all work enqueued on the context's stream. */
+int lvs_sync(lvs_context* ctx);
+
+/* ------------------------------------------------------------- bootstraps */
+
+/* Workspace bytes for lvs_pbs_batch with B ciphertexts. */
+size_t lvs_pbs_workspace_bytes(size_t B);
+
+/* B independent programmable bootstraps (Section 2.2): d_out[b] =
+ * PBS(d_in[b]; table lut(b)) with lut(b) = d_lut_ids[b] if d_lut_ids is not
+ * NULL (device bytes), else lut_id.  Each runs key switch -> modulus switch ->
+ * blind rotation -> sample extraction; results are bit-identical to the
+ * schoolbook definition.  d_in and d_out are [B][N+1] and must not overlap. */
+int lvs_pbs_batch(lvs_context* ctx, const uint64_t* d_in, const uint8_t* d_lut_ids, int lut_id, size_t B,
+                  uint64_t* d_out, void* d_work, size_t work_bytes);
+
+/* --------------------------------------------------------- edit distance */
+
+/* Workspace bytes for lvs_equality. */
+size_t lvs_equality_workspace_bytes(size_t m, size_t n, int encoding);
+
+/* Equality of every character pair, all m*n pairs independent of the DP
+ * (Section 4): ASCII follows Algorithm 3 with the eq9 table of Algorithm 4,
+ * eq1 = PBS(x1 - y1; LUT_eq), eq9 = PBS(2 (x2 - y2) + (1 - eq1); LUT_eq9);
+ * DNA uses one bootstrap, eq9 = PBS(x - y; LUT_eq9).  d_eq9 receives the
+ * [m][n] matrix of Enc(9 [a_i = b_j]) (row i = character of a). */
+int lvs_equality(lvs_context* ctx, const uint64_t* d_a, size_t m, const uint64_t* d_b, size_t n, int encoding,
+                 uint64_t* d_eq9, void* d_work, size_t work_bytes);
+
+/* Workspace bytes for lvs_edit_distance_eq9. */
+size_t lvs_edit_distance_eq9_workspace_bytes(size_t m, size_t n);
+
+/* Algorithm 1 over every cell (exact distance, no band) given the [m][n]
+ * eq9 matrix: key = (1 - v[i,j-1]) + 3 (1 + h[i-1,j]) + eq9[i,j]
+ * (Eq. eq_keyeq2), M = PBS(key; LUT_min), v[i,j] = M - h[i-1,j],
+ * h[i,j] = M - v[i,j-1], boundary v[i,0] = h[0,j] = Enc(1), evaluated one
+ * anti-diagonal per batch.  d_h_last receives h[m, 1..n].  d_trace, if not
+ * NULL, receives every M as an [m][n] ciphertext matrix (for checking). */
+int lvs_edit_distance_eq9(lvs_context* ctx, const uint64_t* d_eq9, size_t m, size_t n, uint64_t* d_h_last,
+                          uint64_t* d_trace, void* d_work, size_t work_bytes);
+
+/* Workspace bytes for lvs_edit_distance on an m x n problem. */
+size_t lvs_edit_distance_workspace_bytes(size_t m, size_t n, int encoding);
+
+/* Algorithm 4 (Appendix) on two encrypted strings: the equality of every
+ * character pair (Algorithm 3: 2 PBS for ASCII, 1 PBS for DNA, Section 4),
+ * then the single-PBS cell update of Eq. (mye_eq_2) with key
+ * (1 - v) + 3 (1 + h) + eq9 over every cell, anti-diagonal by anti-diagonal
+ * (Section 6.2: cells on one anti-diagonal are independent).  d_a is the
+ * encrypted [m][nsym][N+1] string, d_b [n][nsym][N+1]; d_h_last receives the n
+ * ciphertexts h[m, 1..n].  m = 0 or n = 0 returns n noise-free encryptions of
+ * 1 (distance max(m, n)).  LVS_E_NOISE_BUDGET if min(m, n) exceeds 1024. */
+int lvs_edit_distance(lvs_context* ctx, const uint64_t* d_a, size_t m, const uint64_t* d_b, size_t n, int encoding,
+                      uint64_t* d_h_last, void* d_work, size_t work_bytes);
+
+/* Workspace bytes for lvs_preprocess. */
+size_t lvs_preprocess_workspace_bytes(size_t m, size_t alphabet_len, int encoding);
+
+/* Section 5 preprocessing of an encrypted string against a cleartext
+ * alphabet S: d_table[c][i] = Enc(9 [a_i = S_c]) ([alen][m][N+1] words), at a
+ * cost of nsym * alen * m bootstraps. */
+int lvs_preprocess(lvs_context* ctx, const uint64_t* d_a, size_t m, int encoding, const uint8_t* alphabet,
+                   size_t alen, uint64_t* d_table, void* d_work, size_t work_bytes);
+
+/* Workspace bytes for lvs_edit_distance_clear. */
+size_t lvs_edit_distance_clear_workspace_bytes(size_t m, size_t n);
+
+/* Main pass with one cleartext string b (Section 5): eq9[i,j] is read from
+ * the preprocessing table row of b_j, so every cell costs one bootstrap.
+ * LVS_E_ALPHABET if some b_j is not in the table's alphabet. */
+int lvs_edit_distance_clear(lvs_context* ctx, const uint64_t* d_table, size_t m, const uint8_t* alphabet,
+                            size_t alen, const uint8_t* b, size_t n, uint64_t* d_h_last, void* d_work,
+                            size_t work_bytes);
+
+/* Releases a handle created by the library (keys, contexts). */
+void lvs_free(void* handle);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LVS_H */

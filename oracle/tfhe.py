@@ -175,8 +175,11 @@ class Keys:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().orc_keys_free(h)
+        if h and _LIB is not None:
+            try:
+                _LIB.orc_keys_free(h)
+            except TypeError:       # interpreter shutdown
+                pass
             self._h = None
 
     @property

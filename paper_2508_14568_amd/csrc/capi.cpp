@@ -1,0 +1,604 @@
+// C ABI of liblvs: keys, device context, bootstrap batches and the plain
+// anti-diagonal edit-distance driver (Algorithm 4 of arXiv 2508.14568 with the
+// Section 6.2 observation that cells of one anti-diagonal are independent).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+#include "lvs_internal.h"
+
+namespace lvs {
+
+namespace {
+
+thread_local std::string g_error = "no error";
+
+constexpr size_t kAlign = 256;
+constexpr size_t kPbsChunk = 8192;          // bootstraps per key-switch / blind-rotation launch
+constexpr size_t kMaxLen = 4096;            // longest string the no-refresh noise budget admits
+constexpr size_t W = kCtWords;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Context : Handle {
+    lvs_params p{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint8_t* arena = nullptr;
+    size_t arena_bytes = 0;
+    uint32_t* bsk = nullptr;      // NTT domain
+    uint64_t* ksk = nullptr;
+    uint32_t* tw = nullptr;       // fwd, fwd_s, inv, inv_s, scale, scale_s
+    uint64_t* luts = nullptr;     // [LVS_LUT_SLOTS][N]
+    DevTables tables{};
+};
+
+struct ArenaLayout {
+    size_t bsk, ksk, tw, luts, total;
+};
+
+ArenaLayout arena_layout() {
+    ArenaLayout L{};
+    size_t off = 0;
+    L.bsk = off;
+    off = align_up(off + sizeof(uint32_t) * size_t(kSmallN) * kPrimes * 4 * kN);
+    L.ksk = off;
+    off = align_up(off + sizeof(uint64_t) * size_t(kKsRows) * kSmallWords);
+    L.tw = off;
+    off = align_up(off + sizeof(uint32_t) * (4 * size_t(kPrimes) * kN + 2 * kPrimes));
+    L.luts = off;
+    off = align_up(off + sizeof(uint64_t) * size_t(LVS_LUT_SLOTS) * kN);
+    L.total = off;
+    return L;
+}
+
+// Test polynomial of a 16-entry table: coefficient t holds f(t / 128) * 2^59,
+// then the polynomial is multiplied by X^-64 so each value's box is centred.
+void build_test_poly(const int32_t f16[16], uint64_t* out) {
+    std::vector<uint64_t> v(kN);
+    const int box = kN / 16;
+    for (int t = 0; t < kN; ++t) v[t] = uint64_t(uint32_t(f16[t / box]) & 31u) << kDeltaLog;
+    const int half = box / 2;
+    for (int t = 0; t < kN; ++t) out[t] = (t + half < kN) ? v[t + half] : uint64_t(0) - v[t + half - kN];
+}
+
+#define LVS_HIP(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                   \
+            return LVS_E_DEVICE;                                                           \
+        }                                                                                  \
+    } while (0)
+
+#define LVS_REQUIRE(cond, code, msg) \
+    do {                             \
+        if (!(cond)) {               \
+            set_error(msg);          \
+            return (code);           \
+        }                            \
+    } while (0)
+
+Context* as_ctx(lvs_context* c) {
+    auto* h = reinterpret_cast<Context*>(c);
+    return (h && h->kind == kContext) ? h : nullptr;
+}
+const ClientKey* as_ck(const lvs_client_key* c) {
+    auto* h = reinterpret_cast<const ClientKey*>(c);
+    return (h && h->kind == kClientKey) ? h : nullptr;
+}
+const ServerKey* as_sk(const lvs_server_key* c) {
+    auto* h = reinterpret_cast<const ServerKey*>(c);
+    return (h && h->kind == kServerKey) ? h : nullptr;
+}
+
+int nsym_of(int encoding) { return encoding == LVS_ENC_ASCII7 ? 2 : 1; }
+
+// ------------------------------------------------------------ bootstraps
+
+size_t pbs_ws(size_t B) { return align_up(sizeof(uint64_t) * std::min(B, kPbsChunk) * kSmallWords); }
+
+int run_pbs(Context* C, const uint64_t* in, const uint8_t* lut_ids, int lut, size_t B, uint64_t* out,
+            uint64_t* ks_buf) {
+    for (size_t b0 = 0; b0 < B; b0 += kPbsChunk) {
+        const int nb = int(std::min(kPbsChunk, B - b0));
+        LVS_HIP(launch_keyswitch(in + b0 * W, C->ksk, ks_buf, nb, C->stream));
+        LVS_HIP(launch_blind_rotate(ks_buf, lut_ids ? lut_ids + b0 : nullptr, lut, C->luts, C->bsk, C->tables,
+                                    out + b0 * W, nb, 0, C->stream));
+    }
+    return LVS_OK;
+}
+
+// --------------------------------------------------------- edit distance
+
+struct DpLayout {
+    size_t V, H, key, M, ks, col, total;
+};
+
+DpLayout dp_layout(size_t m, size_t n) {
+    DpLayout L{};
+    const size_t width = std::max<size_t>(1, std::min(m, n));
+    size_t off = 0;
+    L.V = off; off = align_up(off + sizeof(uint64_t) * (m + 1) * W);
+    L.H = off; off = align_up(off + sizeof(uint64_t) * (n + 1) * W);
+    L.key = off; off = align_up(off + sizeof(uint64_t) * width * W);
+    L.M = off; off = align_up(off + sizeof(uint64_t) * width * W);
+    L.ks = off; off = align_up(off + pbs_ws(width));
+    L.col = off; off = align_up(off + sizeof(int32_t) * std::max<size_t>(n, 1));
+    L.total = off;
+    return L;
+}
+
+// The anti-diagonal wavefront: for s = 2 .. m+n, the cells (i, s-i) form one
+// batch: key (linear), bootstrap with LUT_min, difference update (linear).
+int run_dp(Context* C, size_t m, size_t n, const uint64_t* EQ, size_t eq_si, size_t eq_sj, const int32_t* d_col,
+           uint64_t* d_h_last, uint64_t* d_trace, uint8_t* ws) {
+    const DpLayout L = dp_layout(m, n);
+    auto* V = reinterpret_cast<uint64_t*>(ws + L.V);
+    auto* H = reinterpret_cast<uint64_t*>(ws + L.H);
+    auto* key = reinterpret_cast<uint64_t*>(ws + L.key);
+    auto* M = reinterpret_cast<uint64_t*>(ws + L.M);
+    auto* ks = reinterpret_cast<uint64_t*>(ws + L.ks);
+    LVS_HIP(launch_trivial(V, int(m + 1), 1, C->stream));
+    LVS_HIP(launch_trivial(H, int(n + 1), 1, C->stream));
+    for (size_t s = 2; s <= m + n; ++s) {
+        const size_t i_lo = (s > n + 1) ? s - n : 1;
+        const size_t i_hi = std::min(m, s - 1);
+        const int count = int(i_hi - i_lo + 1);
+        LVS_HIP(launch_key(V, H, EQ, eq_si, eq_sj, d_col, key, int(i_lo), int(s), count, C->stream));
+        int rc = run_pbs(C, key, nullptr, LVS_LUT_MIN, size_t(count), M, ks);
+        if (rc) return rc;
+        LVS_HIP(launch_update(V, H, M, int(i_lo), int(s), count, d_trace, int(n), C->stream));
+    }
+    LVS_HIP(hipMemcpyAsync(d_h_last, H + W, sizeof(uint64_t) * n * W, hipMemcpyDeviceToDevice, C->stream));
+    return LVS_OK;
+}
+
+struct EqLayout {
+    size_t z, eq1, eq9, ks, total;
+};
+
+// Equality phase buffers for cells processed in chunks of kPbsChunk.
+EqLayout eq_layout(size_t cells) {
+    EqLayout L{};
+    const size_t ch = std::max<size_t>(1, std::min(cells, kPbsChunk));
+    size_t off = 0;
+    L.z = off; off = align_up(off + sizeof(uint64_t) * ch * W);
+    L.eq1 = off; off = align_up(off + sizeof(uint64_t) * ch * W);
+    L.ks = off; off = align_up(off + pbs_ws(ch));
+    L.eq9 = off; off = align_up(off + sizeof(uint64_t) * cells * W);   // last: callers may supply it
+    L.total = off;
+    return L;
+}
+
+// eq9[c] for cells c = i * n + j of A x B (Algorithm 3 / Algorithm 4 equality;
+// DNA: one bootstrap of x - y).  B == nullptr: cleartext symbols per column.
+int run_equality_into(Context* C, const uint64_t* A, size_t m, const uint64_t* B, const uint8_t* clear_lo,
+                      const uint8_t* clear_hi, size_t n, int encoding, uint64_t* eq9, uint8_t* ws, EqLayout L) {
+    const size_t cells = m * n;
+    auto* z = reinterpret_cast<uint64_t*>(ws + L.z);
+    auto* eq1 = reinterpret_cast<uint64_t*>(ws + L.eq1);
+    auto* ks = reinterpret_cast<uint64_t*>(ws + L.ks);
+    const int ns = nsym_of(encoding);
+    const int stride = ns * int(W);
+    for (size_t c0 = 0; c0 < cells; c0 += kPbsChunk) {
+        const long cnt = long(std::min(kPbsChunk, cells - c0));
+        if (encoding == LVS_ENC_DNA2) {
+            LVS_HIP(launch_pair(A, stride, 0, B, stride, 0, clear_lo, nullptr, 1, 0, z, int(n), long(c0), cnt,
+                                C->stream));
+            int rc = run_pbs(C, z, nullptr, LVS_LUT_EQ9, size_t(cnt), eq9 + c0 * W, ks);
+            if (rc) return rc;
+        } else {
+            // z1 = x1 - y1; eq1 = PBS(z1; LUT_eq)
+            LVS_HIP(launch_pair(A, stride, 0, B, stride, 0, clear_lo, nullptr, 1, 0, z, int(n), long(c0), cnt,
+                                C->stream));
+            int rc = run_pbs(C, z, nullptr, LVS_LUT_EQ, size_t(cnt), eq1, ks);
+            if (rc) return rc;
+            // z2 = 2 (x2 - y2) + (1 - eq1); eq9 = PBS(z2; LUT_eq9)
+            LVS_HIP(launch_pair(A, stride, 1, B, stride, 1, clear_hi, eq1, 2, uint64_t(1) << kDeltaLog, z, int(n),
+                                long(c0), cnt, C->stream));
+            rc = run_pbs(C, z, nullptr, LVS_LUT_EQ9, size_t(cnt), eq9 + c0 * W, ks);
+            if (rc) return rc;
+        }
+    }
+    return LVS_OK;
+}
+
+int run_equality(Context* C, const uint64_t* A, size_t m, const uint64_t* B, const uint8_t* clear_lo,
+                 const uint8_t* clear_hi, size_t n, int encoding, uint64_t* eq9, uint8_t* ws) {
+    return run_equality_into(C, A, m, B, clear_lo, clear_hi, n, encoding, eq9, ws, eq_layout(m * n));
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+bool params_supported(const lvs_params& p) {
+    return p.n_lwe == uint32_t(kSmallN) && p.glwe_k == 1 && p.poly_N == uint32_t(kN) &&
+           p.pbs_base_log == uint32_t(kPbsBaseLog) && p.pbs_level == 1 && p.ks_base_log == uint32_t(kKsBaseLog) &&
+           p.ks_level == uint32_t(kKsLevel);
+}
+
+}  // namespace lvs
+
+using namespace lvs;
+
+extern "C" {
+
+const char* lvs_last_error(void) { return g_error.c_str(); }
+
+int lvs_params_default(lvs_params* out) {
+    LVS_REQUIRE(out, LVS_E_INVAL, "lvs_params_default: out is NULL");
+    out->n_lwe = kSmallN;
+    out->glwe_k = 1;
+    out->poly_N = kN;
+    out->pbs_base_log = kPbsBaseLog;
+    out->pbs_level = 1;
+    out->ks_base_log = kKsBaseLog;
+    out->ks_level = kKsLevel;
+    out->lwe_noise_q64 = 130415703530680ULL;   // 7.069849454709433e-06 * 2^64
+    out->glwe_noise_q64 = 5424ULL;             // 2.9403601535432533e-16 * 2^64
+    return LVS_OK;
+}
+
+size_t lvs_ct_words(void) { return kCtWords; }
+
+int lvs_keygen(const lvs_params* params, uint64_t seed, lvs_client_key** ck, lvs_server_key** sk) {
+    LVS_REQUIRE(params && ck && sk, LVS_E_INVAL, "lvs_keygen: NULL argument");
+    LVS_REQUIRE(params_supported(*params), LVS_E_PARAMS, "lvs_keygen: unsupported parameter set");
+    ClientKey* c = new (std::nothrow) ClientKey();
+    ServerKey* s = new (std::nothrow) ServerKey();
+    if (!c || !s) {
+        delete c;
+        delete s;
+        set_error("lvs_keygen: out of host memory");
+        return LVS_E_NOMEM_HOST;
+    }
+    c->kind = kClientKey;
+    s->kind = kServerKey;
+    try {
+        keygen(*params, seed, *c, *s);
+    } catch (const std::bad_alloc&) {
+        delete c;
+        delete s;
+        set_error("lvs_keygen: out of host memory");
+        return LVS_E_NOMEM_HOST;
+    }
+    *ck = reinterpret_cast<lvs_client_key*>(c);
+    *sk = reinterpret_cast<lvs_server_key*>(s);
+    return LVS_OK;
+}
+
+int lvs_lwe_encrypt(const lvs_client_key* ck, uint32_t mu, uint64_t seed, uint64_t index, uint64_t* h_ct) {
+    const ClientKey* c = as_ck(ck);
+    LVS_REQUIRE(c && h_ct, LVS_E_INVAL, "lvs_lwe_encrypt: bad argument");
+    LVS_REQUIRE(mu < 32, LVS_E_INVAL, "lvs_lwe_encrypt: mu must be in 0..31");
+    encrypt(*c, mu, seed, index, h_ct);
+    return LVS_OK;
+}
+
+int lvs_lwe_decrypt(const lvs_client_key* ck, const uint64_t* h_ct, uint32_t* mu, int64_t* phase_err) {
+    const ClientKey* c = as_ck(ck);
+    LVS_REQUIRE(c && h_ct && mu, LVS_E_INVAL, "lvs_lwe_decrypt: bad argument");
+    const uint64_t ph = phase(*c, h_ct);
+    const uint32_t v = uint32_t((((ph >> (kDeltaLog - 1)) + 1) >> 1) & 31u);
+    *mu = v;
+    if (phase_err) *phase_err = int64_t(ph - (uint64_t(v) << kDeltaLog));
+    return LVS_OK;
+}
+
+int lvs_encrypt_string(const lvs_client_key* ck, const uint8_t* s, size_t len, int encoding, uint64_t seed,
+                       uint64_t* h_out) {
+    const ClientKey* c = as_ck(ck);
+    LVS_REQUIRE(c && (s || len == 0) && (h_out || len == 0), LVS_E_INVAL, "lvs_encrypt_string: bad argument");
+    LVS_REQUIRE(encoding == LVS_ENC_ASCII7 || encoding == LVS_ENC_DNA2, LVS_E_INVAL, "unknown encoding");
+    const int ns = nsym_of(encoding);
+    for (size_t i = 0; i < len; ++i)
+        LVS_REQUIRE(encoding == LVS_ENC_ASCII7 ? s[i] < 128 : s[i] < 4, LVS_E_ALPHABET,
+                    "lvs_encrypt_string: symbol outside the alphabet");
+    for (size_t i = 0; i < len; ++i) {
+        uint32_t sym[2];
+        if (encoding == LVS_ENC_ASCII7) {
+            sym[0] = s[i] & 15u;
+            sym[1] = s[i] >> 4;
+        } else {
+            sym[0] = s[i];
+        }
+        for (int r = 0; r < ns; ++r) encrypt(*c, sym[r], seed, i * ns + r, h_out + (i * ns + r) * W);
+    }
+    return LVS_OK;
+}
+
+int lvs_decrypt_distance(const lvs_client_key* ck, const uint64_t* h_last, size_t m, size_t n, int64_t* out) {
+    const ClientKey* c = as_ck(ck);
+    LVS_REQUIRE(c && (h_last || n == 0) && out, LVS_E_INVAL, "lvs_decrypt_distance: bad argument");
+    int64_t d = int64_t(m);
+    for (size_t j = 0; j < n; ++j) {
+        const uint64_t ph = phase(*c, h_last + j * W);
+        uint32_t v = uint32_t((((ph >> (kDeltaLog - 1)) + 1) >> 1) & 31u);
+        d += (v >= 16) ? int64_t(v) - 32 : int64_t(v);
+    }
+    *out = d;
+    return LVS_OK;
+}
+
+int lvs_key_export(const lvs_client_key* ck, const lvs_server_key* sk, int kind, void* buf, size_t* len) {
+    LVS_REQUIRE(len, LVS_E_INVAL, "lvs_key_export: len is NULL");
+    const ClientKey* c = as_ck(ck);
+    const ServerKey* s = as_sk(sk);
+    const void* src = nullptr;
+    size_t bytes = 0;
+    if (kind == 0 && c) { src = c->s.data(); bytes = c->s.size(); }
+    else if (kind == 1 && c) { src = c->S.data(); bytes = c->S.size(); }
+    else if (kind == 2 && s) { src = s->bsk.data(); bytes = s->bsk.size() * 8; }
+    else if (kind == 3 && s) { src = s->ksk.data(); bytes = s->ksk.size() * 8; }
+    else { set_error("lvs_key_export: bad kind or handle"); return LVS_E_INVAL; }
+    if (buf) {
+        LVS_REQUIRE(*len >= bytes, LVS_E_INVAL, "lvs_key_export: buffer too small");
+        std::memcpy(buf, src, bytes);
+    }
+    *len = bytes;
+    return LVS_OK;
+}
+
+int lvs_context_bytes(const lvs_params* params, size_t* bytes) {
+    LVS_REQUIRE(params && bytes, LVS_E_INVAL, "lvs_context_bytes: NULL argument");
+    LVS_REQUIRE(params_supported(*params), LVS_E_PARAMS, "lvs_context_bytes: unsupported parameter set");
+    *bytes = arena_layout().total;
+    return LVS_OK;
+}
+
+int lvs_context_create(const lvs_server_key* sk, int device, void* hip_stream, void* d_arena, size_t arena_bytes,
+                       lvs_context** out) {
+    const ServerKey* s = as_sk(sk);
+    LVS_REQUIRE(s && out && d_arena, LVS_E_INVAL, "lvs_context_create: NULL argument");
+    LVS_REQUIRE(reinterpret_cast<uintptr_t>(d_arena) % kAlign == 0, LVS_E_INVAL,
+                "lvs_context_create: arena must be 256-byte aligned");
+    const ArenaLayout L = arena_layout();
+    LVS_REQUIRE(arena_bytes >= L.total, LVS_E_NOMEM_DEVICE, "lvs_context_create: arena too small");
+    LVS_HIP(hipSetDevice(device));
+    Context* C = new (std::nothrow) Context();
+    LVS_REQUIRE(C, LVS_E_NOMEM_HOST, "lvs_context_create: out of host memory");
+    C->kind = kContext;
+    C->p = s->p;
+    C->device = device;
+    C->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    C->arena = reinterpret_cast<uint8_t*>(d_arena);
+    C->arena_bytes = arena_bytes;
+    C->bsk = reinterpret_cast<uint32_t*>(C->arena + L.bsk);
+    C->ksk = reinterpret_cast<uint64_t*>(C->arena + L.ksk);
+    C->tw = reinterpret_cast<uint32_t*>(C->arena + L.tw);
+    C->luts = reinterpret_cast<uint64_t*>(C->arena + L.luts);
+    const PrimeTables& T = prime_tables();
+    const size_t tn = size_t(kPrimes) * kN;
+    std::vector<uint32_t> tw(4 * tn + 2 * kPrimes);
+    std::copy(T.fwd.begin(), T.fwd.end(), tw.begin());
+    std::copy(T.fwd_shoup.begin(), T.fwd_shoup.end(), tw.begin() + tn);
+    std::copy(T.inv.begin(), T.inv.end(), tw.begin() + 2 * tn);
+    std::copy(T.inv_shoup.begin(), T.inv_shoup.end(), tw.begin() + 3 * tn);
+    for (int r = 0; r < kPrimes; ++r) {
+        tw[4 * tn + r] = T.bsk_scale[r];
+        tw[4 * tn + kPrimes + r] = uint32_t((uint64_t(T.bsk_scale[r]) << 32) / T.p[r]);
+    }
+    C->tables = DevTables{C->tw, C->tw + tn, C->tw + 2 * tn, C->tw + 3 * tn, C->tw + 4 * tn, C->tw + 4 * tn + kPrimes};
+    auto fail = [&](int code) { delete C; return code; };
+    hipError_t e = hipMemcpy(C->tw, tw.data(), tw.size() * 4, hipMemcpyHostToDevice);
+    // the 64-bit bootstrapping key is staged in the key-switching key's slot
+    if (e == hipSuccess) e = hipMemcpy(C->ksk, s->bsk.data(), s->bsk.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_bsk_convert(C->ksk, C->bsk, C->tables, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(C->ksk, s->ksk.data(), s->ksk.size() * 8, hipMemcpyHostToDevice);
+    std::vector<uint64_t> luts(size_t(LVS_LUT_SLOTS) * kN, 0);
+    const int32_t f_eq[16] = {1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int32_t f_eq9[16] = {9, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    // 1 + min(-eq, dv, dh) under key (1 - dv) + 3 (1 + dh) + 9 eq: the value is 1
+    // exactly when eq = 0, dh >= 0 and dv >= 0, i.e. keys 3, 4, 6, 7.
+    const int32_t f_min[16] = {0, 0, 0, 1, 1, 0, 1, 1, 0, 0, 0, 0, 0, 0, 0, 0};
+    build_test_poly(f_eq, &luts[size_t(LVS_LUT_EQ) * kN]);
+    build_test_poly(f_eq9, &luts[size_t(LVS_LUT_EQ9) * kN]);
+    build_test_poly(f_min, &luts[size_t(LVS_LUT_MIN) * kN]);
+    if (e == hipSuccess) e = hipMemcpy(C->luts, luts.data(), luts.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        set_error(std::string("lvs_context_create: ") + hipGetErrorString(e));
+        return fail(LVS_E_DEVICE);
+    }
+    *out = reinterpret_cast<lvs_context*>(C);
+    return LVS_OK;
+}
+
+int lvs_context_set_stream(lvs_context* ctx, void* hip_stream) {
+    Context* C = as_ctx(ctx);
+    LVS_REQUIRE(C, LVS_E_INVAL, "lvs_context_set_stream: bad context");
+    C->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return LVS_OK;
+}
+
+int lvs_context_set_lut(lvs_context* ctx, int slot, const int32_t f16[16]) {
+    Context* C = as_ctx(ctx);
+    LVS_REQUIRE(C && f16, LVS_E_INVAL, "lvs_context_set_lut: bad argument");
+    LVS_REQUIRE(slot >= LVS_LUT_USER && slot < LVS_LUT_SLOTS, LVS_E_INVAL, "lvs_context_set_lut: bad slot");
+    std::vector<uint64_t> poly(kN);
+    build_test_poly(f16, poly.data());
+    LVS_HIP(hipSetDevice(C->device));
+    LVS_HIP(hipMemcpyAsync(C->luts + size_t(slot) * kN, poly.data(), kN * 8, hipMemcpyHostToDevice, C->stream));
+    LVS_HIP(hipStreamSynchronize(C->stream));
+    return LVS_OK;
+}
+
+int lvs_sync(lvs_context* ctx) {
+    Context* C = as_ctx(ctx);
+    LVS_REQUIRE(C, LVS_E_INVAL, "lvs_sync: bad context");
+    LVS_HIP(hipStreamSynchronize(C->stream));
+    return LVS_OK;
+}
+
+size_t lvs_pbs_workspace_bytes(size_t B) { return pbs_ws(std::max<size_t>(B, 1)); }
+
+int lvs_pbs_batch(lvs_context* ctx, const uint64_t* d_in, const uint8_t* d_lut_ids, int lut_id, size_t B,
+                  uint64_t* d_out, void* d_work, size_t work_bytes) {
+    Context* C = as_ctx(ctx);
+    LVS_REQUIRE(C, LVS_E_INVAL, "lvs_pbs_batch: bad context");
+    if (B == 0) return LVS_OK;
+    LVS_REQUIRE(d_in && d_out && d_work, LVS_E_INVAL, "lvs_pbs_batch: NULL buffer");
+    LVS_REQUIRE(d_lut_ids || (lut_id >= 0 && lut_id < LVS_LUT_SLOTS), LVS_E_INVAL, "lvs_pbs_batch: bad lut id");
+    LVS_REQUIRE(work_bytes >= lvs_pbs_workspace_bytes(B), LVS_E_NOMEM_DEVICE, "lvs_pbs_batch: workspace too small");
+    LVS_REQUIRE(d_out + B * W <= d_in || d_in + B * W <= d_out, LVS_E_INVAL, "lvs_pbs_batch: in and out overlap");
+    LVS_HIP(hipSetDevice(C->device));
+    return run_pbs(C, d_in, d_lut_ids, lut_id, B, d_out, reinterpret_cast<uint64_t*>(d_work));
+}
+
+size_t lvs_equality_workspace_bytes(size_t m, size_t n, int encoding) {
+    (void)encoding;
+    return eq_layout(m * n).eq9;
+}
+
+int lvs_equality(lvs_context* ctx, const uint64_t* d_a, size_t m, const uint64_t* d_b, size_t n, int encoding,
+                 uint64_t* d_eq9, void* d_work, size_t work_bytes) {
+    Context* C = as_ctx(ctx);
+    LVS_REQUIRE(C, LVS_E_INVAL, "lvs_equality: bad context");
+    LVS_REQUIRE(encoding == LVS_ENC_ASCII7 || encoding == LVS_ENC_DNA2, LVS_E_INVAL, "unknown encoding");
+    if (m == 0 || n == 0) return LVS_OK;
+    LVS_REQUIRE(d_a && d_b && d_eq9 && d_work, LVS_E_INVAL, "lvs_equality: NULL buffer");
+    LVS_REQUIRE(work_bytes >= lvs_equality_workspace_bytes(m, n, encoding), LVS_E_NOMEM_DEVICE,
+                "lvs_equality: workspace too small");
+    LVS_HIP(hipSetDevice(C->device));
+    // the caller's buffer takes the place of the layout's last slot (eq9)
+    const EqLayout E = eq_layout(m * n);
+    uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
+    return run_equality_into(C, d_a, m, d_b, nullptr, nullptr, n, encoding, d_eq9, ws, E);
+}
+
+size_t lvs_edit_distance_eq9_workspace_bytes(size_t m, size_t n) { return dp_layout(m, n).total; }
+
+int lvs_edit_distance_eq9(lvs_context* ctx, const uint64_t* d_eq9, size_t m, size_t n, uint64_t* d_h_last,
+                          uint64_t* d_trace, void* d_work, size_t work_bytes) {
+    Context* C = as_ctx(ctx);
+    LVS_REQUIRE(C, LVS_E_INVAL, "lvs_edit_distance_eq9: bad context");
+    LVS_REQUIRE((d_eq9 || m * n == 0) && (d_h_last || n == 0), LVS_E_INVAL, "lvs_edit_distance_eq9: NULL buffer");
+    LVS_REQUIRE(std::min(m, n) <= kMaxLen, LVS_E_NOISE_BUDGET, "lvs_edit_distance_eq9: noise budget");
+    LVS_HIP(hipSetDevice(C->device));
+    if (n == 0) return LVS_OK;
+    if (m == 0) {
+        LVS_HIP(launch_trivial(d_h_last, int(n), 1, C->stream));
+        return LVS_OK;
+    }
+    LVS_REQUIRE(d_work && work_bytes >= lvs_edit_distance_eq9_workspace_bytes(m, n), LVS_E_NOMEM_DEVICE,
+                "lvs_edit_distance_eq9: workspace too small");
+    return run_dp(C, m, n, d_eq9, n, 1, nullptr, d_h_last, d_trace, reinterpret_cast<uint8_t*>(d_work));
+}
+
+size_t lvs_edit_distance_workspace_bytes(size_t m, size_t n, int encoding) {
+    (void)encoding;
+    const size_t cells = m * n;
+    return eq_layout(cells).total + dp_layout(m, n).total;
+}
+
+int lvs_edit_distance(lvs_context* ctx, const uint64_t* d_a, size_t m, const uint64_t* d_b, size_t n, int encoding,
+                      uint64_t* d_h_last, void* d_work, size_t work_bytes) {
+    Context* C = as_ctx(ctx);
+    LVS_REQUIRE(C, LVS_E_INVAL, "lvs_edit_distance: bad context");
+    LVS_REQUIRE(encoding == LVS_ENC_ASCII7 || encoding == LVS_ENC_DNA2, LVS_E_INVAL, "unknown encoding");
+    LVS_REQUIRE((d_a || m == 0) && (d_b || n == 0) && (d_h_last || n == 0), LVS_E_INVAL,
+                "lvs_edit_distance: NULL buffer");
+    LVS_REQUIRE(std::min(m, n) <= kMaxLen, LVS_E_NOISE_BUDGET, "lvs_edit_distance: strings exceed the noise budget");
+    LVS_HIP(hipSetDevice(C->device));
+    if (n == 0) return LVS_OK;
+    if (m == 0) {
+        LVS_HIP(launch_trivial(d_h_last, int(n), 1, C->stream));
+        return LVS_OK;
+    }
+    LVS_REQUIRE(d_work && work_bytes >= lvs_edit_distance_workspace_bytes(m, n, encoding), LVS_E_NOMEM_DEVICE,
+                "lvs_edit_distance: workspace too small");
+    uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
+    const EqLayout E = eq_layout(m * n);
+    auto* eq9 = reinterpret_cast<uint64_t*>(ws + E.eq9);
+    int rc = run_equality(C, d_a, m, d_b, nullptr, nullptr, n, encoding, eq9, ws);
+    if (rc) return rc;
+    uint8_t* dpws = ws + E.total;
+    return run_dp(C, m, n, eq9, n, 1, nullptr, d_h_last, nullptr, dpws);
+}
+
+size_t lvs_preprocess_workspace_bytes(size_t m, size_t alphabet_len, int encoding) {
+    (void)encoding;
+    const size_t cells = m * alphabet_len;
+    return eq_layout(cells).total + align_up(2 * std::max<size_t>(alphabet_len, 1));
+}
+
+int lvs_preprocess(lvs_context* ctx, const uint64_t* d_a, size_t m, int encoding, const uint8_t* alphabet,
+                   size_t alen, uint64_t* d_table, void* d_work, size_t work_bytes) {
+    Context* C = as_ctx(ctx);
+    LVS_REQUIRE(C, LVS_E_INVAL, "lvs_preprocess: bad context");
+    LVS_REQUIRE(encoding == LVS_ENC_ASCII7 || encoding == LVS_ENC_DNA2, LVS_E_INVAL, "unknown encoding");
+    if (m == 0 || alen == 0) return LVS_OK;
+    LVS_REQUIRE(d_a && alphabet && d_table && d_work, LVS_E_INVAL, "lvs_preprocess: NULL buffer");
+    LVS_REQUIRE(work_bytes >= lvs_preprocess_workspace_bytes(m, alen, encoding), LVS_E_NOMEM_DEVICE,
+                "lvs_preprocess: workspace too small");
+    std::vector<uint8_t> syms(2 * alen);
+    for (size_t c = 0; c < alen; ++c) {
+        LVS_REQUIRE(encoding == LVS_ENC_ASCII7 ? alphabet[c] < 128 : alphabet[c] < 4, LVS_E_ALPHABET,
+                    "lvs_preprocess: alphabet symbol outside the encoding");
+        syms[c] = encoding == LVS_ENC_ASCII7 ? (alphabet[c] & 15) : alphabet[c];
+        syms[alen + c] = encoding == LVS_ENC_ASCII7 ? (alphabet[c] >> 4) : 0;
+    }
+    LVS_HIP(hipSetDevice(C->device));
+    uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
+    const EqLayout E = eq_layout(m * alen);
+    uint8_t* d_syms = ws + E.total;
+    LVS_HIP(hipMemcpyAsync(d_syms, syms.data(), syms.size(), hipMemcpyHostToDevice, C->stream));
+    auto* eq9 = reinterpret_cast<uint64_t*>(ws + E.eq9);     // [m][alen]
+    int rc = run_equality(C, d_a, m, nullptr, d_syms, d_syms + alen, alen, encoding, eq9, ws);
+    if (rc) return rc;
+    LVS_HIP(launch_table_scatter(eq9, d_table, int(m), int(alen), 0, long(m * alen), C->stream));
+    LVS_HIP(hipStreamSynchronize(C->stream));   // the staged symbols leave scope
+    return LVS_OK;
+}
+
+size_t lvs_edit_distance_clear_workspace_bytes(size_t m, size_t n) { return dp_layout(m, n).total; }
+
+int lvs_edit_distance_clear(lvs_context* ctx, const uint64_t* d_table, size_t m, const uint8_t* alphabet, size_t alen,
+                            const uint8_t* b, size_t n, uint64_t* d_h_last, void* d_work, size_t work_bytes) {
+    Context* C = as_ctx(ctx);
+    LVS_REQUIRE(C, LVS_E_INVAL, "lvs_edit_distance_clear: bad context");
+    LVS_REQUIRE((d_table || m == 0) && (alphabet || alen == 0) && (b || n == 0) && (d_h_last || n == 0),
+                LVS_E_INVAL, "lvs_edit_distance_clear: NULL buffer");
+    LVS_REQUIRE(std::min(m, n) <= kMaxLen, LVS_E_NOISE_BUDGET, "lvs_edit_distance_clear: noise budget");
+    std::vector<int32_t> col(std::max<size_t>(n, 1));
+    for (size_t j = 0; j < n; ++j) {
+        const uint8_t* hit = std::find(alphabet, alphabet + alen, b[j]);
+        LVS_REQUIRE(hit != alphabet + alen, LVS_E_ALPHABET, "lvs_edit_distance_clear: symbol not in the table");
+        col[j] = int32_t(hit - alphabet);
+    }
+    LVS_HIP(hipSetDevice(C->device));
+    if (n == 0) return LVS_OK;
+    if (m == 0) {
+        LVS_HIP(launch_trivial(d_h_last, int(n), 1, C->stream));
+        return LVS_OK;
+    }
+    LVS_REQUIRE(d_work && work_bytes >= lvs_edit_distance_clear_workspace_bytes(m, n), LVS_E_NOMEM_DEVICE,
+                "lvs_edit_distance_clear: workspace too small");
+    uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
+    const DpLayout L = dp_layout(m, n);
+    auto* d_col = reinterpret_cast<int32_t*>(ws + L.col);
+    LVS_HIP(hipMemcpyAsync(d_col, col.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, C->stream));
+    int rc = run_dp(C, m, n, d_table, 1, m, d_col, d_h_last, nullptr, ws);
+    LVS_HIP(hipStreamSynchronize(C->stream));   // the staged columns leave scope
+    return rc;
+}
+
+void lvs_free(void* handle) {
+    if (!handle) return;
+    switch (reinterpret_cast<Handle*>(handle)->kind) {
+        case kClientKey: delete reinterpret_cast<ClientKey*>(handle); break;
+        case kServerKey: delete reinterpret_cast<ServerKey*>(handle); break;
+        case kContext: delete reinterpret_cast<Context*>(handle); break;
+        default: break;
+    }
+}
+
+}  // extern "C"

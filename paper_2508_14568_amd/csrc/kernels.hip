@@ -1,0 +1,661 @@
+// gfx950 kernels of liblvs: key switching, blind rotation with exact
+// multi-prime NTT products, bootstrapping-key conversion, and the linear
+// ciphertext operations of the Leuvenshtein cell update.
+//
+// Integer arithmetic only.  A negacyclic product of the blind rotation is
+// evaluated modulo four primes p_r < 2^30 (p_r = 1 mod 2N) by length-2048
+// negacyclic NTTs and recombined with Garner's CRT and a signed lift; the
+// integers involved are below 2^97 in magnitude while prod p_r ~ 2^120, so the
+// torus result mod 2^64 is exact.
+//
+// Work mapping of the blind rotation: one workgroup of 4 wavefronts per
+// bootstrap; wavefront r owns prime p_r and runs the forward transforms of
+// both decomposed polynomials, the products with the bootstrapping key and
+// the two inverse transforms in registers (32 coefficients per lane), with
+// LDS transposes between the stage groups and a DPP lane-pair exchange for the
+// stride-32 stage.  The accumulator lives in LDS as 64-bit words; after each
+// external product the four residue sets meet in LDS and every thread
+// reconstructs 16 coefficients.
+#include <hip/hip_runtime.h>
+
+#include "launch.h"
+#include "lvs_internal.h"
+
+namespace lvs {
+namespace dev {
+
+constexpr int kWave = 64;
+constexpr int kEpl = kN / kWave;          // 32 coefficients per lane per polynomial
+constexpr int kPadStride = kN + kN / 32;  // LDS words of one padded polynomial
+
+struct CrtConsts {
+    uint32_t p[kPrimes];
+    uint32_t mont[kPrimes];
+    uint32_t garner[kPrimes][kPrimes];
+    uint32_t garner_s[kPrimes][kPrimes];
+    uint64_t prod[kPrimes];
+    uint64_t Q;
+};
+
+struct Tw {
+    const uint32_t* fwd;    // [kPrimes][kN]
+    const uint32_t* fwd_s;
+    const uint32_t* inv;
+    const uint32_t* inv_s;
+};
+
+__device__ __forceinline__ uint32_t pad(uint32_t j) { return j + (j >> 5); }
+
+// arr[w] for a wave-uniform w without dynamic indexing of kernel arguments.
+__device__ __forceinline__ uint32_t pick(const uint32_t (&arr)[kPrimes], int w) {
+    return w == 0 ? arr[0] : w == 1 ? arr[1] : w == 2 ? arr[2] : arr[3];
+}
+
+// a * w mod p in [0, 2p) for any a < 2^32 (Shoup, ws = floor(w 2^32 / p)).
+__device__ __forceinline__ uint32_t mul_shoup(uint32_t a, uint32_t w, uint32_t ws, uint32_t p) {
+    const uint32_t q = __umulhi(a, ws);
+    return a * w - q * p;
+}
+
+// x - c if x >= c else x (unsigned).
+__device__ __forceinline__ uint32_t csub(uint32_t x, uint32_t c) { return min(x, x - c); }
+
+// Montgomery reduction: T * 2^-32 mod p in [0, 2p) for T < p 2^32.
+__device__ __forceinline__ uint32_t redc(uint64_t T, uint32_t p, uint32_t mont) {
+    const uint32_t m = uint32_t(T) * mont;
+    return uint32_t((T + uint64_t(m) * p) >> 32);
+}
+
+__device__ __forceinline__ uint32_t swap_pair(uint32_t v) {
+    // quad_perm [1, 0, 3, 2]: lane l reads lane l ^ 1
+    return uint32_t(__builtin_amdgcn_mov_dpp(int(v), 0xB1, 0xF, 0xF, false));
+}
+
+// Forward negacyclic NTT (Cooley-Tukey, psi-merged twiddles, natural order in,
+// bit-reversed order out), Harvey lazy butterflies: values stay in [0, 4p).
+// In: lane l element e holds coefficient l + 64 e.  Out: lane l element e
+// holds transform position 32 l + e.  scratch: NP padded polynomials of this
+// wavefront's private LDS.
+template <int NP>
+__device__ __forceinline__ void ntt_forward(uint32_t (&x)[NP][kEpl], uint32_t* scratch, const uint32_t* w,
+                                            const uint32_t* ws, uint32_t p, int lane) {
+    const uint32_t two_p = 2 * p;
+    // stages with stride 1024 .. 64: partners in the same lane, twiddle uniform
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+        const int half = 16 >> s;
+#pragma unroll
+        for (int e = 0; e < kEpl; ++e) {
+            if (e & half) continue;
+            const int idx = (1 << s) + (e >> (5 - s));
+            const uint32_t tw = w[idx], tws = ws[idx];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const uint32_t a = csub(x[q][e], two_p);
+                const uint32_t t = mul_shoup(x[q][e + half], tw, tws, p);
+                x[q][e] = a + t;
+                x[q][e + half] = a - t + two_p;
+            }
+        }
+    }
+    // transpose: coefficient l + 64 e -> lane (j >> 5), element (j & 31)
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+        for (int e = 0; e < kEpl; ++e) scratch[q * kPadStride + pad(lane + 64 * e)] = x[q][e];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+        for (int e = 0; e < kEpl; ++e) x[q][e] = scratch[q * kPadStride + pad(32 * lane + e)];
+    __builtin_amdgcn_wave_barrier();
+    // stride 32: partner is lane l ^ 1, twiddle per lane pair
+    {
+        const int idx = 32 + (lane >> 1);
+        const uint32_t tw = w[idx], tws = ws[idx];
+        const bool odd = lane & 1;
+#pragma unroll
+        for (int q = 0; q < NP; ++q)
+#pragma unroll
+            for (int e = 0; e < kEpl; ++e) {
+                const uint32_t v = x[q][e];
+                const uint32_t a = csub(v, two_p);
+                const uint32_t t = mul_shoup(v, tw, tws, p);
+                const uint32_t got = swap_pair(odd ? t : a);
+                x[q][e] = odd ? got - t + two_p : a + got;
+            }
+    }
+    // strides 16 .. 1 inside the lane
+#pragma unroll
+    for (int s = 6; s < 11; ++s) {
+        const int half = 1 << (10 - s);
+#pragma unroll
+        for (int e = 0; e < kEpl; ++e) {
+            if (e & half) continue;
+            const int idx = (1 << s) + (lane << (s - 6)) + (e >> (11 - s));
+            const uint32_t tw = w[idx], tws = ws[idx];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const uint32_t a = csub(x[q][e], two_p);
+                const uint32_t t = mul_shoup(x[q][e + half], tw, tws, p);
+                x[q][e] = a + t;
+                x[q][e + half] = a - t + two_p;
+            }
+        }
+    }
+}
+
+// Inverse negacyclic NTT without the 1/N factor (Gentleman-Sande, inverse
+// psi twiddles, bit-reversed order in, natural order out); inputs in [0, 2p),
+// outputs in [0, 2p).  Layouts mirror ntt_forward.
+template <int NP>
+__device__ __forceinline__ void ntt_inverse(uint32_t (&x)[NP][kEpl], uint32_t* scratch, const uint32_t* w,
+                                            const uint32_t* ws, uint32_t p, int lane) {
+    const uint32_t two_p = 2 * p;
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+        const int half = 1 << u;
+#pragma unroll
+        for (int e = 0; e < kEpl; ++e) {
+            if (e & half) continue;
+            const int idx = (1 << (10 - u)) + (lane << (4 - u)) + (e >> (u + 1));
+            const uint32_t tw = w[idx], tws = ws[idx];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const uint32_t a = x[q][e], b = x[q][e + half];
+                x[q][e] = csub(a + b, two_p);
+                x[q][e + half] = mul_shoup(a - b + two_p, tw, tws, p);
+            }
+        }
+    }
+    {
+        const int idx = 32 + (lane >> 1);
+        const uint32_t tw = w[idx], tws = ws[idx];
+        const bool odd = lane & 1;
+#pragma unroll
+        for (int q = 0; q < NP; ++q)
+#pragma unroll
+            for (int e = 0; e < kEpl; ++e) {
+                const uint32_t v = x[q][e];
+                const uint32_t got = swap_pair(v);
+                const uint32_t sum = csub(v + got, two_p);
+                const uint32_t diff = (odd ? got - v : v - got) + two_p;
+                const uint32_t prod = mul_shoup(diff, tw, tws, p);
+                x[q][e] = odd ? prod : sum;
+            }
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+        for (int e = 0; e < kEpl; ++e) scratch[q * kPadStride + pad(32 * lane + e)] = x[q][e];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+        for (int e = 0; e < kEpl; ++e) x[q][e] = scratch[q * kPadStride + pad(lane + 64 * e)];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int u = 6; u < 11; ++u) {
+        const int half = 1 << (u - 6);
+#pragma unroll
+        for (int e = 0; e < kEpl; ++e) {
+            if (e & half) continue;
+            const int idx = (1 << (10 - u)) + (e >> (u - 5));
+            const uint32_t tw = w[idx], tws = ws[idx];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const uint32_t a = x[q][e], b = x[q][e + half];
+                x[q][e] = csub(a + b, two_p);
+                x[q][e + half] = mul_shoup(a - b + two_p, tw, tws, p);
+            }
+        }
+    }
+}
+
+// Residues r[0..3] (each in [0, p_i)) of a signed integer |X| < prod/2 ->
+// X mod 2^64 (Garner mixed radix, then the signed lift).
+__device__ __forceinline__ uint64_t crt_lift(const uint32_t (&r)[kPrimes], const CrtConsts& C) {
+    uint32_t v[kPrimes];
+    v[0] = r[0];
+#pragma unroll
+    for (int i = 1; i < kPrimes; ++i) {
+        const uint32_t p = C.p[i];
+        uint32_t t = r[i];
+#pragma unroll
+        for (int j = 0; j < i; ++j) {
+            // t = (t - v_j) * p_j^{-1} mod p_i; v_j < p_j < 2 p_i
+            t = mul_shoup(t + 2 * p - v[j], C.garner[i][j], C.garner_s[i][j], p);
+            t = csub(t, p);
+        }
+        v[i] = t;
+    }
+    uint64_t x = v[0];
+#pragma unroll
+    for (int i = 1; i < kPrimes; ++i) x += uint64_t(v[i]) * C.prod[i];
+    if (v[kPrimes - 1] > (C.p[kPrimes - 1] >> 1)) x -= C.Q;
+    return x;
+}
+
+// ------------------------------------------------------------ key switch
+
+constexpr int kKsTile = 8;                       // ciphertexts per workgroup
+constexpr int kKsSplit = 16;                     // row chunks (grid.y)
+constexpr int kKsChunk = kN / kKsSplit;          // input coefficients per chunk
+constexpr int kKsCols = (kSmallWords + 255) / 256;
+
+__global__ void __launch_bounds__(256) fill_u64_kernel(uint64_t* p, size_t count, uint64_t v) {
+    for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < count; i += size_t(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+// ks_out[b] += (0, b_body) - sum_{j in chunk, t} d_{j,t} KSK[j*5+t]; ks_out must
+// be zero before the launch.  Digits: round to 15 bits, then balanced base-8
+// digits from the least significant level with a carry (level t weight
+// 2^(64-3t)); the carry out of the top level is dropped.
+__global__ void __launch_bounds__(256) keyswitch_kernel(const uint64_t* __restrict__ in, const uint64_t* __restrict__ ksk,
+                                                        uint64_t* __restrict__ ks_out, int B) {
+    __shared__ uint64_t digits[kKsChunk * kKsLevel];   // 8 signed bytes: one per tile ciphertext
+    const int tid = threadIdx.x;
+    const int b0 = blockIdx.x * kKsTile;
+    const int j0 = blockIdx.y * kKsChunk;
+    uint8_t* dig8 = reinterpret_cast<uint8_t*>(digits);
+    for (int idx = tid; idx < kKsTile * kKsChunk; idx += 256) {
+        const int bb = idx / kKsChunk, jj = idx % kKsChunk;
+        uint64_t c = 0;
+        if (b0 + bb < B) c = in[size_t(b0 + bb) * kCtWords + j0 + jj];
+        uint64_t r = (((c >> 48) + 1) >> 1) & 0x7FFFu;     // round(c / 2^49) mod 2^15
+#pragma unroll
+        for (int lev = kKsLevel - 1; lev >= 0; --lev) {
+            int d = int(r & 7u);
+            r >>= 3;
+            if (d >= 4) { d -= 8; r += 1; }
+            dig8[(jj * kKsLevel + lev) * 8 + bb] = uint8_t(int8_t(d));
+        }
+    }
+    __syncthreads();
+    uint64_t acc[kKsTile][kKsCols];
+#pragma unroll
+    for (int bb = 0; bb < kKsTile; ++bb)
+#pragma unroll
+        for (int cs = 0; cs < kKsCols; ++cs) acc[bb][cs] = 0;
+    const uint64_t* rows = ksk + size_t(j0) * kKsLevel * kSmallWords;
+    for (int rr = 0; rr < kKsChunk * kKsLevel; ++rr) {
+        const uint64_t dp = digits[rr];
+        uint64_t k[kKsCols];
+#pragma unroll
+        for (int cs = 0; cs < kKsCols; ++cs) {
+            const int col = tid + 256 * cs;
+            k[cs] = (col < kSmallWords) ? rows[size_t(rr) * kSmallWords + col] : 0;
+        }
+#pragma unroll
+        for (int bb = 0; bb < kKsTile; ++bb) {
+            const int64_t d = int8_t(uint8_t(dp >> (8 * bb)));
+#pragma unroll
+            for (int cs = 0; cs < kKsCols; ++cs) acc[bb][cs] -= uint64_t(d) * k[cs];
+        }
+    }
+#pragma unroll
+    for (int bb = 0; bb < kKsTile; ++bb) {
+        if (b0 + bb >= B) break;
+#pragma unroll
+        for (int cs = 0; cs < kKsCols; ++cs) {
+            const int col = tid + 256 * cs;
+            if (col >= kSmallWords) continue;
+            uint64_t v = acc[bb][cs];
+            if (col == kSmallN && blockIdx.y == 0) v += in[size_t(b0 + bb) * kCtWords + kN];
+            atomicAdd(reinterpret_cast<unsigned long long*>(&ks_out[size_t(b0 + bb) * kSmallWords + col]),
+                      static_cast<unsigned long long>(v));
+        }
+    }
+}
+
+// ---------------------------------------------------------- blind rotation
+
+struct BrArgs {
+    const uint64_t* ks;        // [B][n+1] key-switched ciphertexts (before modulus switching)
+    const uint8_t* lut_ids;    // [B] or nullptr
+    int lut_id;
+    const uint64_t* luts;      // [LVS_LUT_SLOTS][N] test polynomials
+    const uint32_t* bsk;       // [n][kPrimes][2 rows][2 comps][N] NTT domain, Montgomery form, 1/N folded
+    Tw tw;
+    CrtConsts crt;
+    uint64_t* out;             // [B][N+1]
+    int B;
+};
+
+constexpr int kBrThreads = 256;
+constexpr size_t kBrLds = sizeof(uint64_t) * 2 * kN                       // accumulator
+                          + sizeof(uint32_t) * kPrimes * 2 * kPadStride   // per-wave scratch / residues
+                          + sizeof(uint32_t) * (kSmallWords + 1);         // switched mask and body
+
+__global__ void __launch_bounds__(kBrThreads, 1) blind_rotate_kernel(BrArgs A) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint64_t* acc = reinterpret_cast<uint64_t*>(lds);                                   // [2][N]
+    uint32_t* exch = reinterpret_cast<uint32_t*>(lds + sizeof(uint64_t) * 2 * kN);      // [4][2][pad]
+    uint32_t* abar = exch + kPrimes * 2 * kPadStride;                                   // [n+1]
+
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const uint32_t p = pick(A.crt.p, wave);
+    const uint32_t mont = pick(A.crt.mont, wave);
+    const uint32_t* fw = A.tw.fwd + size_t(wave) * kN;
+    const uint32_t* fws = A.tw.fwd_s + size_t(wave) * kN;
+    const uint32_t* iw = A.tw.inv + size_t(wave) * kN;
+    const uint32_t* iws = A.tw.inv_s + size_t(wave) * kN;
+    uint32_t* scratch = exch + wave * 2 * kPadStride;
+
+    for (int b = blockIdx.x; b < A.B; b += gridDim.x) {
+        // modulus switch to Z_{2N}: round(x / 2^52)
+        for (int c = tid; c < kSmallWords; c += kBrThreads)
+            abar[c] = uint32_t((((A.ks[size_t(b) * kSmallWords + c] >> 51) + 1) >> 1) & (2 * kN - 1));
+        __syncthreads();
+        const int lut = min(A.lut_ids ? int(A.lut_ids[b]) : A.lut_id, LVS_LUT_SLOTS - 1);   // ids past the table clamp
+        const uint64_t* tp = A.luts + size_t(lut) * kN;
+        const uint32_t bbar = abar[kSmallN];
+        // ACC = (0, X^{-bbar} * testpoly)
+        for (int t = tid; t < kN; t += kBrThreads) {
+            const uint32_t src = (uint32_t(t) + bbar) & (2 * kN - 1);
+            const uint64_t v = tp[src & (kN - 1)];
+            acc[t] = 0;
+            acc[kN + t] = (src < uint32_t(kN)) ? v : uint64_t(0) - v;
+        }
+        __syncthreads();
+
+        for (int i = 0; i < kSmallN; ++i) {
+            const uint32_t a = abar[i];
+            // bootstrapping-key rows of this step and prime, in transform order
+            const uint32_t* K = A.bsk + (size_t(i) * kPrimes + wave) * 4 * kN;
+            // digits of X^a ACC - ACC (one signed 23-bit digit per coefficient)
+            uint32_t x[2][kEpl];
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int e = 0; e < kEpl; ++e) {
+                    const uint32_t j = uint32_t(lane + 64 * e);
+                    const uint32_t src = (j - a) & (2 * kN - 1);
+                    uint64_t r = acc[q * kN + (src & (kN - 1))];
+                    if (src >= uint32_t(kN)) r = uint64_t(0) - r;
+                    const uint64_t t = r - acc[q * kN + j];
+                    const uint32_t dg = ((uint32_t(t >> 40) + 1) >> 1) & 0x7FFFFFu;   // round(t / 2^41) mod 2^23
+                    x[q][e] = (dg >= 0x400000u) ? dg - 0x800000u + p : dg;            // balanced digit mod p
+                }
+            ntt_forward<2>(x, scratch, fw, fws, p, lane);
+            // products with the GGSW rows: mask += D0 K00 + D1 K10, body += D0 K01 + D1 K11
+            uint32_t y[2][kEpl];
+#pragma unroll
+            for (int e = 0; e < kEpl; ++e) {
+                const int o = e * 64 + lane;
+                const uint32_t d0 = csub(x[0][e], 2 * p), d1 = csub(x[1][e], 2 * p);
+                const uint32_t k00 = K[0 * kN + o], k01 = K[1 * kN + o], k10 = K[2 * kN + o], k11 = K[3 * kN + o];
+                y[0][e] = redc(uint64_t(d0) * k00 + uint64_t(d1) * k10, p, mont);
+                y[1][e] = redc(uint64_t(d0) * k01 + uint64_t(d1) * k11, p, mont);
+            }
+            ntt_inverse<2>(y, scratch, iw, iws, p, lane);
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int e = 0; e < kEpl; ++e) scratch[q * kPadStride + pad(lane + 64 * e)] = csub(y[q][e], p);
+            __syncthreads();
+            // CRT: 16 coefficients per thread
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int k = 0; k < kN / kBrThreads; ++k) {
+                    const int c = tid + kBrThreads * k;
+                    uint32_t r[kPrimes];
+#pragma unroll
+                    for (int w = 0; w < kPrimes; ++w) r[w] = exch[(w * 2 + q) * kPadStride + pad(c)];
+                    acc[q * kN + c] += crt_lift(r, A.crt);
+                }
+            __syncthreads();
+        }
+        // sample extraction of coefficient 0
+        uint64_t* o = A.out + size_t(b) * kCtWords;
+        for (int t = tid; t < kCtWords; t += kBrThreads) {
+            uint64_t v;
+            if (t == 0) v = acc[0];
+            else if (t < kN) v = uint64_t(0) - acc[kN - t];
+            else v = acc[kN];
+            o[t] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------ bootstrapping-key conversion
+
+// One wavefront per (polynomial, prime): signed lift of the 64-bit
+// coefficients, reduction mod p, forward NTT, scaling by (1/N) 2^32 mod p, and
+// store in the transform order the blind rotation reads.
+__global__ void __launch_bounds__(64) bsk_convert_kernel(const uint64_t* __restrict__ bsk, uint32_t* __restrict__ out,
+                                                        Tw tw, CrtConsts C, const uint32_t* scale,
+                                                        const uint32_t* scale_s) {
+    __shared__ uint32_t scratch[kPadStride];
+    const int lane = threadIdx.x;
+    const int poly = blockIdx.x;            // i * 4 + row * 2 + comp
+    const int r = blockIdx.y;               // prime
+    const int i = poly >> 2, rc = poly & 3;
+    const uint32_t p = pick(C.p, r);
+    const uint64_t two64_mod_p = ((~uint64_t(0)) % p + 1) % p;
+    uint32_t x[1][kEpl];
+#pragma unroll
+    for (int e = 0; e < kEpl; ++e) {
+        const uint64_t c = bsk[size_t(poly) * kN + lane + 64 * e];
+        uint64_t m = c % p;
+        if (c >> 63) m = (m + p - two64_mod_p) % p;     // c read as c - 2^64
+        x[0][e] = uint32_t(m);
+    }
+    ntt_forward<1>(x, scratch, tw.fwd + size_t(r) * kN, tw.fwd_s + size_t(r) * kN, p, lane);
+    const uint32_t sc = scale[r], scs = scale_s[r];
+    uint32_t* dst = out + ((size_t(i) * kPrimes + r) * 4 + rc) * kN;
+#pragma unroll
+    for (int e = 0; e < kEpl; ++e) dst[e * 64 + lane] = csub(mul_shoup(x[0][e], sc, scs, p), p);
+}
+
+// ----------------------------------------------------- linear operations
+
+constexpr int kWordBlocks = (kCtWords + 255) / 256;   // 256-word slices of a ciphertext
+
+// out[c - c0] = alpha (A[i][sa] - B[j][sb]) + (delta on the body) - E[c - c0]
+// for cells c = i*n + j in [c0, c0 + count) (E optional).  Without B the
+// second operand is a cleartext symbol: (0, ..., 0, sym_j * 2^59).
+struct PairArgs {
+    const uint64_t* A; int a_stride; int sa;            // A + i * a_stride + sa * W
+    const uint64_t* B; int b_stride; int sb;
+    const uint8_t* clear_syms;                          // if B == nullptr: device symbols [n]
+    const uint64_t* E;
+    uint64_t alpha;
+    uint64_t delta;
+    uint64_t* out;
+    int n;
+    long c0;
+};
+
+__global__ void __launch_bounds__(256) pair_kernel(PairArgs P) {
+    const long local = blockIdx.x / kWordBlocks;
+    const int w = (blockIdx.x % kWordBlocks) * 256 + threadIdx.x;
+    if (w >= kCtWords) return;
+    const long cell = P.c0 + local;
+    const long i = cell / P.n, j = cell % P.n;
+    const uint64_t av = P.A[i * P.a_stride + size_t(P.sa) * kCtWords + w];
+    uint64_t bv;
+    if (P.B) bv = P.B[j * P.b_stride + size_t(P.sb) * kCtWords + w];
+    else bv = (w == kN) ? (uint64_t(P.clear_syms[j]) << kDeltaLog) : 0;
+    uint64_t v = P.alpha * (av - bv);
+    if (w == kN) v += P.delta;
+    if (P.E) v -= P.E[local * kCtWords + w];
+    P.out[local * kCtWords + w] = v;
+}
+
+// Cells of anti-diagonal s = i + j, i = i0 + c: key = 4 - V[i] + 3 H[j] + eq9(i, j)
+// with eq9(i, j) = EQ + (i-1) eq_si + col[j-1] eq_sj (in ciphertexts).
+struct KeyArgs {
+    const uint64_t* V;         // [m+1][W], V[i] = v[i, latest j]
+    const uint64_t* H;         // [n+1][W]
+    const uint64_t* EQ;
+    size_t eq_si, eq_sj;
+    const int32_t* col;        // [n] column of b_j in EQ (nullptr: j - 1)
+    uint64_t* key;             // [count][W]
+    int i0, s;
+};
+
+__global__ void __launch_bounds__(256) key_kernel(KeyArgs K) {
+    const int c = blockIdx.x / kWordBlocks;
+    const int w = (blockIdx.x % kWordBlocks) * 256 + threadIdx.x;
+    if (w >= kCtWords) return;
+    const int i = K.i0 + c, j = K.s - i;
+    const size_t cj = K.col ? size_t(K.col[j - 1]) : size_t(j - 1);
+    const uint64_t v = K.V[size_t(i) * kCtWords + w];
+    const uint64_t h = K.H[size_t(j) * kCtWords + w];
+    const uint64_t eq = K.EQ[(size_t(i - 1) * K.eq_si + cj * K.eq_sj) * kCtWords + w];
+    uint64_t r = 3 * h - v + eq;
+    if (w == kN) r += uint64_t(4) << kDeltaLog;
+    K.key[size_t(c) * kCtWords + w] = r;
+}
+
+// v[i,j] = M - h[i-1,j], h[i,j] = M - v[i,j-1] for the cells of one diagonal;
+// trace (optional, [m][n]) keeps every M.
+__global__ void __launch_bounds__(256) update_kernel(uint64_t* V, uint64_t* H, const uint64_t* M, int i0, int s,
+                                                     uint64_t* trace, int n) {
+    const int c = blockIdx.x / kWordBlocks;
+    const int w = (blockIdx.x % kWordBlocks) * 256 + threadIdx.x;
+    if (w >= kCtWords) return;
+    const int i = i0 + c, j = s - i;
+    const uint64_t mv = M[size_t(c) * kCtWords + w];
+    if (trace) trace[(size_t(i - 1) * n + (j - 1)) * kCtWords + w] = mv;
+    const uint64_t hv = H[size_t(j) * kCtWords + w];
+    const uint64_t vv = V[size_t(i) * kCtWords + w];
+    V[size_t(i) * kCtWords + w] = mv - hv;
+    H[size_t(j) * kCtWords + w] = mv - vv;
+}
+
+// Noise-free encryptions of mu in rows [0, count).
+__global__ void __launch_bounds__(256) trivial_kernel(uint64_t* out, uint32_t mu) {
+    const int r = blockIdx.x / kWordBlocks;
+    const int w = (blockIdx.x % kWordBlocks) * 256 + threadIdx.x;
+    if (w >= kCtWords) return;
+    out[size_t(r) * kCtWords + w] = (w == kN) ? (uint64_t(mu) << kDeltaLog) : 0;
+}
+
+// Preprocessing table rows: dst[c][i] = src[i * alen + c - c0] for cells
+// i * alen + c in [c0, c0 + count).
+__global__ void __launch_bounds__(256) table_scatter_kernel(const uint64_t* src, uint64_t* dst, int m, int alen,
+                                                            long c0) {
+    const long local = blockIdx.x / kWordBlocks;
+    const int w = (blockIdx.x % kWordBlocks) * 256 + threadIdx.x;
+    if (w >= kCtWords) return;
+    const long cell = c0 + local;
+    const long i = cell / alen, c = cell % alen;
+    dst[(c * m + i) * kCtWords + w] = src[local * kCtWords + w];
+}
+
+}  // namespace dev
+
+// ------------------------------------------------------------- launchers
+
+namespace {
+dev::CrtConsts make_crt() {
+    const PrimeTables& T = prime_tables();
+    dev::CrtConsts C{};
+    for (int i = 0; i < kPrimes; ++i) {
+        C.p[i] = T.p[i];
+        C.mont[i] = T.mont_neg_inv[i];
+        C.prod[i] = T.prod_mod64[i];
+        for (int j = 0; j < kPrimes; ++j) {
+            C.garner[i][j] = T.garner[i][j];
+            C.garner_s[i][j] = T.garner_shoup[i][j];
+        }
+    }
+    C.Q = T.Q_mod64;
+    return C;
+}
+}  // namespace
+
+hipError_t launch_fill_u64(uint64_t* p, size_t count, uint64_t v, hipStream_t st) {
+    if (!count) return hipSuccess;
+    const int blocks = int(std::min<size_t>((count + 255) / 256, 4096));
+    hipLaunchKernelGGL(dev::fill_u64_kernel, dim3(blocks), dim3(256), 0, st, p, count, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_keyswitch(const uint64_t* in, const uint64_t* ksk, uint64_t* ks_out, int B, hipStream_t st) {
+    hipError_t e = launch_fill_u64(ks_out, size_t(B) * kSmallWords, 0, st);
+    if (e != hipSuccess) return e;
+    dim3 grid((B + dev::kKsTile - 1) / dev::kKsTile, dev::kKsSplit);
+    hipLaunchKernelGGL(dev::keyswitch_kernel, grid, dim3(256), 0, st, in, ksk, ks_out, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_blind_rotate(const uint64_t* ks, const uint8_t* lut_ids, int lut_id, const uint64_t* luts,
+                               const uint32_t* bsk, const DevTables& t, uint64_t* out, int B, int grid,
+                               hipStream_t st) {
+    static bool attr_done = false;
+    if (!attr_done) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(dev::blind_rotate_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(dev::kBrLds));
+        if (e != hipSuccess) return e;
+        attr_done = true;
+    }
+    dev::BrArgs A{};
+    A.ks = ks;
+    A.lut_ids = lut_ids;
+    A.lut_id = lut_id;
+    A.luts = luts;
+    A.bsk = bsk;
+    A.tw = dev::Tw{t.fwd, t.fwd_s, t.inv, t.inv_s};
+    A.crt = make_crt();
+    A.out = out;
+    A.B = B;
+    if (grid <= 0 || grid > B) grid = B;
+    hipLaunchKernelGGL(dev::blind_rotate_kernel, dim3(grid), dim3(dev::kBrThreads), dev::kBrLds, st, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_bsk_convert(const uint64_t* bsk_u64, uint32_t* out, const DevTables& t, hipStream_t st) {
+    dim3 grid(kSmallN * 4, kPrimes);
+    hipLaunchKernelGGL(dev::bsk_convert_kernel, grid, dim3(64), 0, st, bsk_u64, out,
+                       dev::Tw{t.fwd, t.fwd_s, t.inv, t.inv_s}, make_crt(), t.scale, t.scale_s);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair(const uint64_t* A, int a_stride, int sa, const uint64_t* B, int b_stride, int sb,
+                       const uint8_t* clear_syms, const uint64_t* E, uint64_t alpha, uint64_t delta, uint64_t* out,
+                       int n, long c0, long count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    dev::PairArgs P{A, a_stride, sa, B, b_stride, sb, clear_syms, E, alpha, delta, out, n, c0};
+    hipLaunchKernelGGL(dev::pair_kernel, dim3(unsigned(count * dev::kWordBlocks)), dim3(256), 0, st, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_key(const uint64_t* V, const uint64_t* H, const uint64_t* EQ, size_t eq_si, size_t eq_sj,
+                      const int32_t* col, uint64_t* key, int i0, int s, int count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    dev::KeyArgs K{V, H, EQ, eq_si, eq_sj, col, key, i0, s};
+    hipLaunchKernelGGL(dev::key_kernel, dim3(unsigned(count * dev::kWordBlocks)), dim3(256), 0, st, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(uint64_t* V, uint64_t* H, const uint64_t* M, int i0, int s, int count, uint64_t* trace,
+                         int n, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dev::update_kernel, dim3(unsigned(count * dev::kWordBlocks)), dim3(256), 0, st, V, H, M, i0, s,
+                       trace, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_trivial(uint64_t* out, int count, uint32_t mu, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dev::trivial_kernel, dim3(unsigned(count * dev::kWordBlocks)), dim3(256), 0, st, out, mu);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_scatter(const uint64_t* src, uint64_t* dst, int m, int alen, long c0, long count,
+                                hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dev::table_scatter_kernel, dim3(unsigned(count * dev::kWordBlocks)), dim3(256), 0, st, src,
+                       dst, m, alen, c0);
+    return hipGetLastError();
+}
+
+}  // namespace lvs

@@ -1,0 +1,318 @@
+"""Python binding of liblvs (argument marshalling only).
+
+Every function mirrors the C entry point of the same name declared in
+``include/lvs.h``; all computation happens in the library's host code and HIP
+kernels.  PyTorch supplies device memory (tensors used as raw buffers) and the
+HIP stream.  The library must be built (``paper_2508_14568_amd.build``); there
+is no fallback: loading fails loudly when it is missing.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblvs.so")
+
+LVS_ENC_ASCII7 = 0
+LVS_ENC_DNA2 = 1
+LVS_LUT_EQ, LVS_LUT_EQ9, LVS_LUT_MIN, LVS_LUT_USER, LVS_LUT_SLOTS = 0, 1, 2, 3, 8
+CT_WORDS = 2049
+
+ERRORS = {-1: "LVS_E_INVAL", -2: "LVS_E_ALPHABET", -3: "LVS_E_NOISE_BUDGET", -4: "LVS_E_NOMEM_HOST",
+          -5: "LVS_E_NOMEM_DEVICE", -6: "LVS_E_DEVICE", -7: "LVS_E_PARAMS"}
+
+
+class LvsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class lvs_params(ctypes.Structure):
+    _fields_ = [("n_lwe", ctypes.c_uint32), ("glwe_k", ctypes.c_uint32), ("poly_N", ctypes.c_uint32),
+                ("pbs_base_log", ctypes.c_uint32), ("pbs_level", ctypes.c_uint32),
+                ("ks_base_log", ctypes.c_uint32), ("ks_level", ctypes.c_uint32),
+                ("lwe_noise_q64", ctypes.c_uint64), ("glwe_noise_q64", ctypes.c_uint64)]
+
+
+_L = None
+VP, SZ, U64, I32, U32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "lvs_last_error": (ctypes.c_char_p, []),
+    "lvs_params_default": (I32, [ctypes.POINTER(lvs_params)]),
+    "lvs_ct_words": (SZ, []),
+    "lvs_keygen": (I32, [ctypes.POINTER(lvs_params), U64, ctypes.POINTER(VP), ctypes.POINTER(VP)]),
+    "lvs_lwe_encrypt": (I32, [VP, U32, U64, U64, VP]),
+    "lvs_lwe_decrypt": (I32, [VP, VP, ctypes.POINTER(U32), ctypes.POINTER(ctypes.c_int64)]),
+    "lvs_encrypt_string": (I32, [VP, VP, SZ, I32, U64, VP]),
+    "lvs_decrypt_distance": (I32, [VP, VP, SZ, SZ, ctypes.POINTER(ctypes.c_int64)]),
+    "lvs_key_export": (I32, [VP, VP, I32, VP, ctypes.POINTER(SZ)]),
+    "lvs_context_bytes": (I32, [ctypes.POINTER(lvs_params), ctypes.POINTER(SZ)]),
+    "lvs_context_create": (I32, [VP, I32, VP, VP, SZ, ctypes.POINTER(VP)]),
+    "lvs_context_set_stream": (I32, [VP, VP]),
+    "lvs_context_set_lut": (I32, [VP, I32, ctypes.POINTER(ctypes.c_int32)]),
+    "lvs_sync": (I32, [VP]),
+    "lvs_pbs_workspace_bytes": (SZ, [SZ]),
+    "lvs_pbs_batch": (I32, [VP, VP, VP, I32, SZ, VP, VP, SZ]),
+    "lvs_equality_workspace_bytes": (SZ, [SZ, SZ, I32]),
+    "lvs_equality": (I32, [VP, VP, SZ, VP, SZ, I32, VP, VP, SZ]),
+    "lvs_edit_distance_eq9_workspace_bytes": (SZ, [SZ, SZ]),
+    "lvs_edit_distance_eq9": (I32, [VP, VP, SZ, SZ, VP, VP, VP, SZ]),
+    "lvs_edit_distance_workspace_bytes": (SZ, [SZ, SZ, I32]),
+    "lvs_edit_distance": (I32, [VP, VP, SZ, VP, SZ, I32, VP, VP, SZ]),
+    "lvs_preprocess_workspace_bytes": (SZ, [SZ, SZ, I32]),
+    "lvs_preprocess": (I32, [VP, VP, SZ, I32, VP, SZ, VP, VP, SZ]),
+    "lvs_edit_distance_clear_workspace_bytes": (SZ, [SZ, SZ]),
+    "lvs_edit_distance_clear": (I32, [VP, VP, SZ, VP, SZ, VP, SZ, VP, VP, SZ]),
+    "lvs_free": (None, [VP]),
+}
+
+
+def lib():
+    """The loaded liblvs.so; raises if it has not been built."""
+    global _L
+    if _L is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"liblvs.so not built ({LIB_PATH}); run paper_2508_14568_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _L = L
+    return _L
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def _check(rc):
+    if rc != 0:
+        raise LvsError(rc, lib().lvs_last_error().decode())
+
+
+def _np_ptr(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ handles
+
+class _Handle:
+    def __init__(self, ptr):
+        self.ptr = ptr
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _L is not None:
+            _L.lvs_free(self.ptr)
+            self.ptr = None
+
+    @property
+    def _as_parameter_(self):
+        return self.ptr
+
+
+# ------------------------------------------------------------- host side
+
+def lvs_params_default() -> lvs_params:
+    p = lvs_params()
+    _check(lib().lvs_params_default(ctypes.byref(p)))
+    return p
+
+
+def lvs_keygen(params: lvs_params, seed: int):
+    ck, sk = VP(), VP()
+    _check(lib().lvs_keygen(ctypes.byref(params), seed, ctypes.byref(ck), ctypes.byref(sk)))
+    return _Handle(ck), _Handle(sk)
+
+
+def lvs_lwe_encrypt(ck, mu: int, seed: int, index: int) -> np.ndarray:
+    out = np.zeros(CT_WORDS, dtype=np.uint64)
+    _check(lib().lvs_lwe_encrypt(ck, mu, seed, index, _np_ptr(out)))
+    return out
+
+
+def lvs_lwe_decrypt(ck, ct: np.ndarray):
+    ct = np.ascontiguousarray(ct, dtype=np.uint64)
+    mu, err = U32(), ctypes.c_int64()
+    _check(lib().lvs_lwe_decrypt(ck, _np_ptr(ct), ctypes.byref(mu), ctypes.byref(err)))
+    return int(mu.value), int(err.value)
+
+
+def nsym(encoding: int) -> int:
+    return 2 if encoding == LVS_ENC_ASCII7 else 1
+
+
+def lvs_encrypt_string(ck, s: bytes, encoding: int, seed: int) -> np.ndarray:
+    s = bytes(s)
+    out = np.zeros((len(s), nsym(encoding), CT_WORDS), dtype=np.uint64)
+    buf = (ctypes.c_uint8 * max(1, len(s))).from_buffer_copy(s or b"\0")
+    _check(lib().lvs_encrypt_string(ck, buf, len(s), encoding, seed, _np_ptr(out)))
+    return out
+
+
+def lvs_decrypt_distance(ck, h_last: np.ndarray, m: int) -> int:
+    h_last = np.ascontiguousarray(h_last, dtype=np.uint64).reshape(-1, CT_WORDS)
+    out = ctypes.c_int64()
+    _check(lib().lvs_decrypt_distance(ck, _np_ptr(h_last), m, h_last.shape[0], ctypes.byref(out)))
+    return int(out.value)
+
+
+def lvs_key_export(ck, sk, kind: int) -> np.ndarray:
+    n = SZ()
+    _check(lib().lvs_key_export(ck, sk, kind, None, ctypes.byref(n)))
+    out = np.zeros(n.value, dtype=np.uint8)
+    _check(lib().lvs_key_export(ck, sk, kind, _np_ptr(out), ctypes.byref(n)))
+    return out if kind < 2 else out.view(np.uint64)
+
+
+# ------------------------------------------------------------ device side
+
+def _torch():
+    import torch
+    return torch
+
+
+def device_buffer(nbytes: int, device):
+    """Raw device memory from torch's allocator (256-byte aligned)."""
+    torch = _torch()
+    return torch.empty(max(1, (nbytes + 7) // 8), dtype=torch.int64, device=device)
+
+
+def to_device(arr: np.ndarray, device):
+    torch = _torch()
+    a = np.ascontiguousarray(arr, dtype=np.uint64)
+    return torch.from_numpy(a.view(np.int64)).to(device)
+
+
+def to_host(t) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+class Context(_Handle):
+    """A device context; keeps its torch arena alive."""
+
+    def __init__(self, ptr, arena, device):
+        super().__init__(ptr)
+        self.arena = arena
+        self.device = device
+
+
+def lvs_context_bytes(params: lvs_params) -> int:
+    n = SZ()
+    _check(lib().lvs_context_bytes(ctypes.byref(params), ctypes.byref(n)))
+    return n.value
+
+
+def lvs_context_create(sk, params: lvs_params, device=0, stream=None) -> Context:
+    torch = _torch()
+    dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+    nbytes = lvs_context_bytes(params)
+    arena = device_buffer(nbytes, dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    out = VP()
+    _check(lib().lvs_context_create(sk, dev.index or 0, VP(st.cuda_stream), _dptr(arena), nbytes, ctypes.byref(out)))
+    return Context(out, arena, dev)
+
+
+def lvs_context_set_stream(ctx: Context, stream):
+    _check(lib().lvs_context_set_stream(ctx, VP(stream.cuda_stream)))
+
+
+def lvs_context_set_lut(ctx: Context, slot: int, f16):
+    arr = (ctypes.c_int32 * 16)(*[int(v) for v in f16])
+    _check(lib().lvs_context_set_lut(ctx, slot, arr))
+
+
+def lvs_sync(ctx: Context):
+    _check(lib().lvs_sync(ctx))
+
+
+def lvs_pbs_workspace_bytes(B: int) -> int:
+    return lib().lvs_pbs_workspace_bytes(B)
+
+
+def lvs_pbs_batch(ctx: Context, d_in, B: int, d_out, lut_id: int = 0, d_lut_ids=None, d_work=None):
+    need = lvs_pbs_workspace_bytes(B)
+    if d_work is None:
+        d_work = device_buffer(need, ctx.device)
+    _check(lib().lvs_pbs_batch(ctx, _dptr(d_in), _dptr(d_lut_ids), lut_id, B, _dptr(d_out), _dptr(d_work),
+                               d_work.numel() * d_work.element_size()))
+    return d_work
+
+
+def lvs_equality_workspace_bytes(m: int, n: int, encoding: int) -> int:
+    return lib().lvs_equality_workspace_bytes(m, n, encoding)
+
+
+def lvs_equality(ctx: Context, d_a, m: int, d_b, n: int, encoding: int, d_eq9, d_work=None):
+    need = lvs_equality_workspace_bytes(m, n, encoding)
+    if d_work is None:
+        d_work = device_buffer(need, ctx.device)
+    _check(lib().lvs_equality(ctx, _dptr(d_a), m, _dptr(d_b), n, encoding, _dptr(d_eq9), _dptr(d_work),
+                              d_work.numel() * d_work.element_size()))
+    return d_work
+
+
+def lvs_edit_distance_eq9_workspace_bytes(m: int, n: int) -> int:
+    return lib().lvs_edit_distance_eq9_workspace_bytes(m, n)
+
+
+def lvs_edit_distance_eq9(ctx: Context, d_eq9, m: int, n: int, d_h_last, d_trace=None, d_work=None):
+    need = lvs_edit_distance_eq9_workspace_bytes(m, n)
+    if d_work is None:
+        d_work = device_buffer(need, ctx.device)
+    _check(lib().lvs_edit_distance_eq9(ctx, _dptr(d_eq9), m, n, _dptr(d_h_last), _dptr(d_trace), _dptr(d_work),
+                                       d_work.numel() * d_work.element_size()))
+    return d_work
+
+
+def lvs_edit_distance_workspace_bytes(m: int, n: int, encoding: int) -> int:
+    return lib().lvs_edit_distance_workspace_bytes(m, n, encoding)
+
+
+def lvs_edit_distance(ctx: Context, d_a, m: int, d_b, n: int, encoding: int, d_h_last, d_work=None):
+    need = lvs_edit_distance_workspace_bytes(m, n, encoding)
+    if d_work is None:
+        d_work = device_buffer(need, ctx.device)
+    _check(lib().lvs_edit_distance(ctx, _dptr(d_a), m, _dptr(d_b), n, encoding, _dptr(d_h_last), _dptr(d_work),
+                                   d_work.numel() * d_work.element_size()))
+    return d_work
+
+
+def lvs_preprocess_workspace_bytes(m: int, alen: int, encoding: int) -> int:
+    return lib().lvs_preprocess_workspace_bytes(m, alen, encoding)
+
+
+def lvs_preprocess(ctx: Context, d_a, m: int, encoding: int, alphabet: bytes, d_table, d_work=None):
+    need = lvs_preprocess_workspace_bytes(m, len(alphabet), encoding)
+    if d_work is None:
+        d_work = device_buffer(need, ctx.device)
+    ab = (ctypes.c_uint8 * max(1, len(alphabet))).from_buffer_copy(bytes(alphabet) or b"\0")
+    _check(lib().lvs_preprocess(ctx, _dptr(d_a), m, encoding, ab, len(alphabet), _dptr(d_table), _dptr(d_work),
+                                d_work.numel() * d_work.element_size()))
+    return d_work
+
+
+def lvs_edit_distance_clear_workspace_bytes(m: int, n: int) -> int:
+    return lib().lvs_edit_distance_clear_workspace_bytes(m, n)
+
+
+def lvs_edit_distance_clear(ctx: Context, d_table, m: int, alphabet: bytes, b: bytes, d_h_last, d_work=None):
+    need = lvs_edit_distance_clear_workspace_bytes(m, len(b))
+    if d_work is None:
+        d_work = device_buffer(need, ctx.device)
+    ab = (ctypes.c_uint8 * max(1, len(alphabet))).from_buffer_copy(bytes(alphabet) or b"\0")
+    bb = (ctypes.c_uint8 * max(1, len(b))).from_buffer_copy(bytes(b) or b"\0")
+    _check(lib().lvs_edit_distance_clear(ctx, _dptr(d_table), m, ab, len(alphabet), bb, len(b), _dptr(d_h_last),
+                                         _dptr(d_work), d_work.numel() * d_work.element_size()))
+    return d_work
