@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""Benchmark of the Leuvenshtein hot path on one MI355X.
+
+A step is one encrypted edit distance of the plain workload: one pair of
+32-character ASCII strings (uniform letters, 20% of positions copied),
+both encrypted -- 2 equality bootstraps per character pair (Algorithm 3) and
+one bootstrap per cell (Algorithm 1/4), 3 * 32 * 32 = 3072 bootstraps, with
+the encrypted strings resident in HBM when the timed region starts.
+
+Prints one JSON line.  value = bootstraps per second of the whole step;
+roofline = the blind-rotation kernel's integer-multiply throughput (HIP
+events around its launches over the timed region) against the chip's
+32-bit VALU multiply peak; cpu_baseline = the oracle's bootstraps per second
+on the host cores for a bounded sample of the same bootstraps.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work of one bootstrap (n = 742 external products, 4 primes):
+# per prime and step, 4 length-2048 NTTs of 11 * 1024 butterflies plus the
+# 2 x 2 products with the GGSW row over 2048 positions = 53248 modular
+# multiplications; each needs 3 32-bit multiplies (Shoup / Montgomery).
+MODMUL_PER_PBS = 742 * 4 * (4 * 11 * 1024 + 4 * 2048)
+INT_MUL_PER_PBS = 3 * MODMUL_PER_PBS
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit multiply per lane per cycle
+# (v_mul_lo_u32 / v_mul_hi_u32 issue at the full VALU rate on gfx950).
+VALU_INT_MUL_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def kernel_source_digest():
+    with open(os.path.join(ROOT, "paper_2508_14568_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_per_launch(avg_pbs_per_launch):
+    """HBM bytes per blind-rotation launch from the committed rocprofv3
+    counter summary, or None when it is absent or the kernel changed since."""
+    path = os.path.join(ROOT, "profiles", "blind_rotate_traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernels_hip_sha256") != kernel_source_digest():
+        return None
+    return t["bytes_per_pbs"] * avg_pbs_per_launch
+
+
+def cpu_baseline(workload_cts, seconds_hint=20.0):
+    """Oracle bootstraps per second on this host's cores (bounded sample)."""
+    from oracle import leuvenshtein as OL
+    from oracle import tfhe as OT
+    import numpy as np
+    threads = OT.default_threads()
+    keys = OT.Keys(OT.default_params(), seed=1, nthreads=threads)
+    polys = OL.lut_polys(keys.N)
+    sample = workload_cts[: 2 * threads]
+    t0 = time.perf_counter()
+    keys.pbs_batch(sample, polys, OL.LUT_IDS["eq"], threads)
+    dt = time.perf_counter() - t0
+    return {"value": round(len(sample) / dt, 3), "unit": "PBS/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(sample)} equality bootstraps of the plain 32x32 ASCII workload "
+                      f"(z1 = x1_i - y1_j, LUT_eq), {threads} threads, {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build runs on a single MI355X "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2508_14568_amd import lvs as L
+    import workloads as W
+    from oracle import plaintext as P
+
+    a, b = W.plain_ascii()
+    m, n = len(a), len(b)
+    params = L.lvs_params_default()
+    ck, sk = L.lvs_keygen(params, 1)
+    ctx = L.lvs_context_create(sk, params, 0)
+    A = L.lvs_encrypt_string(ck, a, L.LVS_ENC_ASCII7, 1001)
+    B = L.lvs_encrypt_string(ck, b, L.LVS_ENC_ASCII7, 1002)
+    dA, dB = L.to_device(A, ctx.device), L.to_device(B, ctx.device)
+    d_h = torch.zeros(n * L.CT_WORDS, dtype=torch.int64, device=ctx.device)
+    d_work = L.device_buffer(L.lvs_edit_distance_workspace_bytes(m, n, L.LVS_ENC_ASCII7), ctx.device)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        L.lvs_edit_distance(ctx, dA, m, dB, n, L.LVS_ENC_ASCII7, d_h, d_work)
+    torch.cuda.synchronize()
+    L.lvs_profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        L.lvs_edit_distance(ctx, dA, m, dB, n, L.LVS_ENC_ASCII7, d_h, d_work)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    br_ms, br_launches, br_pbs = L.lvs_profile_read(ctx, L.KERNEL_BLIND_ROTATE)
+    ks_ms, ks_launches, _ = L.lvs_profile_read(ctx, L.KERNEL_KEYSWITCH)
+    L.lvs_profile_enable(ctx, False)
+
+    dist = L.lvs_decrypt_distance(ck, L.to_host(d_h).reshape(n, L.CT_WORDS), m)
+    if dist != P.edit_distance(a, b):
+        print(f"wrong distance {dist} != {P.edit_distance(a, b)}", file=sys.stderr)
+        sys.exit(1)
+
+    pbs_per_step = 3 * m * n
+    ms_per_step = 1000 * elapsed / args.steps
+    pbs_s = pbs_per_step * args.steps / elapsed
+    avg_launch_ms = br_ms / max(1, br_launches)
+    avg_pbs_launch = br_pbs / max(1, br_launches)
+    achieved = INT_MUL_PER_PBS * avg_pbs_launch / (avg_launch_ms / 1000) / 1e12
+    roofline = {
+        "bound": "alu", "kernel": "blind_rotate_kernel",
+        "achieved": round(achieved, 3), "peak": round(VALU_INT_MUL_PEAK_TOPS, 3), "unit": "TOP/s",
+        "frac": round(achieved / VALU_INT_MUL_PEAK_TOPS, 4),
+        "traffic": traffic_per_launch(avg_pbs_launch),
+        "ops": "32-bit integer multiplies, 3 per modular multiplication, "
+               f"{INT_MUL_PER_PBS} per bootstrap",
+        "avg_launch_ms": round(avg_launch_ms, 4), "launches": br_launches,
+        "avg_pbs_per_launch": round(avg_pbs_launch, 2),
+        "keyswitch_ms_per_step": round(ks_ms / args.steps, 3),
+        "blind_rotate_ms_per_step": round(br_ms / args.steps, 3),
+    }
+    line = {
+        "metric": "PBS/s & DP cells/s; batched vs plain queries/s; p50/p99 query latency",
+        "value": round(pbs_s, 2), "unit": "PBS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "plain_ascii_32x32", "m": m, "n": n, "encoding": "ascii7",
+                   "pbs_per_step": pbs_per_step, "cells_per_step": m * n,
+                   "params": "n=742 k=1 N=2048 q=2^64 pbs 2^23x1 ks 2^3x5", "path": "plain per-diagonal"},
+        "cells_per_s": round(m * n * args.steps / elapsed, 2),
+        "queries_per_s": round(args.steps / elapsed, 4),
+        "distance": dist,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        z1 = (A[:, None, 0, :] - B[None, :, 0, :]).reshape(m * n, L.CT_WORDS).astype(np.uint64)
+        line["cpu_baseline"] = cpu_baseline(z1)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

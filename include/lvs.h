@@ -200,6 +200,19 @@ int lvs_edit_distance_clear(lvs_context* ctx, const uint64_t* d_table, size_t m,
                             size_t alen, const uint8_t* b, size_t n, uint64_t* d_h_last, void* d_work,
                             size_t work_bytes);
 
+/* ------------------------------------------------------------ measurement */
+
+/* Kernel timing for measurement: while enabled, every launch of the blind
+ * rotation (kernel 0) and of the key switch (kernel 1) is bracketed by HIP
+ * events on the context's stream.  Enabling (or disabling) waits for the
+ * stream and clears earlier records. */
+int lvs_profile_enable(lvs_context* ctx, int enable);
+
+/* Sum of the recorded launch durations of `kernel` (milliseconds), the
+ * number of launches and the bootstraps they processed.  Waits for the
+ * recorded events. */
+int lvs_profile_read(lvs_context* ctx, int kernel, double* total_ms, uint64_t* launches, uint64_t* units);
+
 /* Releases a handle created by the library (keys, contexts). */
 void lvs_free(void* handle);
 

@@ -36,6 +36,40 @@ struct Context : Handle {
     uint32_t* tw = nullptr;       // fwd, fwd_s, inv, inv_s, scale, scale_s
     uint64_t* luts = nullptr;     // [LVS_LUT_SLOTS][N]
     DevTables tables{};
+    // kernel timing (lvs_profile_*): event pairs recorded around launches
+    bool profiling = false;
+    struct Timed { hipEvent_t start, end; int kernel; uint64_t units; };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> spare;
+};
+
+hipEvent_t take_event(Context* C) {
+    hipEvent_t e = nullptr;
+    if (!C->spare.empty()) {
+        e = C->spare.back();
+        C->spare.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+    }
+    return e;
+}
+
+// Brackets one launch with events when profiling is on.
+struct TimedLaunch {
+    Context* C;
+    hipEvent_t a = nullptr;
+    int kernel;
+    uint64_t units;
+    TimedLaunch(Context* c, int k, uint64_t u) : C(c), kernel(k), units(u) {
+        if (C->profiling && (a = take_event(C))) hipEventRecord(a, C->stream);
+    }
+    ~TimedLaunch() {
+        if (!a) return;
+        hipEvent_t b = take_event(C);
+        if (!b) return;
+        hipEventRecord(b, C->stream);
+        C->timed.push_back({a, b, kernel, units});
+    }
 };
 
 struct ArenaLayout {
@@ -107,9 +141,15 @@ int run_pbs(Context* C, const uint64_t* in, const uint8_t* lut_ids, int lut, siz
             uint64_t* ks_buf) {
     for (size_t b0 = 0; b0 < B; b0 += kPbsChunk) {
         const int nb = int(std::min(kPbsChunk, B - b0));
-        LVS_HIP(launch_keyswitch(in + b0 * W, C->ksk, ks_buf, nb, C->stream));
-        LVS_HIP(launch_blind_rotate(ks_buf, lut_ids ? lut_ids + b0 : nullptr, lut, C->luts, C->bsk, C->tables,
-                                    out + b0 * W, nb, 0, C->stream));
+        {
+            TimedLaunch t(C, 1, uint64_t(nb));
+            LVS_HIP(launch_keyswitch(in + b0 * W, C->ksk, ks_buf, nb, C->stream));
+        }
+        {
+            TimedLaunch t(C, 0, uint64_t(nb));
+            LVS_HIP(launch_blind_rotate(ks_buf, lut_ids ? lut_ids + b0 : nullptr, lut, C->luts, C->bsk, C->tables,
+                                        out + b0 * W, nb, 0, C->stream));
+        }
     }
     return LVS_OK;
 }
@@ -591,12 +631,56 @@ int lvs_edit_distance_clear(lvs_context* ctx, const uint64_t* d_table, size_t m,
     return rc;
 }
 
+int lvs_profile_enable(lvs_context* ctx, int enable) {
+    Context* C = as_ctx(ctx);
+    LVS_REQUIRE(C, LVS_E_INVAL, "lvs_profile_enable: bad context");
+    LVS_HIP(hipSetDevice(C->device));
+    LVS_HIP(hipStreamSynchronize(C->stream));
+    for (auto& t : C->timed) {
+        C->spare.push_back(t.start);
+        C->spare.push_back(t.end);
+    }
+    C->timed.clear();
+    C->profiling = enable != 0;
+    return LVS_OK;
+}
+
+int lvs_profile_read(lvs_context* ctx, int kernel, double* total_ms, uint64_t* launches, uint64_t* units) {
+    Context* C = as_ctx(ctx);
+    LVS_REQUIRE(C && total_ms && launches && units, LVS_E_INVAL, "lvs_profile_read: bad argument");
+    LVS_HIP(hipSetDevice(C->device));
+    double ms = 0;
+    uint64_t n = 0, u = 0;
+    for (auto& t : C->timed) {
+        if (t.kernel != kernel) continue;
+        LVS_HIP(hipEventSynchronize(t.end));
+        float dt = 0;
+        LVS_HIP(hipEventElapsedTime(&dt, t.start, t.end));
+        ms += dt;
+        ++n;
+        u += t.units;
+    }
+    *total_ms = ms;
+    *launches = n;
+    *units = u;
+    return LVS_OK;
+}
+
 void lvs_free(void* handle) {
     if (!handle) return;
     switch (reinterpret_cast<Handle*>(handle)->kind) {
         case kClientKey: delete reinterpret_cast<ClientKey*>(handle); break;
         case kServerKey: delete reinterpret_cast<ServerKey*>(handle); break;
-        case kContext: delete reinterpret_cast<Context*>(handle); break;
+        case kContext: {
+            Context* C = reinterpret_cast<Context*>(handle);
+            for (auto& t : C->timed) {
+                hipEventDestroy(t.start);
+                hipEventDestroy(t.end);
+            }
+            for (auto e : C->spare) hipEventDestroy(e);
+            delete C;
+            break;
+        }
         default: break;
     }
 }

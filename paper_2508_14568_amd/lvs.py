@@ -67,6 +67,8 @@ _SIGS = {
     "lvs_preprocess": (I32, [VP, VP, SZ, I32, VP, SZ, VP, VP, SZ]),
     "lvs_edit_distance_clear_workspace_bytes": (SZ, [SZ, SZ]),
     "lvs_edit_distance_clear": (I32, [VP, VP, SZ, VP, SZ, VP, SZ, VP, VP, SZ]),
+    "lvs_profile_enable": (I32, [VP, I32]),
+    "lvs_profile_read": (I32, [VP, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(U64), ctypes.POINTER(U64)]),
     "lvs_free": (None, [VP]),
 }
 
@@ -316,3 +318,20 @@ def lvs_edit_distance_clear(ctx: Context, d_table, m: int, alphabet: bytes, b: b
     _check(lib().lvs_edit_distance_clear(ctx, _dptr(d_table), m, ab, len(alphabet), bb, len(b), _dptr(d_h_last),
                                          _dptr(d_work), d_work.numel() * d_work.element_size()))
     return d_work
+
+
+# ------------------------------------------------------------ measurement
+
+KERNEL_BLIND_ROTATE = 0
+KERNEL_KEYSWITCH = 1
+
+
+def lvs_profile_enable(ctx: Context, enable: bool):
+    _check(lib().lvs_profile_enable(ctx, 1 if enable else 0))
+
+
+def lvs_profile_read(ctx: Context, kernel: int):
+    """(total milliseconds, launches, bootstraps) recorded for a kernel."""
+    ms, n, u = ctypes.c_double(), U64(), U64()
+    _check(lib().lvs_profile_read(ctx, kernel, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(u)))
+    return ms.value, n.value, u.value
