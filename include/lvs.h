@@ -135,11 +135,13 @@ int lvs_sync(lvs_context* ctx);
 size_t lvs_pbs_workspace_bytes(size_t B);
 
 /* B independent programmable bootstraps (Section 2.2): d_out[b] =
- * PBS(d_in[b]; table lut(b)) with lut(b) = d_lut_ids[b] if d_lut_ids is not
- * NULL (device bytes), else lut_id.  Each runs key switch -> modulus switch ->
- * blind rotation -> sample extraction; results are bit-identical to the
- * schoolbook definition.  d_in and d_out are [B][N+1] and must not overlap. */
-int lvs_pbs_batch(lvs_context* ctx, const uint64_t* d_in, const uint8_t* d_lut_ids, int lut_id, size_t B,
+ * PBS(d_in[b]; table lut(b)) with lut(b) = lut_ids[b] if lut_ids (host bytes,
+ * each < LVS_LUT_SLOTS) is not NULL, else lut_id.  Each runs key switch ->
+ * modulus switch -> blind rotation -> sample extraction; results are
+ * bit-identical to the schoolbook definition.  d_in and d_out are [B][N+1]
+ * and must not overlap.  Waits for earlier work on the stream before
+ * enqueueing (its job list is staged through host memory). */
+int lvs_pbs_batch(lvs_context* ctx, const uint64_t* d_in, const uint8_t* lut_ids, int lut_id, size_t B,
                   uint64_t* d_out, void* d_work, size_t work_bytes);
 
 /* --------------------------------------------------------- edit distance */
@@ -200,11 +202,55 @@ int lvs_edit_distance_clear(lvs_context* ctx, const uint64_t* d_table, size_t m,
                             size_t alen, const uint8_t* b, size_t n, uint64_t* d_h_last, void* d_work,
                             size_t work_bytes);
 
+/* ------------------------------------------------------------ batch plans */
+
+/* One edit distance of a batch.  Both strings encrypted: d_a ([m][nsym][N+1])
+ * and d_b ([n][nsym][N+1]).  One cleartext string (Section 5): d_b = NULL,
+ * d_table = lvs_preprocess output of a over `alphabet` (host, alen symbols),
+ * b_clear = the cleartext string (host, n symbols).  d_h_last receives
+ * h[m, 1..n] ([n][N+1]). */
+typedef struct {
+    const uint64_t* d_a;
+    size_t m;
+    const uint64_t* d_b;
+    size_t n;
+    const uint64_t* d_table;
+    const uint8_t* alphabet;
+    size_t alen;
+    const uint8_t* b_clear;
+    uint64_t* d_h_last;
+} lvs_query;
+
+typedef struct lvs_plan lvs_plan;
+
+enum { LVS_PLAN_GRAPH = 1 };   /* capture the whole schedule as one HIP graph */
+
+/* Workspace bytes of lvs_plan_create for these queries. */
+int lvs_plan_workspace_bytes(const lvs_query* queries, size_t nq, int encoding, size_t* bytes);
+
+/* Batch of edit distances (batch input matching, Section 6.2): the equality
+ * bootstraps of every pair of every query form the first step(s); then step
+ * s = 2 .. max(m + n) bootstraps every ready cell (i, s - i) of every query
+ * in one key-switch launch and one persistent blind-rotation launch.  The
+ * schedule is static (no data-dependent branch exists under encryption), so
+ * it is built and uploaded once into d_work and, with LVS_PLAN_GRAPH,
+ * captured as one HIP graph.  Query buffers are referenced, not copied: they
+ * must stay valid while the plan is used.  Results are bit-identical to
+ * computing each query alone. */
+int lvs_plan_create(lvs_context* ctx, const lvs_query* queries, size_t nq, int encoding, int flags, void* d_work,
+                    size_t work_bytes, lvs_plan** out);
+
+/* Enqueues one execution of the plan on the context's stream. */
+int lvs_plan_run(lvs_plan* plan);
+
+/* Steps, bootstraps and the largest step of a plan (any may be NULL). */
+int lvs_plan_info(const lvs_plan* plan, size_t* steps, size_t* bootstraps, size_t* max_step);
+
 /* ------------------------------------------------------------ measurement */
 
 /* Kernel timing for measurement: while enabled, every launch of the blind
- * rotation (kernel 0) and of the key switch (kernel 1) is bracketed by HIP
- * events on the context's stream.  Enabling (or disabling) waits for the
+ * rotation (kernel 0), of the key switch (kernel 1) and of a plan's graph
+ * (kernel 2) is bracketed by HIP events on the context's stream.  Enabling (or disabling) waits for the
  * stream and clears earlier records. */
 int lvs_profile_enable(lvs_context* ctx, int enable);
 
@@ -213,7 +259,7 @@ int lvs_profile_enable(lvs_context* ctx, int enable);
  * recorded events. */
 int lvs_profile_read(lvs_context* ctx, int kernel, double* total_ms, uint64_t* launches, uint64_t* units);
 
-/* Releases a handle created by the library (keys, contexts). */
+/* Releases a handle created by the library (keys, contexts, plans). */
 void lvs_free(void* handle);
 
 #ifdef __cplusplus

@@ -9,8 +9,10 @@
 #include <string>
 #include <vector>
 
+#include "context.h"
 #include "launch.h"
 #include "lvs_internal.h"
+#include "plan.h"
 
 namespace lvs {
 
@@ -19,58 +21,10 @@ namespace {
 thread_local std::string g_error = "no error";
 
 constexpr size_t kAlign = 256;
-constexpr size_t kPbsChunk = 8192;          // bootstraps per key-switch / blind-rotation launch
 constexpr size_t kMaxLen = 4096;            // longest string the no-refresh noise budget admits
 constexpr size_t W = kCtWords;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-struct Context : Handle {
-    lvs_params p{};
-    int device = 0;
-    hipStream_t stream = nullptr;
-    uint8_t* arena = nullptr;
-    size_t arena_bytes = 0;
-    uint32_t* bsk = nullptr;      // NTT domain
-    uint64_t* ksk = nullptr;
-    uint32_t* tw = nullptr;       // fwd, fwd_s, inv, inv_s, scale, scale_s
-    uint64_t* luts = nullptr;     // [LVS_LUT_SLOTS][N]
-    DevTables tables{};
-    // kernel timing (lvs_profile_*): event pairs recorded around launches
-    bool profiling = false;
-    struct Timed { hipEvent_t start, end; int kernel; uint64_t units; };
-    std::vector<Timed> timed;
-    std::vector<hipEvent_t> spare;
-};
-
-hipEvent_t take_event(Context* C) {
-    hipEvent_t e = nullptr;
-    if (!C->spare.empty()) {
-        e = C->spare.back();
-        C->spare.pop_back();
-    } else if (hipEventCreate(&e) != hipSuccess) {
-        e = nullptr;
-    }
-    return e;
-}
-
-// Brackets one launch with events when profiling is on.
-struct TimedLaunch {
-    Context* C;
-    hipEvent_t a = nullptr;
-    int kernel;
-    uint64_t units;
-    TimedLaunch(Context* c, int k, uint64_t u) : C(c), kernel(k), units(u) {
-        if (C->profiling && (a = take_event(C))) hipEventRecord(a, C->stream);
-    }
-    ~TimedLaunch() {
-        if (!a) return;
-        hipEvent_t b = take_event(C);
-        if (!b) return;
-        hipEventRecord(b, C->stream);
-        C->timed.push_back({a, b, kernel, units});
-    }
-};
 
 struct ArenaLayout {
     size_t bsk, ksk, tw, luts, total;
@@ -133,125 +87,33 @@ const ServerKey* as_sk(const lvs_server_key* c) {
 
 int nsym_of(int encoding) { return encoding == LVS_ENC_ASCII7 ? 2 : 1; }
 
-// ------------------------------------------------------------ bootstraps
+// ------------------------------------------------------------- plans
 
-size_t pbs_ws(size_t B) { return align_up(sizeof(uint64_t) * std::min(B, kPbsChunk) * kSmallWords); }
+bool valid_encoding(int e) { return e == LVS_ENC_ASCII7 || e == LVS_ENC_DNA2; }
 
-int run_pbs(Context* C, const uint64_t* in, const uint8_t* lut_ids, int lut, size_t B, uint64_t* out,
-            uint64_t* ks_buf) {
-    for (size_t b0 = 0; b0 < B; b0 += kPbsChunk) {
-        const int nb = int(std::min(kPbsChunk, B - b0));
-        {
-            TimedLaunch t(C, 1, uint64_t(nb));
-            LVS_HIP(launch_keyswitch(in + b0 * W, C->ksk, ks_buf, nb, C->stream));
-        }
-        {
-            TimedLaunch t(C, 0, uint64_t(nb));
-            LVS_HIP(launch_blind_rotate(ks_buf, lut_ids ? lut_ids + b0 : nullptr, lut, C->luts, C->bsk, C->tables,
-                                        out + b0 * W, nb, 0, C->stream));
-        }
-    }
+// Uploads and runs a plan built for one call; ws must hold plan_bytes().
+int execute(Context* C, Plan& P, uint8_t* ws) {
+    LVS_HIP(upload_plan(P, ws, C->stream));
+    LVS_HIP(run_plan(C, P));
     return LVS_OK;
 }
 
-// --------------------------------------------------------- edit distance
-
-struct DpLayout {
-    size_t V, H, key, M, ks, col, total;
-};
-
-DpLayout dp_layout(size_t m, size_t n) {
-    DpLayout L{};
-    const size_t width = std::max<size_t>(1, std::min(m, n));
-    size_t off = 0;
-    L.V = off; off = align_up(off + sizeof(uint64_t) * (m + 1) * W);
-    L.H = off; off = align_up(off + sizeof(uint64_t) * (n + 1) * W);
-    L.key = off; off = align_up(off + sizeof(uint64_t) * width * W);
-    L.M = off; off = align_up(off + sizeof(uint64_t) * width * W);
-    L.ks = off; off = align_up(off + pbs_ws(width));
-    L.col = off; off = align_up(off + sizeof(int32_t) * std::max<size_t>(n, 1));
-    L.total = off;
-    return L;
-}
-
-// The anti-diagonal wavefront: for s = 2 .. m+n, the cells (i, s-i) form one
-// batch: key (linear), bootstrap with LUT_min, difference update (linear).
-int run_dp(Context* C, size_t m, size_t n, const uint64_t* EQ, size_t eq_si, size_t eq_sj, const int32_t* d_col,
-           uint64_t* d_h_last, uint64_t* d_trace, uint8_t* ws) {
-    const DpLayout L = dp_layout(m, n);
-    auto* V = reinterpret_cast<uint64_t*>(ws + L.V);
-    auto* H = reinterpret_cast<uint64_t*>(ws + L.H);
-    auto* key = reinterpret_cast<uint64_t*>(ws + L.key);
-    auto* M = reinterpret_cast<uint64_t*>(ws + L.M);
-    auto* ks = reinterpret_cast<uint64_t*>(ws + L.ks);
-    LVS_HIP(launch_trivial(V, int(m + 1), 1, C->stream));
-    LVS_HIP(launch_trivial(H, int(n + 1), 1, C->stream));
-    for (size_t s = 2; s <= m + n; ++s) {
-        const size_t i_lo = (s > n + 1) ? s - n : 1;
-        const size_t i_hi = std::min(m, s - 1);
-        const int count = int(i_hi - i_lo + 1);
-        LVS_HIP(launch_key(V, H, EQ, eq_si, eq_sj, d_col, key, int(i_lo), int(s), count, C->stream));
-        int rc = run_pbs(C, key, nullptr, LVS_LUT_MIN, size_t(count), M, ks);
-        if (rc) return rc;
-        LVS_HIP(launch_update(V, H, M, int(i_lo), int(s), count, d_trace, int(n), C->stream));
+size_t max_step_of(const std::vector<QuerySpec>& qs) {
+    size_t eq = 0, diag = 0;
+    for (const auto& q : qs) {
+        if (q.B && !q.eq9_in) eq += q.m * q.n;
+        diag += std::min(q.m, q.n);
     }
-    LVS_HIP(hipMemcpyAsync(d_h_last, H + W, sizeof(uint64_t) * n * W, hipMemcpyDeviceToDevice, C->stream));
-    return LVS_OK;
+    return std::max(eq, diag);
 }
 
-struct EqLayout {
-    size_t z, eq1, eq9, ks, total;
-};
-
-// Equality phase buffers for cells processed in chunks of kPbsChunk.
-EqLayout eq_layout(size_t cells) {
-    EqLayout L{};
-    const size_t ch = std::max<size_t>(1, std::min(cells, kPbsChunk));
-    size_t off = 0;
-    L.z = off; off = align_up(off + sizeof(uint64_t) * ch * W);
-    L.eq1 = off; off = align_up(off + sizeof(uint64_t) * ch * W);
-    L.ks = off; off = align_up(off + pbs_ws(ch));
-    L.eq9 = off; off = align_up(off + sizeof(uint64_t) * cells * W);   // last: callers may supply it
-    L.total = off;
-    return L;
-}
-
-// eq9[c] for cells c = i * n + j of A x B (Algorithm 3 / Algorithm 4 equality;
-// DNA: one bootstrap of x - y).  B == nullptr: cleartext symbols per column.
-int run_equality_into(Context* C, const uint64_t* A, size_t m, const uint64_t* B, const uint8_t* clear_lo,
-                      const uint8_t* clear_hi, size_t n, int encoding, uint64_t* eq9, uint8_t* ws, EqLayout L) {
-    const size_t cells = m * n;
-    auto* z = reinterpret_cast<uint64_t*>(ws + L.z);
-    auto* eq1 = reinterpret_cast<uint64_t*>(ws + L.eq1);
-    auto* ks = reinterpret_cast<uint64_t*>(ws + L.ks);
-    const int ns = nsym_of(encoding);
-    const int stride = ns * int(W);
-    for (size_t c0 = 0; c0 < cells; c0 += kPbsChunk) {
-        const long cnt = long(std::min(kPbsChunk, cells - c0));
-        if (encoding == LVS_ENC_DNA2) {
-            LVS_HIP(launch_pair(A, stride, 0, B, stride, 0, clear_lo, nullptr, 1, 0, z, int(n), long(c0), cnt,
-                                C->stream));
-            int rc = run_pbs(C, z, nullptr, LVS_LUT_EQ9, size_t(cnt), eq9 + c0 * W, ks);
-            if (rc) return rc;
-        } else {
-            // z1 = x1 - y1; eq1 = PBS(z1; LUT_eq)
-            LVS_HIP(launch_pair(A, stride, 0, B, stride, 0, clear_lo, nullptr, 1, 0, z, int(n), long(c0), cnt,
-                                C->stream));
-            int rc = run_pbs(C, z, nullptr, LVS_LUT_EQ, size_t(cnt), eq1, ks);
-            if (rc) return rc;
-            // z2 = 2 (x2 - y2) + (1 - eq1); eq9 = PBS(z2; LUT_eq9)
-            LVS_HIP(launch_pair(A, stride, 1, B, stride, 1, clear_hi, eq1, 2, uint64_t(1) << kDeltaLog, z, int(n),
-                                long(c0), cnt, C->stream));
-            rc = run_pbs(C, z, nullptr, LVS_LUT_EQ9, size_t(cnt), eq9 + c0 * W, ks);
-            if (rc) return rc;
-        }
+size_t plan_ws(const std::vector<QuerySpec>& qs) {
+    size_t b = 0, jobs = 0;
+    for (const auto& q : qs) {
+        b += query_buffer_bytes(q);
+        jobs += query_jobs(q);
     }
-    return LVS_OK;
-}
-
-int run_equality(Context* C, const uint64_t* A, size_t m, const uint64_t* B, const uint8_t* clear_lo,
-                 const uint8_t* clear_hi, size_t n, int encoding, uint64_t* eq9, uint8_t* ws) {
-    return run_equality_into(C, A, m, B, clear_lo, clear_hi, n, encoding, eq9, ws, eq_layout(m * n));
+    return b + plan_bytes(jobs, max_step_of(qs));
 }
 
 }  // namespace
@@ -427,7 +289,8 @@ int lvs_context_create(const lvs_server_key* sk, int device, void* hip_stream, v
     }
     C->tables = DevTables{C->tw, C->tw + tn, C->tw + 2 * tn, C->tw + 3 * tn, C->tw + 4 * tn, C->tw + 4 * tn + kPrimes};
     auto fail = [&](int code) { delete C; return code; };
-    hipError_t e = hipMemcpy(C->tw, tw.data(), tw.size() * 4, hipMemcpyHostToDevice);
+    hipError_t e = prepare_kernels();
+    if (e == hipSuccess) e = hipMemcpy(C->tw, tw.data(), tw.size() * 4, hipMemcpyHostToDevice);
     // the 64-bit bootstrapping key is staged in the key-switching key's slot
     if (e == hipSuccess) e = hipMemcpy(C->ksk, s->bsk.data(), s->bsk.size() * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_bsk_convert(C->ksk, C->bsk, C->tables, nullptr);
@@ -478,43 +341,81 @@ int lvs_sync(lvs_context* ctx) {
     return LVS_OK;
 }
 
-size_t lvs_pbs_workspace_bytes(size_t B) { return pbs_ws(std::max<size_t>(B, 1)); }
+size_t lvs_pbs_workspace_bytes(size_t B) { return plan_bytes(std::max<size_t>(B, 1), std::max<size_t>(B, 1)); }
 
-int lvs_pbs_batch(lvs_context* ctx, const uint64_t* d_in, const uint8_t* d_lut_ids, int lut_id, size_t B,
+int lvs_pbs_batch(lvs_context* ctx, const uint64_t* d_in, const uint8_t* lut_ids, int lut_id, size_t B,
                   uint64_t* d_out, void* d_work, size_t work_bytes) {
     Context* C = as_ctx(ctx);
     LVS_REQUIRE(C, LVS_E_INVAL, "lvs_pbs_batch: bad context");
     if (B == 0) return LVS_OK;
     LVS_REQUIRE(d_in && d_out && d_work, LVS_E_INVAL, "lvs_pbs_batch: NULL buffer");
-    LVS_REQUIRE(d_lut_ids || (lut_id >= 0 && lut_id < LVS_LUT_SLOTS), LVS_E_INVAL, "lvs_pbs_batch: bad lut id");
+    if (lut_ids) {
+        for (size_t k = 0; k < B; ++k)
+            LVS_REQUIRE(lut_ids[k] < LVS_LUT_SLOTS, LVS_E_INVAL, "lvs_pbs_batch: bad lut id");
+    } else {
+        LVS_REQUIRE(lut_id >= 0 && lut_id < LVS_LUT_SLOTS, LVS_E_INVAL, "lvs_pbs_batch: bad lut id");
+    }
     LVS_REQUIRE(work_bytes >= lvs_pbs_workspace_bytes(B), LVS_E_NOMEM_DEVICE, "lvs_pbs_batch: workspace too small");
     LVS_REQUIRE(d_out + B * W <= d_in || d_in + B * W <= d_out, LVS_E_INVAL, "lvs_pbs_batch: in and out overlap");
     LVS_HIP(hipSetDevice(C->device));
-    return run_pbs(C, d_in, d_lut_ids, lut_id, B, d_out, reinterpret_cast<uint64_t*>(d_work));
+    Plan P;
+    build_pbs_plan(d_in, lut_ids, lut_id, B, d_out, P);
+    return execute(C, P, reinterpret_cast<uint8_t*>(d_work));
 }
 
+namespace {
+QuerySpec pair_query(const uint64_t* d_a, size_t m, const uint64_t* d_b, size_t n, int encoding, uint64_t* h) {
+    QuerySpec q;
+    q.encoding = encoding;
+    q.A = d_a;
+    q.m = m;
+    q.B = d_b;
+    q.n = n;
+    q.h_last = h;
+    return q;
+}
+
+// Fills h[0..n) with Enc(1): the result for an empty first string.
+int empty_first(Context* C, size_t n, uint64_t* d_h_last) {
+    LVS_HIP(launch_trivial(d_h_last, int(n), 1, C->stream));
+    return LVS_OK;
+}
+}  // namespace
+
 size_t lvs_equality_workspace_bytes(size_t m, size_t n, int encoding) {
-    (void)encoding;
-    return eq_layout(m * n).eq9;
+    const size_t eq1 = encoding == LVS_ENC_ASCII7 ? align256(sizeof(uint64_t) * m * n * W) : 0;
+    return eq1 + plan_bytes(m * n * (encoding == LVS_ENC_ASCII7 ? 2 : 1), m * n);
 }
 
 int lvs_equality(lvs_context* ctx, const uint64_t* d_a, size_t m, const uint64_t* d_b, size_t n, int encoding,
                  uint64_t* d_eq9, void* d_work, size_t work_bytes) {
     Context* C = as_ctx(ctx);
     LVS_REQUIRE(C, LVS_E_INVAL, "lvs_equality: bad context");
-    LVS_REQUIRE(encoding == LVS_ENC_ASCII7 || encoding == LVS_ENC_DNA2, LVS_E_INVAL, "unknown encoding");
+    LVS_REQUIRE(valid_encoding(encoding), LVS_E_INVAL, "unknown encoding");
     if (m == 0 || n == 0) return LVS_OK;
     LVS_REQUIRE(d_a && d_b && d_eq9 && d_work, LVS_E_INVAL, "lvs_equality: NULL buffer");
     LVS_REQUIRE(work_bytes >= lvs_equality_workspace_bytes(m, n, encoding), LVS_E_NOMEM_DEVICE,
                 "lvs_equality: workspace too small");
     LVS_HIP(hipSetDevice(C->device));
-    // the caller's buffer takes the place of the layout's last slot (eq9)
-    const EqLayout E = eq_layout(m * n);
     uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
-    return run_equality_into(C, d_a, m, d_b, nullptr, nullptr, n, encoding, d_eq9, ws, E);
+    std::vector<QuerySpec> qs{pair_query(d_a, m, d_b, n, encoding, nullptr)};
+    qs[0].eq9 = d_eq9;
+    if (encoding == LVS_ENC_ASCII7) {
+        qs[0].eq1 = reinterpret_cast<uint64_t*>(ws);
+        ws += align256(sizeof(uint64_t) * m * n * W);
+    }
+    Plan P;
+    build_edit_distance_plan(qs, P, /*with_dp=*/false);
+    return execute(C, P, ws);
 }
 
-size_t lvs_edit_distance_eq9_workspace_bytes(size_t m, size_t n) { return dp_layout(m, n).total; }
+size_t lvs_edit_distance_eq9_workspace_bytes(size_t m, size_t n) {
+    QuerySpec q;
+    q.m = m;
+    q.n = n;
+    q.eq9_in = reinterpret_cast<const uint64_t*>(16);
+    return query_buffer_bytes(q) + plan_bytes(m * n, std::min(m, n));
+}
 
 int lvs_edit_distance_eq9(lvs_context* ctx, const uint64_t* d_eq9, size_t m, size_t n, uint64_t* d_h_last,
                           uint64_t* d_trace, void* d_work, size_t work_bytes) {
@@ -524,82 +425,88 @@ int lvs_edit_distance_eq9(lvs_context* ctx, const uint64_t* d_eq9, size_t m, siz
     LVS_REQUIRE(std::min(m, n) <= kMaxLen, LVS_E_NOISE_BUDGET, "lvs_edit_distance_eq9: noise budget");
     LVS_HIP(hipSetDevice(C->device));
     if (n == 0) return LVS_OK;
-    if (m == 0) {
-        LVS_HIP(launch_trivial(d_h_last, int(n), 1, C->stream));
-        return LVS_OK;
-    }
+    if (m == 0) return empty_first(C, n, d_h_last);
     LVS_REQUIRE(d_work && work_bytes >= lvs_edit_distance_eq9_workspace_bytes(m, n), LVS_E_NOMEM_DEVICE,
                 "lvs_edit_distance_eq9: workspace too small");
-    return run_dp(C, m, n, d_eq9, n, 1, nullptr, d_h_last, d_trace, reinterpret_cast<uint8_t*>(d_work));
+    std::vector<QuerySpec> qs(1);
+    qs[0].m = m;
+    qs[0].n = n;
+    qs[0].eq9_in = d_eq9;
+    qs[0].h_last = d_h_last;
+    qs[0].trace = d_trace;
+    uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
+    assign_buffers(qs, ws);
+    Plan P;
+    build_edit_distance_plan(qs, P);
+    return execute(C, P, ws);
 }
 
 size_t lvs_edit_distance_workspace_bytes(size_t m, size_t n, int encoding) {
-    (void)encoding;
-    const size_t cells = m * n;
-    return eq_layout(cells).total + dp_layout(m, n).total;
+    std::vector<QuerySpec> qs{pair_query(nullptr, m, reinterpret_cast<const uint64_t*>(16), n, encoding, nullptr)};
+    return plan_ws(qs);
 }
 
 int lvs_edit_distance(lvs_context* ctx, const uint64_t* d_a, size_t m, const uint64_t* d_b, size_t n, int encoding,
                       uint64_t* d_h_last, void* d_work, size_t work_bytes) {
     Context* C = as_ctx(ctx);
     LVS_REQUIRE(C, LVS_E_INVAL, "lvs_edit_distance: bad context");
-    LVS_REQUIRE(encoding == LVS_ENC_ASCII7 || encoding == LVS_ENC_DNA2, LVS_E_INVAL, "unknown encoding");
+    LVS_REQUIRE(valid_encoding(encoding), LVS_E_INVAL, "unknown encoding");
     LVS_REQUIRE((d_a || m == 0) && (d_b || n == 0) && (d_h_last || n == 0), LVS_E_INVAL,
                 "lvs_edit_distance: NULL buffer");
     LVS_REQUIRE(std::min(m, n) <= kMaxLen, LVS_E_NOISE_BUDGET, "lvs_edit_distance: strings exceed the noise budget");
     LVS_HIP(hipSetDevice(C->device));
     if (n == 0) return LVS_OK;
-    if (m == 0) {
-        LVS_HIP(launch_trivial(d_h_last, int(n), 1, C->stream));
-        return LVS_OK;
-    }
+    if (m == 0) return empty_first(C, n, d_h_last);
     LVS_REQUIRE(d_work && work_bytes >= lvs_edit_distance_workspace_bytes(m, n, encoding), LVS_E_NOMEM_DEVICE,
                 "lvs_edit_distance: workspace too small");
+    std::vector<QuerySpec> qs{pair_query(d_a, m, d_b, n, encoding, d_h_last)};
     uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
-    const EqLayout E = eq_layout(m * n);
-    auto* eq9 = reinterpret_cast<uint64_t*>(ws + E.eq9);
-    int rc = run_equality(C, d_a, m, d_b, nullptr, nullptr, n, encoding, eq9, ws);
-    if (rc) return rc;
-    uint8_t* dpws = ws + E.total;
-    return run_dp(C, m, n, eq9, n, 1, nullptr, d_h_last, nullptr, dpws);
+    assign_buffers(qs, ws);
+    Plan P;
+    build_edit_distance_plan(qs, P);
+    return execute(C, P, ws);
 }
 
 size_t lvs_preprocess_workspace_bytes(size_t m, size_t alphabet_len, int encoding) {
-    (void)encoding;
     const size_t cells = m * alphabet_len;
-    return eq_layout(cells).total + align_up(2 * std::max<size_t>(alphabet_len, 1));
+    const bool ascii = encoding == LVS_ENC_ASCII7;
+    return (ascii ? align256(sizeof(uint64_t) * cells * W) : 0) + plan_bytes(cells * (ascii ? 2 : 1), cells);
 }
 
 int lvs_preprocess(lvs_context* ctx, const uint64_t* d_a, size_t m, int encoding, const uint8_t* alphabet,
                    size_t alen, uint64_t* d_table, void* d_work, size_t work_bytes) {
     Context* C = as_ctx(ctx);
     LVS_REQUIRE(C, LVS_E_INVAL, "lvs_preprocess: bad context");
-    LVS_REQUIRE(encoding == LVS_ENC_ASCII7 || encoding == LVS_ENC_DNA2, LVS_E_INVAL, "unknown encoding");
+    LVS_REQUIRE(valid_encoding(encoding), LVS_E_INVAL, "unknown encoding");
     if (m == 0 || alen == 0) return LVS_OK;
     LVS_REQUIRE(d_a && alphabet && d_table && d_work, LVS_E_INVAL, "lvs_preprocess: NULL buffer");
     LVS_REQUIRE(work_bytes >= lvs_preprocess_workspace_bytes(m, alen, encoding), LVS_E_NOMEM_DEVICE,
                 "lvs_preprocess: workspace too small");
-    std::vector<uint8_t> syms(2 * alen);
+    std::vector<uint8_t> lo(alen), hi(alen);
     for (size_t c = 0; c < alen; ++c) {
         LVS_REQUIRE(encoding == LVS_ENC_ASCII7 ? alphabet[c] < 128 : alphabet[c] < 4, LVS_E_ALPHABET,
                     "lvs_preprocess: alphabet symbol outside the encoding");
-        syms[c] = encoding == LVS_ENC_ASCII7 ? (alphabet[c] & 15) : alphabet[c];
-        syms[alen + c] = encoding == LVS_ENC_ASCII7 ? (alphabet[c] >> 4) : 0;
+        lo[c] = encoding == LVS_ENC_ASCII7 ? (alphabet[c] & 15) : alphabet[c];
+        hi[c] = encoding == LVS_ENC_ASCII7 ? (alphabet[c] >> 4) : 0;
     }
     LVS_HIP(hipSetDevice(C->device));
     uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
-    const EqLayout E = eq_layout(m * alen);
-    uint8_t* d_syms = ws + E.total;
-    LVS_HIP(hipMemcpyAsync(d_syms, syms.data(), syms.size(), hipMemcpyHostToDevice, C->stream));
-    auto* eq9 = reinterpret_cast<uint64_t*>(ws + E.eq9);     // [m][alen]
-    int rc = run_equality(C, d_a, m, nullptr, d_syms, d_syms + alen, alen, encoding, eq9, ws);
-    if (rc) return rc;
-    LVS_HIP(launch_table_scatter(eq9, d_table, int(m), int(alen), 0, long(m * alen), C->stream));
-    LVS_HIP(hipStreamSynchronize(C->stream));   // the staged symbols leave scope
-    return LVS_OK;
+    uint64_t* eq1 = nullptr;
+    if (encoding == LVS_ENC_ASCII7) {
+        eq1 = reinterpret_cast<uint64_t*>(ws);
+        ws += align256(sizeof(uint64_t) * m * alen * W);
+    }
+    Plan P;
+    build_preprocess_plan(d_a, m, encoding, lo, hi, d_table, eq1, P);
+    return execute(C, P, ws);
 }
 
-size_t lvs_edit_distance_clear_workspace_bytes(size_t m, size_t n) { return dp_layout(m, n).total; }
+size_t lvs_edit_distance_clear_workspace_bytes(size_t m, size_t n) {
+    QuerySpec q;
+    q.m = m;
+    q.n = n;
+    return query_buffer_bytes(q) + plan_bytes(m * n, std::min(m, n));
+}
 
 int lvs_edit_distance_clear(lvs_context* ctx, const uint64_t* d_table, size_t m, const uint8_t* alphabet, size_t alen,
                             const uint8_t* b, size_t n, uint64_t* d_h_last, void* d_work, size_t work_bytes) {
@@ -608,27 +515,119 @@ int lvs_edit_distance_clear(lvs_context* ctx, const uint64_t* d_table, size_t m,
     LVS_REQUIRE((d_table || m == 0) && (alphabet || alen == 0) && (b || n == 0) && (d_h_last || n == 0),
                 LVS_E_INVAL, "lvs_edit_distance_clear: NULL buffer");
     LVS_REQUIRE(std::min(m, n) <= kMaxLen, LVS_E_NOISE_BUDGET, "lvs_edit_distance_clear: noise budget");
-    std::vector<int32_t> col(std::max<size_t>(n, 1));
+    std::vector<QuerySpec> qs(1);
+    qs[0].cols.resize(n);
     for (size_t j = 0; j < n; ++j) {
         const uint8_t* hit = std::find(alphabet, alphabet + alen, b[j]);
         LVS_REQUIRE(hit != alphabet + alen, LVS_E_ALPHABET, "lvs_edit_distance_clear: symbol not in the table");
-        col[j] = int32_t(hit - alphabet);
+        qs[0].cols[j] = int32_t(hit - alphabet);
     }
     LVS_HIP(hipSetDevice(C->device));
     if (n == 0) return LVS_OK;
-    if (m == 0) {
-        LVS_HIP(launch_trivial(d_h_last, int(n), 1, C->stream));
-        return LVS_OK;
-    }
+    if (m == 0) return empty_first(C, n, d_h_last);
     LVS_REQUIRE(d_work && work_bytes >= lvs_edit_distance_clear_workspace_bytes(m, n), LVS_E_NOMEM_DEVICE,
                 "lvs_edit_distance_clear: workspace too small");
+    qs[0].m = m;
+    qs[0].n = n;
+    qs[0].table = d_table;
+    qs[0].h_last = d_h_last;
     uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
-    const DpLayout L = dp_layout(m, n);
-    auto* d_col = reinterpret_cast<int32_t*>(ws + L.col);
-    LVS_HIP(hipMemcpyAsync(d_col, col.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, C->stream));
-    int rc = run_dp(C, m, n, d_table, 1, m, d_col, d_h_last, nullptr, ws);
-    LVS_HIP(hipStreamSynchronize(C->stream));   // the staged columns leave scope
-    return rc;
+    assign_buffers(qs, ws);
+    Plan P;
+    build_edit_distance_plan(qs, P);
+    return execute(C, P, ws);
+}
+
+// ------------------------------------------------------------ batch plans
+
+namespace {
+struct PlanHandle : Handle {
+    Context* C = nullptr;
+    Plan P;
+};
+
+int make_specs(const lvs_query* q, size_t nq, int encoding, std::vector<QuerySpec>& qs) {
+    qs.resize(nq);
+    for (size_t k = 0; k < nq; ++k) {
+        const lvs_query& x = q[k];
+        QuerySpec& s = qs[k];
+        s.encoding = encoding;
+        s.m = x.m;
+        s.n = x.n;
+        s.A = x.d_a;
+        s.h_last = x.d_h_last;
+        LVS_REQUIRE(std::min(x.m, x.n) <= kMaxLen, LVS_E_NOISE_BUDGET, "lvs_plan: strings exceed the noise budget");
+        if (x.d_b) {
+            s.B = x.d_b;
+            LVS_REQUIRE((x.d_a || x.m == 0) && (x.d_h_last || x.n == 0), LVS_E_INVAL, "lvs_plan: NULL buffer");
+        } else {
+            LVS_REQUIRE((x.d_table || x.m == 0) && (x.b_clear || x.n == 0) && (x.alphabet || x.alen == 0) &&
+                            (x.d_h_last || x.n == 0), LVS_E_INVAL, "lvs_plan: NULL buffer (cleartext query)");
+            s.table = x.d_table;
+            s.cols.resize(x.n);
+            for (size_t j = 0; j < x.n; ++j) {
+                const uint8_t* hit = std::find(x.alphabet, x.alphabet + x.alen, x.b_clear[j]);
+                LVS_REQUIRE(hit != x.alphabet + x.alen, LVS_E_ALPHABET, "lvs_plan: symbol not in the table");
+                s.cols[j] = int32_t(hit - x.alphabet);
+            }
+        }
+    }
+    return LVS_OK;
+}
+}  // namespace
+
+int lvs_plan_workspace_bytes(const lvs_query* queries, size_t nq, int encoding, size_t* bytes) {
+    LVS_REQUIRE(bytes && (queries || nq == 0), LVS_E_INVAL, "lvs_plan_workspace_bytes: NULL argument");
+    std::vector<QuerySpec> qs;
+    int rc = make_specs(queries, nq, encoding, qs);
+    if (rc) return rc;
+    *bytes = plan_ws(qs);
+    return LVS_OK;
+}
+
+int lvs_plan_create(lvs_context* ctx, const lvs_query* queries, size_t nq, int encoding, int flags, void* d_work,
+                    size_t work_bytes, lvs_plan** out) {
+    Context* C = as_ctx(ctx);
+    LVS_REQUIRE(C && out && (queries || nq == 0), LVS_E_INVAL, "lvs_plan_create: bad argument");
+    LVS_REQUIRE(valid_encoding(encoding), LVS_E_INVAL, "unknown encoding");
+    std::vector<QuerySpec> qs;
+    int rc = make_specs(queries, nq, encoding, qs);
+    if (rc) return rc;
+    LVS_REQUIRE(d_work && work_bytes >= plan_ws(qs), LVS_E_NOMEM_DEVICE, "lvs_plan_create: workspace too small");
+    LVS_HIP(hipSetDevice(C->device));
+    PlanHandle* H = new (std::nothrow) PlanHandle();
+    LVS_REQUIRE(H, LVS_E_NOMEM_HOST, "lvs_plan_create: out of host memory");
+    H->kind = kPlan;
+    H->C = C;
+    uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
+    assign_buffers(qs, ws);
+    build_edit_distance_plan(qs, H->P);
+    hipError_t e = upload_plan(H->P, ws, C->stream);
+    if (e == hipSuccess && (flags & LVS_PLAN_GRAPH)) e = capture_plan(C, H->P);
+    if (e != hipSuccess) {
+        delete H;
+        set_error(std::string("lvs_plan_create: ") + hipGetErrorString(e));
+        return LVS_E_DEVICE;
+    }
+    *out = reinterpret_cast<lvs_plan*>(H);
+    return LVS_OK;
+}
+
+int lvs_plan_run(lvs_plan* plan) {
+    auto* H = reinterpret_cast<PlanHandle*>(plan);
+    LVS_REQUIRE(H && H->kind == kPlan, LVS_E_INVAL, "lvs_plan_run: bad plan");
+    LVS_HIP(hipSetDevice(H->C->device));
+    LVS_HIP(run_plan(H->C, H->P));
+    return LVS_OK;
+}
+
+int lvs_plan_info(const lvs_plan* plan, size_t* steps, size_t* bootstraps, size_t* max_step) {
+    auto* H = reinterpret_cast<const PlanHandle*>(plan);
+    LVS_REQUIRE(H && H->kind == kPlan, LVS_E_INVAL, "lvs_plan_info: bad plan");
+    if (steps) *steps = H->P.steps.size();
+    if (bootstraps) *bootstraps = H->P.pbs();
+    if (max_step) *max_step = H->P.max_step;
+    return LVS_OK;
 }
 
 int lvs_profile_enable(lvs_context* ctx, int enable) {
@@ -671,6 +670,12 @@ void lvs_free(void* handle) {
     switch (reinterpret_cast<Handle*>(handle)->kind) {
         case kClientKey: delete reinterpret_cast<ClientKey*>(handle); break;
         case kServerKey: delete reinterpret_cast<ServerKey*>(handle); break;
+        case kPlan: {
+            auto* H = reinterpret_cast<PlanHandle*>(handle);
+            if (H->P.graph) hipGraphExecDestroy(H->P.graph);
+            delete H;
+            break;
+        }
         case kContext: {
             Context* C = reinterpret_cast<Context*>(handle);
             for (auto& t : C->timed) {
@@ -678,6 +683,7 @@ void lvs_free(void* handle) {
                 hipEventDestroy(t.end);
             }
             for (auto e : C->spare) hipEventDestroy(e);
+            if (C->capture_stream) hipStreamDestroy(C->capture_stream);
             delete C;
             break;
         }

@@ -1,0 +1,66 @@
+// Device context of liblvs.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <vector>
+
+#include "launch.h"
+#include "lvs_internal.h"
+
+namespace lvs {
+
+struct Context : Handle {
+    lvs_params p{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;   // created on first graph capture
+    uint8_t* arena = nullptr;
+    size_t arena_bytes = 0;
+    uint32_t* bsk = nullptr;      // NTT domain
+    uint64_t* ksk = nullptr;
+    uint32_t* tw = nullptr;       // fwd, fwd_s, inv, inv_s, scale, scale_s
+    uint64_t* luts = nullptr;     // [LVS_LUT_SLOTS][N]
+    DevTables tables{};
+    int br_grid = 0;              // persistent blind-rotation grid (0: one workgroup per job)
+    // kernel timing (lvs_profile_*): event pairs recorded around launches
+    bool profiling = false;
+    struct Timed {
+        hipEvent_t start, end;
+        int kernel;
+        uint64_t units;
+    };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> spare;
+};
+
+inline hipEvent_t take_event(Context* C) {
+    hipEvent_t e = nullptr;
+    if (!C->spare.empty()) {
+        e = C->spare.back();
+        C->spare.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+    }
+    return e;
+}
+
+// Brackets one launch with events when profiling is on.
+struct TimedLaunch {
+    Context* C;
+    hipEvent_t a = nullptr;
+    int kernel;
+    uint64_t units;
+    TimedLaunch(Context* c, int k, uint64_t u) : C(c), kernel(k), units(u) {
+        if (k >= 0 && C->profiling && (a = take_event(C))) hipEventRecord(a, C->stream);
+    }
+    ~TimedLaunch() {
+        if (!a) return;
+        hipEvent_t b = take_event(C);
+        if (!b) return;
+        hipEventRecord(b, C->stream);
+        C->timed.push_back({a, b, kernel, units});
+    }
+};
+
+}  // namespace lvs

@@ -239,8 +239,7 @@ __device__ __forceinline__ uint64_t crt_lift(const uint32_t (&r)[kPrimes], const
 // ------------------------------------------------------------ key switch
 
 constexpr int kKsTile = 8;                       // ciphertexts per workgroup
-constexpr int kKsSplit = 16;                     // row chunks (grid.y)
-constexpr int kKsChunk = kN / kKsSplit;          // input coefficients per chunk
+constexpr int kKsSub = 128;                      // input coefficients per LDS round
 constexpr int kKsCols = (kSmallWords + 255) / 256;
 
 __global__ void __launch_bounds__(256) fill_u64_kernel(uint64_t* p, size_t count, uint64_t v) {
@@ -248,50 +247,64 @@ __global__ void __launch_bounds__(256) fill_u64_kernel(uint64_t* p, size_t count
         p[i] = v;
 }
 
-// ks_out[b] += (0, b_body) - sum_{j in chunk, t} d_{j,t} KSK[j*5+t]; ks_out must
-// be zero before the launch.  Digits: round to 15 bits, then balanced base-8
-// digits from the least significant level with a carry (level t weight
-// 2^(64-3t)); the carry out of the top level is dropped.
-__global__ void __launch_bounds__(256) keyswitch_kernel(const uint64_t* __restrict__ in, const uint64_t* __restrict__ ksk,
-                                                        uint64_t* __restrict__ ks_out, int B) {
-    __shared__ uint64_t digits[kKsChunk * kKsLevel];   // 8 signed bytes: one per tile ciphertext
+// Input word w of a job: sum_k coef[k] * src[k][w] (the body delta is added
+// by the blind rotation, which reads the body itself).
+__device__ __forceinline__ uint64_t job_word(const Job& J, int w) {
+    uint64_t v = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        if (J.src[k]) v += uint64_t(int64_t(J.coef[k])) * J.src[k][w];
+    return v;
+}
+
+// part[split][b][c] = - sum_{j in split, t} d_{j,t} KSK[j*5+t][c] for the
+// input of job b (mask coefficients only; the body is added later).  Digits:
+// round to 15 bits, then balanced base-8 digits from the least significant
+// level with a carry (level t weight 2^(64-3t)); the top carry is dropped.
+__global__ void __launch_bounds__(256) keyswitch_jobs_kernel(const Job* __restrict__ jobs, int B,
+                                                             const uint64_t* __restrict__ ksk,
+                                                             uint64_t* __restrict__ part, int chunk) {
+    __shared__ uint64_t digits[kKsSub * kKsLevel];   // 8 signed bytes per row: one per tile ciphertext
     const int tid = threadIdx.x;
     const int b0 = blockIdx.x * kKsTile;
-    const int j0 = blockIdx.y * kKsChunk;
+    const int split = blockIdx.y;
     uint8_t* dig8 = reinterpret_cast<uint8_t*>(digits);
-    for (int idx = tid; idx < kKsTile * kKsChunk; idx += 256) {
-        const int bb = idx / kKsChunk, jj = idx % kKsChunk;
-        uint64_t c = 0;
-        if (b0 + bb < B) c = in[size_t(b0 + bb) * kCtWords + j0 + jj];
-        uint64_t r = (((c >> 48) + 1) >> 1) & 0x7FFFu;     // round(c / 2^49) mod 2^15
-#pragma unroll
-        for (int lev = kKsLevel - 1; lev >= 0; --lev) {
-            int d = int(r & 7u);
-            r >>= 3;
-            if (d >= 4) { d -= 8; r += 1; }
-            dig8[(jj * kKsLevel + lev) * 8 + bb] = uint8_t(int8_t(d));
-        }
-    }
-    __syncthreads();
     uint64_t acc[kKsTile][kKsCols];
 #pragma unroll
     for (int bb = 0; bb < kKsTile; ++bb)
 #pragma unroll
         for (int cs = 0; cs < kKsCols; ++cs) acc[bb][cs] = 0;
-    const uint64_t* rows = ksk + size_t(j0) * kKsLevel * kSmallWords;
-    for (int rr = 0; rr < kKsChunk * kKsLevel; ++rr) {
-        const uint64_t dp = digits[rr];
-        uint64_t k[kKsCols];
+    for (int j0 = split * chunk; j0 < (split + 1) * chunk; j0 += kKsSub) {
+        __syncthreads();
+        for (int idx = tid; idx < kKsTile * kKsSub; idx += 256) {
+            const int bb = idx / kKsSub, jj = idx % kKsSub;
+            uint64_t c = 0;
+            if (b0 + bb < B) c = job_word(jobs[b0 + bb], j0 + jj);
+            uint64_t r = (((c >> 48) + 1) >> 1) & 0x7FFFu;     // round(c / 2^49) mod 2^15
 #pragma unroll
-        for (int cs = 0; cs < kKsCols; ++cs) {
-            const int col = tid + 256 * cs;
-            k[cs] = (col < kSmallWords) ? rows[size_t(rr) * kSmallWords + col] : 0;
+            for (int lev = kKsLevel - 1; lev >= 0; --lev) {
+                int d = int(r & 7u);
+                r >>= 3;
+                if (d >= 4) { d -= 8; r += 1; }
+                dig8[(jj * kKsLevel + lev) * 8 + bb] = uint8_t(int8_t(d));
+            }
         }
+        __syncthreads();
+        const uint64_t* rows = ksk + size_t(j0) * kKsLevel * kSmallWords;
+        for (int rr = 0; rr < kKsSub * kKsLevel; ++rr) {
+            const uint64_t dp = digits[rr];
+            uint64_t k[kKsCols];
 #pragma unroll
-        for (int bb = 0; bb < kKsTile; ++bb) {
-            const int64_t d = int8_t(uint8_t(dp >> (8 * bb)));
+            for (int cs = 0; cs < kKsCols; ++cs) {
+                const int col = tid + 256 * cs;
+                k[cs] = (col < kSmallWords) ? rows[size_t(rr) * kSmallWords + col] : 0;
+            }
 #pragma unroll
-            for (int cs = 0; cs < kKsCols; ++cs) acc[bb][cs] -= uint64_t(d) * k[cs];
+            for (int bb = 0; bb < kKsTile; ++bb) {
+                const int64_t d = int8_t(uint8_t(dp >> (8 * bb)));
+#pragma unroll
+                for (int cs = 0; cs < kKsCols; ++cs) acc[bb][cs] -= uint64_t(d) * k[cs];
+            }
         }
     }
 #pragma unroll
@@ -300,11 +313,7 @@ __global__ void __launch_bounds__(256) keyswitch_kernel(const uint64_t* __restri
 #pragma unroll
         for (int cs = 0; cs < kKsCols; ++cs) {
             const int col = tid + 256 * cs;
-            if (col >= kSmallWords) continue;
-            uint64_t v = acc[bb][cs];
-            if (col == kSmallN && blockIdx.y == 0) v += in[size_t(b0 + bb) * kCtWords + kN];
-            atomicAdd(reinterpret_cast<unsigned long long*>(&ks_out[size_t(b0 + bb) * kSmallWords + col]),
-                      static_cast<unsigned long long>(v));
+            if (col < kSmallWords) part[(size_t(split) * B + b0 + bb) * kSmallWords + col] = acc[bb][cs];
         }
     }
 }
@@ -312,14 +321,13 @@ __global__ void __launch_bounds__(256) keyswitch_kernel(const uint64_t* __restri
 // ---------------------------------------------------------- blind rotation
 
 struct BrArgs {
-    const uint64_t* ks;        // [B][n+1] key-switched ciphertexts (before modulus switching)
-    const uint8_t* lut_ids;    // [B] or nullptr
-    int lut_id;
+    const Job* jobs;           // [B]
+    const uint64_t* part;      // [nsplit][B][n+1] key-switch partial sums (before modulus switching)
+    int nsplit;
     const uint64_t* luts;      // [LVS_LUT_SLOTS][N] test polynomials
     const uint32_t* bsk;       // [n][kPrimes][2 rows][2 comps][N] NTT domain, Montgomery form, 1/N folded
     Tw tw;
     CrtConsts crt;
-    uint64_t* out;             // [B][N+1]
     int B;
 };
 
@@ -346,11 +354,17 @@ __global__ void __launch_bounds__(kBrThreads, 1) blind_rotate_kernel(BrArgs A) {
     uint32_t* scratch = exch + wave * 2 * kPadStride;
 
     for (int b = blockIdx.x; b < A.B; b += gridDim.x) {
-        // modulus switch to Z_{2N}: round(x / 2^52)
-        for (int c = tid; c < kSmallWords; c += kBrThreads)
-            abar[c] = uint32_t((((A.ks[size_t(b) * kSmallWords + c] >> 51) + 1) >> 1) & (2 * kN - 1));
+        const Job& J = A.jobs[b];
+        // finish the key switch (sum of the partial sums, plus the input body)
+        // and switch the modulus to Z_{2N}: round(x / 2^52)
+        for (int c = tid; c < kSmallWords; c += kBrThreads) {
+            uint64_t v = 0;
+            for (int sp = 0; sp < A.nsplit; ++sp) v += A.part[(size_t(sp) * A.B + b) * kSmallWords + c];
+            if (c == kSmallN) v += job_word(J, kN) + J.delta;
+            abar[c] = uint32_t((((v >> 51) + 1) >> 1) & (2 * kN - 1));
+        }
         __syncthreads();
-        const int lut = min(A.lut_ids ? int(A.lut_ids[b]) : A.lut_id, LVS_LUT_SLOTS - 1);   // ids past the table clamp
+        const int lut = min(int(J.lut), LVS_LUT_SLOTS - 1);   // ids past the table clamp
         const uint64_t* tp = A.luts + size_t(lut) * kN;
         const uint32_t bbar = abar[kSmallN];
         // ACC = (0, X^{-bbar} * testpoly)
@@ -410,14 +424,19 @@ __global__ void __launch_bounds__(kBrThreads, 1) blind_rotate_kernel(BrArgs A) {
                 }
             __syncthreads();
         }
-        // sample extraction of coefficient 0
-        uint64_t* o = A.out + size_t(b) * kCtWords;
+        // sample extraction of coefficient 0, then the job's output rule
         for (int t = tid; t < kCtWords; t += kBrThreads) {
             uint64_t v;
             if (t == 0) v = acc[0];
             else if (t < kN) v = uint64_t(0) - acc[kN - t];
             else v = acc[kN];
-            o[t] = v;
+            const uint64_t s0 = J.sub[0] ? J.sub[0][t] : 0;
+            const uint64_t s1 = J.sub[1] ? J.sub[1][t] : 0;
+            const uint64_t c0 = (t == kN) ? J.sub_delta[0] : 0;
+            const uint64_t c1 = (t == kN) ? J.sub_delta[1] : 0;
+            if (J.dst[0]) J.dst[0][t] = v - s0 - c0;
+            if (J.dst[1]) J.dst[1][t] = v - s1 - c1;
+            if (J.dst[2]) J.dst[2][t] = v;
         }
         __syncthreads();
     }
@@ -579,33 +598,40 @@ hipError_t launch_fill_u64(uint64_t* p, size_t count, uint64_t v, hipStream_t st
     return hipGetLastError();
 }
 
-hipError_t launch_keyswitch(const uint64_t* in, const uint64_t* ksk, uint64_t* ks_out, int B, hipStream_t st) {
-    hipError_t e = launch_fill_u64(ks_out, size_t(B) * kSmallWords, 0, st);
-    if (e != hipSuccess) return e;
-    dim3 grid((B + dev::kKsTile - 1) / dev::kKsTile, dev::kKsSplit);
-    hipLaunchKernelGGL(dev::keyswitch_kernel, grid, dim3(256), 0, st, in, ksk, ks_out, B);
+int keyswitch_splits(int B) {
+    // enough workgroups to fill the chip: tiles x splits >= 1024
+    const int tiles = (B + dev::kKsTile - 1) / dev::kKsTile;
+    int s = 1;
+    while (s < 16 && tiles * s < 1024) s *= 2;
+    return s;
+}
+
+size_t keyswitch_part_words(int B) { return size_t(keyswitch_splits(B)) * size_t(B) * kSmallWords; }
+
+hipError_t launch_keyswitch_jobs(const Job* jobs, int B, const uint64_t* ksk, uint64_t* part, hipStream_t st) {
+    if (B <= 0) return hipSuccess;
+    const int ns = keyswitch_splits(B);
+    dim3 grid((B + dev::kKsTile - 1) / dev::kKsTile, ns);
+    hipLaunchKernelGGL(dev::keyswitch_jobs_kernel, grid, dim3(256), 0, st, jobs, B, ksk, part, kN / ns);
     return hipGetLastError();
 }
 
-hipError_t launch_blind_rotate(const uint64_t* ks, const uint8_t* lut_ids, int lut_id, const uint64_t* luts,
-                               const uint32_t* bsk, const DevTables& t, uint64_t* out, int B, int grid,
-                               hipStream_t st) {
-    static bool attr_done = false;
-    if (!attr_done) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(dev::blind_rotate_kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(dev::kBrLds));
-        if (e != hipSuccess) return e;
-        attr_done = true;
-    }
+hipError_t prepare_kernels() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(dev::blind_rotate_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(dev::kBrLds));
+}
+
+hipError_t launch_blind_rotate_jobs(const Job* jobs, int B, const uint64_t* part, const uint64_t* luts,
+                                    const uint32_t* bsk, const DevTables& t, int grid, hipStream_t st) {
+    if (B <= 0) return hipSuccess;
     dev::BrArgs A{};
-    A.ks = ks;
-    A.lut_ids = lut_ids;
-    A.lut_id = lut_id;
+    A.jobs = jobs;
+    A.part = part;
+    A.nsplit = keyswitch_splits(B);
     A.luts = luts;
     A.bsk = bsk;
     A.tw = dev::Tw{t.fwd, t.fwd_s, t.inv, t.inv_s};
     A.crt = make_crt();
-    A.out = out;
     A.B = B;
     if (grid <= 0 || grid > B) grid = B;
     hipLaunchKernelGGL(dev::blind_rotate_kernel, dim3(grid), dim3(dev::kBrThreads), dev::kBrLds, st, A);

@@ -7,6 +7,24 @@
 
 namespace lvs {
 
+// One bootstrap of a step.  Its input ciphertext is the linear combination
+// sum_k coef[k] * src[k] (+ delta on the body), so the key of a cell and the
+// differences of the equality test are formed while the key switch reads
+// them; its output M (the sample-extracted result) is written to every
+// non-null dst[k] as M - sub[k] - sub_delta[k] (sub[k] may be null; sub_delta
+// is subtracted from the body only), which applies the difference update of
+// a cell in the same pass.  A thread reads every sub[] word before writing the
+// dst[] words of the same index, so dst and sub may alias.
+struct Job {
+    const uint64_t* src[3];
+    int32_t coef[3];
+    uint32_t lut;
+    uint64_t delta;
+    uint64_t* dst[3];
+    const uint64_t* sub[2];
+    uint64_t sub_delta[2];
+};
+
 struct DevTables {
     const uint32_t* fwd;      // [kPrimes][N] forward twiddles psi^brv(k)
     const uint32_t* fwd_s;    // Shoup companions
@@ -17,10 +35,14 @@ struct DevTables {
 };
 
 hipError_t launch_fill_u64(uint64_t* p, size_t count, uint64_t v, hipStream_t st);
-hipError_t launch_keyswitch(const uint64_t* in, const uint64_t* ksk, uint64_t* ks_out, int B, hipStream_t st);
-hipError_t launch_blind_rotate(const uint64_t* ks, const uint8_t* lut_ids, int lut_id, const uint64_t* luts,
-                               const uint32_t* bsk, const DevTables& t, uint64_t* out, int B, int grid,
-                               hipStream_t st);
+// Key switch of B job inputs into partial sums part[split][B][n+1]; returns
+// the number of splits used (they are summed by the blind rotation).
+int keyswitch_splits(int B);
+size_t keyswitch_part_words(int B);
+hipError_t launch_keyswitch_jobs(const Job* jobs, int B, const uint64_t* ksk, uint64_t* part, hipStream_t st);
+hipError_t launch_blind_rotate_jobs(const Job* jobs, int B, const uint64_t* part, const uint64_t* luts,
+                                    const uint32_t* bsk, const DevTables& t, int grid, hipStream_t st);
+hipError_t prepare_kernels();
 hipError_t launch_bsk_convert(const uint64_t* bsk_u64, uint32_t* out, const DevTables& t, hipStream_t st);
 hipError_t launch_pair(const uint64_t* A, int a_stride, int sa, const uint64_t* B, int b_stride, int sb,
                        const uint8_t* clear_syms, const uint64_t* E, uint64_t alpha, uint64_t delta, uint64_t* out,

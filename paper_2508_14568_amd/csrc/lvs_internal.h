@@ -24,7 +24,7 @@ constexpr int kDeltaLog = 59;      // x in Z_32 encodes as x << 59
 constexpr int kPrimes = 4;         // NTT primes of the exact negacyclic products
 
 // Every handle starts with a tag so lvs_free can dispatch.
-enum HandleKind : uint32_t { kClientKey = 0x4C565301, kServerKey = 0x4C565302, kContext = 0x4C565303 };
+enum HandleKind : uint32_t { kClientKey = 0x4C565301, kServerKey = 0x4C565302, kContext = 0x4C565303, kPlan = 0x4C565304 };
 
 struct Handle {
     uint32_t kind;

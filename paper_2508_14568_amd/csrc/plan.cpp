@@ -1,0 +1,312 @@
+// Plans: every step is a list of bootstraps whose inputs are ready.
+//
+// Equality (Section 4, Algorithm 3 with the eq9 table of Algorithm 4): all
+// character pairs of all queries are independent of the DP, so they form one
+// step (two for ASCII: eq1, then eq9).  Main loop (Algorithm 1/4): the cells
+// of anti-diagonal s = i + j depend only on diagonal s - 1 (Section 6.2), so
+// step s holds every query's cells with i + j = s.  The key of a cell and the
+// difference update are folded into the bootstrap's job (see launch.h).
+#include "plan.h"
+
+#include <algorithm>
+
+#include "context.h"
+
+namespace lvs {
+
+namespace {
+
+constexpr size_t W = kCtWords;
+constexpr uint64_t kOne = uint64_t(1) << kDeltaLog;   // Enc(1) body of a noise-free ciphertext
+
+int nsym(int encoding) { return encoding == LVS_ENC_ASCII7 ? 2 : 1; }
+
+Job blank_job() {
+    Job j{};
+    return j;
+}
+
+struct Builder {
+    Plan& P;
+    explicit Builder(Plan& p) : P(p) {}
+    void step() { P.steps.push_back({P.jobs.size(), 0}); }
+    void add(const Job& j) {
+        P.jobs.push_back(j);
+        P.steps.back().count++;
+    }
+};
+
+bool both_encrypted(const QuerySpec& q) { return q.B != nullptr && q.eq9_in == nullptr; }
+
+}  // namespace
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+size_t query_buffer_bytes(const QuerySpec& q) {
+    size_t b = align256(sizeof(uint64_t) * (q.m + 1) * W);
+    if (both_encrypted(q)) {
+        b += align256(sizeof(uint64_t) * q.m * q.n * W);                     // eq9
+        if (q.encoding == LVS_ENC_ASCII7) b += align256(sizeof(uint64_t) * q.m * q.n * W);   // eq1
+    }
+    return b;
+}
+
+size_t query_jobs(const QuerySpec& q) {
+    const size_t cells = q.m * q.n;
+    if (!both_encrypted(q)) return cells;
+    return cells * (q.encoding == LVS_ENC_ASCII7 ? 3 : 2);
+}
+
+size_t plan_bytes(size_t njobs, size_t max_step) {
+    max_step = std::min(max_step, kMaxStep);
+    return align256(sizeof(Job) * std::max<size_t>(njobs, 1)) +
+           align256(sizeof(uint64_t) * keyswitch_part_words(int(std::max<size_t>(max_step, 1))));
+}
+
+void assign_buffers(std::vector<QuerySpec>& qs, uint8_t*& ws) {
+    for (auto& q : qs) {
+        q.V = reinterpret_cast<uint64_t*>(ws);
+        ws += align256(sizeof(uint64_t) * (q.m + 1) * W);
+        if (both_encrypted(q)) {
+            q.eq9 = reinterpret_cast<uint64_t*>(ws);
+            ws += align256(sizeof(uint64_t) * q.m * q.n * W);
+            if (q.encoding == LVS_ENC_ASCII7) {
+                q.eq1 = reinterpret_cast<uint64_t*>(ws);
+                ws += align256(sizeof(uint64_t) * q.m * q.n * W);
+            }
+        }
+    }
+}
+
+void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool with_dp) {
+    Builder b(P);
+    // ---- equality of every pair (both strings encrypted)
+    bool any_eq = false, any_ascii = false;
+    for (const auto& q : qs)
+        if (both_encrypted(q) && q.m && q.n) {
+            any_eq = true;
+            any_ascii |= q.encoding == LVS_ENC_ASCII7;
+        }
+    if (any_eq) {
+        // eq1 = PBS(x1 - y1; LUT_eq) (ASCII) or eq9 = PBS(x - y; LUT_eq9) (DNA)
+        b.step();
+        for (const auto& q : qs) {
+            if (!both_encrypted(q)) continue;
+            const size_t ns = nsym(q.encoding);
+            for (size_t i = 0; i < q.m; ++i)
+                for (size_t j = 0; j < q.n; ++j) {
+                    Job J = blank_job();
+                    J.src[0] = q.A + (i * ns) * W;
+                    J.src[1] = q.B + (j * ns) * W;
+                    J.coef[0] = 1;
+                    J.coef[1] = -1;
+                    const size_t c = i * q.n + j;
+                    if (q.encoding == LVS_ENC_ASCII7) {
+                        J.lut = LVS_LUT_EQ;
+                        J.dst[0] = q.eq1 + c * W;
+                    } else {
+                        J.lut = LVS_LUT_EQ9;
+                        J.dst[0] = q.eq9 + c * W;
+                    }
+                    b.add(J);
+                }
+        }
+        if (any_ascii) {
+            // eq9 = PBS(2 (x2 - y2) + (1 - eq1); LUT_eq9)
+            b.step();
+            for (const auto& q : qs) {
+                if (!both_encrypted(q) || q.encoding != LVS_ENC_ASCII7) continue;
+                for (size_t i = 0; i < q.m; ++i)
+                    for (size_t j = 0; j < q.n; ++j) {
+                        const size_t c = i * q.n + j;
+                        Job J = blank_job();
+                        J.src[0] = q.A + (i * 2 + 1) * W;
+                        J.src[1] = q.B + (j * 2 + 1) * W;
+                        J.src[2] = q.eq1 + c * W;
+                        J.coef[0] = 2;
+                        J.coef[1] = -2;
+                        J.coef[2] = -1;
+                        J.delta = kOne;
+                        J.lut = LVS_LUT_EQ9;
+                        J.dst[0] = q.eq9 + c * W;
+                        b.add(J);
+                    }
+            }
+        }
+    }
+    if (!with_dp) return;
+    // an empty first string leaves h[0, 1..n] = Enc(1) as the result
+    for (const auto& q : qs)
+        if (q.m == 0 && q.n) P.fills.push_back({q.h_last, q.n});
+    // ---- the wavefront: anti-diagonal s holds every query's cells (i, s - i)
+    size_t smax = 0;
+    for (const auto& q : qs)
+        if (q.m && q.n) smax = std::max(smax, q.m + q.n);
+    for (size_t s = 2; s <= smax; ++s) {
+        b.step();
+        for (const auto& q : qs) {
+            if (!q.m || !q.n || s > q.m + q.n) continue;
+            uint64_t* H = q.h_last - W;            // H[j] = h[latest i, j], j >= 1
+            const size_t i_lo = (s > q.n + 1) ? s - q.n : 1;
+            const size_t i_hi = std::min(q.m, s - 1);
+            for (size_t i = i_lo; i <= i_hi; ++i) {
+                const size_t j = s - i;
+                const uint64_t* eq;
+                if (q.eq9_in) eq = q.eq9_in + ((i - 1) * q.n + (j - 1)) * W;
+                else if (q.B) eq = q.eq9 + ((i - 1) * q.n + (j - 1)) * W;
+                else eq = q.table + (size_t(q.cols[j - 1]) * q.m + (i - 1)) * W;
+                // v_in = v[i, j-1] (Enc(1) on the left border), h_in = h[i-1, j]
+                // (Enc(1) on the top border); key = 4 - v_in + 3 h_in + eq9
+                const uint64_t* v_in = (j == 1) ? nullptr : q.V + i * W;
+                const uint64_t* h_in = (i == 1) ? nullptr : H + j * W;
+                Job J = blank_job();
+                J.src[0] = v_in;
+                J.src[1] = h_in;
+                J.src[2] = eq;
+                J.coef[0] = -1;
+                J.coef[1] = 3;
+                J.coef[2] = 1;
+                J.delta = 4 * kOne - (v_in ? 0 : kOne) + (h_in ? 0 : 3 * kOne);
+                J.lut = LVS_LUT_MIN;
+                // v[i,j] = M - h_in, h[i,j] = M - v_in
+                J.dst[0] = q.V + i * W;
+                J.sub[0] = h_in;
+                J.sub_delta[0] = h_in ? 0 : kOne;
+                J.dst[1] = H + j * W;
+                J.sub[1] = v_in;
+                J.sub_delta[1] = v_in ? 0 : kOne;
+                J.dst[2] = q.trace ? q.trace + ((i - 1) * q.n + (j - 1)) * W : nullptr;
+                b.add(J);
+            }
+        }
+    }
+}
+
+void build_preprocess_plan(const uint64_t* A, size_t m, int encoding, const std::vector<uint8_t>& syms_lo,
+                           const std::vector<uint8_t>& syms_hi, uint64_t* table, uint64_t* eq1, Plan& P) {
+    Builder b(P);
+    const size_t alen = syms_lo.size();
+    const size_t ns = nsym(encoding);
+    // z1 = x1 - c1 (the cleartext symbol is a noise-free ciphertext)
+    b.step();
+    for (size_t c = 0; c < alen; ++c)
+        for (size_t i = 0; i < m; ++i) {
+            Job J = blank_job();
+            J.src[0] = A + (i * ns) * W;
+            J.coef[0] = 1;
+            J.delta = uint64_t(0) - uint64_t(syms_lo[c]) * kOne;
+            if (encoding == LVS_ENC_ASCII7) {
+                J.lut = LVS_LUT_EQ;
+                J.dst[0] = eq1 + (c * m + i) * W;
+            } else {
+                J.lut = LVS_LUT_EQ9;
+                J.dst[0] = table + (c * m + i) * W;
+            }
+            b.add(J);
+        }
+    if (encoding != LVS_ENC_ASCII7) return;
+    // z2 = 2 (x2 - c2) + (1 - eq1)
+    b.step();
+    for (size_t c = 0; c < alen; ++c)
+        for (size_t i = 0; i < m; ++i) {
+            Job J = blank_job();
+            J.src[0] = A + (i * 2 + 1) * W;
+            J.src[1] = eq1 + (c * m + i) * W;
+            J.coef[0] = 2;
+            J.coef[1] = -1;
+            J.delta = kOne - 2 * uint64_t(syms_hi[c]) * kOne;
+            J.lut = LVS_LUT_EQ9;
+            J.dst[0] = table + (c * m + i) * W;
+            b.add(J);
+        }
+}
+
+void build_pbs_plan(const uint64_t* in, const uint8_t* lut_ids, int lut, size_t B, uint64_t* out, Plan& P) {
+    Builder b(P);
+    b.step();
+    for (size_t k = 0; k < B; ++k) {
+        Job J = blank_job();
+        J.src[0] = in + k * W;
+        J.coef[0] = 1;
+        J.lut = uint32_t(lut_ids ? lut_ids[k] : lut);
+        J.dst[2] = out + k * W;
+        b.add(J);
+    }
+}
+
+hipError_t upload_plan(Plan& P, uint8_t*& ws, hipStream_t st) {
+    // split oversized steps (their jobs are independent)
+    std::vector<PlanStep> steps;
+    for (const auto& s : P.steps)
+        for (size_t o = 0; o < s.count; o += kMaxStep) steps.push_back({s.off + o, std::min(kMaxStep, s.count - o)});
+    P.steps.swap(steps);
+    P.max_step = 0;
+    for (const auto& s : P.steps) P.max_step = std::max(P.max_step, s.count);
+    P.d_jobs = reinterpret_cast<Job*>(ws);
+    ws += align256(sizeof(Job) * std::max<size_t>(P.jobs.size(), 1));
+    P.d_part = reinterpret_cast<uint64_t*>(ws);
+    ws += align256(sizeof(uint64_t) * keyswitch_part_words(int(std::max<size_t>(P.max_step, 1))));
+    if (P.jobs.empty()) return hipSuccess;
+    hipError_t e = hipMemcpyAsync(P.d_jobs, P.jobs.data(), sizeof(Job) * P.jobs.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);     // the host copy may change after return
+}
+
+namespace {
+hipError_t launch_steps(Context* C, const Plan& P, hipStream_t st, bool timed) {
+    for (const auto& f : P.fills) {
+        hipError_t e = launch_trivial(f.first, int(f.second), 1, st);
+        if (e != hipSuccess) return e;
+    }
+    for (const auto& s : P.steps) {
+        if (!s.count) continue;
+        const int B = int(s.count);
+        {
+            TimedLaunch t(C, timed ? 1 : -1, uint64_t(B));
+            hipError_t e = launch_keyswitch_jobs(P.d_jobs + s.off, B, C->ksk, P.d_part, st);
+            if (e != hipSuccess) return e;
+        }
+        {
+            TimedLaunch t(C, timed ? 0 : -1, uint64_t(B));
+            hipError_t e = launch_blind_rotate_jobs(P.d_jobs + s.off, B, P.d_part, C->luts, C->bsk, C->tables,
+                                                    C->br_grid, st);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+}  // namespace
+
+hipError_t run_plan(Context* C, const Plan& P) {
+    if (P.graph) {
+        TimedLaunch t(C, 2, uint64_t(P.pbs()));
+        return hipGraphLaunch(P.graph, C->stream);
+    }
+    return launch_steps(C, P, C->stream, true);
+}
+
+hipError_t capture_plan(Context* C, Plan& P) {
+    hipError_t e;
+    if (!C->capture_stream) {
+        e = hipStreamCreateWithFlags(&C->capture_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+    }
+    e = hipStreamBeginCapture(C->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const bool prof = C->profiling;
+    C->profiling = false;   // no events inside the graph
+    hipError_t le = launch_steps(C, P, C->capture_stream, false);
+    C->profiling = prof;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(C->capture_stream, &g);
+    if (le != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return le;
+    }
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&P.graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    return e;
+}
+
+}  // namespace lvs

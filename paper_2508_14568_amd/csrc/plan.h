@@ -1,0 +1,83 @@
+// Static bootstrap schedules ("plans") shared by the plain, batched and
+// serving paths.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <vector>
+
+#include "launch.h"
+#include "lvs_internal.h"
+
+namespace lvs {
+
+constexpr size_t kMaxStep = 65536;   // bootstraps per launch
+
+struct Context;
+
+// One edit distance of a plan.
+struct QuerySpec {
+    int encoding = LVS_ENC_ASCII7;
+    const uint64_t* A = nullptr;   // [m][nsym][W] encrypted string a
+    size_t m = 0;
+    const uint64_t* B = nullptr;   // [n][nsym][W] encrypted string b (both encrypted)
+    size_t n = 0;
+    const uint64_t* table = nullptr;        // [alen][m][W] preprocessing table (cleartext b)
+    std::vector<int32_t> cols;              // table row of b_j (cleartext b)
+    const uint64_t* eq9_in = nullptr;       // [m][n][W] given equality matrix (Algorithm 1)
+    uint64_t* h_last = nullptr;             // [n][W] result; doubles as H[1..n]
+    uint64_t* trace = nullptr;              // optional [m][n][W] record of every M
+    // workspace buffers assigned by assign_buffers()
+    uint64_t* V = nullptr;                  // [m+1][W]
+    uint64_t* eq1 = nullptr;                // [m][n][W] (ASCII, both encrypted)
+    uint64_t* eq9 = nullptr;                // [m][n][W] (both encrypted)
+};
+
+struct PlanStep {
+    size_t off, count;
+};
+
+struct Plan {
+    std::vector<std::pair<uint64_t*, size_t>> fills;   // rows set to Enc(1) at the start of every run
+    std::vector<Job> jobs;
+    std::vector<PlanStep> steps;
+    size_t max_step = 0;
+    Job* d_jobs = nullptr;
+    uint64_t* d_part = nullptr;
+    hipGraphExec_t graph = nullptr;
+    size_t pbs() const { return jobs.size(); }
+};
+
+// Bytes of per-query workspace (V, eq1, eq9) and of a plan's jobs/partials.
+size_t query_buffer_bytes(const QuerySpec& q);
+size_t plan_bytes(size_t njobs, size_t max_step);
+size_t align256(size_t x);
+
+// Bootstraps a query contributes and its largest step.
+size_t query_jobs(const QuerySpec& q);
+
+// Carves V / eq1 / eq9 of every query from ws (advancing it).
+void assign_buffers(std::vector<QuerySpec>& qs, uint8_t*& ws);
+
+// Builds the jobs: equality steps (both encrypted), then one step per
+// anti-diagonal s = 2 .. max(m + n) holding every query's cells on it.
+void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool with_dp = true);
+
+// Jobs of the Section 5 table: T[c][i] = Enc(9 [a_i = S_c]).
+void build_preprocess_plan(const uint64_t* A, size_t m, int encoding, const std::vector<uint8_t>& syms_lo,
+                           const std::vector<uint8_t>& syms_hi, uint64_t* table, uint64_t* eq1, Plan& P);
+
+// Independent bootstraps d_out[b] = PBS(d_in[b]).
+void build_pbs_plan(const uint64_t* in, const uint8_t* lut_ids, int lut, size_t B, uint64_t* out, Plan& P);
+
+// Splits oversized steps, uploads the jobs into ws (advancing it) and
+// reserves the key-switch partial sums.
+hipError_t upload_plan(Plan& P, uint8_t*& ws, hipStream_t st);
+
+// Enqueues every step (or the captured graph).
+hipError_t run_plan(Context* C, const Plan& P);
+
+// Captures the plan's launches into a graph executable.
+hipError_t capture_plan(Context* C, Plan& P);
+
+}  // namespace lvs

@@ -67,6 +67,10 @@ _SIGS = {
     "lvs_preprocess": (I32, [VP, VP, SZ, I32, VP, SZ, VP, VP, SZ]),
     "lvs_edit_distance_clear_workspace_bytes": (SZ, [SZ, SZ]),
     "lvs_edit_distance_clear": (I32, [VP, VP, SZ, VP, SZ, VP, SZ, VP, VP, SZ]),
+    "lvs_plan_workspace_bytes": (I32, [VP, SZ, I32, ctypes.POINTER(SZ)]),
+    "lvs_plan_create": (I32, [VP, VP, SZ, I32, I32, VP, SZ, ctypes.POINTER(VP)]),
+    "lvs_plan_run": (I32, [VP]),
+    "lvs_plan_info": (I32, [VP, ctypes.POINTER(SZ), ctypes.POINTER(SZ), ctypes.POINTER(SZ)]),
     "lvs_profile_enable": (I32, [VP, I32]),
     "lvs_profile_read": (I32, [VP, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(U64), ctypes.POINTER(U64)]),
     "lvs_free": (None, [VP]),
@@ -243,12 +247,17 @@ def lvs_pbs_workspace_bytes(B: int) -> int:
     return lib().lvs_pbs_workspace_bytes(B)
 
 
-def lvs_pbs_batch(ctx: Context, d_in, B: int, d_out, lut_id: int = 0, d_lut_ids=None, d_work=None):
+def lvs_pbs_batch(ctx: Context, d_in, B: int, d_out, lut_id: int = 0, lut_ids=None, d_work=None):
+    """lut_ids: optional host sequence of per-ciphertext table slots."""
     need = lvs_pbs_workspace_bytes(B)
     if d_work is None:
         d_work = device_buffer(need, ctx.device)
-    _check(lib().lvs_pbs_batch(ctx, _dptr(d_in), _dptr(d_lut_ids), lut_id, B, _dptr(d_out), _dptr(d_work),
-                               d_work.numel() * d_work.element_size()))
+    ids = None
+    if lut_ids is not None:
+        ids = np.ascontiguousarray(np.asarray(lut_ids, dtype=np.uint8))
+        assert ids.size == B
+    _check(lib().lvs_pbs_batch(ctx, _dptr(d_in), None if ids is None else _np_ptr(ids), lut_id, B, _dptr(d_out),
+                               _dptr(d_work), d_work.numel() * d_work.element_size()))
     return d_work
 
 
@@ -320,10 +329,82 @@ def lvs_edit_distance_clear(ctx: Context, d_table, m: int, alphabet: bytes, b: b
     return d_work
 
 
+# ------------------------------------------------------------ batch plans
+
+LVS_PLAN_GRAPH = 1
+
+
+class lvs_query(ctypes.Structure):
+    _fields_ = [("d_a", VP), ("m", SZ), ("d_b", VP), ("n", SZ), ("d_table", VP), ("alphabet", VP), ("alen", SZ),
+                ("b_clear", VP), ("d_h_last", VP)]
+
+
+class Plan(_Handle):
+    """A batch plan; keeps the query structs, host strings and workspace alive."""
+
+    def __init__(self, ptr, keep):
+        super().__init__(ptr)
+        self._keep = keep
+
+
+def make_queries(items):
+    """items: dicts with d_a, m, d_h_last and either d_b, n or d_table,
+    alphabet (bytes), b_clear (bytes)."""
+    arr = (lvs_query * max(1, len(items)))()
+    keep = []
+    for k, it in enumerate(items):
+        q = arr[k]
+        q.d_a = _dptr(it.get("d_a"))
+        q.m = it["m"]
+        q.d_h_last = _dptr(it.get("d_h_last"))
+        if it.get("d_b") is not None:
+            q.d_b = _dptr(it["d_b"])
+            q.n = it["n"]
+        else:
+            ab = (ctypes.c_uint8 * max(1, len(it["alphabet"]))).from_buffer_copy(bytes(it["alphabet"]) or b"\0")
+            bc = (ctypes.c_uint8 * max(1, len(it["b_clear"]))).from_buffer_copy(bytes(it["b_clear"]) or b"\0")
+            keep += [ab, bc]
+            q.d_table = _dptr(it.get("d_table"))
+            q.alphabet = ctypes.cast(ab, VP)
+            q.alen = len(it["alphabet"])
+            q.b_clear = ctypes.cast(bc, VP)
+            q.n = len(it["b_clear"])
+    return arr, keep
+
+
+def lvs_plan_workspace_bytes(items, encoding: int) -> int:
+    arr, keep = make_queries(items)
+    n = SZ()
+    _check(lib().lvs_plan_workspace_bytes(arr, len(items), encoding, ctypes.byref(n)))
+    return n.value
+
+
+def lvs_plan_create(ctx: Context, items, encoding: int, graph: bool = False, d_work=None) -> Plan:
+    arr, keep = make_queries(items)
+    need = lvs_plan_workspace_bytes(items, encoding)
+    if d_work is None:
+        d_work = device_buffer(need, ctx.device)
+    out = VP()
+    _check(lib().lvs_plan_create(ctx, arr, len(items), encoding, LVS_PLAN_GRAPH if graph else 0, _dptr(d_work),
+                                 d_work.numel() * d_work.element_size(), ctypes.byref(out)))
+    return Plan(out, (arr, keep, d_work, items))
+
+
+def lvs_plan_run(plan: Plan):
+    _check(lib().lvs_plan_run(plan))
+
+
+def lvs_plan_info(plan: Plan):
+    st, pb, mx = SZ(), SZ(), SZ()
+    _check(lib().lvs_plan_info(plan, ctypes.byref(st), ctypes.byref(pb), ctypes.byref(mx)))
+    return st.value, pb.value, mx.value
+
+
 # ------------------------------------------------------------ measurement
 
 KERNEL_BLIND_ROTATE = 0
 KERNEL_KEYSWITCH = 1
+KERNEL_GRAPH = 2
 
 
 def lvs_profile_enable(ctx: Context, enable: bool):

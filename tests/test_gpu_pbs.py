@@ -22,8 +22,8 @@ def run_pbs(g, cts, lut_id=0, lut_ids=None):
     d_out = torch.zeros_like(d_in)
     d_ids = None
     if lut_ids is not None:
-        d_ids = torch.tensor(np.asarray(lut_ids, dtype=np.uint8), device=g.dev)
-    L.lvs_pbs_batch(g.ctx, d_in, B, d_out, lut_id=lut_id, d_lut_ids=d_ids)
+        d_ids = np.asarray(lut_ids, dtype=np.uint8)
+    L.lvs_pbs_batch(g.ctx, d_in, B, d_out, lut_id=lut_id, lut_ids=d_ids)
     torch.cuda.synchronize()
     return L.to_host(d_out).reshape(B, L.CT_WORDS)
 
@@ -66,7 +66,7 @@ def test_tables_exhaustive(gpu, okeys, name):
 
 def test_mixed_luts_ragged_batch(gpu, okeys):
     """37 bootstraps (not a multiple of the key-switch tile of 8) with a
-    per-ciphertext table id in device memory; every output bit-exact."""
+    per-ciphertext table id; every output bit-exact."""
     say("mixed luts ragged")
     g = gpu
     rng = np.random.default_rng(7)
