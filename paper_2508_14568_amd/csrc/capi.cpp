@@ -279,15 +279,17 @@ int lvs_context_create(const lvs_server_key* sk, int device, void* hip_stream, v
     const PrimeTables& T = prime_tables();
     const size_t tn = size_t(kPrimes) * kN;
     std::vector<uint32_t> tw(4 * tn + 2 * kPrimes);
-    std::copy(T.fwd.begin(), T.fwd.end(), tw.begin());
-    std::copy(T.fwd_shoup.begin(), T.fwd_shoup.end(), tw.begin() + tn);
-    std::copy(T.inv.begin(), T.inv.end(), tw.begin() + 2 * tn);
-    std::copy(T.inv_shoup.begin(), T.inv_shoup.end(), tw.begin() + 3 * tn);
+    for (size_t k = 0; k < tn; ++k) {
+        tw[2 * k] = T.fwd[k];
+        tw[2 * k + 1] = T.fwd_shoup[k];
+        tw[2 * tn + 2 * k] = T.inv[k];
+        tw[2 * tn + 2 * k + 1] = T.inv_shoup[k];
+    }
     for (int r = 0; r < kPrimes; ++r) {
         tw[4 * tn + r] = T.bsk_scale[r];
         tw[4 * tn + kPrimes + r] = uint32_t((uint64_t(T.bsk_scale[r]) << 32) / T.p[r]);
     }
-    C->tables = DevTables{C->tw, C->tw + tn, C->tw + 2 * tn, C->tw + 3 * tn, C->tw + 4 * tn, C->tw + 4 * tn + kPrimes};
+    C->tables = DevTables{C->tw, C->tw + 2 * tn, C->tw + 4 * tn, C->tw + 4 * tn + kPrimes};
     auto fail = [&](int code) { delete C; return code; };
     hipError_t e = prepare_kernels();
     if (e == hipSuccess) e = hipMemcpy(C->tw, tw.data(), tw.size() * 4, hipMemcpyHostToDevice);

@@ -19,7 +19,7 @@ struct Context : Handle {
     size_t arena_bytes = 0;
     uint32_t* bsk = nullptr;      // NTT domain
     uint64_t* ksk = nullptr;
-    uint32_t* tw = nullptr;       // fwd, fwd_s, inv, inv_s, scale, scale_s
+    uint32_t* tw = nullptr;       // forward pairs, inverse pairs, scale, scale companion
     uint64_t* luts = nullptr;     // [LVS_LUT_SLOTS][N]
     DevTables tables{};
     int br_grid = 0;              // persistent blind-rotation grid (0: one workgroup per job)

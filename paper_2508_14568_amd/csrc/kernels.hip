@@ -9,13 +9,16 @@
 // torus result mod 2^64 is exact.
 //
 // Work mapping of the blind rotation: one workgroup of 4 wavefronts per
-// bootstrap; wavefront r owns prime p_r and runs the forward transforms of
-// both decomposed polynomials, the products with the bootstrapping key and
-// the two inverse transforms in registers (32 coefficients per lane), with
-// LDS transposes between the stage groups and a DPP lane-pair exchange for the
-// stride-32 stage.  The accumulator lives in LDS as 64-bit words; after each
-// external product the four residue sets meet in LDS and every thread
-// reconstructs 16 coefficients.
+// bootstrap; wavefront r owns prime p_r.  Its lanes 0-31 transform the
+// decomposed mask polynomial and lanes 32-63 the decomposed body polynomial,
+// 64 coefficients per lane in registers: 6 butterfly stages inside the lane,
+// one LDS transpose, 5 more stages inside the lane.  A lane-half swap
+// (ds_bpermute) gives every lane both transformed digits of its positions
+// for the products with the bootstrapping key; the inverse transform runs
+// the same way back.  The 64-bit accumulator lives in LDS; the decomposition
+// digits are computed once per workgroup, and after each external product
+// the four residue sets meet in LDS where every thread reconstructs 16
+// coefficients.
 #include <hip/hip_runtime.h>
 
 #include "launch.h"
@@ -24,13 +27,14 @@
 namespace lvs {
 namespace dev {
 
-constexpr int kWave = 64;
-constexpr int kEpl = kN / kWave;          // 32 coefficients per lane per polynomial
-constexpr int kPadStride = kN + kN / 32;  // LDS words of one padded polynomial
+constexpr int kHalfLanes = 32;            // lanes per polynomial
+constexpr int kEh = kN / kHalfLanes;       // 64 coefficients per lane
+constexpr int kPoly = kN + kN / 64;        // LDS words of one padded polynomial
 
 struct CrtConsts {
     uint32_t p[kPrimes];
     uint32_t mont[kPrimes];
+    uint32_t red[kPrimes];                 // floor(2^32 / p)
     uint32_t garner[kPrimes][kPrimes];
     uint32_t garner_s[kPrimes][kPrimes];
     uint64_t prod[kPrimes];
@@ -38,13 +42,13 @@ struct CrtConsts {
 };
 
 struct Tw {
-    const uint32_t* fwd;    // [kPrimes][kN]
-    const uint32_t* fwd_s;
-    const uint32_t* inv;
-    const uint32_t* inv_s;
+    const uint2* fwd;       // [kPrimes][kN] (twiddle, Shoup companion)
+    const uint2* inv;
 };
 
-__device__ __forceinline__ uint32_t pad(uint32_t j) { return j + (j >> 5); }
+// LDS word of coefficient j: one pad word per 64 keeps both transpose
+// directions free of bank conflicts.
+__device__ __forceinline__ uint32_t pad(uint32_t j) { return j + (j >> 6); }
 
 // arr[w] for a wave-uniform w without dynamic indexing of kernel arguments.
 __device__ __forceinline__ uint32_t pick(const uint32_t (&arr)[kPrimes], int w) {
@@ -66,150 +70,107 @@ __device__ __forceinline__ uint32_t redc(uint64_t T, uint32_t p, uint32_t mont) 
     return uint32_t((T + uint64_t(m) * p) >> 32);
 }
 
-__device__ __forceinline__ uint32_t swap_pair(uint32_t v) {
-    // quad_perm [1, 0, 3, 2]: lane l reads lane l ^ 1
-    return uint32_t(__builtin_amdgcn_mov_dpp(int(v), 0xB1, 0xF, 0xF, false));
+// x mod p in [0, 2p) for any 32-bit x (Shoup reduction by 1, q = floor(2^32/p)).
+__device__ __forceinline__ uint32_t reduce2p(uint32_t x, uint32_t q, uint32_t p) { return x - __umulhi(x, q) * p; }
+
+// Value of the same register in lane ^ 32 (the other polynomial's lane).
+__device__ __forceinline__ uint32_t swap_halves(uint32_t v, int lane) {
+    return uint32_t(__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, int(v)));
 }
 
-// Forward negacyclic NTT (Cooley-Tukey, psi-merged twiddles, natural order in,
-// bit-reversed order out), Harvey lazy butterflies: values stay in [0, 4p).
-// In: lane l element e holds coefficient l + 64 e.  Out: lane l element e
-// holds transform position 32 l + e.  scratch: NP padded polynomials of this
-// wavefront's private LDS.
-template <int NP>
-__device__ __forceinline__ void ntt_forward(uint32_t (&x)[NP][kEpl], uint32_t* scratch, const uint32_t* w,
-                                            const uint32_t* ws, uint32_t p, int lane) {
+// Forward negacyclic NTT of one polynomial held by a half wavefront
+// (Cooley-Tukey, psi-merged twiddles, natural order in, bit-reversed order
+// out).  In: lane lh holds coefficient lh + 32 e in x[e], each < 2p.  Out: x[e]
+// holds transform position 64 lh + e, each < 24p.  No reduction is needed:
+// a butterfly adds at most 2p to a value (x' = a + t, y' = a - t + 2p with
+// t = w b mod p in [0, 2p)), and 2p + 11 * 2p < 2^31 for p < 2^26.
+// Every stage is a template instance so that all register indices are
+// compile-time constants.
+template <int S>
+__device__ __forceinline__ void fwd_stage(uint32_t (&x)[kEh], const uint2* w, uint32_t p, int lh) {
+    // S < 6: stride 1024 >> S, partners 32 >> S elements apart, uniform twiddles;
+    // S >= 6: partners 1 << (10 - S) elements apart, one twiddle block per lane
+    constexpr int half = (S < 6) ? (32 >> S) : (1 << (10 - S));
+    const int base = (S < 6) ? (1 << S) : (1 << S) + (lh << (S - 5));
     const uint32_t two_p = 2 * p;
-    // stages with stride 1024 .. 64: partners in the same lane, twiddle uniform
 #pragma unroll
-    for (int s = 0; s < 5; ++s) {
-        const int half = 16 >> s;
-#pragma unroll
-        for (int e = 0; e < kEpl; ++e) {
-            if (e & half) continue;
-            const int idx = (1 << s) + (e >> (5 - s));
-            const uint32_t tw = w[idx], tws = ws[idx];
-#pragma unroll
-            for (int q = 0; q < NP; ++q) {
-                const uint32_t a = csub(x[q][e], two_p);
-                const uint32_t t = mul_shoup(x[q][e + half], tw, tws, p);
-                x[q][e] = a + t;
-                x[q][e + half] = a - t + two_p;
-            }
-        }
+    for (int e = 0; e < kEh; ++e) {
+        if (e & half) continue;
+        const uint2 tw = w[base + ((S < 6) ? (e >> (6 - S)) : (e >> (11 - S)))];
+        const uint32_t t = mul_shoup(x[e + half], tw.x, tw.y, p);
+        const uint32_t a = x[e];
+        x[e] = a + t;
+        x[e + half] = a + two_p - t;
     }
-    // transpose: coefficient l + 64 e -> lane (j >> 5), element (j & 31)
+}
+
+__device__ __forceinline__ void ntt_forward(uint32_t (&x)[kEh], uint32_t* scr, const uint2* w, uint32_t p, int lh) {
+    fwd_stage<0>(x, w, p, lh);
+    fwd_stage<1>(x, w, p, lh);
+    fwd_stage<2>(x, w, p, lh);
+    fwd_stage<3>(x, w, p, lh);
+    fwd_stage<4>(x, w, p, lh);
+    fwd_stage<5>(x, w, p, lh);
+    // transpose: coefficient lh + 32 e -> lane j >> 6, element j & 63
 #pragma unroll
-    for (int q = 0; q < NP; ++q)
-#pragma unroll
-        for (int e = 0; e < kEpl; ++e) scratch[q * kPadStride + pad(lane + 64 * e)] = x[q][e];
+    for (int e = 0; e < kEh; ++e) scr[pad(lh + 32 * e)] = x[e];
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int q = 0; q < NP; ++q)
-#pragma unroll
-        for (int e = 0; e < kEpl; ++e) x[q][e] = scratch[q * kPadStride + pad(32 * lane + e)];
+    for (int e = 0; e < kEh; ++e) x[e] = scr[pad(64 * lh + e)];
     __builtin_amdgcn_wave_barrier();
-    // stride 32: partner is lane l ^ 1, twiddle per lane pair
-    {
-        const int idx = 32 + (lane >> 1);
-        const uint32_t tw = w[idx], tws = ws[idx];
-        const bool odd = lane & 1;
-#pragma unroll
-        for (int q = 0; q < NP; ++q)
-#pragma unroll
-            for (int e = 0; e < kEpl; ++e) {
-                const uint32_t v = x[q][e];
-                const uint32_t a = csub(v, two_p);
-                const uint32_t t = mul_shoup(v, tw, tws, p);
-                const uint32_t got = swap_pair(odd ? t : a);
-                x[q][e] = odd ? got - t + two_p : a + got;
-            }
-    }
-    // strides 16 .. 1 inside the lane
-#pragma unroll
-    for (int s = 6; s < 11; ++s) {
-        const int half = 1 << (10 - s);
-#pragma unroll
-        for (int e = 0; e < kEpl; ++e) {
-            if (e & half) continue;
-            const int idx = (1 << s) + (lane << (s - 6)) + (e >> (11 - s));
-            const uint32_t tw = w[idx], tws = ws[idx];
-#pragma unroll
-            for (int q = 0; q < NP; ++q) {
-                const uint32_t a = csub(x[q][e], two_p);
-                const uint32_t t = mul_shoup(x[q][e + half], tw, tws, p);
-                x[q][e] = a + t;
-                x[q][e + half] = a - t + two_p;
-            }
-        }
-    }
+    fwd_stage<6>(x, w, p, lh);
+    fwd_stage<7>(x, w, p, lh);
+    fwd_stage<8>(x, w, p, lh);
+    fwd_stage<9>(x, w, p, lh);
+    fwd_stage<10>(x, w, p, lh);
 }
 
 // Inverse negacyclic NTT without the 1/N factor (Gentleman-Sande, inverse
-// psi twiddles, bit-reversed order in, natural order out); inputs in [0, 2p),
-// outputs in [0, 2p).  Layouts mirror ntt_forward.
-template <int NP>
-__device__ __forceinline__ void ntt_inverse(uint32_t (&x)[NP][kEpl], uint32_t* scratch, const uint32_t* w,
-                                            const uint32_t* ws, uint32_t p, int lane) {
-    const uint32_t two_p = 2 * p;
+// psi twiddles, bit-reversed order in, natural order out).  In: x[e] holds
+// position 64 lh + e, each < 2p.  Out: x[e] holds coefficient lh + 32 e,
+// reduced to [0, p).  A butterfly maps inputs below B to a sum below 2B and a
+// product below 2p; the sums are brought back below 2p after stages 3 and 7,
+// so B never exceeds 16p and a + B - b stays below 32p < 2^31.
+template <int U>
+__device__ __forceinline__ void inv_stage(uint32_t (&x)[kEh], const uint2* w, uint32_t p, uint32_t q, int lh) {
+    constexpr int half = (U < 5) ? (1 << U) : (1 << (U - 5));
+    constexpr int since = (U <= 3) ? U : (U <= 7 ? U - 4 : U - 8);   // stages since the last reduction
+    constexpr bool reduce = (U == 3 || U == 7);
+    const uint32_t bound = (2 * p) << since;
+    const int base = (U < 5) ? (1 << (10 - U)) + (lh << (5 - U)) : (1 << (10 - U));
 #pragma unroll
-    for (int u = 0; u < 5; ++u) {
-        const int half = 1 << u;
-#pragma unroll
-        for (int e = 0; e < kEpl; ++e) {
-            if (e & half) continue;
-            const int idx = (1 << (10 - u)) + (lane << (4 - u)) + (e >> (u + 1));
-            const uint32_t tw = w[idx], tws = ws[idx];
-#pragma unroll
-            for (int q = 0; q < NP; ++q) {
-                const uint32_t a = x[q][e], b = x[q][e + half];
-                x[q][e] = csub(a + b, two_p);
-                x[q][e + half] = mul_shoup(a - b + two_p, tw, tws, p);
-            }
-        }
+    for (int e = 0; e < kEh; ++e) {
+        if (e & half) continue;
+        const uint2 tw = w[base + ((U < 5) ? (e >> (U + 1)) : (e >> (U - 4)))];
+        const uint32_t a = x[e], b = x[e + half];
+        const uint32_t sum = a + b;
+        x[e] = reduce ? reduce2p(sum, q, p) : sum;
+        x[e + half] = mul_shoup(a + bound - b, tw.x, tw.y, p);
     }
-    {
-        const int idx = 32 + (lane >> 1);
-        const uint32_t tw = w[idx], tws = ws[idx];
-        const bool odd = lane & 1;
+}
+
+__device__ __forceinline__ void ntt_inverse(uint32_t (&x)[kEh], uint32_t* scr, const uint2* w, uint32_t p, uint32_t q,
+                                            int lh) {
+    inv_stage<0>(x, w, p, q, lh);
+    inv_stage<1>(x, w, p, q, lh);
+    inv_stage<2>(x, w, p, q, lh);
+    inv_stage<3>(x, w, p, q, lh);
+    inv_stage<4>(x, w, p, q, lh);
+    // transpose: position 64 lh + e -> lane j & 31, element j >> 5
 #pragma unroll
-        for (int q = 0; q < NP; ++q)
-#pragma unroll
-            for (int e = 0; e < kEpl; ++e) {
-                const uint32_t v = x[q][e];
-                const uint32_t got = swap_pair(v);
-                const uint32_t sum = csub(v + got, two_p);
-                const uint32_t diff = (odd ? got - v : v - got) + two_p;
-                const uint32_t prod = mul_shoup(diff, tw, tws, p);
-                x[q][e] = odd ? prod : sum;
-            }
-    }
-#pragma unroll
-    for (int q = 0; q < NP; ++q)
-#pragma unroll
-        for (int e = 0; e < kEpl; ++e) scratch[q * kPadStride + pad(32 * lane + e)] = x[q][e];
+    for (int e = 0; e < kEh; ++e) scr[pad(64 * lh + e)] = x[e];
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int q = 0; q < NP; ++q)
-#pragma unroll
-        for (int e = 0; e < kEpl; ++e) x[q][e] = scratch[q * kPadStride + pad(lane + 64 * e)];
+    for (int e = 0; e < kEh; ++e) x[e] = scr[pad(lh + 32 * e)];
     __builtin_amdgcn_wave_barrier();
+    inv_stage<5>(x, w, p, q, lh);
+    inv_stage<6>(x, w, p, q, lh);
+    inv_stage<7>(x, w, p, q, lh);
+    inv_stage<8>(x, w, p, q, lh);
+    inv_stage<9>(x, w, p, q, lh);
+    inv_stage<10>(x, w, p, q, lh);
 #pragma unroll
-    for (int u = 6; u < 11; ++u) {
-        const int half = 1 << (u - 6);
-#pragma unroll
-        for (int e = 0; e < kEpl; ++e) {
-            if (e & half) continue;
-            const int idx = (1 << (10 - u)) + (e >> (u - 5));
-            const uint32_t tw = w[idx], tws = ws[idx];
-#pragma unroll
-            for (int q = 0; q < NP; ++q) {
-                const uint32_t a = x[q][e], b = x[q][e + half];
-                x[q][e] = csub(a + b, two_p);
-                x[q][e + half] = mul_shoup(a - b + two_p, tw, tws, p);
-            }
-        }
-    }
+    for (int e = 0; e < kEh; ++e) x[e] = csub(reduce2p(x[e], q, p), p);
 }
 
 // Residues r[0..3] (each in [0, p_i)) of a signed integer |X| < prod/2 ->
@@ -332,26 +293,32 @@ struct BrArgs {
 };
 
 constexpr int kBrThreads = 256;
-constexpr size_t kBrLds = sizeof(uint64_t) * 2 * kN                       // accumulator
-                          + sizeof(uint32_t) * kPrimes * 2 * kPadStride   // per-wave scratch / residues
-                          + sizeof(uint32_t) * (kSmallWords + 1);         // switched mask and body
+constexpr size_t kBrLds = sizeof(uint64_t) * 2 * kN                          // accumulator
+                          + sizeof(uint32_t) * 2 * kN                        // biased digits
+                          + sizeof(uint32_t) * kPrimes * 2 * kPoly           // per-half scratch / residues
+                          + sizeof(uint32_t) * (kSmallWords + 1);            // switched mask and body
 
 __global__ void __launch_bounds__(kBrThreads, 1) blind_rotate_kernel(BrArgs A) {
     extern __shared__ __align__(16) uint8_t lds[];
     uint64_t* acc = reinterpret_cast<uint64_t*>(lds);                                   // [2][N]
-    uint32_t* exch = reinterpret_cast<uint32_t*>(lds + sizeof(uint64_t) * 2 * kN);      // [4][2][pad]
-    uint32_t* abar = exch + kPrimes * 2 * kPadStride;                                   // [n+1]
+    uint32_t* dig = reinterpret_cast<uint32_t*>(lds + sizeof(uint64_t) * 2 * kN);       // [2][N]
+    uint32_t* scratch = dig + 2 * kN;                                                   // [4][2][kPoly]
+    uint32_t* abar = scratch + kPrimes * 2 * kPoly;                                     // [n+1]
 
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
+    const int h = lane >> 5;          // 0: mask polynomial, 1: body polynomial
+    const int lh = lane & 31;
     const uint32_t p = pick(A.crt.p, wave);
     const uint32_t mont = pick(A.crt.mont, wave);
-    const uint32_t* fw = A.tw.fwd + size_t(wave) * kN;
-    const uint32_t* fws = A.tw.fwd_s + size_t(wave) * kN;
-    const uint32_t* iw = A.tw.inv + size_t(wave) * kN;
-    const uint32_t* iws = A.tw.inv_s + size_t(wave) * kN;
-    uint32_t* scratch = exch + wave * 2 * kPadStride;
+    const uint32_t q = pick(A.crt.red, wave);
+    const uint2* fw = A.tw.fwd + size_t(wave) * kN;
+    const uint2* iw = A.tw.inv + size_t(wave) * kN;
+    uint32_t* scr = scratch + (wave * 2 + h) * kPoly;
+    // a digit d in [-2^22, 2^22) is stored as d + 2^22; adding p - 2^22 gives
+    // a residue of d below 2p
+    const uint32_t unbias = p - (1u << 22);
 
     for (int b = blockIdx.x; b < A.B; b += gridDim.x) {
         const Job& J = A.jobs[b];
@@ -378,50 +345,57 @@ __global__ void __launch_bounds__(kBrThreads, 1) blind_rotate_kernel(BrArgs A) {
 
         for (int i = 0; i < kSmallN; ++i) {
             const uint32_t a = abar[i];
-            // bootstrapping-key rows of this step and prime, in transform order
-            const uint32_t* K = A.bsk + (size_t(i) * kPrimes + wave) * 4 * kN;
-            // digits of X^a ACC - ACC (one signed 23-bit digit per coefficient)
-            uint32_t x[2][kEpl];
+            // this step's bootstrapping-key values of the lane, fetched now so
+            // that the loads complete behind the digit phase and the forward
+            // transform: kq[k] = (K0[2k], K1[2k], K0[2k+1], K1[2k+1]) of
+            // positions 64 lh + 2k and 64 lh + 2k + 1
+            const uint4* K = reinterpret_cast<const uint4*>(A.bsk) + ((size_t(i) * kPrimes + wave) * 2 + h) * (kN / 2) + lh;
+            uint4 kq[kEh / 2];
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
+            for (int k = 0; k < kEh / 2; ++k) kq[k] = K[k * 32];
+            asm volatile("" ::: "memory");
+            // digits of X^a ACC - ACC: round(t / 2^41) as a balanced 23-bit digit
 #pragma unroll
-                for (int e = 0; e < kEpl; ++e) {
-                    const uint32_t j = uint32_t(lane + 64 * e);
-                    const uint32_t src = (j - a) & (2 * kN - 1);
-                    uint64_t r = acc[q * kN + (src & (kN - 1))];
-                    if (src >= uint32_t(kN)) r = uint64_t(0) - r;
-                    const uint64_t t = r - acc[q * kN + j];
-                    const uint32_t dg = ((uint32_t(t >> 40) + 1) >> 1) & 0x7FFFFFu;   // round(t / 2^41) mod 2^23
-                    x[q][e] = (dg >= 0x400000u) ? dg - 0x800000u + p : dg;            // balanced digit mod p
-                }
-            ntt_forward<2>(x, scratch, fw, fws, p, lane);
-            // products with the GGSW rows: mask += D0 K00 + D1 K10, body += D0 K01 + D1 K11
-            uint32_t y[2][kEpl];
-#pragma unroll
-            for (int e = 0; e < kEpl; ++e) {
-                const int o = e * 64 + lane;
-                const uint32_t d0 = csub(x[0][e], 2 * p), d1 = csub(x[1][e], 2 * p);
-                const uint32_t k00 = K[0 * kN + o], k01 = K[1 * kN + o], k10 = K[2 * kN + o], k11 = K[3 * kN + o];
-                y[0][e] = redc(uint64_t(d0) * k00 + uint64_t(d1) * k10, p, mont);
-                y[1][e] = redc(uint64_t(d0) * k01 + uint64_t(d1) * k11, p, mont);
+            for (int k = 0; k < 2 * kN / kBrThreads; ++k) {
+                const int qq = k & 1;
+                const uint32_t c = uint32_t(tid + kBrThreads * (k >> 1));
+                const uint32_t src = (c - a) & (2 * kN - 1);
+                uint64_t r = acc[qq * kN + (src & (kN - 1))];
+                if (src >= uint32_t(kN)) r = uint64_t(0) - r;
+                const uint64_t t = r - acc[qq * kN + c];
+                const uint32_t u = ((uint32_t(t >> 40) + 1) >> 1) & 0x7FFFFFu;   // round(t / 2^41) mod 2^23
+                dig[qq * kN + c] = (u + 0x400000u) & 0x7FFFFFu;                   // balanced digit + 2^22
             }
-            ntt_inverse<2>(y, scratch, iw, iws, p, lane);
+            __syncthreads();
+            uint32_t x[kEh];
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
+            for (int e = 0; e < kEh; ++e) x[e] = dig[h * kN + lh + 32 * e] + unbias;
+            ntt_forward(x, scr, fw, p, lh);
+            // products with the GGSW rows: out_h = D0 K[0][h] + D1 K[1][h]
 #pragma unroll
-                for (int e = 0; e < kEpl; ++e) scratch[q * kPadStride + pad(lane + 64 * e)] = csub(y[q][e], p);
+            for (int e = 0; e < kEh; ++e) {
+                const uint32_t own = x[e];
+                const uint32_t other = swap_halves(own, lane);
+                const uint32_t d0 = h ? other : own;
+                const uint32_t d1 = h ? own : other;
+                const uint32_t k0 = (e & 1) ? kq[e >> 1].z : kq[e >> 1].x;
+                const uint32_t k1 = (e & 1) ? kq[e >> 1].w : kq[e >> 1].y;
+                x[e] = redc(uint64_t(d0) * k0 + uint64_t(d1) * k1, p, mont);
+            }
+            ntt_inverse(x, scr, iw, p, q, lh);
+#pragma unroll
+            for (int e = 0; e < kEh; ++e) scr[pad(lh + 32 * e)] = x[e];
             __syncthreads();
             // CRT: 16 coefficients per thread
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
+            for (int k = 0; k < 2 * kN / kBrThreads; ++k) {
+                const int qq = k & 1;
+                const int c = tid + kBrThreads * (k >> 1);
+                uint32_t r[kPrimes];
 #pragma unroll
-                for (int k = 0; k < kN / kBrThreads; ++k) {
-                    const int c = tid + kBrThreads * k;
-                    uint32_t r[kPrimes];
-#pragma unroll
-                    for (int w = 0; w < kPrimes; ++w) r[w] = exch[(w * 2 + q) * kPadStride + pad(c)];
-                    acc[q * kN + c] += crt_lift(r, A.crt);
-                }
+                for (int w = 0; w < kPrimes; ++w) r[w] = scratch[(w * 2 + qq) * kPoly + pad(c)];
+                acc[qq * kN + c] += crt_lift(r, A.crt);
+            }
             __syncthreads();
         }
         // sample extraction of coefficient 0, then the job's output rule
@@ -444,32 +418,36 @@ __global__ void __launch_bounds__(kBrThreads, 1) blind_rotate_kernel(BrArgs A) {
 
 // ------------------------------------------------ bootstrapping-key conversion
 
-// One wavefront per (polynomial, prime): signed lift of the 64-bit
-// coefficients, reduction mod p, forward NTT, scaling by (1/N) 2^32 mod p, and
-// store in the transform order the blind rotation reads.
+// One wavefront per (GGSW row, prime): lanes 0-31 take the row's mask
+// polynomial, lanes 32-63 its body polynomial; signed lift of the 64-bit
+// coefficients, reduction mod p, forward NTT, scaling by (1/N) 2^32 mod p,
+// and store in the order the blind rotation reads ([i][prime][row][h][e][lh]).
 __global__ void __launch_bounds__(64) bsk_convert_kernel(const uint64_t* __restrict__ bsk, uint32_t* __restrict__ out,
                                                         Tw tw, CrtConsts C, const uint32_t* scale,
                                                         const uint32_t* scale_s) {
-    __shared__ uint32_t scratch[kPadStride];
+    // output order [i][prime][h][e / 2][lh][e % 2][rho]: one 16-byte load gives
+    // both rows' values of two neighbouring positions
+    __shared__ uint32_t scratch[2 * kPoly];
     const int lane = threadIdx.x;
-    const int poly = blockIdx.x;            // i * 4 + row * 2 + comp
+    const int h = lane >> 5, lh = lane & 31;
+    const int row = blockIdx.x;             // i * 2 + rho
     const int r = blockIdx.y;               // prime
-    const int i = poly >> 2, rc = poly & 3;
     const uint32_t p = pick(C.p, r);
     const uint64_t two64_mod_p = ((~uint64_t(0)) % p + 1) % p;
-    uint32_t x[1][kEpl];
+    uint32_t x[kEh];
 #pragma unroll
-    for (int e = 0; e < kEpl; ++e) {
-        const uint64_t c = bsk[size_t(poly) * kN + lane + 64 * e];
+    for (int e = 0; e < kEh; ++e) {
+        const uint64_t c = bsk[(size_t(row) * 2 + h) * kN + lh + 32 * e];
         uint64_t m = c % p;
         if (c >> 63) m = (m + p - two64_mod_p) % p;     // c read as c - 2^64
-        x[0][e] = uint32_t(m);
+        x[e] = uint32_t(m);
     }
-    ntt_forward<1>(x, scratch, tw.fwd + size_t(r) * kN, tw.fwd_s + size_t(r) * kN, p, lane);
+    ntt_forward(x, scratch + h * kPoly, tw.fwd + size_t(r) * kN, p, lh);
     const uint32_t sc = scale[r], scs = scale_s[r];
-    uint32_t* dst = out + ((size_t(i) * kPrimes + r) * 4 + rc) * kN;
+    const int i = row >> 1, rho = row & 1;
+    uint32_t* dst = out + ((size_t(i) * kPrimes + r) * 2 + h) * (2 * kN) + lh * 4 + rho;
 #pragma unroll
-    for (int e = 0; e < kEpl; ++e) dst[e * 64 + lane] = csub(mul_shoup(x[0][e], sc, scs, p), p);
+    for (int e = 0; e < kEh; ++e) dst[(e >> 1) * 128 + (e & 1) * 2] = csub(mul_shoup(x[e], sc, scs, p), p);
 }
 
 // ----------------------------------------------------- linear operations
@@ -580,6 +558,7 @@ dev::CrtConsts make_crt() {
     for (int i = 0; i < kPrimes; ++i) {
         C.p[i] = T.p[i];
         C.mont[i] = T.mont_neg_inv[i];
+        C.red[i] = T.reduce_q[i];
         C.prod[i] = T.prod_mod64[i];
         for (int j = 0; j < kPrimes; ++j) {
             C.garner[i][j] = T.garner[i][j];
@@ -630,7 +609,7 @@ hipError_t launch_blind_rotate_jobs(const Job* jobs, int B, const uint64_t* part
     A.nsplit = keyswitch_splits(B);
     A.luts = luts;
     A.bsk = bsk;
-    A.tw = dev::Tw{t.fwd, t.fwd_s, t.inv, t.inv_s};
+    A.tw = dev::Tw{reinterpret_cast<const uint2*>(t.fwd), reinterpret_cast<const uint2*>(t.inv)};
     A.crt = make_crt();
     A.B = B;
     if (grid <= 0 || grid > B) grid = B;
@@ -639,9 +618,10 @@ hipError_t launch_blind_rotate_jobs(const Job* jobs, int B, const uint64_t* part
 }
 
 hipError_t launch_bsk_convert(const uint64_t* bsk_u64, uint32_t* out, const DevTables& t, hipStream_t st) {
-    dim3 grid(kSmallN * 4, kPrimes);
+    dim3 grid(kSmallN * 2, kPrimes);
     hipLaunchKernelGGL(dev::bsk_convert_kernel, grid, dim3(64), 0, st, bsk_u64, out,
-                       dev::Tw{t.fwd, t.fwd_s, t.inv, t.inv_s}, make_crt(), t.scale, t.scale_s);
+                       dev::Tw{reinterpret_cast<const uint2*>(t.fwd), reinterpret_cast<const uint2*>(t.inv)}, make_crt(),
+                       t.scale, t.scale_s);
     return hipGetLastError();
 }
 

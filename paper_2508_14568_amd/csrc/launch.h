@@ -26,10 +26,8 @@ struct Job {
 };
 
 struct DevTables {
-    const uint32_t* fwd;      // [kPrimes][N] forward twiddles psi^brv(k)
-    const uint32_t* fwd_s;    // Shoup companions
-    const uint32_t* inv;      // [kPrimes][N] inverse twiddles psi^-brv(k)
-    const uint32_t* inv_s;
+    const uint32_t* fwd;      // [kPrimes][N][2] forward twiddles psi^brv(k) with Shoup companions
+    const uint32_t* inv;      // [kPrimes][N][2] inverse twiddles psi^-brv(k) with Shoup companions
     const uint32_t* scale;    // [kPrimes] (1/N) 2^32 mod p
     const uint32_t* scale_s;
 };

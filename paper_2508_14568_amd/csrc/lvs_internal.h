@@ -22,6 +22,7 @@ constexpr int kKsLevel = 5;
 constexpr int kKsRows = kN * kKsLevel;
 constexpr int kDeltaLog = 59;      // x in Z_32 encodes as x << 59
 constexpr int kPrimes = 4;         // NTT primes of the exact negacyclic products
+constexpr int kPrimeBits = 26;     // every prime is below 2^26
 
 // Every handle starts with a tag so lvs_free can dispatch.
 enum HandleKind : uint32_t { kClientKey = 0x4C565301, kServerKey = 0x4C565302, kContext = 0x4C565303, kPlan = 0x4C565304 };
@@ -61,6 +62,7 @@ struct PrimeTables {
     // forward / inverse twiddles psi^{+-brv(k)} in [0, p) with Shoup companions floor(w 2^32 / p)
     std::vector<uint32_t> fwd, fwd_shoup, inv, inv_shoup;   // [kPrimes][kN]
     uint32_t bsk_scale[kPrimes];             // N^{-1} * 2^32 mod p (Montgomery form of the 1/N)
+    uint32_t reduce_q[kPrimes];              // floor(2^32 / p): reduction of a word to [0, 2p)
     // Garner CRT: c[i][j] = p_j^{-1} mod p_i (j < i), with Shoup companions
     uint32_t garner[kPrimes][kPrimes], garner_shoup[kPrimes][kPrimes];
     uint64_t prod_mod64[kPrimes];            // p_0 ... p_{i-1} mod 2^64 (prod_mod64[0] = 1)

@@ -4,9 +4,10 @@
 // A product of a decomposed polynomial (23-bit signed digits) with a GGSW row
 // (64-bit coefficients read as signed) has integer coefficients bounded by
 // 2 * N * 2^22 * 2^63 = 2^97 for the two rows of one external product.  With
-// four primes p_r < 2^30, p_r = 1 mod 2N, Q = prod p_r ~ 2^120 > 2^98, so the
+// four primes p_r < 2^26, p_r = 1 mod 2N, Q = prod p_r ~ 2^104 > 2^98, so the
 // residues determine the signed integer exactly (CRT with a signed lift) and
-// its value mod 2^64 is the torus result.
+// its value mod 2^64 is the torus result.  Primes below 2^26 leave 6 bits of
+// headroom in 32-bit words, so the transforms can skip most reductions.
 #include <mutex>
 
 #include "lvs_internal.h"
@@ -58,11 +59,11 @@ uint32_t shoup(uint32_t w, uint32_t p) { return uint32_t((uint64_t(w) << 32) / p
 
 PrimeTables build() {
     PrimeTables t{};
-    // The four largest primes below 2^30 that are 1 mod 2N = 4096.
+    // The four largest primes below 2^26 that are 1 mod 2N = 4096.
     int found = 0;
-    for (uint64_t k = ((uint64_t(1) << 30) - 1) / (2 * kN); found < kPrimes; --k) {
+    for (uint64_t k = ((uint64_t(1) << kPrimeBits) - 1) / (2 * kN); found < kPrimes; --k) {
         const uint64_t p = k * 2 * kN + 1;
-        if (p < (uint64_t(1) << 30) && is_prime(p)) t.p[found++] = uint32_t(p);
+        if (p < (uint64_t(1) << kPrimeBits) && is_prime(p)) t.p[found++] = uint32_t(p);
     }
     t.fwd.resize(size_t(kPrimes) * kN);
     t.fwd_shoup.resize(size_t(kPrimes) * kN);
@@ -93,6 +94,7 @@ PrimeTables build() {
         // bootstrapping key, stored in Montgomery form (times 2^32).
         const uint64_t ninv = powmod(kN, p - 2, p);
         t.bsk_scale[r] = uint32_t(mulmod(ninv, (uint64_t(1) << 32) % p, p));
+        t.reduce_q[r] = uint32_t((uint64_t(1) << 32) / p);
     }
     for (int i = 0; i < kPrimes; ++i)
         for (int j = 0; j < kPrimes; ++j) {
