@@ -246,6 +246,53 @@ int lvs_plan_run(lvs_plan* plan);
 /* Steps, bootstraps and the largest step of a plan (any may be NULL). */
 int lvs_plan_info(const lvs_plan* plan, size_t* steps, size_t* bootstraps, size_t* max_step);
 
+/* --------------------------------------------------------------- serving */
+
+/* Continuous batching of encrypted name queries against a cleartext name
+ * list (Section 5: an encrypted query against an unencrypted database; the
+ * query is preprocessed once, then every name costs one bootstrap per cell).
+ * The caller passes one device arena: lvs_server_fixed_bytes(max_step) bytes
+ * for the job list and key-switch partials, the rest is the pool requests are
+ * admitted into (admission by device memory). */
+typedef struct lvs_server lvs_server;
+
+/* Fixed part of the arena for at most max_step bootstraps per launch. */
+size_t lvs_server_fixed_bytes(size_t max_step);
+
+/* Pool bytes one request of length m occupies: its ciphertexts, the eq1 and
+ * preprocessing tables over the alphabet, and one DP frontier plus result
+ * row per name. */
+size_t lvs_server_request_bytes(const uint8_t* names, const size_t* name_lens, size_t n_names, size_t alen,
+                                size_t m);
+
+/* Server over n_names cleartext names (concatenated in `names`, lengths in
+ * name_lens, every symbol in `alphabet`, 7-bit ASCII).  d_arena is borrowed
+ * for the server's lifetime (256-byte aligned). */
+int lvs_server_create(lvs_context* ctx, const uint8_t* names, const size_t* name_lens, size_t n_names,
+                      const uint8_t* alphabet, size_t alen, size_t max_step, void* d_arena, size_t arena_bytes,
+                      lvs_server** out);
+
+/* Queues a request: h_query is the encrypted ASCII query ([m][2][N+1], host,
+ * copied).  Requests are admitted in arrival order at the next step that
+ * has room.  LVS_E_NOMEM_DEVICE if it could never fit. */
+int lvs_server_submit(lvs_server* srv, const uint64_t* h_query, size_t m, uint64_t* ticket);
+
+/* One engine step: admits queued requests while their buffers fit, then runs
+ * one batched launch over the ready bootstraps of every admitted request
+ * (preprocessing rounds of new requests and the current anti-diagonal of
+ * every running one), and advances them.  Waits for the step to finish.
+ * Reports the requests still running, still queued, and the step's
+ * bootstraps (any may be NULL). */
+int lvs_server_step(lvs_server* srv, size_t* active, size_t* queued, size_t* step_jobs);
+
+/* *done = 1 once the request has finished; then, if h_out is not NULL, copies
+ * its results (for every name k in order, the n_k ciphertexts h[m, 1..n_k],
+ * [sum n_k][N+1]) and releases the request. */
+int lvs_server_poll(lvs_server* srv, uint64_t ticket, uint64_t* h_out, int* done);
+
+/* Steps run and bootstraps executed so far (any may be NULL). */
+int lvs_server_stats(const lvs_server* srv, uint64_t* steps, uint64_t* bootstraps);
+
 /* ------------------------------------------------------------ measurement */
 
 /* Kernel timing for measurement: while enabled, every launch of the blind
@@ -259,7 +306,7 @@ int lvs_profile_enable(lvs_context* ctx, int enable);
  * recorded events. */
 int lvs_profile_read(lvs_context* ctx, int kernel, double* total_ms, uint64_t* launches, uint64_t* units);
 
-/* Releases a handle created by the library (keys, contexts, plans). */
+/* Releases a handle created by the library (keys, contexts, plans, servers). */
 void lvs_free(void* handle);
 
 #ifdef __cplusplus

@@ -667,11 +667,14 @@ int lvs_profile_read(lvs_context* ctx, int kernel, double* total_ms, uint64_t* l
     return LVS_OK;
 }
 
+void lvs_server_free_impl(void* h);
+
 void lvs_free(void* handle) {
     if (!handle) return;
     switch (reinterpret_cast<Handle*>(handle)->kind) {
         case kClientKey: delete reinterpret_cast<ClientKey*>(handle); break;
         case kServerKey: delete reinterpret_cast<ServerKey*>(handle); break;
+        case kServer: lvs_server_free_impl(handle); break;
         case kPlan: {
             auto* H = reinterpret_cast<PlanHandle*>(handle);
             if (H->P.graph) hipGraphExecDestroy(H->P.graph);

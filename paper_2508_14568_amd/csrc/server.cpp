@@ -1,0 +1,412 @@
+// Serving: continuous batching of encrypted name queries against a cleartext
+// list of names (Section 5's "encrypted query against a large unencrypted
+// database": preprocess the query once, then one bootstrap per cell for every
+// name).
+//
+// Each request goes through three phases: the preprocessing table's two
+// bootstrap rounds (eq1, then eq9 = T[c][i]), then the anti-diagonals
+// s = 2 .. m + max(n_k) of one DP instance per name, all instances of the
+// request advancing together.  An engine step gathers the ready bootstraps of
+// every admitted request (any mix of phases and tables) into one key-switch
+// launch and one persistent blind-rotation launch.  Requests are admitted in
+// arrival order when their device buffers fit in the caller's arena, and join
+// at the next step boundary.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "context.h"
+#include "launch.h"
+#include "lvs_internal.h"
+#include "plan.h"
+
+namespace lvs {
+
+namespace {
+
+constexpr size_t W = kCtWords;
+constexpr uint64_t kOne = uint64_t(1) << kDeltaLog;
+
+// First-fit allocator over a byte range of the arena (offsets, 256-aligned).
+class Pool {
+public:
+    void init(size_t bytes) {
+        free_.clear();
+        if (bytes) free_[0] = bytes;
+        total_ = bytes;
+    }
+    bool alloc(size_t bytes, size_t* off) {
+        bytes = align256(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes;
+            const size_t at = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = align256(bytes);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t total() const { return total_; }
+
+private:
+    std::map<size_t, size_t> free_;
+    size_t total_ = 0;
+};
+
+enum Phase { kQueued, kPre1, kPre2, kDp, kDone };
+
+struct Request {
+    uint64_t ticket = 0;
+    size_t m = 0;
+    std::vector<uint64_t> host_query;   // [m][2][W] until admitted
+    Phase phase = kQueued;
+    size_t s = 2;                        // current anti-diagonal in the DP phase
+    size_t off = 0, bytes = 0;           // block in the pool
+    uint64_t* A = nullptr;               // [m][2][W]
+    uint64_t* eq1 = nullptr;             // [alen][m][W]
+    uint64_t* T = nullptr;               // [alen][m][W]
+    uint64_t* V = nullptr;               // [names][m+1][W]
+    uint64_t* H = nullptr;               // [sum n_k][W] results
+};
+
+}  // namespace
+
+struct Server : Handle {
+    Context* C = nullptr;
+    uint8_t* arena = nullptr;
+    size_t arena_bytes = 0;
+    size_t max_step = 0;
+    // names
+    std::vector<size_t> name_len, name_start;  // first result row of every name
+    std::vector<int32_t> cols;                 // concatenated alphabet index of every name symbol
+    size_t total_len = 0, max_len = 0;
+    std::vector<uint8_t> sym_lo, sym_hi;       // alphabet symbols (4-bit, 3-bit)
+    // device regions
+    Job* d_jobs = nullptr;
+    uint64_t* d_part = nullptr;
+    Pool pool;
+    uint8_t* pool_base = nullptr;
+    // requests
+    uint64_t next_ticket = 1;
+    std::deque<Request*> queue;                // arrival order, not admitted yet
+    std::vector<Request*> active;              // admitted, arrival order
+    std::map<uint64_t, std::unique_ptr<Request>> all;
+    std::vector<Job> jobs;
+    uint64_t steps = 0, bootstraps = 0;
+
+    size_t request_bytes(size_t m) const {
+        const size_t alen = sym_lo.size();
+        return align256(sizeof(uint64_t) * m * 2 * W) + 2 * align256(sizeof(uint64_t) * alen * m * W) +
+               align256(sizeof(uint64_t) * name_len.size() * (m + 1) * W) +
+               align256(sizeof(uint64_t) * total_len * W);
+    }
+
+    void carve(Request* r) {
+        uint8_t* p = pool_base + r->off;
+        const size_t alen = sym_lo.size(), m = r->m;
+        r->A = reinterpret_cast<uint64_t*>(p);
+        p += align256(sizeof(uint64_t) * m * 2 * W);
+        r->eq1 = reinterpret_cast<uint64_t*>(p);
+        p += align256(sizeof(uint64_t) * alen * m * W);
+        r->T = reinterpret_cast<uint64_t*>(p);
+        p += align256(sizeof(uint64_t) * alen * m * W);
+        r->V = reinterpret_cast<uint64_t*>(p);
+        p += align256(sizeof(uint64_t) * name_len.size() * (m + 1) * W);
+        r->H = reinterpret_cast<uint64_t*>(p);
+    }
+
+    // Jobs of one request's current phase.
+    void gather(Request* r, std::vector<Job>& out) const {
+        const size_t alen = sym_lo.size(), m = r->m;
+        if (r->phase == kPre1 || r->phase == kPre2) {
+            for (size_t c = 0; c < alen; ++c)
+                for (size_t i = 0; i < m; ++i) {
+                    Job J{};
+                    if (r->phase == kPre1) {     // z1 = x1 - c1, eq1 = PBS(z1; LUT_eq)
+                        J.src[0] = r->A + (i * 2) * W;
+                        J.coef[0] = 1;
+                        J.delta = uint64_t(0) - uint64_t(sym_lo[c]) * kOne;
+                        J.lut = LVS_LUT_EQ;
+                        J.dst[0] = r->eq1 + (c * m + i) * W;
+                    } else {                     // z2 = 2 (x2 - c2) + 1 - eq1, T = PBS(z2; LUT_eq9)
+                        J.src[0] = r->A + (i * 2 + 1) * W;
+                        J.src[1] = r->eq1 + (c * m + i) * W;
+                        J.coef[0] = 2;
+                        J.coef[1] = -1;
+                        J.delta = kOne - 2 * uint64_t(sym_hi[c]) * kOne;
+                        J.lut = LVS_LUT_EQ9;
+                        J.dst[0] = r->T + (c * m + i) * W;
+                    }
+                    out.push_back(J);
+                }
+            return;
+        }
+        // DP: every name's cells (i, s - i) on anti-diagonal s
+        const size_t s = r->s;
+        for (size_t k = 0; k < name_len.size(); ++k) {
+            const size_t n = name_len[k];
+            if (n == 0 || s > m + n) continue;
+            uint64_t* V = r->V + k * (m + 1) * W;
+            uint64_t* H = r->H + name_start[k] * W - W;     // H[j] = h[latest i, j], j >= 1
+            const int32_t* col = cols.data() + name_start[k];
+            const size_t i_lo = (s > n + 1) ? s - n : 1;
+            const size_t i_hi = std::min(m, s - 1);
+            for (size_t i = i_lo; i <= i_hi; ++i) {
+                const size_t j = s - i;
+                const uint64_t* v_in = (j == 1) ? nullptr : V + i * W;
+                const uint64_t* h_in = (i == 1) ? nullptr : H + j * W;
+                Job J{};
+                J.src[0] = v_in;
+                J.src[1] = h_in;
+                J.src[2] = r->T + (size_t(col[j - 1]) * m + (i - 1)) * W;
+                J.coef[0] = -1;
+                J.coef[1] = 3;
+                J.coef[2] = 1;
+                J.delta = 4 * kOne - (v_in ? 0 : kOne) + (h_in ? 0 : 3 * kOne);
+                J.lut = LVS_LUT_MIN;
+                J.dst[0] = V + i * W;
+                J.sub[0] = h_in;
+                J.sub_delta[0] = h_in ? 0 : kOne;
+                J.dst[1] = H + j * W;
+                J.sub[1] = v_in;
+                J.sub_delta[1] = v_in ? 0 : kOne;
+                out.push_back(J);
+            }
+        }
+    }
+
+    void advance(Request* r) const {
+        if (r->phase == kPre1) r->phase = kPre2;
+        else if (r->phase == kPre2) { r->phase = kDp; r->s = 2; }
+        else if (r->phase == kDp) {
+            r->s++;
+            if (r->s > r->m + max_len) r->phase = kDone;
+        }
+    }
+};
+
+}  // namespace lvs
+
+using namespace lvs;
+
+namespace {
+
+thread_local std::string g_srv_error;
+
+Server* as_srv(lvs_server* s) {
+    auto* h = reinterpret_cast<Server*>(s);
+    return (h && h->kind == kServer) ? h : nullptr;
+}
+
+#define SRV_FAIL(code, msg)   \
+    do {                      \
+        set_error(msg);       \
+        return (code);        \
+    } while (0)
+
+#define SRV_HIP(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) SRV_FAIL(LVS_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+size_t lvs_server_fixed_bytes(size_t max_step) {
+    return align256(sizeof(Job) * max_step) + align256(sizeof(uint64_t) * keyswitch_part_words(int(max_step)));
+}
+
+size_t lvs_server_request_bytes(const uint8_t* names, const size_t* name_lens, size_t n_names, size_t alen,
+                                size_t m) {
+    (void)names;
+    size_t total = 0;
+    for (size_t k = 0; k < n_names; ++k) total += name_lens[k];
+    return align256(sizeof(uint64_t) * m * 2 * W) + 2 * align256(sizeof(uint64_t) * alen * m * W) +
+           align256(sizeof(uint64_t) * n_names * (m + 1) * W) + align256(sizeof(uint64_t) * total * W);
+}
+
+int lvs_server_create(lvs_context* ctx, const uint8_t* names, const size_t* name_lens, size_t n_names,
+                      const uint8_t* alphabet, size_t alen, size_t max_step, void* d_arena, size_t arena_bytes,
+                      lvs_server** out) {
+    auto* C = reinterpret_cast<Context*>(ctx);
+    if (!C || C->kind != kContext || !out || (!names && n_names) || (!name_lens && n_names) || !alphabet || !alen)
+        SRV_FAIL(LVS_E_INVAL, "lvs_server_create: bad argument");
+    if (max_step == 0 || max_step > kMaxStep) SRV_FAIL(LVS_E_INVAL, "lvs_server_create: max_step out of range");
+    const size_t fixed = lvs_server_fixed_bytes(max_step);
+    if (!d_arena || arena_bytes < fixed || reinterpret_cast<uintptr_t>(d_arena) % 256)
+        SRV_FAIL(LVS_E_NOMEM_DEVICE, "lvs_server_create: arena too small or misaligned");
+    auto S = std::unique_ptr<Server>(new (std::nothrow) Server());
+    if (!S) SRV_FAIL(LVS_E_NOMEM_HOST, "lvs_server_create: out of host memory");
+    S->kind = kServer;
+    S->C = C;
+    S->arena = reinterpret_cast<uint8_t*>(d_arena);
+    S->arena_bytes = arena_bytes;
+    S->max_step = max_step;
+    for (size_t c = 0; c < alen; ++c) {
+        if (alphabet[c] >= 128) SRV_FAIL(LVS_E_ALPHABET, "lvs_server_create: alphabet symbol >= 128");
+        S->sym_lo.push_back(alphabet[c] & 15);
+        S->sym_hi.push_back(alphabet[c] >> 4);
+    }
+    size_t pos = 0;
+    for (size_t k = 0; k < n_names; ++k) {
+        const size_t n = name_lens[k];
+        if (n > 4096) SRV_FAIL(LVS_E_NOISE_BUDGET, "lvs_server_create: name exceeds the noise budget");
+        S->name_len.push_back(n);
+        S->name_start.push_back(S->total_len);
+        for (size_t j = 0; j < n; ++j) {
+            const uint8_t* hit = std::find(alphabet, alphabet + alen, names[pos + j]);
+            if (hit == alphabet + alen) SRV_FAIL(LVS_E_ALPHABET, "lvs_server_create: name symbol not in the alphabet");
+            S->cols.push_back(int32_t(hit - alphabet));
+        }
+        pos += n;
+        S->total_len += n;
+        S->max_len = std::max(S->max_len, n);
+    }
+    S->d_jobs = reinterpret_cast<Job*>(S->arena);
+    S->d_part = reinterpret_cast<uint64_t*>(S->arena + align256(sizeof(Job) * max_step));
+    S->pool_base = S->arena + fixed;
+    S->pool.init(arena_bytes - fixed);
+    *out = reinterpret_cast<lvs_server*>(S.release());
+    return LVS_OK;
+}
+
+int lvs_server_submit(lvs_server* srv, const uint64_t* h_query, size_t m, uint64_t* ticket) {
+    Server* S = as_srv(srv);
+    if (!S || !ticket || (!h_query && m)) SRV_FAIL(LVS_E_INVAL, "lvs_server_submit: bad argument");
+    if (m == 0 || m > 4096) SRV_FAIL(LVS_E_INVAL, "lvs_server_submit: query length must be 1..4096");
+    if (S->request_bytes(m) > S->pool.total())
+        SRV_FAIL(LVS_E_NOMEM_DEVICE, "lvs_server_submit: the request can never fit in the arena");
+    auto r = std::unique_ptr<Request>(new (std::nothrow) Request());
+    if (!r) SRV_FAIL(LVS_E_NOMEM_HOST, "lvs_server_submit: out of host memory");
+    r->ticket = S->next_ticket++;
+    r->m = m;
+    r->host_query.assign(h_query, h_query + m * 2 * W);
+    S->queue.push_back(r.get());
+    *ticket = r->ticket;
+    S->all[r->ticket] = std::move(r);
+    return LVS_OK;
+}
+
+int lvs_server_step(lvs_server* srv, size_t* active, size_t* queued, size_t* step_jobs) {
+    Server* S = as_srv(srv);
+    if (!S) SRV_FAIL(LVS_E_INVAL, "lvs_server_step: bad server");
+    Context* C = S->C;
+    SRV_HIP(hipSetDevice(C->device));
+    // admission in arrival order while the request's buffers fit
+    while (!S->queue.empty()) {
+        Request* r = S->queue.front();
+        size_t off;
+        if (!S->pool.alloc(S->request_bytes(r->m), &off)) break;
+        r->off = off;
+        r->bytes = S->request_bytes(r->m);
+        S->carve(r);
+        SRV_HIP(hipMemcpyAsync(r->A, r->host_query.data(), r->host_query.size() * 8, hipMemcpyHostToDevice,
+                               C->stream));
+        r->phase = kPre1;
+        S->queue.pop_front();
+        S->active.push_back(r);
+    }
+    // gather every admitted request's ready bootstraps, within the step cap
+    S->jobs.clear();
+    std::vector<Request*> stepped;
+    for (Request* r : S->active) {
+        if (r->phase == kDone) continue;
+        const size_t before = S->jobs.size();
+        S->gather(r, S->jobs);
+        if (S->jobs.size() > S->max_step && before > 0) {   // defer this request (and keep order)
+            S->jobs.resize(before);
+            break;
+        }
+        stepped.push_back(r);
+    }
+    // a single request larger than the cap runs in several launches
+    if (!S->jobs.empty()) {
+        SRV_HIP(hipMemcpyAsync(S->d_jobs, S->jobs.data(), sizeof(Job) * std::min(S->jobs.size(), S->max_step),
+                               hipMemcpyHostToDevice, C->stream));
+        for (size_t o = 0; o < S->jobs.size(); o += S->max_step) {
+            const int B = int(std::min(S->max_step, S->jobs.size() - o));
+            if (o) {
+                SRV_HIP(hipStreamSynchronize(C->stream));
+                SRV_HIP(hipMemcpyAsync(S->d_jobs, S->jobs.data() + o, sizeof(Job) * size_t(B), hipMemcpyHostToDevice,
+                                       C->stream));
+            }
+            {
+                TimedLaunch t(C, 1, uint64_t(B));
+                SRV_HIP(launch_keyswitch_jobs(S->d_jobs, B, C->ksk, S->d_part, C->stream));
+            }
+            {
+                TimedLaunch t(C, 0, uint64_t(B));
+                SRV_HIP(launch_blind_rotate_jobs(S->d_jobs, B, S->d_part, C->luts, C->bsk, C->tables, C->br_grid,
+                                                 C->stream));
+            }
+        }
+        SRV_HIP(hipStreamSynchronize(C->stream));   // job list is reused by the next step
+        S->steps++;
+        S->bootstraps += S->jobs.size();
+    }
+    for (Request* r : stepped) S->advance(r);
+    // requests with no name work left are done as well
+    for (Request* r : S->active)
+        if (r->phase == kDp && r->s > r->m + S->max_len) r->phase = kDone;
+    size_t na = 0;
+    for (Request* r : S->active) na += (r->phase != kDone);
+    if (active) *active = na;
+    if (queued) *queued = S->queue.size();
+    if (step_jobs) *step_jobs = S->jobs.size();
+    return LVS_OK;
+}
+
+int lvs_server_poll(lvs_server* srv, uint64_t ticket, uint64_t* h_out, int* done) {
+    Server* S = as_srv(srv);
+    if (!S || !done) SRV_FAIL(LVS_E_INVAL, "lvs_server_poll: bad argument");
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) SRV_FAIL(LVS_E_INVAL, "lvs_server_poll: unknown ticket");
+    Request* r = it->second.get();
+    *done = r->phase == kDone;
+    if (!*done || !h_out) return LVS_OK;
+    SRV_HIP(hipSetDevice(S->C->device));
+    SRV_HIP(hipMemcpy(h_out, r->H, sizeof(uint64_t) * S->total_len * W, hipMemcpyDeviceToHost));
+    S->pool.release(r->off, r->bytes);
+    S->active.erase(std::remove(S->active.begin(), S->active.end(), r), S->active.end());
+    S->all.erase(it);
+    return LVS_OK;
+}
+
+int lvs_server_stats(const lvs_server* srv, uint64_t* steps, uint64_t* bootstraps) {
+    auto* S = reinterpret_cast<const Server*>(srv);
+    if (!S || S->kind != kServer) SRV_FAIL(LVS_E_INVAL, "lvs_server_stats: bad server");
+    if (steps) *steps = S->steps;
+    if (bootstraps) *bootstraps = S->bootstraps;
+    return LVS_OK;
+}
+
+void lvs_server_free_impl(void* h) { delete reinterpret_cast<Server*>(h); }
+
+}  // extern "C"

@@ -71,6 +71,13 @@ _SIGS = {
     "lvs_plan_create": (I32, [VP, VP, SZ, I32, I32, VP, SZ, ctypes.POINTER(VP)]),
     "lvs_plan_run": (I32, [VP]),
     "lvs_plan_info": (I32, [VP, ctypes.POINTER(SZ), ctypes.POINTER(SZ), ctypes.POINTER(SZ)]),
+    "lvs_server_fixed_bytes": (SZ, [SZ]),
+    "lvs_server_request_bytes": (SZ, [VP, VP, SZ, SZ, SZ]),
+    "lvs_server_create": (I32, [VP, VP, VP, SZ, VP, SZ, SZ, VP, SZ, ctypes.POINTER(VP)]),
+    "lvs_server_submit": (I32, [VP, VP, SZ, ctypes.POINTER(U64)]),
+    "lvs_server_step": (I32, [VP, ctypes.POINTER(SZ), ctypes.POINTER(SZ), ctypes.POINTER(SZ)]),
+    "lvs_server_poll": (I32, [VP, U64, VP, ctypes.POINTER(ctypes.c_int)]),
+    "lvs_server_stats": (I32, [VP, ctypes.POINTER(U64), ctypes.POINTER(U64)]),
     "lvs_profile_enable": (I32, [VP, I32]),
     "lvs_profile_read": (I32, [VP, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(U64), ctypes.POINTER(U64)]),
     "lvs_free": (None, [VP]),
@@ -398,6 +405,75 @@ def lvs_plan_info(plan: Plan):
     st, pb, mx = SZ(), SZ(), SZ()
     _check(lib().lvs_plan_info(plan, ctypes.byref(st), ctypes.byref(pb), ctypes.byref(mx)))
     return st.value, pb.value, mx.value
+
+
+# --------------------------------------------------------------- serving
+
+class Server(_Handle):
+    """A serving engine; keeps its arena and name table alive."""
+
+    def __init__(self, ptr, keep, total_len):
+        super().__init__(ptr)
+        self._keep = keep
+        self.total_len = total_len
+
+
+def _names_buf(names):
+    cat = b"".join(bytes(x) for x in names)
+    buf = (ctypes.c_uint8 * max(1, len(cat))).from_buffer_copy(cat or b"\0")
+    lens = (SZ * max(1, len(names)))(*[len(x) for x in names])
+    return buf, lens
+
+
+def lvs_server_fixed_bytes(max_step: int) -> int:
+    return lib().lvs_server_fixed_bytes(max_step)
+
+
+def lvs_server_request_bytes(names, alen: int, m: int) -> int:
+    buf, lens = _names_buf(names)
+    return lib().lvs_server_request_bytes(buf, lens, len(names), alen, m)
+
+
+def lvs_server_create(ctx: Context, names, alphabet: bytes, arena_bytes: int, max_step: int = 65536) -> Server:
+    buf, lens = _names_buf(names)
+    ab = (ctypes.c_uint8 * len(alphabet)).from_buffer_copy(bytes(alphabet))
+    arena = device_buffer(arena_bytes, ctx.device)
+    out = VP()
+    _check(lib().lvs_server_create(ctx, buf, lens, len(names), ab, len(alphabet), max_step, _dptr(arena),
+                                   arena.numel() * arena.element_size(), ctypes.byref(out)))
+    return Server(out, (buf, lens, ab, arena, ctx), sum(len(x) for x in names))
+
+
+def lvs_server_submit(srv: Server, query_ct: np.ndarray) -> int:
+    q = np.ascontiguousarray(query_ct, dtype=np.uint64)
+    m = q.shape[0]
+    t = U64()
+    _check(lib().lvs_server_submit(srv, _np_ptr(q), m, ctypes.byref(t)))
+    return t.value
+
+
+def lvs_server_step(srv: Server):
+    """(running requests, queued requests, bootstraps of the step)."""
+    a, q, j = SZ(), SZ(), SZ()
+    _check(lib().lvs_server_step(srv, ctypes.byref(a), ctypes.byref(q), ctypes.byref(j)))
+    return a.value, q.value, j.value
+
+
+def lvs_server_poll(srv: Server, ticket: int):
+    """None while running, else the [sum n_k][N+1] result rows."""
+    done = ctypes.c_int()
+    _check(lib().lvs_server_poll(srv, ticket, None, ctypes.byref(done)))
+    if not done.value:
+        return None
+    out = np.zeros((srv.total_len, CT_WORDS), dtype=np.uint64)
+    _check(lib().lvs_server_poll(srv, ticket, _np_ptr(out), ctypes.byref(done)))
+    return out
+
+
+def lvs_server_stats(srv: Server):
+    st, pb = U64(), U64()
+    _check(lib().lvs_server_stats(srv, ctypes.byref(st), ctypes.byref(pb)))
+    return st.value, pb.value
 
 
 # ------------------------------------------------------------ measurement
