@@ -34,6 +34,11 @@ INT_MUL_PER_PBS = 3 * MODMUL_PER_PBS
 VALU_INT_MUL_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
+def note(msg):
+    """Progress on stderr; stdout carries only the result line."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_digest():
     with open(os.path.join(ROOT, "paper_2508_14568_amd", "csrc", "kernels.hip"), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()
@@ -59,6 +64,7 @@ def cpu_baseline(workload_cts, seconds_hint=20.0):
     from oracle import tfhe as OT
     import numpy as np
     threads = OT.default_threads()
+    note(f"cpu baseline: oracle on {threads} threads")
     keys = OT.Keys(OT.default_params(), seed=1, nthreads=threads)
     polys = OL.lut_polys(keys.N)
     sample = workload_cts[: 2 * threads]
@@ -97,6 +103,7 @@ def batched_block(L, ck, ctx, nq, plain_sample):
         keep += [dA, dB]
         outs.append(d_h)
         items.append({"d_a": dA, "m": len(a), "d_b": dB, "n": len(b), "d_h_last": d_h})
+    note(f"batched: {nq} queries as one graph plan")
     plan = L.lvs_plan_create(ctx, items, L.LVS_ENC_ASCII7, graph=True)
     steps, pbs, max_step = L.lvs_plan_info(plan)
     L.lvs_plan_run(plan)                       # warm-up
@@ -109,6 +116,7 @@ def batched_block(L, ck, ctx, nq, plain_sample):
         h = L.to_host(d_h).reshape(len(b), L.CT_WORDS)
         if L.lvs_decrypt_distance(ck, h, len(a)) != levenshtein(a, b):
             raise SystemExit("batched: wrong distance")
+    note(f"batched: {plain_sample} queries through the plain path")
     # plain path: the first queries one at a time
     t_plain, pbs_plain = 0.0, 0
     for k in range(plain_sample):
@@ -137,6 +145,64 @@ def batched_block(L, ck, ctx, nq, plain_sample):
     }
 
 
+def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos):
+    """The serving workload on the first n_names of its 1024 cleartext server
+    names: n_sat queries submitted at once (saturated queries/s), then
+    n_poisson queries per load factor rho arriving as a Poisson process at
+    rho x the saturated rate (p50/p99 latency from arrival to results on the
+    host).  Every query's distances to every name are checked."""
+    import numpy as np
+    import workloads as W
+    from paper_2508_14568_amd import serving as S
+    server, queries = W.serving(n_queries=1 + n_sat + n_poisson * len(rhos))
+    names = server[:n_names]
+    alpha = W.alphabet_of(names)
+    cts = [L.lvs_encrypt_string(ck, q, L.LVS_ENC_ASCII7, 40000 + k) for k, q in enumerate(queries)]
+    max_step = 8192
+    per = L.lvs_server_request_bytes(names, len(alpha), max(len(q) for q in queries))
+    cap = max(4, min(128, (4 << 30) // per))
+    srv = L.lvs_server_create(ctx, names, alpha, L.lvs_server_fixed_bytes(max_step) + per * cap + 4096,
+                              max_step=max_step)
+
+    def check(k, out):
+        q, row = queries[k], 0
+        for nm in names:
+            if L.lvs_decrypt_distance(ck, out[row:row + len(nm)], len(q)) != levenshtein(q, nm):
+                raise SystemExit(f"serving: wrong distance for query {k}")
+            row += len(nm)
+
+    S.run(srv, cts[:1], [0.0], on_result=check)            # warm-up
+    st0, pbs0 = L.lvs_server_stats(srv)
+    note(f"serving: {n_names} names, saturated run of {n_sat} queries")
+    lat, wall, _ = S.run(srv, cts[1:1 + n_sat], [0.0] * n_sat, on_result=lambda k, o: check(1 + k, o))
+    st1, pbs1 = L.lvs_server_stats(srv)
+    sat_qps = n_sat / wall
+    res = {
+        "workload": f"serving: first {n_names} of 1024 cleartext names (lengths lognormal, mean 15), "
+                    f"alphabet {len(alpha)} letters, encrypted queries of the same length law",
+        "names": n_names, "alphabet": len(alpha), "max_requests_resident": cap,
+        "saturated": {"queries": n_sat, "seconds": round(wall, 3), "queries_per_s": round(sat_qps, 4),
+                      "pbs_per_s": round((pbs1 - pbs0) / wall, 1), "steps": st1 - st0,
+                      "pbs_per_query": round((pbs1 - pbs0) / n_sat, 1),
+                      **{k: round(v, 3) for k, v in S.percentiles(lat).items()}},
+        "poisson": [],
+    }
+    base = 1 + n_sat
+    for r, rho in enumerate(rhos):
+        idx = range(base + r * n_poisson, base + (r + 1) * n_poisson)
+        arr = W.poisson_arrivals(6 + r, rho * sat_qps, n_poisson)
+        note(f"serving: Poisson arrivals at rho={rho}, {n_poisson} queries")
+        st0, pbs0 = L.lvs_server_stats(srv)
+        lat, wall, _ = S.run(srv, [cts[k] for k in idx], list(arr),
+                             on_result=lambda k, o, b=idx.start: check(b + k, o))
+        st1, pbs1 = L.lvs_server_stats(srv)
+        res["poisson"].append({"rho": rho, "queries": n_poisson, "rate_per_s": round(rho * sat_qps, 4),
+                               "seconds": round(wall, 3), "pbs_per_s": round((pbs1 - pbs0) / wall, 1),
+                               **{k: round(v, 3) for k, v in S.percentiles(lat).items()},
+                               "mean": round(float(np.mean(lat)), 3)})
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +212,11 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=4)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-names", type=int, default=32)
+    ap.add_argument("--serving-queries", type=int, default=16, help="queries of the saturated run")
+    ap.add_argument("--poisson-queries", type=int, default=40, help="queries per load factor")
+    ap.add_argument("--rho", type=str, default="0.8", help="comma-separated load factors")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -175,6 +246,7 @@ def main():
     torch.cuda.synchronize()
     L.lvs_profile_enable(ctx, True)
     torch.cuda.synchronize()
+    note(f"plain: {args.steps} timed steps")
     t0 = time.perf_counter()
     for _ in range(args.steps):
         L.lvs_edit_distance(ctx, dA, m, dB, n, L.LVS_ENC_ASCII7, d_h, d_work)
@@ -223,6 +295,9 @@ def main():
     if not args.no_batched and args.batched_queries > 0:
         line["batched"] = batched_block(L, ck, ctx, args.batched_queries, min(args.plain_sample,
                                                                             args.batched_queries))
+    if not args.no_serving and args.serving_names > 0:
+        line["serving"] = serving_block(L, ck, ctx, args.serving_names, args.serving_queries,
+                                        args.poisson_queries, [float(x) for x in args.rho.split(",") if x])
     if not args.no_cpu_baseline:
         z1 = (A[:, None, 0, :] - B[None, :, 0, :]).reshape(m * n, L.CT_WORDS).astype(np.uint64)
         line["cpu_baseline"] = cpu_baseline(z1)

@@ -3,9 +3,9 @@
 // ciphertext operations of the Leuvenshtein cell update.
 //
 // Integer arithmetic only.  A negacyclic product of the blind rotation is
-// evaluated modulo four primes p_r < 2^30 (p_r = 1 mod 2N) by length-2048
+// evaluated modulo four primes p_r < 2^26 (p_r = 1 mod 2N) by length-2048
 // negacyclic NTTs and recombined with Garner's CRT and a signed lift; the
-// integers involved are below 2^97 in magnitude while prod p_r ~ 2^120, so the
+// integers involved are below 2^97 in magnitude while prod p_r ~ 2^104, so the
 // torus result mod 2^64 is exact.
 //
 // Work mapping of the blind rotation: one workgroup of 4 wavefronts per
@@ -20,6 +20,8 @@
 // the four residue sets meet in LDS where every thread reconstructs 16
 // coefficients.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "launch.h"
 #include "lvs_internal.h"
@@ -585,7 +587,16 @@ int keyswitch_splits(int B) {
     return s;
 }
 
-size_t keyswitch_part_words(int B) { return size_t(keyswitch_splits(B)) * size_t(B) * kSmallWords; }
+size_t keyswitch_part_words(int B) {
+    // A smaller batch can take more splits than a larger one, so the buffer
+    // must hold the largest splits(b) * b over every b <= B.  splits(b) * b
+    // stays below 2 * 1024 * kKsTile once b has that many ciphertexts.
+    size_t most = 0;
+    const int top = std::min(B, 2 * 1024 * dev::kKsTile);
+    for (int b = 1; b <= top; ++b) most = std::max(most, size_t(keyswitch_splits(b)) * size_t(b));
+    most = std::max(most, size_t(keyswitch_splits(B)) * size_t(B));
+    return most * kSmallWords;
+}
 
 hipError_t launch_keyswitch_jobs(const Job* jobs, int B, const uint64_t* ksk, uint64_t* part, hipStream_t st) {
     if (B <= 0) return hipSuccess;

@@ -148,3 +148,25 @@ def test_request_that_never_fits(gpu):
     with pytest.raises(L.LvsError) as e:
         L.lvs_server_submit(srv, big)
     assert e.value.code == -5
+
+
+def test_step_below_cap_with_more_splits(gpu):
+    """A step smaller than the cap can split the key switch more ways than a
+    step at the cap (600 preprocessing bootstraps under a 8192 cap): the
+    partial sums must still fit the server's fixed region."""
+    say("serving step below cap")
+    g = gpu
+    L = g.L
+    alpha = alphabet()
+    q = (b"AnnaBerthaCyDominikEvaAnnBertha" * 2)[:600 // len(alpha) + 1]
+    ct = L.lvs_encrypt_string(g.ck, q, L.LVS_ENC_ASCII7, 777)
+    max_step = 8192
+    per = L.lvs_server_request_bytes(NAMES, len(alpha), len(q))
+    srv = L.lvs_server_create(g.ctx, NAMES, alpha, L.lvs_server_fixed_bytes(max_step) + 2 * per + 4096,
+                              max_step=max_step)
+    t = L.lvs_server_submit(srv, ct)
+    out = None
+    while out is None:
+        L.lvs_server_step(srv)
+        out = L.lvs_server_poll(srv, t)
+    check_distances(g, q, out)
