@@ -129,6 +129,46 @@ int lvs_context_set_lut(lvs_context* ctx, int slot, const int32_t f16[16]);
 /* Waits for all work enqueued on the context's stream. */
 int lvs_sync(lvs_context* ctx);
 
+/* ----------------------------------------------------------------- tuning */
+
+/* Launch shape of the blind rotation kernel (the dominant cost of every
+ * bootstrap, Section 2.2).  br_grid: workgroups per launch, each looping over
+ * the batch (0: one workgroup per bootstrap).  latency_form_max: batches of
+ * at most this many bootstraps use the form with one workgroup per CU, which
+ * prefetches each step's key values; larger batches use the form with two
+ * workgroups per CU.  A new context starts at {0, number of CUs}.  Plans
+ * captured as graphs keep the shape they were captured with. */
+typedef struct lvs_tuning {
+    int32_t br_grid;
+    int32_t latency_form_max;
+} lvs_tuning;
+
+int lvs_context_get_tuning(const lvs_context* ctx, lvs_tuning* out);
+/* Rejects negative values (LVS_E_INVAL). */
+int lvs_context_set_tuning(lvs_context* ctx, const lvs_tuning* t);
+
+/* One timing of the autotuner: mean duration (ms) of a blind-rotation launch
+ * of `batch` bootstraps in `form` (1 or 2) with `grid` workgroups. */
+typedef struct lvs_tune_sample {
+    int32_t batch;
+    int32_t form;
+    int32_t grid;
+    double ms;
+} lvs_tune_sample;
+
+/* Device workspace bytes of lvs_autotune (256-byte aligned, caller-owned). */
+size_t lvs_autotune_workspace_bytes(size_t max_batch);
+
+/* Times both forms, and a persistent grid of twice the CU count, on batches
+ * from half to four times the CU count (at most max_batch, 1..65536) of zero
+ * ciphertexts, installs the fastest shape in the context and returns it in
+ * *best.  Up to max_samples timings go to samples (may be NULL); *n_samples
+ * (may be NULL) receives how many were taken.  Synchronous; uses the
+ * context's stream.  Errors: LVS_E_INVAL, LVS_E_NOMEM_DEVICE (workspace too
+ * small), LVS_E_DEVICE. */
+int lvs_autotune(lvs_context* ctx, size_t max_batch, void* d_work, size_t work_bytes, lvs_tuning* best,
+                 lvs_tune_sample* samples, size_t max_samples, size_t* n_samples);
+
 /* ------------------------------------------------------------- bootstraps */
 
 /* Workspace bytes for lvs_pbs_batch with B ciphertexts. */

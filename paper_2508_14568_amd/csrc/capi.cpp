@@ -291,7 +291,9 @@ int lvs_context_create(const lvs_server_key* sk, int device, void* hip_stream, v
     }
     C->tables = DevTables{C->tw, C->tw + 2 * tn, C->tw + 4 * tn, C->tw + 4 * tn + kPrimes};
     auto fail = [&](int code) { delete C; return code; };
-    hipError_t e = prepare_kernels();
+    hipError_t e = hipDeviceGetAttribute(&C->cus, hipDeviceAttributeMultiprocessorCount, device);
+    C->latency_form_max = C->cus;
+    if (e == hipSuccess) e = prepare_kernels();
     if (e == hipSuccess) e = hipMemcpy(C->tw, tw.data(), tw.size() * 4, hipMemcpyHostToDevice);
     // the 64-bit bootstrapping key is staged in the key-switching key's slot
     if (e == hipSuccess) e = hipMemcpy(C->ksk, s->bsk.data(), s->bsk.size() * 8, hipMemcpyHostToDevice);

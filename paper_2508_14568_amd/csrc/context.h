@@ -22,7 +22,10 @@ struct Context : Handle {
     uint32_t* tw = nullptr;       // forward pairs, inverse pairs, scale, scale companion
     uint64_t* luts = nullptr;     // [LVS_LUT_SLOTS][N]
     DevTables tables{};
-    int br_grid = 0;              // persistent blind-rotation grid (0: one workgroup per job)
+    int cus = 0;                  // compute units of the device
+    // launch shape of the blind rotation (lvs_context_set_tuning / lvs_autotune)
+    int br_grid = 0;              // persistent grid (0: one workgroup per job)
+    int latency_form_max = 0;     // batches up to this size take the one-workgroup-per-CU form
     // kernel timing (lvs_profile_*): event pairs recorded around launches
     bool profiling = false;
     struct Timed {

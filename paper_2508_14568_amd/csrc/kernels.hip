@@ -99,13 +99,19 @@ __device__ __forceinline__ void fwd_stage(uint32_t (&x)[kEh], const uint2* w, ui
     for (int e = 0; e < kEh; ++e) {
         if (e & half) continue;
         const uint2 tw = w[base + ((S < 6) ? (e >> (6 - S)) : (e >> (11 - S)))];
-        const uint32_t t = mul_shoup(x[e + half], tw.x, tw.y, p);
+        // s = q p - w b = -t (mod 2^32) for the Shoup product t = w b mod p in
+        // [0, 2p), so that a + t = a - s and a + 2p - t = a + 2p + s (v_add3)
+        const uint32_t b = x[e + half];
+        const uint32_t s = __umulhi(b, tw.y) * p - b * tw.x;
         const uint32_t a = x[e];
-        x[e] = a + t;
-        x[e + half] = a + two_p - t;
+        x[e] = a - s;
+        x[e + half] = a + two_p + s;
     }
 }
 
+// kSync: a workgroup barrier before the first write to scr (the caller's
+// other waves may still be reading that memory).
+template <bool kSync>
 __device__ __forceinline__ void ntt_forward(uint32_t (&x)[kEh], uint32_t* scr, const uint2* w, uint32_t p, int lh) {
     fwd_stage<0>(x, w, p, lh);
     fwd_stage<1>(x, w, p, lh);
@@ -113,6 +119,7 @@ __device__ __forceinline__ void ntt_forward(uint32_t (&x)[kEh], uint32_t* scr, c
     fwd_stage<3>(x, w, p, lh);
     fwd_stage<4>(x, w, p, lh);
     fwd_stage<5>(x, w, p, lh);
+    if (kSync) __syncthreads();
     // transpose: coefficient lh + 32 e -> lane j >> 6, element j & 63
 #pragma unroll
     for (int e = 0; e < kEh; ++e) scr[pad(lh + 32 * e)] = x[e];
@@ -295,17 +302,38 @@ struct BrArgs {
 };
 
 constexpr int kBrThreads = 256;
-constexpr size_t kBrLds = sizeof(uint64_t) * 2 * kN                          // accumulator
-                          + sizeof(uint32_t) * 2 * kN                        // biased digits
-                          + sizeof(uint32_t) * kPrimes * 2 * kPoly           // per-half scratch / residues
-                          + sizeof(uint32_t) * (kSmallWords + 1);            // switched mask and body
+constexpr int kAccPer = 2 * kN / kBrThreads;   // accumulator coefficients held by a thread
+constexpr size_t kBrLds = sizeof(uint32_t) * kPrimes * 2 * kPoly                 // per-prime regions
+                          + sizeof(uint32_t) * (kSmallWords + 1);                 // switched mask and body
 
-__global__ void __launch_bounds__(kBrThreads, 1) blind_rotate_kernel(BrArgs A) {
+// One workgroup of 4 wavefronts per bootstrap, two workgroups per CU.
+//
+// The 64-bit accumulator lives in registers: thread t owns coefficient
+// c = t + 256 k' of polynomial k & 1 (k' = k >> 1), the same coefficients it
+// reconstructs in the CRT step.  LDS holds four regions of 2 x kPoly words,
+// one per prime; a CMux step uses them in turn as
+//   (1) the accumulator's low and high words (regions 0 and 1), each thread
+//       writing its own coefficients at the positions it alone reads in (5);
+//   (2) the balanced digits of X^a ACC - ACC (region 2), every thread
+//       forming its 16 digits from the rotated copy;
+//   (3) per-wave transpose scratch of the forward transform (region of the
+//       wave's prime), after a barrier that ends every read of the digits;
+//   (4) the inverse transform's scratch, then its residues in natural order;
+//   (5) the CRT of every owned coefficient from the four regions.
+//
+// kOcc = 2 is the throughput form (two workgroups per CU, bootstrapping-key
+// values loaded where the products need them).  kOcc = 1 is the latency form
+// for batches that leave CUs idle: with the whole register file to itself a
+// workgroup fetches the step's key values before the digit phase, so that
+// the loads complete behind the digits and the forward transform.
+template <int kOcc>
+__global__ void __launch_bounds__(kBrThreads, kOcc) blind_rotate_kernel(BrArgs A) {
     extern __shared__ __align__(16) uint8_t lds[];
-    uint64_t* acc = reinterpret_cast<uint64_t*>(lds);                                   // [2][N]
-    uint32_t* dig = reinterpret_cast<uint32_t*>(lds + sizeof(uint64_t) * 2 * kN);       // [2][N]
-    uint32_t* scratch = dig + 2 * kN;                                                   // [4][2][kPoly]
-    uint32_t* abar = scratch + kPrimes * 2 * kPoly;                                     // [n+1]
+    uint32_t* region = reinterpret_cast<uint32_t*>(lds);   // [kPrimes][2][kPoly]
+    uint32_t* abar = region + kPrimes * 2 * kPoly;          // [n+1]
+    uint32_t* acc_lo = region;                             // [2][kPoly], step (1)
+    uint32_t* acc_hi = region + 2 * kPoly;
+    uint32_t* dig = region + 4 * kPoly;                    // [2][kPoly], step (2)
 
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -317,7 +345,7 @@ __global__ void __launch_bounds__(kBrThreads, 1) blind_rotate_kernel(BrArgs A) {
     const uint32_t q = pick(A.crt.red, wave);
     const uint2* fw = A.tw.fwd + size_t(wave) * kN;
     const uint2* iw = A.tw.inv + size_t(wave) * kN;
-    uint32_t* scr = scratch + (wave * 2 + h) * kPoly;
+    uint32_t* scr = region + (wave * 2 + h) * kPoly;
     // a digit d in [-2^22, 2^22) is stored as d + 2^22; adding p - 2^22 gives
     // a residue of d below 2p
     const uint32_t unbias = p - (1u << 22);
@@ -337,75 +365,95 @@ __global__ void __launch_bounds__(kBrThreads, 1) blind_rotate_kernel(BrArgs A) {
         const uint64_t* tp = A.luts + size_t(lut) * kN;
         const uint32_t bbar = abar[kSmallN];
         // ACC = (0, X^{-bbar} * testpoly)
-        for (int t = tid; t < kN; t += kBrThreads) {
-            const uint32_t src = (uint32_t(t) + bbar) & (2 * kN - 1);
+        uint64_t acc[kAccPer];
+#pragma unroll
+        for (int k = 0; k < kAccPer; ++k) {
+            const uint32_t c = uint32_t(tid + kBrThreads * (k >> 1));
+            const uint32_t src = (c + bbar) & (2 * kN - 1);
             const uint64_t v = tp[src & (kN - 1)];
-            acc[t] = 0;
-            acc[kN + t] = (src < uint32_t(kN)) ? v : uint64_t(0) - v;
+            acc[k] = (k & 1) ? ((src < uint32_t(kN)) ? v : uint64_t(0) - v) : uint64_t(0);
         }
-        __syncthreads();
 
         for (int i = 0; i < kSmallN; ++i) {
             const uint32_t a = abar[i];
-            // this step's bootstrapping-key values of the lane, fetched now so
-            // that the loads complete behind the digit phase and the forward
-            // transform: kq[k] = (K0[2k], K1[2k], K0[2k+1], K1[2k+1]) of
-            // positions 64 lh + 2k and 64 lh + 2k + 1
+            // this step's bootstrapping-key values of the lane:
+            // kq = (K0[2k], K1[2k], K0[2k+1], K1[2k+1]) of positions 64 lh + 2k, + 1
             const uint4* K = reinterpret_cast<const uint4*>(A.bsk) + ((size_t(i) * kPrimes + wave) * 2 + h) * (kN / 2) + lh;
-            uint4 kq[kEh / 2];
+            uint4 kpre[kOcc == 1 ? kEh / 2 : 1];
+            if (kOcc == 1) {
 #pragma unroll
-            for (int k = 0; k < kEh / 2; ++k) kq[k] = K[k * 32];
-            asm volatile("" ::: "memory");
-            // digits of X^a ACC - ACC: round(t / 2^41) as a balanced 23-bit digit
+                for (int k = 0; k < kEh / 2; ++k) kpre[k] = K[k * 32];
+                asm volatile("" ::: "memory");
+            }
+            // (1)
 #pragma unroll
-            for (int k = 0; k < 2 * kN / kBrThreads; ++k) {
+            for (int k = 0; k < kAccPer; ++k) {
+                const int at = (k & 1) * kPoly + tid + kBrThreads * (k >> 1);
+                acc_lo[at] = uint32_t(acc[k]);
+                acc_hi[at] = uint32_t(acc[k] >> 32);
+            }
+            __syncthreads();
+            // (2) digits of X^a ACC - ACC: round(t / 2^41) as a balanced 23-bit digit
+#pragma unroll
+            for (int k = 0; k < kAccPer; ++k) {
                 const int qq = k & 1;
                 const uint32_t c = uint32_t(tid + kBrThreads * (k >> 1));
                 const uint32_t src = (c - a) & (2 * kN - 1);
-                uint64_t r = acc[qq * kN + (src & (kN - 1))];
+                const int at = qq * kPoly + int(src & (kN - 1));
+                uint64_t r = uint64_t(acc_lo[at]) | (uint64_t(acc_hi[at]) << 32);
                 if (src >= uint32_t(kN)) r = uint64_t(0) - r;
-                const uint64_t t = r - acc[qq * kN + c];
+                const uint64_t t = r - acc[k];
                 const uint32_t u = ((uint32_t(t >> 40) + 1) >> 1) & 0x7FFFFFu;   // round(t / 2^41) mod 2^23
-                dig[qq * kN + c] = (u + 0x400000u) & 0x7FFFFFu;                   // balanced digit + 2^22
+                dig[qq * kPoly + c] = (u + 0x400000u) & 0x7FFFFFu;                // balanced digit + 2^22
             }
             __syncthreads();
+            // (3)
             uint32_t x[kEh];
 #pragma unroll
-            for (int e = 0; e < kEh; ++e) x[e] = dig[h * kN + lh + 32 * e] + unbias;
-            ntt_forward(x, scr, fw, p, lh);
+            for (int e = 0; e < kEh; ++e) x[e] = dig[h * kPoly + lh + 32 * e] + unbias;
+            ntt_forward<true>(x, scr, fw, p, lh);
             // products with the GGSW rows: out_h = D0 K[0][h] + D1 K[1][h]
 #pragma unroll
-            for (int e = 0; e < kEh; ++e) {
-                const uint32_t own = x[e];
-                const uint32_t other = swap_halves(own, lane);
-                const uint32_t d0 = h ? other : own;
-                const uint32_t d1 = h ? own : other;
-                const uint32_t k0 = (e & 1) ? kq[e >> 1].z : kq[e >> 1].x;
-                const uint32_t k1 = (e & 1) ? kq[e >> 1].w : kq[e >> 1].y;
-                x[e] = redc(uint64_t(d0) * k0 + uint64_t(d1) * k1, p, mont);
+            for (int e = 0; e < kEh; e += 2) {
+                const uint4 kq = (kOcc == 1) ? kpre[(e >> 1) % (kOcc == 1 ? kEh / 2 : 1)] : K[(e >> 1) * 32];
+#pragma unroll
+                for (int o = 0; o < 2; ++o) {
+                    const uint32_t own = x[e + o];
+                    const uint32_t other = swap_halves(own, lane);
+                    const uint32_t d0 = h ? other : own;
+                    const uint32_t d1 = h ? own : other;
+                    const uint32_t k0 = o ? kq.z : kq.x;
+                    const uint32_t k1 = o ? kq.w : kq.y;
+                    x[e + o] = redc(uint64_t(d0) * k0 + uint64_t(d1) * k1, p, mont);
+                }
             }
+            // (4)
             ntt_inverse(x, scr, iw, p, q, lh);
 #pragma unroll
-            for (int e = 0; e < kEh; ++e) scr[pad(lh + 32 * e)] = x[e];
+            for (int e = 0; e < kEh; ++e) scr[lh + 32 * e] = x[e];
             __syncthreads();
-            // CRT: 16 coefficients per thread
+            // (5)
 #pragma unroll
-            for (int k = 0; k < 2 * kN / kBrThreads; ++k) {
-                const int qq = k & 1;
-                const int c = tid + kBrThreads * (k >> 1);
+            for (int k = 0; k < kAccPer; ++k) {
+                const int at = (k & 1) * kPoly + tid + kBrThreads * (k >> 1);
                 uint32_t r[kPrimes];
 #pragma unroll
-                for (int w = 0; w < kPrimes; ++w) r[w] = scratch[(w * 2 + qq) * kPoly + pad(c)];
-                acc[qq * kN + c] += crt_lift(r, A.crt);
+                for (int w = 0; w < kPrimes; ++w) r[w] = region[w * 2 * kPoly + at];
+                acc[k] += crt_lift(r, A.crt);
             }
-            __syncthreads();
         }
         // sample extraction of coefficient 0, then the job's output rule
+#pragma unroll
+        for (int k = 0; k < kAccPer; ++k) {
+            const int at = (k & 1) * kPoly + tid + kBrThreads * (k >> 1);
+            acc_lo[at] = uint32_t(acc[k]);
+            acc_hi[at] = uint32_t(acc[k] >> 32);
+        }
+        __syncthreads();
         for (int t = tid; t < kCtWords; t += kBrThreads) {
-            uint64_t v;
-            if (t == 0) v = acc[0];
-            else if (t < kN) v = uint64_t(0) - acc[kN - t];
-            else v = acc[kN];
+            const int at = (t == 0) ? 0 : (t < kN) ? kN - t : kPoly;
+            const uint64_t m = uint64_t(acc_lo[at]) | (uint64_t(acc_hi[at]) << 32);
+            const uint64_t v = (t > 0 && t < kN) ? uint64_t(0) - m : m;
             const uint64_t s0 = J.sub[0] ? J.sub[0][t] : 0;
             const uint64_t s1 = J.sub[1] ? J.sub[1][t] : 0;
             const uint64_t c0 = (t == kN) ? J.sub_delta[0] : 0;
@@ -444,7 +492,7 @@ __global__ void __launch_bounds__(64) bsk_convert_kernel(const uint64_t* __restr
         if (c >> 63) m = (m + p - two64_mod_p) % p;     // c read as c - 2^64
         x[e] = uint32_t(m);
     }
-    ntt_forward(x, scratch + h * kPoly, tw.fwd + size_t(r) * kN, p, lh);
+    ntt_forward<false>(x, scratch + h * kPoly, tw.fwd + size_t(r) * kN, p, lh);
     const uint32_t sc = scale[r], scs = scale_s[r];
     const int i = row >> 1, rho = row & 1;
     uint32_t* dst = out + ((size_t(i) * kPrimes + r) * 2 + h) * (2 * kN) + lh * 4 + rho;
@@ -456,97 +504,12 @@ __global__ void __launch_bounds__(64) bsk_convert_kernel(const uint64_t* __restr
 
 constexpr int kWordBlocks = (kCtWords + 255) / 256;   // 256-word slices of a ciphertext
 
-// out[c - c0] = alpha (A[i][sa] - B[j][sb]) + (delta on the body) - E[c - c0]
-// for cells c = i*n + j in [c0, c0 + count) (E optional).  Without B the
-// second operand is a cleartext symbol: (0, ..., 0, sym_j * 2^59).
-struct PairArgs {
-    const uint64_t* A; int a_stride; int sa;            // A + i * a_stride + sa * W
-    const uint64_t* B; int b_stride; int sb;
-    const uint8_t* clear_syms;                          // if B == nullptr: device symbols [n]
-    const uint64_t* E;
-    uint64_t alpha;
-    uint64_t delta;
-    uint64_t* out;
-    int n;
-    long c0;
-};
-
-__global__ void __launch_bounds__(256) pair_kernel(PairArgs P) {
-    const long local = blockIdx.x / kWordBlocks;
-    const int w = (blockIdx.x % kWordBlocks) * 256 + threadIdx.x;
-    if (w >= kCtWords) return;
-    const long cell = P.c0 + local;
-    const long i = cell / P.n, j = cell % P.n;
-    const uint64_t av = P.A[i * P.a_stride + size_t(P.sa) * kCtWords + w];
-    uint64_t bv;
-    if (P.B) bv = P.B[j * P.b_stride + size_t(P.sb) * kCtWords + w];
-    else bv = (w == kN) ? (uint64_t(P.clear_syms[j]) << kDeltaLog) : 0;
-    uint64_t v = P.alpha * (av - bv);
-    if (w == kN) v += P.delta;
-    if (P.E) v -= P.E[local * kCtWords + w];
-    P.out[local * kCtWords + w] = v;
-}
-
-// Cells of anti-diagonal s = i + j, i = i0 + c: key = 4 - V[i] + 3 H[j] + eq9(i, j)
-// with eq9(i, j) = EQ + (i-1) eq_si + col[j-1] eq_sj (in ciphertexts).
-struct KeyArgs {
-    const uint64_t* V;         // [m+1][W], V[i] = v[i, latest j]
-    const uint64_t* H;         // [n+1][W]
-    const uint64_t* EQ;
-    size_t eq_si, eq_sj;
-    const int32_t* col;        // [n] column of b_j in EQ (nullptr: j - 1)
-    uint64_t* key;             // [count][W]
-    int i0, s;
-};
-
-__global__ void __launch_bounds__(256) key_kernel(KeyArgs K) {
-    const int c = blockIdx.x / kWordBlocks;
-    const int w = (blockIdx.x % kWordBlocks) * 256 + threadIdx.x;
-    if (w >= kCtWords) return;
-    const int i = K.i0 + c, j = K.s - i;
-    const size_t cj = K.col ? size_t(K.col[j - 1]) : size_t(j - 1);
-    const uint64_t v = K.V[size_t(i) * kCtWords + w];
-    const uint64_t h = K.H[size_t(j) * kCtWords + w];
-    const uint64_t eq = K.EQ[(size_t(i - 1) * K.eq_si + cj * K.eq_sj) * kCtWords + w];
-    uint64_t r = 3 * h - v + eq;
-    if (w == kN) r += uint64_t(4) << kDeltaLog;
-    K.key[size_t(c) * kCtWords + w] = r;
-}
-
-// v[i,j] = M - h[i-1,j], h[i,j] = M - v[i,j-1] for the cells of one diagonal;
-// trace (optional, [m][n]) keeps every M.
-__global__ void __launch_bounds__(256) update_kernel(uint64_t* V, uint64_t* H, const uint64_t* M, int i0, int s,
-                                                     uint64_t* trace, int n) {
-    const int c = blockIdx.x / kWordBlocks;
-    const int w = (blockIdx.x % kWordBlocks) * 256 + threadIdx.x;
-    if (w >= kCtWords) return;
-    const int i = i0 + c, j = s - i;
-    const uint64_t mv = M[size_t(c) * kCtWords + w];
-    if (trace) trace[(size_t(i - 1) * n + (j - 1)) * kCtWords + w] = mv;
-    const uint64_t hv = H[size_t(j) * kCtWords + w];
-    const uint64_t vv = V[size_t(i) * kCtWords + w];
-    V[size_t(i) * kCtWords + w] = mv - hv;
-    H[size_t(j) * kCtWords + w] = mv - vv;
-}
-
 // Noise-free encryptions of mu in rows [0, count).
 __global__ void __launch_bounds__(256) trivial_kernel(uint64_t* out, uint32_t mu) {
     const int r = blockIdx.x / kWordBlocks;
     const int w = (blockIdx.x % kWordBlocks) * 256 + threadIdx.x;
     if (w >= kCtWords) return;
     out[size_t(r) * kCtWords + w] = (w == kN) ? (uint64_t(mu) << kDeltaLog) : 0;
-}
-
-// Preprocessing table rows: dst[c][i] = src[i * alen + c - c0] for cells
-// i * alen + c in [c0, c0 + count).
-__global__ void __launch_bounds__(256) table_scatter_kernel(const uint64_t* src, uint64_t* dst, int m, int alen,
-                                                            long c0) {
-    const long local = blockIdx.x / kWordBlocks;
-    const int w = (blockIdx.x % kWordBlocks) * 256 + threadIdx.x;
-    if (w >= kCtWords) return;
-    const long cell = c0 + local;
-    const long i = cell / alen, c = cell % alen;
-    dst[(c * m + i) * kCtWords + w] = src[local * kCtWords + w];
 }
 
 }  // namespace dev
@@ -607,12 +570,17 @@ hipError_t launch_keyswitch_jobs(const Job* jobs, int B, const uint64_t* ksk, ui
 }
 
 hipError_t prepare_kernels() {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(dev::blind_rotate_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, int(dev::kBrLds));
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(dev::blind_rotate_kernel<1>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(dev::kBrLds));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(dev::blind_rotate_kernel<2>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(dev::kBrLds));
+    return e;
 }
 
 hipError_t launch_blind_rotate_jobs(const Job* jobs, int B, const uint64_t* part, const uint64_t* luts,
-                                    const uint32_t* bsk, const DevTables& t, int grid, hipStream_t st) {
+                                    const uint32_t* bsk, const DevTables& t, int grid, int latency_form_max,
+                                    hipStream_t st) {
     if (B <= 0) return hipSuccess;
     dev::BrArgs A{};
     A.jobs = jobs;
@@ -624,7 +592,10 @@ hipError_t launch_blind_rotate_jobs(const Job* jobs, int B, const uint64_t* part
     A.crt = make_crt();
     A.B = B;
     if (grid <= 0 || grid > B) grid = B;
-    hipLaunchKernelGGL(dev::blind_rotate_kernel, dim3(grid), dim3(dev::kBrThreads), dev::kBrLds, st, A);
+    if (B <= latency_form_max)
+        hipLaunchKernelGGL(dev::blind_rotate_kernel<1>, dim3(grid), dim3(dev::kBrThreads), dev::kBrLds, st, A);
+    else
+        hipLaunchKernelGGL(dev::blind_rotate_kernel<2>, dim3(grid), dim3(dev::kBrThreads), dev::kBrLds, st, A);
     return hipGetLastError();
 }
 
@@ -636,42 +607,9 @@ hipError_t launch_bsk_convert(const uint64_t* bsk_u64, uint32_t* out, const DevT
     return hipGetLastError();
 }
 
-hipError_t launch_pair(const uint64_t* A, int a_stride, int sa, const uint64_t* B, int b_stride, int sb,
-                       const uint8_t* clear_syms, const uint64_t* E, uint64_t alpha, uint64_t delta, uint64_t* out,
-                       int n, long c0, long count, hipStream_t st) {
-    if (count <= 0) return hipSuccess;
-    dev::PairArgs P{A, a_stride, sa, B, b_stride, sb, clear_syms, E, alpha, delta, out, n, c0};
-    hipLaunchKernelGGL(dev::pair_kernel, dim3(unsigned(count * dev::kWordBlocks)), dim3(256), 0, st, P);
-    return hipGetLastError();
-}
-
-hipError_t launch_key(const uint64_t* V, const uint64_t* H, const uint64_t* EQ, size_t eq_si, size_t eq_sj,
-                      const int32_t* col, uint64_t* key, int i0, int s, int count, hipStream_t st) {
-    if (count <= 0) return hipSuccess;
-    dev::KeyArgs K{V, H, EQ, eq_si, eq_sj, col, key, i0, s};
-    hipLaunchKernelGGL(dev::key_kernel, dim3(unsigned(count * dev::kWordBlocks)), dim3(256), 0, st, K);
-    return hipGetLastError();
-}
-
-hipError_t launch_update(uint64_t* V, uint64_t* H, const uint64_t* M, int i0, int s, int count, uint64_t* trace,
-                         int n, hipStream_t st) {
-    if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(dev::update_kernel, dim3(unsigned(count * dev::kWordBlocks)), dim3(256), 0, st, V, H, M, i0, s,
-                       trace, n);
-    return hipGetLastError();
-}
-
 hipError_t launch_trivial(uint64_t* out, int count, uint32_t mu, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(dev::trivial_kernel, dim3(unsigned(count * dev::kWordBlocks)), dim3(256), 0, st, out, mu);
-    return hipGetLastError();
-}
-
-hipError_t launch_table_scatter(const uint64_t* src, uint64_t* dst, int m, int alen, long c0, long count,
-                                hipStream_t st) {
-    if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(dev::table_scatter_kernel, dim3(unsigned(count * dev::kWordBlocks)), dim3(256), 0, st, src,
-                       dst, m, alen, c0);
     return hipGetLastError();
 }
 

@@ -269,7 +269,7 @@ hipError_t launch_steps(Context* C, const Plan& P, hipStream_t st, bool timed) {
         {
             TimedLaunch t(C, timed ? 0 : -1, uint64_t(B));
             hipError_t e = launch_blind_rotate_jobs(P.d_jobs + s.off, B, P.d_part, C->luts, C->bsk, C->tables,
-                                                    C->br_grid, st);
+                                                    C->br_grid, C->latency_form_max, st);
             if (e != hipSuccess) return e;
         }
     }

@@ -1,0 +1,168 @@
+// Launch-shape tuning of the blind rotation.
+//
+// The blind rotation has two forms (one workgroup per CU with the step's key
+// values prefetched, or two workgroups per CU) and an optional persistent
+// grid.  Which is faster depends on how a batch fills the device, so the
+// autotuner times both forms, and a persistent grid, on batches around the
+// CU count and keeps the fastest shape per batch size.  Its inputs are zero
+// ciphertexts: the work of a bootstrap does not depend on the values.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <string>
+#include <vector>
+
+#include "context.h"
+#include "launch.h"
+#include "lvs_internal.h"
+#include "plan.h"
+
+using namespace lvs;
+
+namespace {
+
+#define TUNE_FAIL(code, msg) \
+    do {                     \
+        set_error(msg);      \
+        return (code);       \
+    } while (0)
+
+#define TUNE_HIP(expr)                                                                                  \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess) TUNE_FAIL(LVS_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+Context* ctx_of(lvs_context* c) {
+    auto* h = reinterpret_cast<Context*>(c);
+    return (h && h->kind == kContext) ? h : nullptr;
+}
+
+// Batch sizes timed: half the CUs up to four times the CUs.
+std::vector<int> tune_batches(int cus, size_t max_batch) {
+    std::vector<int> out;
+    for (int b : {cus / 2, cus, cus + cus / 4, 2 * cus, 4 * cus})
+        if (b >= 1 && size_t(b) <= max_batch && (out.empty() || b > out.back())) out.push_back(b);
+    if (out.empty()) out.push_back(int(max_batch));
+    return out;
+}
+
+struct Candidate {
+    int form, grid;
+};
+
+}  // namespace
+
+extern "C" {
+
+size_t lvs_autotune_workspace_bytes(size_t max_batch) {
+    const size_t b = std::max<size_t>(max_batch, 1);
+    return 2 * align256(sizeof(uint64_t) * b * kCtWords) + plan_bytes(b, b);
+}
+
+int lvs_context_get_tuning(const lvs_context* ctx, lvs_tuning* out) {
+    Context* C = ctx_of(const_cast<lvs_context*>(ctx));
+    if (!C || !out) TUNE_FAIL(LVS_E_INVAL, "lvs_context_get_tuning: bad argument");
+    out->br_grid = C->br_grid;
+    out->latency_form_max = C->latency_form_max;
+    return LVS_OK;
+}
+
+int lvs_context_set_tuning(lvs_context* ctx, const lvs_tuning* t) {
+    Context* C = ctx_of(ctx);
+    if (!C || !t) TUNE_FAIL(LVS_E_INVAL, "lvs_context_set_tuning: bad argument");
+    if (t->br_grid < 0 || t->latency_form_max < 0) TUNE_FAIL(LVS_E_INVAL, "lvs_context_set_tuning: negative value");
+    C->br_grid = t->br_grid;
+    C->latency_form_max = t->latency_form_max;
+    return LVS_OK;
+}
+
+int lvs_autotune(lvs_context* ctx, size_t max_batch, void* d_work, size_t work_bytes, lvs_tuning* best,
+                 lvs_tune_sample* samples, size_t max_samples, size_t* n_samples) {
+    Context* C = ctx_of(ctx);
+    if (!C || !d_work) TUNE_FAIL(LVS_E_INVAL, "lvs_autotune: bad argument");
+    if (max_batch == 0 || max_batch > kMaxStep) TUNE_FAIL(LVS_E_INVAL, "lvs_autotune: max_batch out of range");
+    if (work_bytes < lvs_autotune_workspace_bytes(max_batch))
+        TUNE_FAIL(LVS_E_NOMEM_DEVICE, "lvs_autotune: workspace too small");
+    if (reinterpret_cast<uintptr_t>(d_work) % 256) TUNE_FAIL(LVS_E_INVAL, "lvs_autotune: workspace misaligned");
+    TUNE_HIP(hipSetDevice(C->device));
+    const hipStream_t st = C->stream;
+    uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
+    uint64_t* in = reinterpret_cast<uint64_t*>(ws);
+    ws += align256(sizeof(uint64_t) * max_batch * kCtWords);
+    uint64_t* out = reinterpret_cast<uint64_t*>(ws);
+    ws += align256(sizeof(uint64_t) * max_batch * kCtWords);
+    TUNE_HIP(launch_fill_u64(in, max_batch * kCtWords, 0, st));
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    TUNE_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        TUNE_FAIL(LVS_E_DEVICE, "lvs_autotune: hipEventCreate failed");
+    }
+    struct Result {
+        int batch, form, grid;
+        double ms;
+    };
+    std::vector<Result> res;
+    hipError_t err = hipSuccess;
+    const int cus = std::max(1, C->cus);
+    for (int B : tune_batches(cus, max_batch)) {
+        Plan P;
+        build_pbs_plan(in, nullptr, LVS_LUT_EQ, size_t(B), out, P);
+        uint8_t* w = ws;
+        err = upload_plan(P, w, st);
+        if (err == hipSuccess) err = launch_keyswitch_jobs(P.d_jobs, B, C->ksk, P.d_part, st);
+        std::vector<Candidate> cands{{1, B}, {2, B}};
+        if (B >= 2 * cus) cands.push_back({2, 2 * cus});
+        for (const Candidate& c : cands) {
+            if (err != hipSuccess) break;
+            const int lf = c.form == 1 ? INT_MAX : 0;
+            // one launch to warm caches, then two timed
+            err = launch_blind_rotate_jobs(P.d_jobs, B, P.d_part, C->luts, C->bsk, C->tables, c.grid, lf, st);
+            if (err == hipSuccess) err = hipEventRecord(e0, st);
+            for (int r = 0; r < 2 && err == hipSuccess; ++r)
+                err = launch_blind_rotate_jobs(P.d_jobs, B, P.d_part, C->luts, C->bsk, C->tables, c.grid, lf, st);
+            if (err == hipSuccess) err = hipEventRecord(e1, st);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
+            float ms = 0;
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+            if (err == hipSuccess) res.push_back({B, c.form, c.grid, double(ms) / 2});
+        }
+        if (err != hipSuccess) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (err != hipSuccess) TUNE_FAIL(LVS_E_DEVICE, std::string("lvs_autotune: ") + hipGetErrorString(err));
+
+    auto time_of = [&](int B, int form, int grid) {
+        for (const auto& r : res)
+            if (r.batch == B && r.form == form && r.grid == grid) return r.ms;
+        return -1.0;
+    };
+    // the latency form while it is at least as fast, in increasing batch order
+    lvs_tuning t{};
+    t.latency_form_max = 0;
+    for (int B : tune_batches(cus, max_batch)) {
+        if (time_of(B, 1, B) <= time_of(B, 2, B)) t.latency_form_max = B;
+        else break;
+    }
+    // a persistent grid only if it wins by more than 1% at every batch that tried it
+    bool tried = false, wins = true;
+    for (const auto& r : res)
+        if (r.grid != r.batch) {
+            tried = true;
+            wins = wins && r.ms < 0.99 * time_of(r.batch, 2, r.batch);
+        }
+    t.br_grid = (tried && wins) ? 2 * cus : 0;
+    C->br_grid = t.br_grid;
+    C->latency_form_max = t.latency_form_max;
+    if (best) *best = t;
+    if (n_samples) *n_samples = res.size();
+    for (size_t k = 0; k < res.size() && samples && k < max_samples; ++k)
+        samples[k] = lvs_tune_sample{res[k].batch, res[k].form, res[k].grid, res[k].ms};
+    return LVS_OK;
+}
+
+}  // extern "C"

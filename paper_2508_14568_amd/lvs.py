@@ -78,6 +78,10 @@ _SIGS = {
     "lvs_server_step": (I32, [VP, ctypes.POINTER(SZ), ctypes.POINTER(SZ), ctypes.POINTER(SZ)]),
     "lvs_server_poll": (I32, [VP, U64, VP, ctypes.POINTER(ctypes.c_int)]),
     "lvs_server_stats": (I32, [VP, ctypes.POINTER(U64), ctypes.POINTER(U64)]),
+    "lvs_context_get_tuning": (I32, [VP, VP]),
+    "lvs_context_set_tuning": (I32, [VP, VP]),
+    "lvs_autotune_workspace_bytes": (SZ, [SZ]),
+    "lvs_autotune": (I32, [VP, SZ, VP, SZ, VP, VP, SZ, ctypes.POINTER(SZ)]),
     "lvs_profile_enable": (I32, [VP, I32]),
     "lvs_profile_read": (I32, [VP, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(U64), ctypes.POINTER(U64)]),
     "lvs_free": (None, [VP]),
@@ -90,6 +94,9 @@ def lib():
     if _L is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"liblvs.so not built ({LIB_PATH}); run paper_2508_14568_amd.build.build()")
+        # PyTorch first: its HIP runtime (same soname) then serves the library
+        # too, so both share one runtime, one device list and one allocator.
+        _torch()
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
@@ -474,6 +481,87 @@ def lvs_server_stats(srv: Server):
     st, pb = U64(), U64()
     _check(lib().lvs_server_stats(srv, ctypes.byref(st), ctypes.byref(pb)))
     return st.value, pb.value
+
+
+# ------------------------------------------------------------------ tuning
+
+class lvs_tuning(ctypes.Structure):
+    _fields_ = [("br_grid", ctypes.c_int32), ("latency_form_max", ctypes.c_int32)]
+
+
+class lvs_tune_sample(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("form", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
+
+
+def lvs_context_get_tuning(ctx: Context) -> dict:
+    t = lvs_tuning()
+    _check(lib().lvs_context_get_tuning(ctx, ctypes.byref(t)))
+    return {"br_grid": t.br_grid, "latency_form_max": t.latency_form_max}
+
+
+def lvs_context_set_tuning(ctx: Context, tuning: dict):
+    t = lvs_tuning(int(tuning["br_grid"]), int(tuning["latency_form_max"]))
+    _check(lib().lvs_context_set_tuning(ctx, ctypes.byref(t)))
+
+
+def lvs_autotune_workspace_bytes(max_batch: int) -> int:
+    return lib().lvs_autotune_workspace_bytes(max_batch)
+
+
+def lvs_autotune(ctx: Context, max_batch: int, d_work=None):
+    """(installed tuning, list of timings) from the library's autotuner."""
+    if d_work is None:
+        d_work = device_buffer(lvs_autotune_workspace_bytes(max_batch), ctx.device)
+    best = lvs_tuning()
+    samples = (lvs_tune_sample * 64)()
+    n = SZ()
+    _check(lib().lvs_autotune(ctx, max_batch, _dptr(d_work), d_work.numel() * d_work.element_size(),
+                              ctypes.byref(best), samples, 64, ctypes.byref(n)))
+    rows = [{"batch": x.batch, "form": x.form, "grid": x.grid, "ms": round(x.ms, 4)} for x in samples[:n.value]]
+    return {"br_grid": best.br_grid, "latency_form_max": best.latency_form_max}, rows
+
+
+def _tuning_key(ctx: Context) -> str:
+    import hashlib
+    torch = _torch()
+    prop = torch.cuda.get_device_properties(ctx.device)
+    with open(LIB_PATH, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()[:16]
+    return f"{getattr(prop, 'gcnArchName', prop.name)}/{prop.multi_processor_count}cu/{digest}"
+
+
+def autotune(ctx: Context, max_batch: int = None, cache: str = None) -> dict:
+    """Installs a launch shape for this device and library build: from the
+    JSON cache when it holds one, else from lvs_autotune (then cached).
+    cache: file path (default $LVS_TUNING_CACHE or ~/.cache/lvs/tuning.json)."""
+    import json
+    torch = _torch()
+    if max_batch is None:
+        max_batch = 4 * torch.cuda.get_device_properties(ctx.device).multi_processor_count
+    path = cache or os.environ.get("LVS_TUNING_CACHE") or os.path.join(
+        os.path.expanduser("~"), ".cache", "lvs", "tuning.json")
+    key = _tuning_key(ctx)
+    try:
+        with open(path) as f:
+            table = json.load(f)
+    except (OSError, ValueError):
+        table = {}
+    hit = table.get(key)
+    if hit and hit.get("max_batch") == max_batch:
+        lvs_context_set_tuning(ctx, hit["tuning"])
+        return dict(hit, cached=True)
+    tuning, rows = lvs_autotune(ctx, max_batch)
+    entry = {"tuning": tuning, "max_batch": max_batch, "samples": rows}
+    table[key] = entry
+    try:
+        os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+        with open(path + ".tmp", "w") as f:
+            json.dump(table, f, indent=1)
+        os.replace(path + ".tmp", path)
+    except OSError:
+        pass                      # an unwritable cache only costs a re-tune
+    return dict(entry, cached=False)
 
 
 # ------------------------------------------------------------ measurement
