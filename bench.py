@@ -44,18 +44,18 @@ def kernel_source_digest():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def traffic_per_launch(avg_pbs_per_launch):
-    """HBM bytes per blind-rotation launch from the committed rocprofv3
-    counter summary, or None when it is absent or the kernel changed since."""
+def traffic_per_launch(kernel, avg_pbs_per_launch):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when it is absent or the kernel source changed since."""
     path = os.path.join(ROOT, "profiles", "blind_rotate_traffic.json")
     try:
         with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernels_hip_sha256") != kernel_source_digest():
+    if t.get("kernels_hip_sha256") != kernel_source_digest() or kernel not in t.get("bytes_per_pbs", {}):
         return None
-    return t["bytes_per_pbs"] * avg_pbs_per_launch
+    return round(t["bytes_per_pbs"][kernel] * avg_pbs_per_launch)
 
 
 def cpu_baseline(workload_cts, seconds_hint=20.0):
@@ -112,6 +112,10 @@ def batched_block(L, ck, ctx, nq, plain_sample):
     L.lvs_plan_run(plan)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    L.lvs_profile_enable(ctx, True)
+    L.lvs_plan_run(plan)
+    g_ms, g_runs, _ = L.lvs_profile_read(ctx, L.KERNEL_GRAPH)
+    L.lvs_profile_enable(ctx, False)
     for (a, b), d_h in zip(pairs, outs):
         h = L.to_host(d_h).reshape(len(b), L.CT_WORDS)
         if L.lvs_decrypt_distance(ck, h, len(a)) != levenshtein(a, b):
@@ -142,6 +146,13 @@ def batched_block(L, ck, ctx, nq, plain_sample):
         "plain_queries_per_s": round(plain_sample / t_plain, 4),
         "plain_queries_per_s_same_work": round(nq / (pbs / plain_pbs_s), 4),
         "speedup_vs_plain": round(batched_pbs_s / plain_pbs_s, 2),
+        # the whole graph (key switches and launch gaps included) against the
+        # blind rotation's multiply peak: a lower bound of the kernel's fraction
+        "roofline_graph": {"bound": "alu", "achieved": round(INT_MUL_PER_PBS * pbs / (g_ms / g_runs / 1e3) / 1e12, 3),
+                           "peak": round(VALU_INT_MUL_PEAK_TOPS, 3), "unit": "TOP/s",
+                           "frac": round(INT_MUL_PER_PBS * pbs / (g_ms / g_runs / 1e3) / 1e12
+                                         / VALU_INT_MUL_PEAK_TOPS, 4),
+                           "graph_ms": round(g_ms / g_runs, 3)},
     }
 
 
@@ -203,6 +214,20 @@ def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos):
     return res
 
 
+def microbench(L, ctx):
+    """Measured ceilings: the butterfly instruction mix from registers on
+    every CU, and a 1 GiB device copy."""
+    import torch
+    ms, muls = L.lvs_microbench_modmul(ctx, 4096)
+    nbytes = 1 << 30
+    src = torch.zeros(nbytes // 8, dtype=torch.int64, device=ctx.device)
+    dst = torch.empty_like(src)
+    copy_ms = L.lvs_microbench_copy(ctx, src, dst, nbytes, 5)
+    del src, dst
+    return {"modmul_probe_tops": round(muls / (ms / 1e3) / 1e12, 3),
+            "copy_gbs": round(2 * nbytes / (copy_ms / 1e3) / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +242,8 @@ def main():
     ap.add_argument("--poisson-queries", type=int, default=40, help="queries per load factor")
     ap.add_argument("--rho", type=str, default="0.8", help="comma-separated load factors")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--no-microbench", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -234,6 +261,10 @@ def main():
     params = L.lvs_params_default()
     ck, sk = L.lvs_keygen(params, 1)
     ctx = L.lvs_context_create(sk, params, 0)
+    tuning = None
+    if not args.no_autotune:
+        note("autotune")
+        tuning = L.autotune(ctx)
     A = L.lvs_encrypt_string(ck, a, L.LVS_ENC_ASCII7, 1001)
     B = L.lvs_encrypt_string(ck, b, L.LVS_ENC_ASCII7, 1002)
     dA, dB = L.to_device(A, ctx.device), L.to_device(B, ctx.device)
@@ -253,6 +284,9 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     br_ms, br_launches, br_pbs = L.lvs_profile_read(ctx, L.KERNEL_BLIND_ROTATE)
+    forms = {name: L.lvs_profile_read(ctx, k) for name, k in
+             (("blind_rotate_kernel<1>", L.KERNEL_BLIND_ROTATE_LATENCY),
+              ("blind_rotate_kernel<2>", L.KERNEL_BLIND_ROTATE_THROUGHPUT))}
     ks_ms, ks_launches, _ = L.lvs_profile_read(ctx, L.KERNEL_KEYSWITCH)
     L.lvs_profile_enable(ctx, False)
 
@@ -264,21 +298,29 @@ def main():
     pbs_per_step = 3 * m * n
     ms_per_step = 1000 * elapsed / args.steps
     pbs_s = pbs_per_step * args.steps / elapsed
-    avg_launch_ms = br_ms / max(1, br_launches)
-    avg_pbs_launch = br_pbs / max(1, br_launches)
+    # the dominant kernel: the blind-rotation form with the most time
+    kname = max(forms, key=lambda k: forms[k][0])
+    k_ms, k_launches, k_pbs = forms[kname]
+    avg_launch_ms = k_ms / max(1, k_launches)
+    avg_pbs_launch = k_pbs / max(1, k_launches)
     achieved = INT_MUL_PER_PBS * avg_pbs_launch / (avg_launch_ms / 1000) / 1e12
     roofline = {
-        "bound": "alu", "kernel": "blind_rotate_kernel",
+        "bound": "alu", "kernel": kname,
         "achieved": round(achieved, 3), "peak": round(VALU_INT_MUL_PEAK_TOPS, 3), "unit": "TOP/s",
         "frac": round(achieved / VALU_INT_MUL_PEAK_TOPS, 4),
-        "traffic": traffic_per_launch(avg_pbs_launch),
+        "traffic": traffic_per_launch(kname, avg_pbs_launch),
         "ops": "32-bit integer multiplies, 3 per modular multiplication, "
                f"{INT_MUL_PER_PBS} per bootstrap",
-        "avg_launch_ms": round(avg_launch_ms, 4), "launches": br_launches,
+        "avg_launch_ms": round(avg_launch_ms, 4), "launches": k_launches,
         "avg_pbs_per_launch": round(avg_pbs_launch, 2),
+        "other_form": {k: {"ms_per_step": round(v[0] / args.steps, 3), "launches": v[1], "pbs": v[2]}
+                       for k, v in forms.items() if k != kname},
         "keyswitch_ms_per_step": round(ks_ms / args.steps, 3),
         "blind_rotate_ms_per_step": round(br_ms / args.steps, 3),
     }
+    if not args.no_microbench:
+        note("microbenchmarks")
+        roofline["measured"] = microbench(L, ctx)
     line = {
         "metric": "PBS/s & DP cells/s; batched vs plain queries/s; p50/p99 query latency",
         "value": round(pbs_s, 2), "unit": "PBS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -292,6 +334,8 @@ def main():
         "distance": dist,
         "roofline": roofline,
     }
+    if tuning is not None:
+        line["tuning"] = dict(tuning["tuning"], cached=tuning["cached"])
     if not args.no_batched and args.batched_queries > 0:
         line["batched"] = batched_block(L, ck, ctx, args.batched_queries, min(args.plain_sample,
                                                                             args.batched_queries))

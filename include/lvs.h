@@ -335,16 +335,37 @@ int lvs_server_stats(const lvs_server* srv, uint64_t* steps, uint64_t* bootstrap
 
 /* ------------------------------------------------------------ measurement */
 
+#define LVS_KERNEL_BLIND_ROTATE 0            /* both forms together */
+#define LVS_KERNEL_KEYSWITCH 1
+#define LVS_KERNEL_GRAPH 2                   /* a graph-captured plan, whole */
+#define LVS_KERNEL_BLIND_ROTATE_LATENCY 3    /* one workgroup per CU */
+#define LVS_KERNEL_BLIND_ROTATE_THROUGHPUT 4 /* two workgroups per CU */
+
 /* Kernel timing for measurement: while enabled, every launch of the blind
- * rotation (kernel 0), of the key switch (kernel 1) and of a plan's graph
- * (kernel 2) is bracketed by HIP events on the context's stream.  Enabling (or disabling) waits for the
- * stream and clears earlier records. */
+ * rotation, of the key switch and of a plan's graph is bracketed by HIP
+ * events on the context's stream (ids above).  Enabling (or disabling) waits
+ * for the stream and clears earlier records. */
 int lvs_profile_enable(lvs_context* ctx, int enable);
 
 /* Sum of the recorded launch durations of `kernel` (milliseconds), the
  * number of launches and the bootstraps they processed.  Waits for the
  * recorded events. */
 int lvs_profile_read(lvs_context* ctx, int kernel, double* total_ms, uint64_t* launches, uint64_t* units);
+
+/* Microbenchmarks of the two ceilings the blind rotation is measured
+ * against.  lvs_microbench_modmul runs the forward-butterfly instruction
+ * sequence (Shoup product by a twiddle: three 32-bit multiplies and three
+ * adds) on 16 independent register chains per thread in eight resident waves
+ * per SIMD on every CU, `iters` rounds, and returns the duration (ms) and the number of
+ * 32-bit multiplies executed.  d_work (>= lvs_microbench_workspace_bytes(),
+ * device) receives per-thread checksums.  lvs_microbench_copy copies `bytes`
+ * (a multiple of 16, device buffers, 16-byte aligned) `reps` times with
+ * 16-byte vector loads and stores and returns the mean ms per copy.
+ * Synchronous; use the context's stream.  Errors: LVS_E_INVAL, LVS_E_DEVICE. */
+size_t lvs_microbench_workspace_bytes(const lvs_context* ctx);
+int lvs_microbench_modmul(lvs_context* ctx, int iters, void* d_work, size_t work_bytes, double* ms,
+                          double* int_muls);
+int lvs_microbench_copy(lvs_context* ctx, const void* d_src, void* d_dst, size_t bytes, int reps, double* ms);
 
 /* Releases a handle created by the library (keys, contexts, plans, servers). */
 void lvs_free(void* handle);

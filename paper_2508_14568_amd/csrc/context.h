@@ -48,6 +48,14 @@ inline hipEvent_t take_event(Context* C) {
     return e;
 }
 
+// Profile ids (lvs_profile_read): 0 sums the two blind-rotation forms, which
+// are recorded as 3 (one workgroup per CU) and 4 (two per CU).
+constexpr int kProfBlindRotate = 0, kProfKeySwitch = 1, kProfGraph = 2, kProfBrLatency = 3, kProfBrThroughput = 4;
+
+inline int br_profile_id(const Context* C, int B) {
+    return B <= C->latency_form_max ? kProfBrLatency : kProfBrThroughput;
+}
+
 // Brackets one launch with events when profiling is on.
 struct TimedLaunch {
     Context* C;

@@ -512,9 +512,64 @@ __global__ void __launch_bounds__(256) trivial_kernel(uint64_t* out, uint32_t mu
     out[size_t(r) * kCtWords + w] = (w == kN) ? (uint64_t(mu) << kDeltaLog) : 0;
 }
 
+// ---------------------------------------------------------- microbenchmarks
+
+constexpr int kProbeChains = 16;
+
+// The forward butterfly's instruction sequence on kProbeChains independent
+// register pairs (the values wrap; only the instruction mix matters).
+__global__ void __launch_bounds__(256) modmul_probe_kernel(uint32_t* out, uint32_t w, uint32_t ws, uint32_t p,
+                                                           int iters) {
+    const uint32_t g = blockIdx.x * 256 + threadIdx.x;
+    uint32_t x[kProbeChains], y[kProbeChains];
+#pragma unroll
+    for (int k = 0; k < kProbeChains; ++k) {
+        x[k] = g * 2654435761u + k;
+        y[k] = g ^ (k * 40503u);
+    }
+    const uint32_t two_p = 2 * p;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int k = 0; k < kProbeChains; ++k) {
+            const uint32_t s = __umulhi(y[k], ws) * p - y[k] * w;
+            const uint32_t a = x[k];
+            x[k] = a - s;
+            y[k] = a + two_p + s;
+        }
+    }
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kProbeChains; ++k) c ^= x[k] + y[k];
+    out[g] = c;
+}
+
+__global__ void __launch_bounds__(256) copy_probe_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                         size_t n) {
+    for (size_t i = blockIdx.x * size_t(256) + threadIdx.x; i < n; i += size_t(gridDim.x) * 256) dst[i] = src[i];
+}
+
 }  // namespace dev
 
 // ------------------------------------------------------------- launchers
+
+hipError_t launch_modmul_probe(uint32_t* out, int blocks, int iters, hipStream_t st) {
+    const PrimeTables& T = prime_tables();
+    const uint32_t p = T.p[0], w = T.fwd[5];
+    const uint32_t ws = T.fwd_shoup[5];
+    hipLaunchKernelGGL(dev::modmul_probe_kernel, dim3(blocks), dim3(256), 0, st, out, w, ws, p, iters);
+    return hipGetLastError();
+}
+
+int modmul_probe_muls_per_thread_iter() { return 3 * dev::kProbeChains; }
+
+hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int cus, hipStream_t st) {
+    const size_t n = bytes / 16;
+    if (!n) return hipSuccess;
+    const int blocks = int(std::min<size_t>((n + 255) / 256, size_t(cus) * 16));
+    hipLaunchKernelGGL(dev::copy_probe_kernel, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const uint4*>(src),
+                       reinterpret_cast<uint4*>(dst), n);
+    return hipGetLastError();
+}
 
 namespace {
 dev::CrtConsts make_crt() {

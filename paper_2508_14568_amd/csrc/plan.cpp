@@ -262,12 +262,12 @@ hipError_t launch_steps(Context* C, const Plan& P, hipStream_t st, bool timed) {
         if (!s.count) continue;
         const int B = int(s.count);
         {
-            TimedLaunch t(C, timed ? 1 : -1, uint64_t(B));
+            TimedLaunch t(C, timed ? kProfKeySwitch : -1, uint64_t(B));
             hipError_t e = launch_keyswitch_jobs(P.d_jobs + s.off, B, C->ksk, P.d_part, st);
             if (e != hipSuccess) return e;
         }
         {
-            TimedLaunch t(C, timed ? 0 : -1, uint64_t(B));
+            TimedLaunch t(C, timed ? br_profile_id(C, B) : -1, uint64_t(B));
             hipError_t e = launch_blind_rotate_jobs(P.d_jobs + s.off, B, P.d_part, C->luts, C->bsk, C->tables,
                                                     C->br_grid, C->latency_form_max, st);
             if (e != hipSuccess) return e;
@@ -279,7 +279,7 @@ hipError_t launch_steps(Context* C, const Plan& P, hipStream_t st, bool timed) {
 
 hipError_t run_plan(Context* C, const Plan& P) {
     if (P.graph) {
-        TimedLaunch t(C, 2, uint64_t(P.pbs()));
+        TimedLaunch t(C, kProfGraph, uint64_t(P.pbs()));
         return hipGraphLaunch(P.graph, C->stream);
     }
     return launch_steps(C, P, C->stream, true);

@@ -358,11 +358,11 @@ int lvs_server_step(lvs_server* srv, size_t* active, size_t* queued, size_t* ste
                                        C->stream));
             }
             {
-                TimedLaunch t(C, 1, uint64_t(B));
+                TimedLaunch t(C, kProfKeySwitch, uint64_t(B));
                 SRV_HIP(launch_keyswitch_jobs(S->d_jobs, B, C->ksk, S->d_part, C->stream));
             }
             {
-                TimedLaunch t(C, 0, uint64_t(B));
+                TimedLaunch t(C, br_profile_id(C, B), uint64_t(B));
                 SRV_HIP(launch_blind_rotate_jobs(S->d_jobs, B, S->d_part, C->luts, C->bsk, C->tables, C->br_grid,
                                                  C->latency_form_max, C->stream));
             }

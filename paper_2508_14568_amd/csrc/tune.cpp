@@ -165,4 +165,60 @@ int lvs_autotune(lvs_context* ctx, size_t max_batch, void* d_work, size_t work_b
     return LVS_OK;
 }
 
+size_t lvs_microbench_workspace_bytes(const lvs_context* ctx) {
+    Context* C = ctx_of(const_cast<lvs_context*>(ctx));
+    return C ? sizeof(uint32_t) * 256 * size_t(8 * std::max(1, C->cus)) : 0;
+}
+
+int lvs_microbench_modmul(lvs_context* ctx, int iters, void* d_work, size_t work_bytes, double* ms,
+                          double* int_muls) {
+    Context* C = ctx_of(ctx);
+    if (!C || !d_work || !ms || !int_muls || iters <= 0) TUNE_FAIL(LVS_E_INVAL, "lvs_microbench_modmul: bad argument");
+    if (work_bytes < lvs_microbench_workspace_bytes(ctx))
+        TUNE_FAIL(LVS_E_INVAL, "lvs_microbench_modmul: workspace too small");
+    TUNE_HIP(hipSetDevice(C->device));
+    const int blocks = 8 * std::max(1, C->cus);   // 8 workgroups of 4 waves per CU: 8 waves per SIMD
+    uint32_t* out = reinterpret_cast<uint32_t*>(d_work);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    TUNE_HIP(hipEventCreate(&e0));
+    hipError_t err = hipEventCreate(&e1);
+    if (err == hipSuccess) err = launch_modmul_probe(out, blocks, std::min(iters, 64), C->stream);   // warm-up
+    if (err == hipSuccess) err = hipEventRecord(e0, C->stream);
+    if (err == hipSuccess) err = launch_modmul_probe(out, blocks, iters, C->stream);
+    if (err == hipSuccess) err = hipEventRecord(e1, C->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float t = 0;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+    hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (err != hipSuccess) TUNE_FAIL(LVS_E_DEVICE, std::string("lvs_microbench_modmul: ") + hipGetErrorString(err));
+    *ms = t;
+    *int_muls = double(blocks) * 256.0 * double(iters) * modmul_probe_muls_per_thread_iter();
+    return LVS_OK;
+}
+
+int lvs_microbench_copy(lvs_context* ctx, const void* d_src, void* d_dst, size_t bytes, int reps, double* ms) {
+    Context* C = ctx_of(ctx);
+    if (!C || !d_src || !d_dst || !ms || reps <= 0 || bytes % 16 ||
+        reinterpret_cast<uintptr_t>(d_src) % 16 || reinterpret_cast<uintptr_t>(d_dst) % 16)
+        TUNE_FAIL(LVS_E_INVAL, "lvs_microbench_copy: bad argument");
+    TUNE_HIP(hipSetDevice(C->device));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    TUNE_HIP(hipEventCreate(&e0));
+    hipError_t err = hipEventCreate(&e1);
+    if (err == hipSuccess) err = launch_copy_probe(d_src, d_dst, bytes, std::max(1, C->cus), C->stream);
+    if (err == hipSuccess) err = hipEventRecord(e0, C->stream);
+    for (int r = 0; r < reps && err == hipSuccess; ++r)
+        err = launch_copy_probe(d_src, d_dst, bytes, std::max(1, C->cus), C->stream);
+    if (err == hipSuccess) err = hipEventRecord(e1, C->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float t = 0;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+    hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (err != hipSuccess) TUNE_FAIL(LVS_E_DEVICE, std::string("lvs_microbench_copy: ") + hipGetErrorString(err));
+    *ms = double(t) / reps;
+    return LVS_OK;
+}
+
 }  // extern "C"

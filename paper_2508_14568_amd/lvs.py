@@ -82,6 +82,10 @@ _SIGS = {
     "lvs_context_set_tuning": (I32, [VP, VP]),
     "lvs_autotune_workspace_bytes": (SZ, [SZ]),
     "lvs_autotune": (I32, [VP, SZ, VP, SZ, VP, VP, SZ, ctypes.POINTER(SZ)]),
+    "lvs_microbench_workspace_bytes": (SZ, [VP]),
+    "lvs_microbench_modmul": (I32, [VP, I32, VP, SZ, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]),
+    "lvs_microbench_copy": (I32, [VP, VP, VP, SZ, I32, ctypes.POINTER(ctypes.c_double)]),
     "lvs_profile_enable": (I32, [VP, I32]),
     "lvs_profile_read": (I32, [VP, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(U64), ctypes.POINTER(U64)]),
     "lvs_free": (None, [VP]),
@@ -566,9 +570,27 @@ def autotune(ctx: Context, max_batch: int = None, cache: str = None) -> dict:
 
 # ------------------------------------------------------------ measurement
 
-KERNEL_BLIND_ROTATE = 0
+KERNEL_BLIND_ROTATE = 0              # both forms
 KERNEL_KEYSWITCH = 1
 KERNEL_GRAPH = 2
+KERNEL_BLIND_ROTATE_LATENCY = 3      # one workgroup per CU
+KERNEL_BLIND_ROTATE_THROUGHPUT = 4   # two workgroups per CU
+
+
+def lvs_microbench_modmul(ctx: Context, iters: int = 4096):
+    """(ms, 32-bit multiplies) of the butterfly instruction-mix probe."""
+    work = device_buffer(lib().lvs_microbench_workspace_bytes(ctx), ctx.device)
+    ms, muls = ctypes.c_double(), ctypes.c_double()
+    _check(lib().lvs_microbench_modmul(ctx, iters, _dptr(work), work.numel() * work.element_size(),
+                                       ctypes.byref(ms), ctypes.byref(muls)))
+    return ms.value, muls.value
+
+
+def lvs_microbench_copy(ctx: Context, d_src, d_dst, nbytes: int, reps: int = 5) -> float:
+    """Mean ms of one nbytes vector copy."""
+    ms = ctypes.c_double()
+    _check(lib().lvs_microbench_copy(ctx, _dptr(d_src), _dptr(d_dst), nbytes, reps, ctypes.byref(ms)))
+    return ms.value
 
 
 def lvs_profile_enable(ctx: Context, enable: bool):
