@@ -16,6 +16,9 @@ of the schoolbook TFHE oracle (``tfhe.py``):
     S; the main loop then reads eq9[i,j] = T[b_j][i] with no bootstrap.
   * Section 6.2 (parallelism over cells): cells on one anti-diagonal are
     independent; ``dp(..., order="diagonal")`` evaluates them as one batch.
+  * Section 3.4 / Algorithm 1 band: only cells with |i - j| <= ell are
+    bootstrapped (and only their equality pairs); the result is the sum of
+    the differences along the diagonal path (``dp_band``).
 """
 import numpy as np
 
@@ -150,6 +153,76 @@ def edit_distance_clear(keys: T.Keys, table: np.ndarray, alphabet, b, encoding: 
     if m == 0 or n == 0:
         return np.tile(T.trivial(1, keys.N), (n, 1))
     return dp(keys, m, n, lambda i, j: table[cols[j - 1], i - 1], order, nthreads, record)
+
+
+def dp_band(keys: T.Keys, m: int, n: int, eq9_at, ell: int, nthreads=None, record: bool = False):
+    """Algorithm 1 restricted to the band |i - j| <= ell (Section 3.4), cells
+    of one anti-diagonal as one batch; neighbours outside the band keep the
+    OneMatrix value (a noise-free 1).  Returns the m + n ciphertexts of the
+    band path (plaintext.band_path; v[1,0] is the noise-free boundary 1) and,
+    when record is set, every computed (v, h) pair."""
+    N = keys.N
+    polys = lut_polys(N)
+    one = T.trivial(1, N)
+    four = T.trivial(4, N)
+    v = {}
+    h = {}
+
+    def v_at(i, j):
+        return v.get((i, j), one)
+
+    def h_at(i, j):
+        return h.get((i, j), one)
+
+    for s in range(2, m + n + 1):
+        cells = [(i, s - i) for i in range(max(1, s - n), min(m, s - 1) + 1) if P.band_contains(i, s - i, ell)]
+        if not cells:
+            continue
+        keys_b = np.stack([(four - v_at(i, j - 1) + T.scale(h_at(i - 1, j), 3) + eq9_at(i, j)).astype(T.U64)
+                           for i, j in cells])
+        Ms = keys.pbs_batch(keys_b, polys, LUT_IDS["min"], nthreads)
+        for (i, j), M in zip(cells, Ms):
+            v[(i, j)] = (M - h_at(i - 1, j)).astype(T.U64)
+            h[(i, j)] = (M - v_at(i, j - 1)).astype(T.U64)
+    path = np.stack([(v_at(i, j) if kind == "v" else h_at(i, j)) for kind, i, j in P.band_path(m, n)]) \
+        if m + n else np.zeros((0, N + 1), dtype=T.U64)
+    return (path, {"v": v, "h": h}) if record else path
+
+
+def edit_distance_band(keys: T.Keys, A: np.ndarray, B: np.ndarray, encoding: int, ell: int, nthreads=None,
+                       record=False):
+    """Equality for the pairs inside the band only, then the banded loop;
+    returns the band path (and records)."""
+    m, n, W = A.shape[0], B.shape[0], keys.N + 1
+    cells = [(i, j) for i in range(1, m + 1) for j in range(1, n + 1) if P.band_contains(i, j, ell)]
+    eq9 = {}
+    if cells:
+        Ai = np.stack([A[i - 1] for i, _ in cells])
+        Bj = np.stack([B[j - 1] for _, j in cells])
+        # equality() over aligned pairs: a (k x 1) grid per cell, batched
+        if encoding == ENC_DNA2:
+            z = (Ai[:, 0, :] - Bj[:, 0, :]).astype(T.U64)
+            e9 = _pbs(keys, z, "eq9", nthreads)
+        else:
+            z1 = (Ai[:, 0, :] - Bj[:, 0, :]).astype(T.U64)
+            e1 = _pbs(keys, z1, "eq", nthreads)
+            z2 = (T.scale(Ai[:, 1, :], 2) - T.scale(Bj[:, 1, :], 2) + T.trivial(1, keys.N)[None, :] - e1)
+            e9 = _pbs(keys, z2.astype(T.U64), "eq9", nthreads)
+        eq9 = {c: e9[k] for k, c in enumerate(cells)}
+    return dp_band(keys, m, n, lambda i, j: eq9[(i, j)], ell, nthreads, record)
+
+
+def edit_distance_clear_band(keys: T.Keys, table: np.ndarray, alphabet, b, ell: int, nthreads=None, record=False):
+    """Banded loop with eq9[i,j] = T[b_j][i] from the preprocessing table."""
+    m, n = table.shape[1], len(b)
+    index = {c: k for k, c in enumerate(alphabet)}
+    cols = [index[c] for c in b]
+    return dp_band(keys, m, n, lambda i, j: table[cols[j - 1], i - 1], ell, nthreads, record)
+
+
+def decrypt_path(keys: T.Keys, path: np.ndarray) -> int:
+    """Sum of the decrypted differences of a band path."""
+    return int(sum(keys.decrypt_signed(ct) for ct in path))
 
 
 def decrypt_distance(keys: T.Keys, m: int, h_last: np.ndarray) -> int:

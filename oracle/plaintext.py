@@ -11,6 +11,8 @@ The cleartext definitions that the encrypted method must reproduce exactly
     (1-dv) + 3(1+dh) + 9eq of Eq. (eq_keyeq2) that Algorithms 1 and 4 use.
   * Equality tables LUT_eq and LUT_eq9, Eqs. (eq_eqlut) and (eq_eqlut9).
   * The 7-bit character split into a 4-bit and a 3-bit symbol (Section 4.3).
+  * Skipping irrelevant cells (Section 3.4, Algorithm 1's band |i - j| <= ell)
+    with the result summed along the diagonal.
 """
 import itertools
 
@@ -73,6 +75,62 @@ def delta_dp(a, b):
             v[i, j] = M[i, j] - h[i - 1, j]
             h[i, j] = M[i, j] - v[i, j - 1]
     return v, h, M
+
+
+def band_contains(i: int, j: int, ell: int) -> bool:
+    """Algorithm 1 computes cell (i, j) only when |i - j| <= ell (Section 3.4,
+    skipping irrelevant cells; Algorithm 4 prints '<', Algorithm 1 and the
+    cell count of Eq. (eq_skip) use '<=')."""
+    return abs(i - j) <= ell
+
+
+def band_cell_count_formula(m: int, ell: int) -> int:
+    """Eq. (eq_skip), m = n and ell < m: m (2 ell + 1) - ell^2 - ell."""
+    return m * (2 * ell + 1) - ell * ell - ell
+
+
+def exact_band(m: int, n: int) -> int:
+    """Band half-width whose result is the exact distance.  Section 3.4 gives
+    ceil(max(m, n) / 2) for m = n; for m != n the band must also reach the
+    corner (m, n), and max(m, n) - floor(min(m, n) / 2) covers every cell of
+    an optimal path (equal to ceil(m / 2) when m = n)."""
+    return max(m, n) - min(m, n) // 2
+
+
+def delta_dp_band(a, b, ell: int):
+    """Algorithm 1's loop (j outer, i inner) over the cells with |i - j| <= ell;
+    the differences of cells never computed keep the OneMatrix value 1.
+    Returns (v, h) as (m+1) x (n+1) integer arrays."""
+    m, n = len(a), len(b)
+    v = np.ones((m + 1, n + 1), dtype=np.int64)
+    h = np.ones((m + 1, n + 1), dtype=np.int64)
+    for j in range(1, n + 1):
+        for i in range(1, m + 1):
+            if band_contains(i, j, ell):
+                eq = 1 if a[i - 1] == b[j - 1] else 0
+                M = cell_M(eq, v[i, j - 1], h[i - 1, j])
+                v[i, j], h[i, j] = M - h[i - 1, j], M - v[i, j - 1]
+    return v, h
+
+
+def band_path(m: int, n: int):
+    """The differences whose sum is the banded result (Section 3.4: the
+    final row is no longer available, so the score is summed along the
+    diagonal): D[k,k] - D[k-1,k-1] = v[k,k-1] + h[k,k] for k = 1..min(m, n),
+    then the rest of the last row (h[m,j], j > m) or column (v[i,n], i > n).
+    Entries are ('v' | 'h', i, j); there are m + n of them."""
+    out = []
+    for k in range(1, min(m, n) + 1):
+        out += [("v", k, k - 1), ("h", k, k)]
+    out += [("h", m, j) for j in range(m + 1, n + 1)]
+    out += [("v", i, n) for i in range(n + 1, m + 1)]
+    return out
+
+
+def band_distance(a, b, ell: int) -> int:
+    """Sum of the band path's differences after the banded loop."""
+    v, h = delta_dp_band(a, b, ell)
+    return int(sum((v if kind == "v" else h)[i, j] for kind, i, j in band_path(len(a), len(b))))
 
 
 def distance_from_last_row(m: int, h_last) -> int:

@@ -117,3 +117,40 @@ def test_small_dna_full_parameters(oracle_keys):
     _, _, M = P.delta_dp(a, b)
     for (i, j), ct in rec["M"].items():
         assert k.decrypt_signed(ct) == M[i, j]
+
+
+def test_band_encrypted_matches_plaintext(oracle_toy_keys):
+    """Algorithm 1's band (Section 3.4) on encrypted DNA: every computed
+    difference decrypts to the plaintext banded loop's value, cells outside
+    the band are never bootstrapped, and the path decrypts to the banded
+    distance (exact band: the Wagner-Fischer distance)."""
+    k = oracle_toy_keys
+    a, b = "ACGTTGCA", "CGTTAGCAT"
+    A = L.encrypt_string(k, a.encode(), L.ENC_DNA2, 11)
+    B = L.encrypt_string(k, b.encode(), L.ENC_DNA2, 12)
+    for ell in (1, 3, P.exact_band(len(a), len(b))):
+        path, rec = L.edit_distance_band(k, A, B, L.ENC_DNA2, ell, record=True)
+        v, h = P.delta_dp_band(a, b, ell)
+        assert set(rec["v"]) == {(i, j) for i in range(1, 9) for j in range(1, 10) if abs(i - j) <= ell}
+        for (i, j), ct in rec["v"].items():
+            assert k.decrypt_signed(ct) == v[i, j]
+            assert k.decrypt_signed(rec["h"][(i, j)]) == h[i, j]
+        assert len(path) == len(a) + len(b)
+        assert L.decrypt_path(k, path) == P.band_distance(a, b, ell)
+    assert L.decrypt_path(k, path) == P.edit_distance(a, b)
+
+
+def test_band_cleartext_equals_encrypted(oracle_toy_keys):
+    """The Section 5 table read by the banded loop gives the same path
+    ciphertexts' values as the both-encrypted banded loop (ASCII)."""
+    k = oracle_toy_keys
+    a, b = b"kitten", b"sitting"
+    A = L.encrypt_string(k, a, L.ENC_ASCII7, 13)
+    alphabet = bytes(sorted(set(b)))
+    table = L.preprocess(k, A, alphabet, L.ENC_ASCII7)
+    ell = P.exact_band(len(a), len(b))
+    path = L.edit_distance_clear_band(k, table, alphabet, b, ell)
+    assert L.decrypt_path(k, path) == P.edit_distance(a, b) == 3
+    B = L.encrypt_string(k, b, L.ENC_ASCII7, 14)
+    path2 = L.edit_distance_band(k, A, B, L.ENC_ASCII7, 1)
+    assert L.decrypt_path(k, path2) == P.band_distance(a, b, 1)

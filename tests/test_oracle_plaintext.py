@@ -148,3 +148,69 @@ def test_key_range_fits_lookup():
 def test_counts_fixture_consistency():
     g = golden("counts.json")
     assert g["exact_total_per_cell_ascii"] == g["equality_pbs_ascii"] + g["pbs_per_cell"]
+
+
+# ---------------------------------------------------------------- band modes
+
+def _random_pairs(seed, count, max_len, alphabets=("ab", "abcd", "ACGT")):
+    rng = np.random.default_rng(seed)
+    for t in range(count):
+        alpha = alphabets[t % len(alphabets)]
+        m, n = (int(x) for x in rng.integers(0, max_len + 1, size=2))
+        a = "".join(alpha[k] for k in rng.integers(0, len(alpha), size=m))
+        b = "".join(alpha[k] for k in rng.integers(0, len(alpha), size=n))
+        yield a, b
+
+
+def test_band_cell_count_eq_skip():
+    """Eq. (eq_skip): cells with |i - j| <= ell of an m x m matrix, by brute
+    force, for every ell < m up to m = 40."""
+    for m in range(1, 41):
+        for ell in range(0, m):
+            count = sum(1 for i in range(1, m + 1) for j in range(1, m + 1) if P.band_contains(i, j, ell))
+            assert count == P.band_cell_count_formula(m, ell), (m, ell)
+
+
+def test_band_path_sums_wf_differences():
+    """The diagonal path of Section 3.4 telescopes: the WF matrix's own
+    differences along it sum to D[m, n] (independent of the banded loop)."""
+    for a, b in _random_pairs(21, 300, 12):
+        D = P.wagner_fischer(a, b)
+        dv, dh = P.deltas_from_matrix(D)
+        path = P.band_path(len(a), len(b))
+        assert len(path) == len(a) + len(b)
+        assert sum((dv if k == "v" else dh)[i, j] for k, i, j in path) == D[len(a), len(b)]
+
+
+def test_exact_band_equals_wf():
+    """Section 3.4: with ell = ceil(max(m, n) / 2) (m = n) the banded result is
+    the exact distance; for m != n with ell = max(m, n) - floor(min / 2)."""
+    for a, b in _random_pairs(22, 1500, 14):
+        assert P.band_distance(a, b, P.exact_band(len(a), len(b))) == P.edit_distance(a, b), (a, b)
+    assert P.exact_band(8, 8) == 4 and P.exact_band(7, 7) == 4 and P.exact_band(1, 5) == 5
+
+
+def test_approximate_band_bounds():
+    """m = n: the band of half-width w never returns less than the distance,
+    and returns it exactly whenever D <= 2w + 1 (an optimal path with cost D
+    stays within floor(D / 2) of the diagonal, Section 3.4)."""
+    seen_over = 0
+    for a, b in _random_pairs(23, 1500, 12):
+        if len(a) != len(b):
+            continue
+        D = P.edit_distance(a, b)
+        for w in range(0, len(a) + 1):
+            r = P.band_distance(a, b, w)
+            assert r >= D, (a, b, w)
+            if D <= 2 * w + 1:
+                assert r == D, (a, b, w)
+            seen_over += r > D
+    assert seen_over > 0        # the bound is not vacuous: small bands do overestimate
+
+
+def test_full_band_equals_delta_dp():
+    """A band covering the whole matrix computes every cell of Algorithm 1."""
+    for a, b in _random_pairs(24, 200, 9):
+        v, h = P.delta_dp_band(a, b, max(len(a), len(b)))
+        v2, h2, _ = P.delta_dp(a, b)
+        assert (v == v2).all() and (h == h2).all()
