@@ -214,6 +214,58 @@ def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos):
     return res
 
 
+def band_block(L, ck, ctx, nq, approx_ell):
+    """Section 3.4's skipping on the batched workload's first nq pairs: the
+    exact band (max(m, n) - floor(min(m, n) / 2), the whole matrix when the
+    lengths are far apart) and a fixed half-width, each as one graph plan,
+    against the full-matrix plan of the same queries."""
+    import torch
+    import workloads as W
+    pairs = W.batched()[:nq]
+    dev = ctx.device
+    enc = [(L.to_device(L.lvs_encrypt_string(ck, a, L.LVS_ENC_ASCII7, 50000 + 2 * k), dev),
+            L.to_device(L.lvs_encrypt_string(ck, b, L.LVS_ENC_ASCII7, 50001 + 2 * k), dev))
+           for k, (a, b) in enumerate(pairs)]
+    res = {"workload": f"batched_ascii first {nq} of 256 pairs, lengths 8..64", "queries": nq}
+    for name, ell_of in (("full", None), ("exact_band", lambda m, n: L.lvs_band_exact(m, n)),
+                         (f"band_{approx_ell}", lambda m, n: approx_ell)):
+        items = []
+        for (a, b), (dA, dB) in zip(pairs, enc):
+            it = {"d_a": dA, "m": len(a), "d_b": dB, "n": len(b)}
+            if ell_of is None:
+                it["d_h_last"] = torch.zeros(len(b) * L.CT_WORDS, dtype=torch.int64, device=dev)
+            else:
+                it["ell"] = ell_of(len(a), len(b))
+                it["d_path"] = torch.zeros((len(a) + len(b)) * L.CT_WORDS, dtype=torch.int64, device=dev)
+            items.append(it)
+        note(f"band: {name} plan")
+        plan = L.lvs_plan_create(ctx, items, L.LVS_ENC_ASCII7, graph=True)
+        steps, pbs, _ = L.lvs_plan_info(plan)
+        L.lvs_plan_run(plan)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.lvs_plan_run(plan)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        exact = over = 0
+        for (a, b), it in zip(pairs, items):
+            if ell_of is None:
+                d = L.lvs_decrypt_distance(ck, L.to_host(it["d_h_last"]).reshape(len(b), L.CT_WORDS), len(a))
+            else:
+                d = L.lvs_decrypt_distance(ck, L.to_host(it["d_path"]).reshape(-1, L.CT_WORDS), 0)
+            wf = levenshtein(a, b)
+            if d < wf or (name != f"band_{approx_ell}" and d != wf):
+                raise SystemExit(f"band: wrong distance ({name})")
+            exact += d == wf
+            over += d > wf
+        res[name] = {"pbs": pbs, "steps": steps, "seconds": round(dt, 3), "pbs_per_s": round(pbs / dt, 1),
+                     "queries_per_s": round(nq / dt, 3), "exact_results": exact, "overestimates": over}
+        del plan
+    res["exact_band_pbs_saving"] = round(1 - res["exact_band"]["pbs"] / res["full"]["pbs"], 4)
+    res["exact_band_speedup"] = round(res["full"]["seconds"] / res["exact_band"]["seconds"], 3)
+    return res
+
+
 def microbench(L, ctx):
     """Measured ceilings: the butterfly instruction mix from registers on
     every CU, and a 1 GiB device copy."""
@@ -242,6 +294,9 @@ def main():
     ap.add_argument("--poisson-queries", type=int, default=40, help="queries per load factor")
     ap.add_argument("--rho", type=str, default="0.8", help="comma-separated load factors")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--band-queries", type=int, default=32)
+    ap.add_argument("--band-ell", type=int, default=4, help="half-width of the approximate band")
+    ap.add_argument("--no-band", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--no-microbench", action="store_true")
     args = ap.parse_args()
@@ -339,6 +394,8 @@ def main():
     if not args.no_batched and args.batched_queries > 0:
         line["batched"] = batched_block(L, ck, ctx, args.batched_queries, min(args.plain_sample,
                                                                             args.batched_queries))
+    if not args.no_band and args.band_queries > 0:
+        line["band"] = band_block(L, ck, ctx, args.band_queries, args.band_ell)
     if not args.no_serving and args.serving_names > 0:
         line["serving"] = serving_block(L, ck, ctx, args.serving_names, args.serving_queries,
                                         args.poisson_queries, [float(x) for x in args.rho.split(",") if x])

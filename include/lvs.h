@@ -242,13 +242,55 @@ int lvs_edit_distance_clear(lvs_context* ctx, const uint64_t* d_table, size_t m,
                             size_t alen, const uint8_t* b, size_t n, uint64_t* d_h_last, void* d_work,
                             size_t work_bytes);
 
+/* ------------------------------------------------------------ band modes */
+
+/* Skipping irrelevant cells (Section 3.4, Algorithm 1): only the cells with
+ * |i - j| <= ell are bootstrapped (and, with both strings encrypted, only
+ * their character pairs get equality bootstraps); a neighbour outside the
+ * band reads as the noise-free 1 of Algorithm 1's set-up.  The last row is
+ * then incomplete, so the result is the diagonal path of differences
+ * d_path ([m+n][N+1]): v[k,k-1], h[k,k] for k = 1..min(m, n) (v[1,0] is the
+ * noise-free boundary 1), then h[m, j] for j = m+1..n or v[i, n] for
+ * i = n+1..m.  The distance is the sum of their decryptions,
+ * lvs_decrypt_distance(ck, path, 0, m + n, &d).
+ *
+ * With ell >= lvs_band_exact(m, n) the result is the exact distance
+ * (ceil(m / 2) for m = n, Section 3.4; for m != n the band has to reach the
+ * corner: max(m, n) - floor(min(m, n) / 2)).  For m = n, a smaller ell gives
+ * a value never below the distance and equal to it whenever the distance is
+ * at most 2 ell + 1 (approximate mode).  ell past m + n is clamped. */
+size_t lvs_band_exact(size_t m, size_t n);
+
+/* Cells with |i - j| <= ell (m (2 ell + 1) - ell^2 - ell for m = n, ell < m;
+ * Eq. eq_skip). */
+size_t lvs_band_cells(size_t m, size_t n, size_t ell);
+
+size_t lvs_edit_distance_band_workspace_bytes(size_t m, size_t n, int encoding, size_t ell);
+
+/* Algorithm 4's pipeline (equality, then the wavefront) restricted to the
+ * band.  Buffers as lvs_edit_distance; d_path receives m + n ciphertexts.
+ * Errors as lvs_edit_distance. */
+int lvs_edit_distance_band(lvs_context* ctx, const uint64_t* d_a, size_t m, const uint64_t* d_b, size_t n,
+                           int encoding, size_t ell, uint64_t* d_path, void* d_work, size_t work_bytes);
+
+size_t lvs_edit_distance_clear_band_workspace_bytes(size_t m, size_t n, size_t ell);
+
+/* The cleartext-string variant (Section 5 table, no bootstrap for equality)
+ * restricted to the band.  Arguments as lvs_edit_distance_clear. */
+int lvs_edit_distance_clear_band(lvs_context* ctx, const uint64_t* d_table, size_t m, const uint8_t* alphabet,
+                                 size_t alen, const uint8_t* b, size_t n, size_t ell, uint64_t* d_path, void* d_work,
+                                 size_t work_bytes);
+
 /* ------------------------------------------------------------ batch plans */
 
 /* One edit distance of a batch.  Both strings encrypted: d_a ([m][nsym][N+1])
  * and d_b ([n][nsym][N+1]).  One cleartext string (Section 5): d_b = NULL,
  * d_table = lvs_preprocess output of a over `alphabet` (host, alen symbols),
  * b_clear = the cleartext string (host, n symbols).  d_h_last receives
- * h[m, 1..n] ([n][N+1]). */
+ * h[m, 1..n] ([n][N+1]).  banded != 0 restricts the query to the band
+ * |i - j| <= ell (see lvs_edit_distance_band); its result goes to d_path
+ * ([m+n][N+1]) and d_h_last is not used.  A zero-initialised query is the
+ * full matrix. */
 typedef struct {
     const uint64_t* d_a;
     size_t m;
@@ -259,6 +301,9 @@ typedef struct {
     size_t alen;
     const uint8_t* b_clear;
     uint64_t* d_h_last;
+    int32_t banded;
+    size_t ell;
+    uint64_t* d_path;
 } lvs_query;
 
 typedef struct lvs_plan lvs_plan;

@@ -101,7 +101,7 @@ int execute(Context* C, Plan& P, uint8_t* ws) {
 size_t max_step_of(const std::vector<QuerySpec>& qs) {
     size_t eq = 0, diag = 0;
     for (const auto& q : qs) {
-        if (q.B && !q.eq9_in) eq += q.m * q.n;
+        if (q.B && !q.eq9_in) eq += band_cells(q.m, q.n, q.band);
         diag += std::min(q.m, q.n);
     }
     return std::max(eq, diag);
@@ -471,6 +471,77 @@ int lvs_edit_distance(lvs_context* ctx, const uint64_t* d_a, size_t m, const uin
     return execute(C, P, ws);
 }
 
+size_t lvs_band_exact(size_t m, size_t n) { return std::max(m, n) - std::min(m, n) / 2; }
+
+size_t lvs_band_cells(size_t m, size_t n, size_t ell) { return band_cells(m, n, long(std::min<size_t>(ell, m + n))); }
+
+size_t lvs_edit_distance_band_workspace_bytes(size_t m, size_t n, int encoding, size_t ell) {
+    std::vector<QuerySpec> qs{pair_query(nullptr, m, reinterpret_cast<const uint64_t*>(16), n, encoding, nullptr)};
+    qs[0].band = long(std::min<size_t>(ell, m + n));
+    return plan_ws(qs);
+}
+
+int lvs_edit_distance_band(lvs_context* ctx, const uint64_t* d_a, size_t m, const uint64_t* d_b, size_t n,
+                           int encoding, size_t ell, uint64_t* d_path, void* d_work, size_t work_bytes) {
+    Context* C = as_ctx(ctx);
+    LVS_REQUIRE(C, LVS_E_INVAL, "lvs_edit_distance_band: bad context");
+    LVS_REQUIRE(valid_encoding(encoding), LVS_E_INVAL, "unknown encoding");
+    LVS_REQUIRE((d_a || m == 0) && (d_b || n == 0) && (d_path || m + n == 0), LVS_E_INVAL,
+                "lvs_edit_distance_band: NULL buffer");
+    LVS_REQUIRE(std::min(m, n) <= kMaxLen, LVS_E_NOISE_BUDGET, "lvs_edit_distance_band: strings exceed the noise budget");
+    if (m + n == 0) return LVS_OK;
+    LVS_REQUIRE(d_work && work_bytes >= lvs_edit_distance_band_workspace_bytes(m, n, encoding, ell),
+                LVS_E_NOMEM_DEVICE, "lvs_edit_distance_band: workspace too small");
+    LVS_HIP(hipSetDevice(C->device));
+    std::vector<QuerySpec> qs{pair_query(d_a, m, d_b, n, encoding, nullptr)};
+    qs[0].band = long(std::min<size_t>(ell, m + n));
+    qs[0].path = d_path;
+    uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
+    assign_buffers(qs, ws);
+    Plan P;
+    build_edit_distance_plan(qs, P);
+    return execute(C, P, ws);
+}
+
+size_t lvs_edit_distance_clear_band_workspace_bytes(size_t m, size_t n, size_t ell) {
+    QuerySpec q;
+    q.m = m;
+    q.n = n;
+    q.band = long(std::min<size_t>(ell, m + n));
+    return query_buffer_bytes(q) + plan_bytes(band_cells(m, n, q.band), std::min(m, n));
+}
+
+int lvs_edit_distance_clear_band(lvs_context* ctx, const uint64_t* d_table, size_t m, const uint8_t* alphabet,
+                                 size_t alen, const uint8_t* b, size_t n, size_t ell, uint64_t* d_path, void* d_work,
+                                 size_t work_bytes) {
+    Context* C = as_ctx(ctx);
+    LVS_REQUIRE(C, LVS_E_INVAL, "lvs_edit_distance_clear_band: bad context");
+    LVS_REQUIRE((d_table || m == 0) && (alphabet || alen == 0) && (b || n == 0) && (d_path || m + n == 0),
+                LVS_E_INVAL, "lvs_edit_distance_clear_band: NULL buffer");
+    LVS_REQUIRE(std::min(m, n) <= kMaxLen, LVS_E_NOISE_BUDGET, "lvs_edit_distance_clear_band: noise budget");
+    std::vector<QuerySpec> qs(1);
+    qs[0].cols.resize(n);
+    for (size_t j = 0; j < n; ++j) {
+        const uint8_t* hit = std::find(alphabet, alphabet + alen, b[j]);
+        LVS_REQUIRE(hit != alphabet + alen, LVS_E_ALPHABET, "lvs_edit_distance_clear_band: symbol not in the table");
+        qs[0].cols[j] = int32_t(hit - alphabet);
+    }
+    if (m + n == 0) return LVS_OK;
+    LVS_REQUIRE(d_work && work_bytes >= lvs_edit_distance_clear_band_workspace_bytes(m, n, ell), LVS_E_NOMEM_DEVICE,
+                "lvs_edit_distance_clear_band: workspace too small");
+    LVS_HIP(hipSetDevice(C->device));
+    qs[0].m = m;
+    qs[0].n = n;
+    qs[0].table = d_table;
+    qs[0].band = long(std::min<size_t>(ell, m + n));
+    qs[0].path = d_path;
+    uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
+    assign_buffers(qs, ws);
+    Plan P;
+    build_edit_distance_plan(qs, P);
+    return execute(C, P, ws);
+}
+
 size_t lvs_preprocess_workspace_bytes(size_t m, size_t alphabet_len, int encoding) {
     const size_t cells = m * alphabet_len;
     const bool ascii = encoding == LVS_ENC_ASCII7;
@@ -559,14 +630,22 @@ int make_specs(const lvs_query* q, size_t nq, int encoding, std::vector<QuerySpe
         s.m = x.m;
         s.n = x.n;
         s.A = x.d_a;
-        s.h_last = x.d_h_last;
         LVS_REQUIRE(std::min(x.m, x.n) <= kMaxLen, LVS_E_NOISE_BUDGET, "lvs_plan: strings exceed the noise budget");
+        const bool banded = x.banded != 0;
+        if (banded) {
+            s.band = long(std::min<size_t>(x.ell, x.m + x.n));
+            s.path = x.d_path;
+            LVS_REQUIRE(x.d_path || x.m + x.n == 0, LVS_E_INVAL, "lvs_plan: NULL band path");
+        } else {
+            s.h_last = x.d_h_last;
+            LVS_REQUIRE(x.d_h_last || x.n == 0, LVS_E_INVAL, "lvs_plan: NULL result buffer");
+        }
         if (x.d_b) {
             s.B = x.d_b;
-            LVS_REQUIRE((x.d_a || x.m == 0) && (x.d_h_last || x.n == 0), LVS_E_INVAL, "lvs_plan: NULL buffer");
+            LVS_REQUIRE(x.d_a || x.m == 0, LVS_E_INVAL, "lvs_plan: NULL buffer");
         } else {
-            LVS_REQUIRE((x.d_table || x.m == 0) && (x.b_clear || x.n == 0) && (x.alphabet || x.alen == 0) &&
-                            (x.d_h_last || x.n == 0), LVS_E_INVAL, "lvs_plan: NULL buffer (cleartext query)");
+            LVS_REQUIRE((x.d_table || x.m == 0) && (x.b_clear || x.n == 0) && (x.alphabet || x.alen == 0),
+                        LVS_E_INVAL, "lvs_plan: NULL buffer (cleartext query)");
             s.table = x.d_table;
             s.cols.resize(x.n);
             for (size_t j = 0; j < x.n; ++j) {

@@ -458,9 +458,11 @@ __global__ void __launch_bounds__(kBrThreads, kOcc) blind_rotate_kernel(BrArgs A
             const uint64_t s1 = J.sub[1] ? J.sub[1][t] : 0;
             const uint64_t c0 = (t == kN) ? J.sub_delta[0] : 0;
             const uint64_t c1 = (t == kN) ? J.sub_delta[1] : 0;
-            if (J.dst[0]) J.dst[0][t] = v - s0 - c0;
-            if (J.dst[1]) J.dst[1][t] = v - s1 - c1;
+            const uint64_t o0 = v - s0 - c0, o1 = v - s1 - c1;
+            if (J.dst[0]) J.dst[0][t] = o0;
+            if (J.dst[1]) J.dst[1][t] = o1;
             if (J.dst[2]) J.dst[2][t] = v;
+            if (J.dst[3]) J.dst[3][t] = J.copy_of ? o1 : o0;
         }
         __syncthreads();
     }

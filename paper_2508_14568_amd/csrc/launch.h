@@ -13,16 +13,19 @@ namespace lvs {
 // them; its output M (the sample-extracted result) is written to every
 // non-null dst[k] as M - sub[k] - sub_delta[k] (sub[k] may be null; sub_delta
 // is subtracted from the body only), which applies the difference update of
-// a cell in the same pass.  A thread reads every sub[] word before writing the
-// dst[] words of the same index, so dst and sub may alias.
+// a cell in the same pass; dst[2] receives M itself and dst[3] a second copy
+// of output copy_of (0 or 1), which collects the differences of a band path.
+// A thread reads every sub[] word before writing the dst[] words of the same
+// index, so dst and sub may alias.
 struct Job {
     const uint64_t* src[3];
     int32_t coef[3];
     uint32_t lut;
     uint64_t delta;
-    uint64_t* dst[3];
+    uint64_t* dst[4];
     const uint64_t* sub[2];
     uint64_t sub_delta[2];
+    uint32_t copy_of;
 };
 
 struct DevTables {

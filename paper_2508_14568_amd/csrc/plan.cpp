@@ -6,6 +6,9 @@
 // of anti-diagonal s = i + j depend only on diagonal s - 1 (Section 6.2), so
 // step s holds every query's cells with i + j = s.  The key of a cell and the
 // difference update are folded into the bootstrap's job (see launch.h).
+// With Algorithm 1's band (Section 3.4) only the pairs and cells with
+// |i - j| <= band get bootstraps, neighbours outside it read as Enc(1), and
+// the result is the diagonal path of differences.
 #include "plan.h"
 
 #include <algorithm>
@@ -42,8 +45,20 @@ bool both_encrypted(const QuerySpec& q) { return q.B != nullptr && q.eq9_in == n
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
+size_t band_cells(size_t m, size_t n, long band) {
+    if (band < 0) return m * n;
+    size_t c = 0;
+    for (size_t i = 1; i <= m; ++i) {
+        const size_t lo = i > size_t(band) ? i - size_t(band) : 1;
+        const size_t hi = std::min(n, i + size_t(band));
+        if (hi >= lo) c += hi - lo + 1;
+    }
+    return c;
+}
+
 size_t query_buffer_bytes(const QuerySpec& q) {
     size_t b = align256(sizeof(uint64_t) * (q.m + 1) * W);
+    if (!q.h_last) b += align256(sizeof(uint64_t) * std::max<size_t>(q.n, 1) * W);   // row state
     if (both_encrypted(q)) {
         b += align256(sizeof(uint64_t) * q.m * q.n * W);                     // eq9
         if (q.encoding == LVS_ENC_ASCII7) b += align256(sizeof(uint64_t) * q.m * q.n * W);   // eq1
@@ -52,7 +67,7 @@ size_t query_buffer_bytes(const QuerySpec& q) {
 }
 
 size_t query_jobs(const QuerySpec& q) {
-    const size_t cells = q.m * q.n;
+    const size_t cells = band_cells(q.m, q.n, q.band);
     if (!both_encrypted(q)) return cells;
     return cells * (q.encoding == LVS_ENC_ASCII7 ? 3 : 2);
 }
@@ -67,6 +82,10 @@ void assign_buffers(std::vector<QuerySpec>& qs, uint8_t*& ws) {
     for (auto& q : qs) {
         q.V = reinterpret_cast<uint64_t*>(ws);
         ws += align256(sizeof(uint64_t) * (q.m + 1) * W);
+        if (!q.h_last) {
+            q.H = reinterpret_cast<uint64_t*>(ws);
+            ws += align256(sizeof(uint64_t) * std::max<size_t>(q.n, 1) * W);
+        }
         if (both_encrypted(q)) {
             q.eq9 = reinterpret_cast<uint64_t*>(ws);
             ws += align256(sizeof(uint64_t) * q.m * q.n * W);
@@ -95,6 +114,7 @@ void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool wi
             const size_t ns = nsym(q.encoding);
             for (size_t i = 0; i < q.m; ++i)
                 for (size_t j = 0; j < q.n; ++j) {
+                    if (!in_band(q, i + 1, j + 1)) continue;
                     Job J = blank_job();
                     J.src[0] = q.A + (i * ns) * W;
                     J.src[1] = q.B + (j * ns) * W;
@@ -118,6 +138,7 @@ void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool wi
                 if (!both_encrypted(q) || q.encoding != LVS_ENC_ASCII7) continue;
                 for (size_t i = 0; i < q.m; ++i)
                     for (size_t j = 0; j < q.n; ++j) {
+                        if (!in_band(q, i + 1, j + 1)) continue;
                         const size_t c = i * q.n + j;
                         Job J = blank_job();
                         J.src[0] = q.A + (i * 2 + 1) * W;
@@ -135,9 +156,28 @@ void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool wi
         }
     }
     if (!with_dp) return;
-    // an empty first string leaves h[0, 1..n] = Enc(1) as the result
-    for (const auto& q : qs)
-        if (q.m == 0 && q.n) P.fills.push_back({q.h_last, q.n});
+    for (const auto& q : qs) {
+        if (q.band < 0) {
+            // an empty first string leaves h[0, 1..n] = Enc(1) as the result
+            if (q.m == 0 && q.n) P.fills.push_back({q.h_last, q.n});
+            continue;
+        }
+        // band path entries that no bootstrap writes keep the OneMatrix 1:
+        // v[1,0], and every path cell outside the band (all of them when a
+        // string is empty)
+        if (q.m == 0 || q.n == 0) {
+            if (q.m + q.n) P.fills.push_back({q.path, q.m + q.n});
+            continue;
+        }
+        P.fills.push_back({q.path, 1});
+        const size_t mn = std::min(q.m, q.n);
+        for (size_t k = 2; k <= mn; ++k)
+            if (!in_band(q, k, k - 1)) P.fills.push_back({q.path + (2 * k - 2) * W, 1});
+        for (size_t j = q.m + 1; j <= q.n; ++j)
+            if (!in_band(q, q.m, j)) P.fills.push_back({q.path + (2 * q.m + (j - q.m - 1)) * W, 1});
+        for (size_t i = q.n + 1; i <= q.m; ++i)
+            if (!in_band(q, i, q.n)) P.fills.push_back({q.path + (2 * q.n + (i - q.n - 1)) * W, 1});
+    }
     // ---- the wavefront: anti-diagonal s holds every query's cells (i, s - i)
     size_t smax = 0;
     for (const auto& q : qs)
@@ -146,19 +186,21 @@ void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool wi
         b.step();
         for (const auto& q : qs) {
             if (!q.m || !q.n || s > q.m + q.n) continue;
-            uint64_t* H = q.h_last - W;            // H[j] = h[latest i, j], j >= 1
+            uint64_t* H = (q.h_last ? q.h_last : q.H) - W;   // H[j] = h[latest i, j], j >= 1
             const size_t i_lo = (s > q.n + 1) ? s - q.n : 1;
             const size_t i_hi = std::min(q.m, s - 1);
             for (size_t i = i_lo; i <= i_hi; ++i) {
                 const size_t j = s - i;
+                if (!in_band(q, i, j)) continue;
                 const uint64_t* eq;
                 if (q.eq9_in) eq = q.eq9_in + ((i - 1) * q.n + (j - 1)) * W;
                 else if (q.B) eq = q.eq9 + ((i - 1) * q.n + (j - 1)) * W;
                 else eq = q.table + (size_t(q.cols[j - 1]) * q.m + (i - 1)) * W;
-                // v_in = v[i, j-1] (Enc(1) on the left border), h_in = h[i-1, j]
-                // (Enc(1) on the top border); key = 4 - v_in + 3 h_in + eq9
-                const uint64_t* v_in = (j == 1) ? nullptr : q.V + i * W;
-                const uint64_t* h_in = (i == 1) ? nullptr : H + j * W;
+                // v_in = v[i, j-1] (Enc(1) on the left border and outside the
+                // band), h_in = h[i-1, j] (Enc(1) on the top border and outside
+                // the band); key = 4 - v_in + 3 h_in + eq9
+                const uint64_t* v_in = (j == 1 || !in_band(q, i, j - 1)) ? nullptr : q.V + i * W;
+                const uint64_t* h_in = (i == 1 || !in_band(q, i - 1, j)) ? nullptr : H + j * W;
                 Job J = blank_job();
                 J.src[0] = v_in;
                 J.src[1] = h_in;
@@ -176,6 +218,24 @@ void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool wi
                 J.sub[1] = v_in;
                 J.sub_delta[1] = v_in ? 0 : kOne;
                 J.dst[2] = q.trace ? q.trace + ((i - 1) * q.n + (j - 1)) * W : nullptr;
+                if (q.band >= 0) {
+                    // the band path: v[k,k-1] and h[k,k] for k <= min(m, n), then
+                    // h[m, j > m] or v[i > n, n]
+                    const size_t mn = std::min(q.m, q.n);
+                    if (i == j) {
+                        J.dst[3] = q.path + (2 * i - 1) * W;
+                        J.copy_of = 1;
+                    } else if (i == j + 1 && i <= mn) {
+                        J.dst[3] = q.path + (2 * i - 2) * W;
+                        J.copy_of = 0;
+                    } else if (i == q.m && j > q.m) {
+                        J.dst[3] = q.path + (2 * q.m + (j - q.m - 1)) * W;
+                        J.copy_of = 1;
+                    } else if (j == q.n && i > q.n) {
+                        J.dst[3] = q.path + (2 * q.n + (i - q.n - 1)) * W;
+                        J.copy_of = 0;
+                    }
+                }
                 b.add(J);
             }
         }

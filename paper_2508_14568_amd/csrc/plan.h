@@ -27,11 +27,25 @@ struct QuerySpec {
     const uint64_t* eq9_in = nullptr;       // [m][n][W] given equality matrix (Algorithm 1)
     uint64_t* h_last = nullptr;             // [n][W] result; doubles as H[1..n]
     uint64_t* trace = nullptr;              // optional [m][n][W] record of every M
+    // Algorithm 1's band (Section 3.4): only cells with |i - j| <= band are
+    // bootstrapped (band < 0: every cell); the result is then the m + n
+    // differences of the diagonal path, written to path ([m+n][W]).
+    long band = -1;
+    uint64_t* path = nullptr;
     // workspace buffers assigned by assign_buffers()
     uint64_t* V = nullptr;                  // [m+1][W]
     uint64_t* eq1 = nullptr;                // [m][n][W] (ASCII, both encrypted)
     uint64_t* eq9 = nullptr;                // [m][n][W] (both encrypted)
+    uint64_t* H = nullptr;                  // [n][W] row state when there is no h_last (band)
 };
+
+// Whether cell (i, j) (1-based) is bootstrapped.
+inline bool in_band(const QuerySpec& q, size_t i, size_t j) {
+    return q.band < 0 || (i > j ? i - j : j - i) <= size_t(q.band);
+}
+
+// Cells of an m x n matrix with |i - j| <= band (every cell if band < 0).
+size_t band_cells(size_t m, size_t n, long band);
 
 struct PlanStep {
     size_t off, count;

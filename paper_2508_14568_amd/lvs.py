@@ -67,6 +67,12 @@ _SIGS = {
     "lvs_preprocess": (I32, [VP, VP, SZ, I32, VP, SZ, VP, VP, SZ]),
     "lvs_edit_distance_clear_workspace_bytes": (SZ, [SZ, SZ]),
     "lvs_edit_distance_clear": (I32, [VP, VP, SZ, VP, SZ, VP, SZ, VP, VP, SZ]),
+    "lvs_band_exact": (SZ, [SZ, SZ]),
+    "lvs_band_cells": (SZ, [SZ, SZ, SZ]),
+    "lvs_edit_distance_band_workspace_bytes": (SZ, [SZ, SZ, I32, SZ]),
+    "lvs_edit_distance_band": (I32, [VP, VP, SZ, VP, SZ, I32, SZ, VP, VP, SZ]),
+    "lvs_edit_distance_clear_band_workspace_bytes": (SZ, [SZ, SZ, SZ]),
+    "lvs_edit_distance_clear_band": (I32, [VP, VP, SZ, VP, SZ, VP, SZ, SZ, VP, VP, SZ]),
     "lvs_plan_workspace_bytes": (I32, [VP, SZ, I32, ctypes.POINTER(SZ)]),
     "lvs_plan_create": (I32, [VP, VP, SZ, I32, I32, VP, SZ, ctypes.POINTER(VP)]),
     "lvs_plan_run": (I32, [VP]),
@@ -347,6 +353,45 @@ def lvs_edit_distance_clear(ctx: Context, d_table, m: int, alphabet: bytes, b: b
     return d_work
 
 
+# ------------------------------------------------------------- band modes
+
+def lvs_band_exact(m: int, n: int) -> int:
+    return lib().lvs_band_exact(m, n)
+
+
+def lvs_band_cells(m: int, n: int, ell: int) -> int:
+    return lib().lvs_band_cells(m, n, ell)
+
+
+def lvs_edit_distance_band_workspace_bytes(m: int, n: int, encoding: int, ell: int) -> int:
+    return lib().lvs_edit_distance_band_workspace_bytes(m, n, encoding, ell)
+
+
+def lvs_edit_distance_band(ctx: Context, d_a, m: int, d_b, n: int, encoding: int, ell: int, d_path, d_work=None):
+    """d_path: [m+n][N+1] device buffer for the band path."""
+    if d_work is None:
+        d_work = device_buffer(lvs_edit_distance_band_workspace_bytes(m, n, encoding, ell), ctx.device)
+    _check(lib().lvs_edit_distance_band(ctx, _dptr(d_a), m, _dptr(d_b), n, encoding, ell, _dptr(d_path),
+                                        _dptr(d_work), d_work.numel() * d_work.element_size()))
+    return d_work
+
+
+def lvs_edit_distance_clear_band_workspace_bytes(m: int, n: int, ell: int) -> int:
+    return lib().lvs_edit_distance_clear_band_workspace_bytes(m, n, ell)
+
+
+def lvs_edit_distance_clear_band(ctx: Context, d_table, m: int, alphabet: bytes, b: bytes, ell: int, d_path,
+                                 d_work=None):
+    need = lvs_edit_distance_clear_band_workspace_bytes(m, len(b), ell)
+    if d_work is None:
+        d_work = device_buffer(need, ctx.device)
+    ab = (ctypes.c_uint8 * max(1, len(alphabet))).from_buffer_copy(bytes(alphabet) or b"\0")
+    bb = (ctypes.c_uint8 * max(1, len(b))).from_buffer_copy(bytes(b) or b"\0")
+    _check(lib().lvs_edit_distance_clear_band(ctx, _dptr(d_table), m, ab, len(alphabet), bb, len(b), ell,
+                                              _dptr(d_path), _dptr(d_work), d_work.numel() * d_work.element_size()))
+    return d_work
+
+
 # ------------------------------------------------------------ batch plans
 
 LVS_PLAN_GRAPH = 1
@@ -354,7 +399,7 @@ LVS_PLAN_GRAPH = 1
 
 class lvs_query(ctypes.Structure):
     _fields_ = [("d_a", VP), ("m", SZ), ("d_b", VP), ("n", SZ), ("d_table", VP), ("alphabet", VP), ("alen", SZ),
-                ("b_clear", VP), ("d_h_last", VP)]
+                ("b_clear", VP), ("d_h_last", VP), ("banded", ctypes.c_int32), ("ell", SZ), ("d_path", VP)]
 
 
 class Plan(_Handle):
@@ -367,7 +412,7 @@ class Plan(_Handle):
 
 def make_queries(items):
     """items: dicts with d_a, m, d_h_last and either d_b, n or d_table,
-    alphabet (bytes), b_clear (bytes)."""
+    alphabet (bytes), b_clear (bytes); optionally ell and d_path (band)."""
     arr = (lvs_query * max(1, len(items)))()
     keep = []
     for k, it in enumerate(items):
@@ -375,6 +420,10 @@ def make_queries(items):
         q.d_a = _dptr(it.get("d_a"))
         q.m = it["m"]
         q.d_h_last = _dptr(it.get("d_h_last"))
+        if it.get("ell") is not None:
+            q.banded = 1
+            q.ell = it["ell"]
+            q.d_path = _dptr(it.get("d_path"))
         if it.get("d_b") is not None:
             q.d_b = _dptr(it["d_b"])
             q.n = it["n"]

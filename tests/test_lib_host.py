@@ -101,3 +101,17 @@ def test_errors(L, both_keys):
     with pytest.raises(L.LvsError) as e:
         L.lvs_keygen(p, 1)
     assert e.value.code == -7
+
+
+def test_band_counts_match_definition():
+    """lvs_band_cells / lvs_band_exact against a brute-force count of
+    |i - j| <= ell and the oracle's exact half-width (host logic, no GPU)."""
+    from paper_2508_14568_amd import lvs as L
+    from oracle import plaintext as P
+    for m in range(0, 25):
+        for n in range(0, 25, 4):
+            for ell in range(0, 30, 5):
+                want = sum(1 for i in range(1, m + 1) for j in range(1, n + 1) if abs(i - j) <= ell)
+                assert L.lvs_band_cells(m, n, ell) == want
+            assert L.lvs_band_exact(m, n) == P.exact_band(m, n)
+    assert L.lvs_band_cells(40, 40, 7) == P.band_cell_count_formula(40, 7)
