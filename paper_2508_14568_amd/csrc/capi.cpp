@@ -98,13 +98,17 @@ int execute(Context* C, Plan& P, uint8_t* ws) {
     return LVS_OK;
 }
 
+// Bound of a wavefront plan's largest step: a diagonal holds at most
+// min(m, n) cells of a query, each step the cells of one diagonal plus one
+// equality stage of each of the next two.
 size_t max_step_of(const std::vector<QuerySpec>& qs) {
-    size_t eq = 0, diag = 0;
+    size_t step = 0;
     for (const auto& q : qs) {
-        if (q.B && !q.eq9_in) eq += band_cells(q.m, q.n, q.band);
-        diag += std::min(q.m, q.n);
+        const size_t w = std::min(q.m, q.n);
+        const bool eq = q.B && !q.eq9_in;
+        step += eq ? (q.encoding == LVS_ENC_ASCII7 ? 3 : 2) * w : w;
     }
-    return std::max(eq, diag);
+    return step;
 }
 
 size_t plan_ws(const std::vector<QuerySpec>& qs) {

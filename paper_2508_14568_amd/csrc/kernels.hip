@@ -136,10 +136,11 @@ __device__ __forceinline__ void ntt_forward(uint32_t (&x)[kEh], uint32_t* scr, c
 
 // Inverse negacyclic NTT without the 1/N factor (Gentleman-Sande, inverse
 // psi twiddles, bit-reversed order in, natural order out).  In: x[e] holds
-// position 64 lh + e, each < 2p.  Out: x[e] holds coefficient lh + 32 e,
-// reduced to [0, p).  A butterfly maps inputs below B to a sum below 2B and a
-// product below 2p; the sums are brought back below 2p after stages 3 and 7,
-// so B never exceeds 16p and a + B - b stays below 32p < 2^31.
+// position 64 lh + e, each < 2p.  Out: x[e] holds coefficient lh + 32 e as a
+// residue below 16p (not reduced: the CRT accepts it).  A butterfly maps
+// inputs below B to a sum below 2B and a product below 2p; the sums are
+// brought back below 2p after stages 3 and 7, so B never exceeds 16p and
+// a + B - b stays below 32p < 2^31.
 template <int U>
 __device__ __forceinline__ void inv_stage(uint32_t (&x)[kEh], const uint2* w, uint32_t p, uint32_t q, int lh) {
     constexpr int half = (U < 5) ? (1 << U) : (1 << (U - 5));
@@ -178,15 +179,15 @@ __device__ __forceinline__ void ntt_inverse(uint32_t (&x)[kEh], uint32_t* scr, c
     inv_stage<8>(x, w, p, q, lh);
     inv_stage<9>(x, w, p, q, lh);
     inv_stage<10>(x, w, p, q, lh);
-#pragma unroll
-    for (int e = 0; e < kEh; ++e) x[e] = csub(reduce2p(x[e], q, p), p);
 }
 
-// Residues r[0..3] (each in [0, p_i)) of a signed integer |X| < prod/2 ->
-// X mod 2^64 (Garner mixed radix, then the signed lift).
+// Residues r[0..3] (each below 16 p_i, not necessarily reduced) of a signed
+// integer |X| < prod/2 -> X mod 2^64 (Garner mixed radix, then the signed
+// lift).  Only v_0 = r_0 mod p_0 needs an explicit reduction: every later
+// digit passes through a Shoup product, which accepts any word below 2^32.
 __device__ __forceinline__ uint64_t crt_lift(const uint32_t (&r)[kPrimes], const CrtConsts& C) {
     uint32_t v[kPrimes];
-    v[0] = r[0];
+    v[0] = csub(reduce2p(r[0], C.red[0], C.p[0]), C.p[0]);
 #pragma unroll
     for (int i = 1; i < kPrimes; ++i) {
         const uint32_t p = C.p[i];

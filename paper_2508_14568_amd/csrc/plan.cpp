@@ -1,10 +1,10 @@
 // Plans: every step is a list of bootstraps whose inputs are ready.
 //
-// Equality (Section 4, Algorithm 3 with the eq9 table of Algorithm 4): all
-// character pairs of all queries are independent of the DP, so they form one
-// step (two for ASCII: eq1, then eq9).  Main loop (Algorithm 1/4): the cells
-// of anti-diagonal s = i + j depend only on diagonal s - 1 (Section 6.2), so
-// step s holds every query's cells with i + j = s.  The key of a cell and the
+// Main loop (Algorithm 1/4): the cells of anti-diagonal s = i + j depend
+// only on diagonal s - 1 (Section 6.2), so step s holds every query's cells
+// with i + j = s.  Equality (Section 4, Algorithm 3 with the eq9 table of
+// Algorithm 4) is independent of the DP; as in Algorithm 4 it runs inside
+// the loop, each stage one step ahead of the cells that read it.  The key of a cell and the
 // difference update are folded into the bootstrap's job (see launch.h).
 // With Algorithm 1's band (Section 3.4) only the pairs and cells with
 // |i - j| <= band get bootstraps, neighbours outside it read as Enc(1), and
@@ -97,65 +97,75 @@ void assign_buffers(std::vector<QuerySpec>& qs, uint8_t*& ws) {
     }
 }
 
+namespace {
+
+// Equality jobs of cell (i, j) (1-based) of a query with both strings
+// encrypted: stage 1 is eq1 = PBS(x1 - y1; LUT_eq) for ASCII, or eq9 =
+// PBS(x - y; LUT_eq9) for DNA; stage 2 is eq9 = PBS(2 (x2 - y2) + (1 - eq1);
+// LUT_eq9) (ASCII only).
+Job equality_job(const QuerySpec& q, size_t i, size_t j, int stage) {
+    const size_t ns = nsym(q.encoding);
+    const size_t c = (i - 1) * q.n + (j - 1);
+    Job J = blank_job();
+    if (stage == 1) {
+        J.src[0] = q.A + ((i - 1) * ns) * W;
+        J.src[1] = q.B + ((j - 1) * ns) * W;
+        J.coef[0] = 1;
+        J.coef[1] = -1;
+        if (q.encoding == LVS_ENC_ASCII7) {
+            J.lut = LVS_LUT_EQ;
+            J.dst[0] = q.eq1 + c * W;
+        } else {
+            J.lut = LVS_LUT_EQ9;
+            J.dst[0] = q.eq9 + c * W;
+        }
+    } else {
+        J.src[0] = q.A + ((i - 1) * 2 + 1) * W;
+        J.src[1] = q.B + ((j - 1) * 2 + 1) * W;
+        J.src[2] = q.eq1 + c * W;
+        J.coef[0] = 2;
+        J.coef[1] = -2;
+        J.coef[2] = -1;
+        J.delta = kOne;
+        J.lut = LVS_LUT_EQ9;
+        J.dst[0] = q.eq9 + c * W;
+    }
+    return J;
+}
+
+// Cells (i, s - i) of anti-diagonal s inside the query's band.
+template <typename F>
+void for_diagonal(const QuerySpec& q, size_t s, F&& f) {
+    if (!q.m || !q.n || s < 2 || s > q.m + q.n) return;
+    const size_t i_lo = (s > q.n + 1) ? s - q.n : 1;
+    const size_t i_hi = std::min(q.m, s - 1);
+    for (size_t i = i_lo; i <= i_hi; ++i)
+        if (in_band(q, i, s - i)) f(i, s - i);
+}
+
+}  // namespace
+
 void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool with_dp) {
     Builder b(P);
-    // ---- equality of every pair (both strings encrypted)
-    bool any_eq = false, any_ascii = false;
+    size_t smax = 0;
+    bool any_ascii = false;
     for (const auto& q : qs)
-        if (both_encrypted(q) && q.m && q.n) {
-            any_eq = true;
-            any_ascii |= q.encoding == LVS_ENC_ASCII7;
+        if (q.m && q.n) {
+            smax = std::max(smax, q.m + q.n);
+            any_ascii |= both_encrypted(q) && q.encoding == LVS_ENC_ASCII7;
         }
-    if (any_eq) {
-        // eq1 = PBS(x1 - y1; LUT_eq) (ASCII) or eq9 = PBS(x - y; LUT_eq9) (DNA)
-        b.step();
-        for (const auto& q : qs) {
-            if (!both_encrypted(q)) continue;
-            const size_t ns = nsym(q.encoding);
-            for (size_t i = 0; i < q.m; ++i)
-                for (size_t j = 0; j < q.n; ++j) {
-                    if (!in_band(q, i + 1, j + 1)) continue;
-                    Job J = blank_job();
-                    J.src[0] = q.A + (i * ns) * W;
-                    J.src[1] = q.B + (j * ns) * W;
-                    J.coef[0] = 1;
-                    J.coef[1] = -1;
-                    const size_t c = i * q.n + j;
-                    if (q.encoding == LVS_ENC_ASCII7) {
-                        J.lut = LVS_LUT_EQ;
-                        J.dst[0] = q.eq1 + c * W;
-                    } else {
-                        J.lut = LVS_LUT_EQ9;
-                        J.dst[0] = q.eq9 + c * W;
-                    }
-                    b.add(J);
-                }
-        }
-        if (any_ascii) {
-            // eq9 = PBS(2 (x2 - y2) + (1 - eq1); LUT_eq9)
+    if (!with_dp) {
+        // equality alone: every pair in one step per stage
+        for (int stage = 1; stage <= (any_ascii ? 2 : 1); ++stage) {
             b.step();
             for (const auto& q : qs) {
-                if (!both_encrypted(q) || q.encoding != LVS_ENC_ASCII7) continue;
-                for (size_t i = 0; i < q.m; ++i)
-                    for (size_t j = 0; j < q.n; ++j) {
-                        if (!in_band(q, i + 1, j + 1)) continue;
-                        const size_t c = i * q.n + j;
-                        Job J = blank_job();
-                        J.src[0] = q.A + (i * 2 + 1) * W;
-                        J.src[1] = q.B + (j * 2 + 1) * W;
-                        J.src[2] = q.eq1 + c * W;
-                        J.coef[0] = 2;
-                        J.coef[1] = -2;
-                        J.coef[2] = -1;
-                        J.delta = kOne;
-                        J.lut = LVS_LUT_EQ9;
-                        J.dst[0] = q.eq9 + c * W;
-                        b.add(J);
-                    }
+                if (!both_encrypted(q) || (stage == 2 && q.encoding != LVS_ENC_ASCII7)) continue;
+                for (size_t s = 2; s <= q.m + q.n; ++s)
+                    for_diagonal(q, s, [&](size_t i, size_t j) { b.add(equality_job(q, i, j, stage)); });
             }
         }
+        return;
     }
-    if (!with_dp) return;
     for (const auto& q : qs) {
         if (q.band < 0) {
             // an empty first string leaves h[0, 1..n] = Enc(1) as the result
@@ -178,20 +188,22 @@ void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool wi
         for (size_t i = q.n + 1; i <= q.m; ++i)
             if (!in_band(q, i, q.n)) P.fills.push_back({q.path + (2 * q.n + (i - q.n - 1)) * W, 1});
     }
-    // ---- the wavefront: anti-diagonal s holds every query's cells (i, s - i)
-    size_t smax = 0;
-    for (const auto& q : qs)
-        if (q.m && q.n) smax = std::max(smax, q.m + q.n);
-    for (size_t s = 2; s <= smax; ++s) {
+    // Step t bootstraps the cells of anti-diagonal t (t >= 2) together with
+    // the equality of the cells they feed: the last equality stage of
+    // diagonal t + 1 and, for ASCII, the first stage of diagonal t + 2
+    // (Algorithm 4 evaluates equality inside the loop; each result is ready
+    // one step before it is read).
+    const size_t t0 = any_ascii ? 0 : 1;
+    for (size_t t = t0; t <= smax; ++t) {
         b.step();
         for (const auto& q : qs) {
-            if (!q.m || !q.n || s > q.m + q.n) continue;
+            if (both_encrypted(q)) {
+                const bool ascii = q.encoding == LVS_ENC_ASCII7;
+                for_diagonal(q, t + 1, [&](size_t i, size_t j) { b.add(equality_job(q, i, j, ascii ? 2 : 1)); });
+                if (ascii) for_diagonal(q, t + 2, [&](size_t i, size_t j) { b.add(equality_job(q, i, j, 1)); });
+            }
             uint64_t* H = (q.h_last ? q.h_last : q.H) - W;   // H[j] = h[latest i, j], j >= 1
-            const size_t i_lo = (s > q.n + 1) ? s - q.n : 1;
-            const size_t i_hi = std::min(q.m, s - 1);
-            for (size_t i = i_lo; i <= i_hi; ++i) {
-                const size_t j = s - i;
-                if (!in_band(q, i, j)) continue;
+            for_diagonal(q, t, [&](size_t i, size_t j) {
                 const uint64_t* eq;
                 if (q.eq9_in) eq = q.eq9_in + ((i - 1) * q.n + (j - 1)) * W;
                 else if (q.B) eq = q.eq9 + ((i - 1) * q.n + (j - 1)) * W;
@@ -237,7 +249,7 @@ void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool wi
                     }
                 }
                 b.add(J);
-            }
+            });
         }
     }
 }
