@@ -340,8 +340,8 @@ def main():
     elapsed = time.perf_counter() - t0
     br_ms, br_launches, br_pbs = L.lvs_profile_read(ctx, L.KERNEL_BLIND_ROTATE)
     forms = {name: L.lvs_profile_read(ctx, k) for name, k in
-             (("blind_rotate_kernel<1>", L.KERNEL_BLIND_ROTATE_LATENCY),
-              ("blind_rotate_kernel<2>", L.KERNEL_BLIND_ROTATE_THROUGHPUT))}
+             (("blind_rotate_latency_kernel", L.KERNEL_BLIND_ROTATE_LATENCY),
+              ("blind_rotate_kernel", L.KERNEL_BLIND_ROTATE_THROUGHPUT))}
     ks_ms, ks_launches, _ = L.lvs_profile_read(ctx, L.KERNEL_KEYSWITCH)
     L.lvs_profile_enable(ctx, False)
 

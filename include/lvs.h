@@ -134,10 +134,12 @@ int lvs_sync(lvs_context* ctx);
 /* Launch shape of the blind rotation kernel (the dominant cost of every
  * bootstrap, Section 2.2).  br_grid: workgroups per launch, each looping over
  * the batch (0: one workgroup per bootstrap).  latency_form_max: batches of
- * at most this many bootstraps use the form with one workgroup per CU, which
- * prefetches each step's key values; larger batches use the form with two
- * workgroups per CU.  A new context starts at {0, number of CUs}.  Plans
- * captured as graphs keep the shape they were captured with. */
+ * at most this many bootstraps use the eight-wave form (one workgroup of 512
+ * threads per CU, two waves per prime); larger batches use the four-wave form
+ * (two workgroups of 256 threads per CU).  A new context starts at
+ * {0, INT32_MAX}: the eight-wave form was the faster one at every batch size
+ * measured on MI355X.  Plans captured as graphs keep the shape they were
+ * captured with. */
 typedef struct lvs_tuning {
     int32_t br_grid;
     int32_t latency_form_max;
@@ -383,8 +385,8 @@ int lvs_server_stats(const lvs_server* srv, uint64_t* steps, uint64_t* bootstrap
 #define LVS_KERNEL_BLIND_ROTATE 0            /* both forms together */
 #define LVS_KERNEL_KEYSWITCH 1
 #define LVS_KERNEL_GRAPH 2                   /* a graph-captured plan, whole */
-#define LVS_KERNEL_BLIND_ROTATE_LATENCY 3    /* one workgroup per CU */
-#define LVS_KERNEL_BLIND_ROTATE_THROUGHPUT 4 /* two workgroups per CU */
+#define LVS_KERNEL_BLIND_ROTATE_LATENCY 3    /* eight-wave form, one workgroup per CU */
+#define LVS_KERNEL_BLIND_ROTATE_THROUGHPUT 4 /* four-wave form, two workgroups per CU */
 
 /* Kernel timing for measurement: while enabled, every launch of the blind
  * rotation, of the key switch and of a plan's graph is bracketed by HIP

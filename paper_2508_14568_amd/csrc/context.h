@@ -25,7 +25,7 @@ struct Context : Handle {
     int cus = 0;                  // compute units of the device
     // launch shape of the blind rotation (lvs_context_set_tuning / lvs_autotune)
     int br_grid = 0;              // persistent grid (0: one workgroup per job)
-    int latency_form_max = 0;     // batches up to this size take the one-workgroup-per-CU form
+    int latency_form_max = 0;     // batches up to this size take the eight-wave form
     // kernel timing (lvs_profile_*): event pairs recorded around launches
     bool profiling = false;
     struct Timed {
@@ -49,7 +49,8 @@ inline hipEvent_t take_event(Context* C) {
 }
 
 // Profile ids (lvs_profile_read): 0 sums the two blind-rotation forms, which
-// are recorded as 3 (one workgroup per CU) and 4 (two per CU).
+// are recorded as 3 (eight-wave workgroup, one per CU) and 4 (four-wave
+// workgroups, two per CU).
 constexpr int kProfBlindRotate = 0, kProfKeySwitch = 1, kProfGraph = 2, kProfBrLatency = 3, kProfBrThroughput = 4;
 
 inline int br_profile_id(const Context* C, int B) {

@@ -8,17 +8,18 @@
 // integers involved are below 2^97 in magnitude while prod p_r ~ 2^104, so the
 // torus result mod 2^64 is exact.
 //
-// Work mapping of the blind rotation: one workgroup of 4 wavefronts per
-// bootstrap; wavefront r owns prime p_r.  Its lanes 0-31 transform the
-// decomposed mask polynomial and lanes 32-63 the decomposed body polynomial,
-// 64 coefficients per lane in registers: 6 butterfly stages inside the lane,
-// one LDS transpose, 5 more stages inside the lane.  A lane-half swap
-// (ds_bpermute) gives every lane both transformed digits of its positions
-// for the products with the bootstrapping key; the inverse transform runs
-// the same way back.  The 64-bit accumulator lives in LDS; the decomposition
-// digits are computed once per workgroup, and after each external product
-// the four residue sets meet in LDS where every thread reconstructs 16
-// coefficients.
+// Work mapping of the blind rotation: one workgroup per bootstrap; the
+// wavefronts of prime p_r transform the decomposed mask polynomial in lanes
+// 0-31 and the decomposed body polynomial in lanes 32-63, 64 (four-wave
+// form) or 32 (eight-wave form, two waves per prime) coefficients per lane in
+// registers: butterfly stages inside the lane, one LDS transpose, more stages
+// inside the lane.  A lane-half swap (ds_bpermute) gives every lane both
+// transformed digits of its positions for the products with the
+// bootstrapping key; the inverse transform runs the same way back.  The 64-bit
+// accumulator lives in registers, spread over the threads as the CRT
+// reconstructs it; the decomposition digits are computed once per workgroup
+// from an LDS copy of it, and after each external product the four residue
+// sets meet in LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -88,24 +89,34 @@ __device__ __forceinline__ uint32_t swap_halves(uint32_t v, int lane) {
 // t = w b mod p in [0, 2p)), and 2p + 11 * 2p < 2^31 for p < 2^26.
 // Every stage is a template instance so that all register indices are
 // compile-time constants.
-template <int S>
-__device__ __forceinline__ void fwd_stage(uint32_t (&x)[kEh], const uint2* w, uint32_t p, int lh) {
+//
+// A lane may hold only NE of the 64 elements, elements e0 .. e0 + NE - 1 (the
+// half-element forms below); stages whose partners lie within that range
+// then run unchanged, with the twiddle of the element's global index.
+template <int S, int NE = kEh>
+__device__ __forceinline__ void fwd_stage(uint32_t (&x)[NE], const uint2* w, uint32_t p, int lh, int e0 = 0) {
     // S < 6: stride 1024 >> S, partners 32 >> S elements apart, uniform twiddles;
     // S >= 6: partners 1 << (10 - S) elements apart, one twiddle block per lane
     constexpr int half = (S < 6) ? (32 >> S) : (1 << (10 - S));
+    static_assert(half < NE, "partners must lie in the lane's elements");
+    // twiddle of element e = e0 + el: w[base + (e >> sh)]; e0 is 0 or 32, a
+    // multiple of 2^sh whenever el < 32 can reach sh < 6, so the index splits
+    // into a per-stage pointer and a compile-time offset
+    constexpr int sh = (S < 6) ? (6 - S) : (11 - S);
     const int base = (S < 6) ? (1 << S) : (1 << S) + (lh << (S - 5));
+    const uint2* wb = w + base + (e0 >> sh);
     const uint32_t two_p = 2 * p;
 #pragma unroll
-    for (int e = 0; e < kEh; ++e) {
-        if (e & half) continue;
-        const uint2 tw = w[base + ((S < 6) ? (e >> (6 - S)) : (e >> (11 - S)))];
+    for (int el = 0; el < NE; ++el) {
+        if (el & half) continue;
+        const uint2 tw = wb[el >> sh];
         // s = q p - w b = -t (mod 2^32) for the Shoup product t = w b mod p in
         // [0, 2p), so that a + t = a - s and a + 2p - t = a + 2p + s (v_add3)
-        const uint32_t b = x[e + half];
+        const uint32_t b = x[el + half];
         const uint32_t s = __umulhi(b, tw.y) * p - b * tw.x;
-        const uint32_t a = x[e];
-        x[e] = a - s;
-        x[e + half] = a + two_p + s;
+        const uint32_t a = x[el];
+        x[el] = a - s;
+        x[el + half] = a + two_p + s;
     }
 }
 
@@ -141,21 +152,25 @@ __device__ __forceinline__ void ntt_forward(uint32_t (&x)[kEh], uint32_t* scr, c
 // inputs below B to a sum below 2B and a product below 2p; the sums are
 // brought back below 2p after stages 3 and 7, so B never exceeds 16p and
 // a + B - b stays below 32p < 2^31.
-template <int U>
-__device__ __forceinline__ void inv_stage(uint32_t (&x)[kEh], const uint2* w, uint32_t p, uint32_t q, int lh) {
+template <int U, int NE = kEh>
+__device__ __forceinline__ void inv_stage(uint32_t (&x)[NE], const uint2* w, uint32_t p, uint32_t q, int lh,
+                                          int e0 = 0) {
     constexpr int half = (U < 5) ? (1 << U) : (1 << (U - 5));
+    static_assert(half < NE, "partners must lie in the lane's elements");
     constexpr int since = (U <= 3) ? U : (U <= 7 ? U - 4 : U - 8);   // stages since the last reduction
     constexpr bool reduce = (U == 3 || U == 7);
     const uint32_t bound = (2 * p) << since;
+    constexpr int sh = (U < 5) ? (U + 1) : (U - 4);
     const int base = (U < 5) ? (1 << (10 - U)) + (lh << (5 - U)) : (1 << (10 - U));
+    const uint2* wb = w + base + (e0 >> sh);
 #pragma unroll
-    for (int e = 0; e < kEh; ++e) {
-        if (e & half) continue;
-        const uint2 tw = w[base + ((U < 5) ? (e >> (U + 1)) : (e >> (U - 4)))];
-        const uint32_t a = x[e], b = x[e + half];
+    for (int el = 0; el < NE; ++el) {
+        if (el & half) continue;
+        const uint2 tw = wb[el >> sh];
+        const uint32_t a = x[el], b = x[el + half];
         const uint32_t sum = a + b;
-        x[e] = reduce ? reduce2p(sum, q, p) : sum;
-        x[e + half] = mul_shoup(a + bound - b, tw.x, tw.y, p);
+        x[el] = reduce ? reduce2p(sum, q, p) : sum;
+        x[el + half] = mul_shoup(a + bound - b, tw.x, tw.y, p);
     }
 }
 
@@ -321,14 +336,9 @@ constexpr size_t kBrLds = sizeof(uint32_t) * kPrimes * 2 * kPoly                
 //       wave's prime), after a barrier that ends every read of the digits;
 //   (4) the inverse transform's scratch, then its residues in natural order;
 //   (5) the CRT of every owned coefficient from the four regions.
-//
-// kOcc = 2 is the throughput form (two workgroups per CU, bootstrapping-key
-// values loaded where the products need them).  kOcc = 1 is the latency form
-// for batches that leave CUs idle: with the whole register file to itself a
-// workgroup fetches the step's key values before the digit phase, so that
-// the loads complete behind the digits and the forward transform.
-template <int kOcc>
-__global__ void __launch_bounds__(kBrThreads, kOcc) blind_rotate_kernel(BrArgs A) {
+// Two workgroups fit on a CU; the bootstrapping-key values are loaded where
+// the products need them.
+__global__ void __launch_bounds__(kBrThreads, 2) blind_rotate_kernel(BrArgs A) {
     extern __shared__ __align__(16) uint8_t lds[];
     uint32_t* region = reinterpret_cast<uint32_t*>(lds);   // [kPrimes][2][kPoly]
     uint32_t* abar = region + kPrimes * 2 * kPoly;          // [n+1]
@@ -378,14 +388,8 @@ __global__ void __launch_bounds__(kBrThreads, kOcc) blind_rotate_kernel(BrArgs A
         for (int i = 0; i < kSmallN; ++i) {
             const uint32_t a = abar[i];
             // this step's bootstrapping-key values of the lane:
-            // kq = (K0[2k], K1[2k], K0[2k+1], K1[2k+1]) of positions 64 lh + 2k, + 1
+            // K[k * 32] = (K0[2k], K1[2k], K0[2k+1], K1[2k+1]) of positions 64 lh + 2k, + 1
             const uint4* K = reinterpret_cast<const uint4*>(A.bsk) + ((size_t(i) * kPrimes + wave) * 2 + h) * (kN / 2) + lh;
-            uint4 kpre[kOcc == 1 ? kEh / 2 : 1];
-            if (kOcc == 1) {
-#pragma unroll
-                for (int k = 0; k < kEh / 2; ++k) kpre[k] = K[k * 32];
-                asm volatile("" ::: "memory");
-            }
             // (1)
 #pragma unroll
             for (int k = 0; k < kAccPer; ++k) {
@@ -416,7 +420,7 @@ __global__ void __launch_bounds__(kBrThreads, kOcc) blind_rotate_kernel(BrArgs A
             // products with the GGSW rows: out_h = D0 K[0][h] + D1 K[1][h]
 #pragma unroll
             for (int e = 0; e < kEh; e += 2) {
-                const uint4 kq = (kOcc == 1) ? kpre[(e >> 1) % (kOcc == 1 ? kEh / 2 : 1)] : K[(e >> 1) * 32];
+                const uint4 kq = K[(e >> 1) * 32];
 #pragma unroll
                 for (int o = 0; o < 2; ++o) {
                     const uint32_t own = x[e + o];
@@ -452,6 +456,221 @@ __global__ void __launch_bounds__(kBrThreads, kOcc) blind_rotate_kernel(BrArgs A
         }
         __syncthreads();
         for (int t = tid; t < kCtWords; t += kBrThreads) {
+            const int at = (t == 0) ? 0 : (t < kN) ? kN - t : kPoly;
+            const uint64_t m = uint64_t(acc_lo[at]) | (uint64_t(acc_hi[at]) << 32);
+            const uint64_t v = (t > 0 && t < kN) ? uint64_t(0) - m : m;
+            const uint64_t s0 = J.sub[0] ? J.sub[0][t] : 0;
+            const uint64_t s1 = J.sub[1] ? J.sub[1][t] : 0;
+            const uint64_t c0 = (t == kN) ? J.sub_delta[0] : 0;
+            const uint64_t c1 = (t == kN) ? J.sub_delta[1] : 0;
+            const uint64_t o0 = v - s0 - c0, o1 = v - s1 - c1;
+            if (J.dst[0]) J.dst[0][t] = o0;
+            if (J.dst[1]) J.dst[1][t] = o1;
+            if (J.dst[2]) J.dst[2][t] = v;
+            if (J.dst[3]) J.dst[3][t] = J.copy_of ? o1 : o0;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------- blind rotation, latency form
+
+// One workgroup of 8 wavefronts per bootstrap, one workgroup per CU: two
+// waves per prime, wave part g holding the lane's elements 32 g .. 32 g + 31
+// of both polynomials, so a bootstrap has twice the waves (and half the
+// dependent work per wave) of the forms above.  Of the 11 forward stages only
+// the first pairs the two halves (coefficients j and j + 1024); each wave
+// computes it for its own half straight from the digits, which it reads for
+// both halves.  Of the 11 inverse stages only the last pairs them; it runs in
+// the CRT step, where one thread holds both coefficients of a pair.  The
+// transposes between the two in-lane layouts go through LDS shared by the two
+// waves of a prime, double-buffered (forward transposes and residues in F,
+// the accumulator copy, digits and inverse transposes in I) so that five
+// barriers per CMux order every access.  Positions after the forward
+// transform are those of the forms above (lane lh, element e = 32 g + e'':
+// position 64 lh + e), so the bootstrapping key is shared with them.
+constexpr int kLatThreads = 512;
+constexpr int kLatE = kEh / 2;                   // elements per lane and wave
+constexpr int kLatAcc = 2 * kN / kLatThreads;    // accumulator coefficients per thread (8)
+constexpr size_t kLatLds = sizeof(uint32_t) * 2 * kPrimes * 2 * kPoly       // F and I
+                           + sizeof(uint32_t) * (kSmallWords + 1);           // switched mask and body
+
+// Coefficient k of thread t: polynomial (k >> 1) & 1, index t + 512 (k >> 2)
+// + 1024 (k & 1), so a thread holds both members (c, c + 1024) of each pair.
+__device__ __forceinline__ int lat_poly(int k) { return (k >> 1) & 1; }
+__device__ __forceinline__ int lat_coef(int tid, int k) { return tid + kLatThreads * (k >> 2) + (kN / 2) * (k & 1); }
+
+__global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(BrArgs A) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint32_t* F = reinterpret_cast<uint32_t*>(lds);      // [kPrimes][2][kPoly]
+    uint32_t* I = F + kPrimes * 2 * kPoly;               // [kPrimes][2][kPoly]
+    uint32_t* abar = I + kPrimes * 2 * kPoly;            // [n+1]
+    uint32_t* acc_lo = I;                                // [2][kPoly]
+    uint32_t* acc_hi = I + 2 * kPoly;
+    uint32_t* dig = I + 4 * kPoly;                       // [2][kPoly]
+
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int r = wave >> 1;          // prime
+    const int g = wave & 1;           // element half
+    const int e0 = kLatE * g;
+    const int lane = tid & 63;
+    const int h = lane >> 5;
+    const int lh = lane & 31;
+    const uint32_t p = pick(A.crt.p, r);
+    const uint32_t mont = pick(A.crt.mont, r);
+    const uint32_t q = pick(A.crt.red, r);
+    const uint2* fw = A.tw.fwd + size_t(r) * kN;
+    const uint2* iw = A.tw.inv + size_t(r) * kN;
+    uint32_t* scrF = F + (r * 2 + h) * kPoly;
+    uint32_t* scrI = I + (r * 2 + h) * kPoly;
+    const uint32_t unbias = p - (1u << 22);
+    const uint2 w0 = fw[1];           // twiddle of forward stage 0
+    uint2 wlast[kPrimes];             // twiddle of the last inverse stage, every prime
+#pragma unroll
+    for (int w = 0; w < kPrimes; ++w) wlast[w] = A.tw.inv[size_t(w) * kN + 1];
+
+    for (int b = blockIdx.x; b < A.B; b += gridDim.x) {
+        const Job& J = A.jobs[b];
+        for (int c = tid; c < kSmallWords; c += kLatThreads) {
+            uint64_t v = 0;
+            for (int sp = 0; sp < A.nsplit; ++sp) v += A.part[(size_t(sp) * A.B + b) * kSmallWords + c];
+            if (c == kSmallN) v += job_word(J, kN) + J.delta;
+            abar[c] = uint32_t((((v >> 51) + 1) >> 1) & (2 * kN - 1));
+        }
+        __syncthreads();
+        const int lut = min(int(J.lut), LVS_LUT_SLOTS - 1);
+        const uint64_t* tp = A.luts + size_t(lut) * kN;
+        const uint32_t bbar = abar[kSmallN];
+        uint64_t acc[kLatAcc];
+#pragma unroll
+        for (int k = 0; k < kLatAcc; ++k) {
+            const uint32_t c = uint32_t(lat_coef(tid, k));
+            const uint32_t src = (c + bbar) & (2 * kN - 1);
+            const uint64_t v = tp[src & (kN - 1)];
+            acc[k] = lat_poly(k) ? ((src < uint32_t(kN)) ? v : uint64_t(0) - v) : uint64_t(0);
+        }
+
+        for (int i = 0; i < kSmallN; ++i) {
+            const uint32_t a = abar[i];
+            const uint4* K = reinterpret_cast<const uint4*>(A.bsk) + ((size_t(i) * kPrimes + r) * 2 + h) * (kN / 2) + lh;
+            uint4 kpre[kLatE / 2];
+#pragma unroll
+            for (int k = 0; k < kLatE / 2; ++k) kpre[k] = K[(e0 / 2 + k) * 32];
+            asm volatile("" ::: "memory");
+            // accumulator copy (low and high words)
+#pragma unroll
+            for (int k = 0; k < kLatAcc; ++k) {
+                const int at = lat_poly(k) * kPoly + lat_coef(tid, k);
+                acc_lo[at] = uint32_t(acc[k]);
+                acc_hi[at] = uint32_t(acc[k] >> 32);
+            }
+            __syncthreads();
+            // digits of X^a ACC - ACC
+#pragma unroll
+            for (int k = 0; k < kLatAcc; ++k) {
+                const int qq = lat_poly(k);
+                const uint32_t c = uint32_t(lat_coef(tid, k));
+                const uint32_t src = (c - a) & (2 * kN - 1);
+                const int at = qq * kPoly + int(src & (kN - 1));
+                uint64_t rr = uint64_t(acc_lo[at]) | (uint64_t(acc_hi[at]) << 32);
+                if (src >= uint32_t(kN)) rr = uint64_t(0) - rr;
+                const uint64_t t = rr - acc[k];
+                const uint32_t u = ((uint32_t(t >> 40) + 1) >> 1) & 0x7FFFFFu;
+                dig[qq * kPoly + c] = (u + 0x400000u) & 0x7FFFFFu;
+            }
+            __syncthreads();
+            // forward transform: stage 0 for this half from both halves' digits
+            uint32_t x[kLatE];
+            const uint32_t* const dj = dig + h * kPoly + lh;   // coefficient lh + 32 el (< 1024) and + 1024
+#pragma unroll
+            for (int el = 0; el < kLatE; ++el) {
+                const uint32_t lo = dj[32 * el] + unbias;
+                const uint32_t hi = dj[32 * el + kN / 2] + unbias;
+                const uint32_t s = __umulhi(hi, w0.y) * p - hi * w0.x;
+                x[el] = g ? lo + 2 * p + s : lo - s;
+            }
+            fwd_stage<1, kLatE>(x, fw, p, lh, e0);
+            fwd_stage<2, kLatE>(x, fw, p, lh, e0);
+            fwd_stage<3, kLatE>(x, fw, p, lh, e0);
+            fwd_stage<4, kLatE>(x, fw, p, lh, e0);
+            fwd_stage<5, kLatE>(x, fw, p, lh, e0);
+            // pad(lh + 32 e) = lh + 32 e + (e >> 1) and pad(64 lh + e) = 65 lh + e (lh < 32, e < 64)
+            uint32_t* const col = scrF + lh + 32 * e0 + (e0 >> 1);
+            uint32_t* const row = scrF + 65 * lh + e0;
+#pragma unroll
+            for (int el = 0; el < kLatE; ++el) col[32 * el + (el >> 1)] = x[el];
+            __syncthreads();
+#pragma unroll
+            for (int el = 0; el < kLatE; ++el) x[el] = row[el];
+            fwd_stage<6, kLatE>(x, fw, p, lh, e0);
+            fwd_stage<7, kLatE>(x, fw, p, lh, e0);
+            fwd_stage<8, kLatE>(x, fw, p, lh, e0);
+            fwd_stage<9, kLatE>(x, fw, p, lh, e0);
+            fwd_stage<10, kLatE>(x, fw, p, lh, e0);
+            // products with the GGSW rows
+#pragma unroll
+            for (int el = 0; el < kLatE; el += 2) {
+                const uint4 kq = kpre[el >> 1];
+#pragma unroll
+                for (int o = 0; o < 2; ++o) {
+                    const uint32_t own = x[el + o];
+                    const uint32_t other = swap_halves(own, lane);
+                    const uint32_t d0 = h ? other : own;
+                    const uint32_t d1 = h ? own : other;
+                    const uint32_t k0 = o ? kq.z : kq.x;
+                    const uint32_t k1 = o ? kq.w : kq.y;
+                    x[el + o] = redc(uint64_t(d0) * k0 + uint64_t(d1) * k1, p, mont);
+                }
+            }
+            // inverse transform, stages 0..9
+            inv_stage<0, kLatE>(x, iw, p, q, lh, e0);
+            inv_stage<1, kLatE>(x, iw, p, q, lh, e0);
+            inv_stage<2, kLatE>(x, iw, p, q, lh, e0);
+            inv_stage<3, kLatE>(x, iw, p, q, lh, e0);
+            inv_stage<4, kLatE>(x, iw, p, q, lh, e0);
+            uint32_t* const rowI = scrI + 65 * lh + e0;
+            uint32_t* const colI = scrI + lh + 32 * e0 + (e0 >> 1);
+#pragma unroll
+            for (int el = 0; el < kLatE; ++el) rowI[el] = x[el];
+            __syncthreads();
+#pragma unroll
+            for (int el = 0; el < kLatE; ++el) x[el] = colI[32 * el + (el >> 1)];
+            inv_stage<5, kLatE>(x, iw, p, q, lh, e0);
+            inv_stage<6, kLatE>(x, iw, p, q, lh, e0);
+            inv_stage<7, kLatE>(x, iw, p, q, lh, e0);
+            inv_stage<8, kLatE>(x, iw, p, q, lh, e0);
+            inv_stage<9, kLatE>(x, iw, p, q, lh, e0);
+            uint32_t* const nat = scrF + lh + 32 * e0;
+#pragma unroll
+            for (int el = 0; el < kLatE; ++el) nat[32 * el] = x[el];
+            __syncthreads();
+            // last inverse stage (coefficients c and c + 1024), then the CRT
+#pragma unroll
+            for (int k = 0; k < kLatAcc; k += 2) {
+                const int at = lat_poly(k) * kPoly + lat_coef(tid, k);
+                uint32_t rlo[kPrimes], rhi[kPrimes];
+#pragma unroll
+                for (int w = 0; w < kPrimes; ++w) {
+                    const uint32_t pw = A.crt.p[w];
+                    const uint32_t u0 = F[w * 2 * kPoly + at];
+                    const uint32_t u1 = F[w * 2 * kPoly + at + kN / 2];
+                    rlo[w] = u0 + u1;                                        // below 16 p_w
+                    rhi[w] = mul_shoup(u0 + 8 * pw - u1, wlast[w].x, wlast[w].y, pw);
+                }
+                acc[k] += crt_lift(rlo, A.crt);
+                acc[k + 1] += crt_lift(rhi, A.crt);
+            }
+        }
+        // sample extraction of coefficient 0, then the job's output rule
+#pragma unroll
+        for (int k = 0; k < kLatAcc; ++k) {
+            const int at = lat_poly(k) * kPoly + lat_coef(tid, k);
+            acc_lo[at] = uint32_t(acc[k]);
+            acc_hi[at] = uint32_t(acc[k] >> 32);
+        }
+        __syncthreads();
+        for (int t = tid; t < kCtWords; t += kLatThreads) {
             const int at = (t == 0) ? 0 : (t < kN) ? kN - t : kPoly;
             const uint64_t m = uint64_t(acc_lo[at]) | (uint64_t(acc_hi[at]) << 32);
             const uint64_t v = (t > 0 && t < kN) ? uint64_t(0) - m : m;
@@ -628,10 +847,10 @@ hipError_t launch_keyswitch_jobs(const Job* jobs, int B, const uint64_t* ksk, ui
 }
 
 hipError_t prepare_kernels() {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(dev::blind_rotate_kernel<1>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(dev::kBrLds));
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(dev::blind_rotate_latency_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(dev::kLatLds));
     if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(dev::blind_rotate_kernel<2>),
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(dev::blind_rotate_kernel),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(dev::kBrLds));
     return e;
 }
@@ -651,9 +870,9 @@ hipError_t launch_blind_rotate_jobs(const Job* jobs, int B, const uint64_t* part
     A.B = B;
     if (grid <= 0 || grid > B) grid = B;
     if (B <= latency_form_max)
-        hipLaunchKernelGGL(dev::blind_rotate_kernel<1>, dim3(grid), dim3(dev::kBrThreads), dev::kBrLds, st, A);
+        hipLaunchKernelGGL(dev::blind_rotate_latency_kernel, dim3(grid), dim3(dev::kLatThreads), dev::kLatLds, st, A);
     else
-        hipLaunchKernelGGL(dev::blind_rotate_kernel<2>, dim3(grid), dim3(dev::kBrThreads), dev::kBrLds, st, A);
+        hipLaunchKernelGGL(dev::blind_rotate_kernel, dim3(grid), dim3(dev::kBrThreads), dev::kBrLds, st, A);
     return hipGetLastError();
 }
 

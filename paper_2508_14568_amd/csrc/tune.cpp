@@ -1,8 +1,7 @@
 // Launch-shape tuning of the blind rotation.
 //
-// The blind rotation has two forms (one workgroup per CU with the step's key
-// values prefetched, or two workgroups per CU) and an optional persistent
-// grid.  Which is faster depends on how a batch fills the device, so the
+// The blind rotation has two forms (one eight-wave workgroup per CU, or two
+// four-wave workgroups per CU) and an optional persistent grid.  Which is faster depends on how a batch fills the device, so the
 // autotuner times both forms, and a persistent grid, on batches around the
 // CU count and keeps the fastest shape per batch size.  Its inputs are zero
 // ciphertexts: the work of a bootstrap does not depend on the values.
@@ -141,12 +140,15 @@ int lvs_autotune(lvs_context* ctx, size_t max_batch, void* d_work, size_t work_b
             if (r.batch == B && r.form == form && r.grid == grid) return r.ms;
         return -1.0;
     };
-    // the latency form while it is at least as fast, in increasing batch order
+    // the latency form while it is at least as fast, in increasing batch
+    // order; if it is at every size tried, it takes every size
     lvs_tuning t{};
     t.latency_form_max = 0;
-    for (int B : tune_batches(cus, max_batch)) {
-        if (time_of(B, 1, B) <= time_of(B, 2, B)) t.latency_form_max = B;
-        else break;
+    const std::vector<int> tried_b = tune_batches(cus, max_batch);
+    for (size_t k = 0; k < tried_b.size(); ++k) {
+        const int B = tried_b[k];
+        if (time_of(B, 1, B) > time_of(B, 2, B)) break;
+        t.latency_form_max = (k + 1 == tried_b.size()) ? INT_MAX : B;
     }
     // a persistent grid only if it wins by more than 1% at every batch that tried it
     bool tried = false, wins = true;

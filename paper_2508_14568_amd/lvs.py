@@ -622,8 +622,8 @@ def autotune(ctx: Context, max_batch: int = None, cache: str = None) -> dict:
 KERNEL_BLIND_ROTATE = 0              # both forms
 KERNEL_KEYSWITCH = 1
 KERNEL_GRAPH = 2
-KERNEL_BLIND_ROTATE_LATENCY = 3      # one workgroup per CU
-KERNEL_BLIND_ROTATE_THROUGHPUT = 4   # two workgroups per CU
+KERNEL_BLIND_ROTATE_LATENCY = 3      # eight-wave form, one workgroup per CU
+KERNEL_BLIND_ROTATE_THROUGHPUT = 4   # four-wave form, two workgroups per CU
 
 
 def lvs_microbench_modmul(ctx: Context, iters: int = 4096):
