@@ -38,10 +38,9 @@ struct CrtConsts {
     uint32_t p[kPrimes];
     uint32_t mont[kPrimes];
     uint32_t red[kPrimes];                 // floor(2^32 / p)
-    uint32_t garner[kPrimes][kPrimes];
-    uint32_t garner_s[kPrimes][kPrimes];
-    uint64_t prod[kPrimes];
-    uint64_t Q;
+    uint32_t g[kPrimes];                   // floor(2^57 / p)
+    uint64_t m[kPrimes];                   // Q / p mod 2^64
+    uint64_t Q;                            // Q mod 2^64
 };
 
 struct Tw {
@@ -196,30 +195,20 @@ __device__ __forceinline__ void ntt_inverse(uint32_t (&x)[kEh], uint32_t* scr, c
     inv_stage<10>(x, w, p, q, lh);
 }
 
-// Residues r[0..3] (each below 16 p_i, not necessarily reduced) of a signed
-// integer |X| < prod/2 -> X mod 2^64 (Garner mixed radix, then the signed
-// lift).  Only v_0 = r_0 mod p_0 needs an explicit reduction: every later
-// digit passes through a Shoup product, which accepts any word below 2^32.
-__device__ __forceinline__ uint64_t crt_lift(const uint32_t (&r)[kPrimes], const CrtConsts& C) {
-    uint32_t v[kPrimes];
-    v[0] = csub(reduce2p(r[0], C.red[0], C.p[0]), C.p[0]);
+// Explicit CRT.  y_i (any representative below 2^30) of X (Q/p_i)^{-1} mod
+// p_i for a signed integer |X| <= 2^97 < Q / 2^6.9 -> X mod 2^64.  As
+// integers sum_i y_i (Q/p_i) = X + K Q with K = sum_i y_i / p_i - X / Q, so K
+// is the integer nearest sum y_i / p_i (within 2^-6.9 of it); the fixed-point
+// sum of y_i floor(2^57 / p_i) is within 2^-25 of that sum, so rounding it
+// gives K exactly, and X = sum y_i (Q/p_i) - K Q mod 2^64.
+__device__ __forceinline__ uint64_t crt_lift(const uint32_t (&y)[kPrimes], const CrtConsts& C) {
+    uint64_t s = uint64_t(1) << 56, x = 0;
 #pragma unroll
-    for (int i = 1; i < kPrimes; ++i) {
-        const uint32_t p = C.p[i];
-        uint32_t t = r[i];
-#pragma unroll
-        for (int j = 0; j < i; ++j) {
-            // t = (t - v_j) * p_j^{-1} mod p_i; v_j < p_j < 2 p_i
-            t = mul_shoup(t + 2 * p - v[j], C.garner[i][j], C.garner_s[i][j], p);
-            t = csub(t, p);
-        }
-        v[i] = t;
+    for (int i = 0; i < kPrimes; ++i) {
+        s += uint64_t(y[i]) * C.g[i];
+        x += uint64_t(y[i]) * C.m[i];
     }
-    uint64_t x = v[0];
-#pragma unroll
-    for (int i = 1; i < kPrimes; ++i) x += uint64_t(v[i]) * C.prod[i];
-    if (v[kPrimes - 1] > (C.p[kPrimes - 1] >> 1)) x -= C.Q;
-    return x;
+    return x - (s >> 57) * C.Q;
 }
 
 // ------------------------------------------------------------ key switch
@@ -801,11 +790,8 @@ dev::CrtConsts make_crt() {
         C.p[i] = T.p[i];
         C.mont[i] = T.mont_neg_inv[i];
         C.red[i] = T.reduce_q[i];
-        C.prod[i] = T.prod_mod64[i];
-        for (int j = 0; j < kPrimes; ++j) {
-            C.garner[i][j] = T.garner[i][j];
-            C.garner_s[i][j] = T.garner_shoup[i][j];
-        }
+        C.g[i] = T.crt_g[i];
+        C.m[i] = T.crt_m[i];
     }
     C.Q = T.Q_mod64;
     return C;

@@ -62,11 +62,13 @@ struct PrimeTables {
     uint32_t mont_neg_inv[kPrimes];          // -p^{-1} mod 2^32
     // forward / inverse twiddles psi^{+-brv(k)} in [0, p) with Shoup companions floor(w 2^32 / p)
     std::vector<uint32_t> fwd, fwd_shoup, inv, inv_shoup;   // [kPrimes][kN]
-    uint32_t bsk_scale[kPrimes];             // N^{-1} * 2^32 mod p (Montgomery form of the 1/N)
+    // N^{-1} (Q/p)^{-1} 2^32 mod p: the bootstrapping key's scale (Montgomery
+    // form of the 1/N of the inverse transform and of the CRT weight)
+    uint32_t bsk_scale[kPrimes];
     uint32_t reduce_q[kPrimes];              // floor(2^32 / p): reduction of a word to [0, 2p)
-    // Garner CRT: c[i][j] = p_j^{-1} mod p_i (j < i), with Shoup companions
-    uint32_t garner[kPrimes][kPrimes], garner_shoup[kPrimes][kPrimes];
-    uint64_t prod_mod64[kPrimes];            // p_0 ... p_{i-1} mod 2^64 (prod_mod64[0] = 1)
+    // explicit CRT: X = sum_i y_i M_i - K Q with y_i = X (Q/p_i)^{-1} mod p_i
+    uint64_t crt_m[kPrimes];                 // M_i = Q / p_i mod 2^64
+    uint32_t crt_g[kPrimes];                 // floor(2^57 / p_i): fixed-point 1/p_i for K
     uint64_t Q_mod64;                        // p_0 p_1 p_2 p_3 mod 2^64
 };
 const PrimeTables& prime_tables();

@@ -1,5 +1,5 @@
 // Constants of the exact negacyclic products: four NTT primes, twiddle
-// tables, Montgomery and Garner (CRT) constants.
+// tables, Montgomery and explicit-CRT constants.
 //
 // A product of a decomposed polynomial (23-bit signed digits) with a GGSW row
 // (64-bit coefficients read as signed) has integer coefficients bounded by
@@ -90,24 +90,28 @@ PrimeTables build() {
         uint32_t inv = uint32_t(p);
         for (int it = 0; it < 5; ++it) inv *= 2u - uint32_t(p) * inv;
         t.mont_neg_inv[r] = 0u - inv;
-        // The inverse transform is left unscaled; 1/N is folded into the
-        // bootstrapping key, stored in Montgomery form (times 2^32).
-        const uint64_t ninv = powmod(kN, p - 2, p);
-        t.bsk_scale[r] = uint32_t(mulmod(ninv, (uint64_t(1) << 32) % p, p));
         t.reduce_q[r] = uint32_t((uint64_t(1) << 32) / p);
     }
-    for (int i = 0; i < kPrimes; ++i)
-        for (int j = 0; j < kPrimes; ++j) {
-            const uint32_t c = (j < i) ? uint32_t(powmod(t.p[j] % t.p[i], t.p[i] - 2, t.p[i])) : 0;
-            t.garner[i][j] = c;
-            t.garner_shoup[i][j] = (j < i) ? shoup(c, t.p[i]) : 0;
-        }
-    uint64_t prod = 1;
-    for (int i = 0; i < kPrimes; ++i) {
-        t.prod_mod64[i] = prod;
-        prod *= t.p[i];
+    // Explicit CRT: the residues reaching the CRT are y_i = X (Q/p_i)^{-1} mod
+    // p_i because the transforms are linear and the weight (Q/p_i)^{-1} is
+    // folded into the key together with 1/N; then X = sum y_i M_i - K Q.
+    uint64_t Q = 1;
+    for (int i = 0; i < kPrimes; ++i) Q *= t.p[i];
+    t.Q_mod64 = Q;
+    for (int r = 0; r < kPrimes; ++r) {
+        const uint64_t p = t.p[r];
+        uint64_t m64 = 1, mp = 1;
+        for (int j = 0; j < kPrimes; ++j)
+            if (j != r) {
+                m64 *= t.p[j];
+                mp = mulmod(mp, t.p[j], p);
+            }
+        t.crt_m[r] = m64;
+        t.crt_g[r] = uint32_t((uint64_t(1) << 57) / p);
+        const uint64_t c = powmod(mp, p - 2, p);            // (Q/p)^{-1} mod p
+        const uint64_t ninv = powmod(kN, p - 2, p);
+        t.bsk_scale[r] = uint32_t(mulmod(mulmod(ninv, c, p), (uint64_t(1) << 32) % p, p));
     }
-    t.Q_mod64 = prod;
     return t;
 }
 
