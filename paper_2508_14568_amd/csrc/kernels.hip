@@ -406,7 +406,8 @@ __global__ void __launch_bounds__(kBrThreads, 2) blind_rotate_kernel(BrArgs A) {
 #pragma unroll
             for (int e = 0; e < kEh; ++e) x[e] = dig[h * kPoly + lh + 32 * e] + unbias;
             ntt_forward<true>(x, scr, fw, p, lh);
-            // products with the GGSW rows: out_h = D0 K[0][h] + D1 K[1][h]
+            // products with the GGSW rows: out_h = D_h K[h][h] + D_{1-h} K[1-h][h]
+            // (the key holds the pair of a lane in that order)
 #pragma unroll
             for (int e = 0; e < kEh; e += 2) {
                 const uint4 kq = K[(e >> 1) * 32];
@@ -414,11 +415,7 @@ __global__ void __launch_bounds__(kBrThreads, 2) blind_rotate_kernel(BrArgs A) {
                 for (int o = 0; o < 2; ++o) {
                     const uint32_t own = x[e + o];
                     const uint32_t other = swap_halves(own, lane);
-                    const uint32_t d0 = h ? other : own;
-                    const uint32_t d1 = h ? own : other;
-                    const uint32_t k0 = o ? kq.z : kq.x;
-                    const uint32_t k1 = o ? kq.w : kq.y;
-                    x[e + o] = redc(uint64_t(d0) * k0 + uint64_t(d1) * k1, p, mont);
+                    x[e + o] = redc(uint64_t(own) * (o ? kq.z : kq.x) + uint64_t(other) * (o ? kq.w : kq.y), p, mont);
                 }
             }
             // (4)
@@ -468,14 +465,13 @@ __global__ void __launch_bounds__(kBrThreads, 2) blind_rotate_kernel(BrArgs A) {
 // waves per prime, wave part g holding the lane's elements 32 g .. 32 g + 31
 // of both polynomials, so a bootstrap has twice the waves (and half the
 // dependent work per wave) of the forms above.  Of the 11 forward stages only
-// the first pairs the two halves (coefficients j and j + 1024); each wave
-// computes it for its own half straight from the digits, which it reads for
-// both halves.  Of the 11 inverse stages only the last pairs them; it runs in
-// the CRT step, where one thread holds both coefficients of a pair.  The
-// transposes between the two in-lane layouts go through LDS shared by the two
-// waves of a prime, double-buffered (forward transposes and residues in F,
-// the accumulator copy, digits and inverse transposes in I) so that five
-// barriers per CMux order every access.  Positions after the forward
+// the first pairs the two halves (coefficients j and j + 1024), and of the 11
+// inverse stages only the last: both run where one thread holds both
+// coefficients of a pair, the first in the digit phase (for all four primes,
+// straight from the digits, which never reach LDS), the last in the CRT step.
+// Two LDS buffers alternate, F (first-stage outputs, inverse transposes) and
+// I (accumulator copy, forward transposes, residues), so that five barriers
+// per CMux order every access.  Positions after the forward
 // transform are those of the forms above (lane lh, element e = 32 g + e'':
 // position 64 lh + e), so the bootstrapping key is shared with them.
 constexpr int kLatThreads = 512;
@@ -494,9 +490,10 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
     uint32_t* F = reinterpret_cast<uint32_t*>(lds);      // [kPrimes][2][kPoly]
     uint32_t* I = F + kPrimes * 2 * kPoly;               // [kPrimes][2][kPoly]
     uint32_t* abar = I + kPrimes * 2 * kPoly;            // [n+1]
+    // the accumulator copy sits at the residue slots of primes 0 and 1 that
+    // the writing thread alone reads in the CRT step
     uint32_t* acc_lo = I;                                // [2][kPoly]
     uint32_t* acc_hi = I + 2 * kPoly;
-    uint32_t* dig = I + 4 * kPoly;                       // [2][kPoly]
 
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -513,11 +510,12 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
     const uint2* iw = A.tw.inv + size_t(r) * kN;
     uint32_t* scrF = F + (r * 2 + h) * kPoly;
     uint32_t* scrI = I + (r * 2 + h) * kPoly;
-    const uint32_t unbias = p - (1u << 22);
-    const uint2 w0 = fw[1];           // twiddle of forward stage 0
-    uint2 wlast[kPrimes];             // twiddle of the last inverse stage, every prime
+    uint2 wfirst[kPrimes], wlast[kPrimes];   // twiddles of forward stage 0 and inverse stage 10, every prime
 #pragma unroll
-    for (int w = 0; w < kPrimes; ++w) wlast[w] = A.tw.inv[size_t(w) * kN + 1];
+    for (int w = 0; w < kPrimes; ++w) {
+        wfirst[w] = A.tw.fwd[size_t(w) * kN + 1];
+        wlast[w] = A.tw.inv[size_t(w) * kN + 1];
+    }
 
     for (int b = blockIdx.x; b < A.B; b += gridDim.x) {
         const Job& J = A.jobs[b];
@@ -555,38 +553,48 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
                 acc_hi[at] = uint32_t(acc[k] >> 32);
             }
             __syncthreads();
-            // digits of X^a ACC - ACC
+            // digits of X^a ACC - ACC for a pair (c, c + 1024), then the first
+            // forward stage of every prime on the pair into F
 #pragma unroll
-            for (int k = 0; k < kLatAcc; ++k) {
+            for (int k = 0; k < kLatAcc; k += 2) {
                 const int qq = lat_poly(k);
-                const uint32_t c = uint32_t(lat_coef(tid, k));
-                const uint32_t src = (c - a) & (2 * kN - 1);
-                const int at = qq * kPoly + int(src & (kN - 1));
-                uint64_t rr = uint64_t(acc_lo[at]) | (uint64_t(acc_hi[at]) << 32);
-                if (src >= uint32_t(kN)) rr = uint64_t(0) - rr;
-                const uint64_t t = rr - acc[k];
-                const uint32_t u = ((uint32_t(t >> 40) + 1) >> 1) & 0x7FFFFFu;
-                dig[qq * kPoly + c] = (u + 0x400000u) & 0x7FFFFFu;
+                uint32_t u[2];
+#pragma unroll
+                for (int o = 0; o < 2; ++o) {
+                    const uint32_t c = uint32_t(lat_coef(tid, k + o));
+                    const uint32_t src = (c - a) & (2 * kN - 1);
+                    const int at = qq * kPoly + int(src & (kN - 1));
+                    uint64_t rr = uint64_t(acc_lo[at]) | (uint64_t(acc_hi[at]) << 32);
+                    if (src >= uint32_t(kN)) rr = uint64_t(0) - rr;
+                    const uint64_t t = rr - acc[k + o];
+                    // round(t / 2^41) as a balanced 23-bit digit d, kept as d + 2^22
+                    u[o] = ((((uint32_t(t >> 40) + 1) >> 1) & 0x7FFFFFu) + 0x400000u) & 0x7FFFFFu;
+                }
+                const int at = qq * kPoly + lat_coef(tid, k);
+#pragma unroll
+                for (int w = 0; w < kPrimes; ++w) {
+                    // residues of the digits below 2p: d + 2^22 + (p - 2^22)
+                    const uint32_t pw = A.crt.p[w];
+                    const uint32_t lo = u[0] + (pw - (1u << 22)), hi = u[1] + (pw - (1u << 22));
+                    const uint32_t s = __umulhi(hi, wfirst[w].y) * pw - hi * wfirst[w].x;
+                    F[w * 2 * kPoly + at] = lo - s;
+                    F[w * 2 * kPoly + at + kN / 2] = lo + 2 * pw + s;
+                }
             }
             __syncthreads();
-            // forward transform: stage 0 for this half from both halves' digits
+            // forward transform, stages 1..10, of this wave's half
             uint32_t x[kLatE];
-            const uint32_t* const dj = dig + h * kPoly + lh;   // coefficient lh + 32 el (< 1024) and + 1024
+            const uint32_t* const nat0 = scrF + lh + 32 * e0;
 #pragma unroll
-            for (int el = 0; el < kLatE; ++el) {
-                const uint32_t lo = dj[32 * el] + unbias;
-                const uint32_t hi = dj[32 * el + kN / 2] + unbias;
-                const uint32_t s = __umulhi(hi, w0.y) * p - hi * w0.x;
-                x[el] = g ? lo + 2 * p + s : lo - s;
-            }
+            for (int el = 0; el < kLatE; ++el) x[el] = nat0[32 * el];
             fwd_stage<1, kLatE>(x, fw, p, lh, e0);
             fwd_stage<2, kLatE>(x, fw, p, lh, e0);
             fwd_stage<3, kLatE>(x, fw, p, lh, e0);
             fwd_stage<4, kLatE>(x, fw, p, lh, e0);
             fwd_stage<5, kLatE>(x, fw, p, lh, e0);
             // pad(lh + 32 e) = lh + 32 e + (e >> 1) and pad(64 lh + e) = 65 lh + e (lh < 32, e < 64)
-            uint32_t* const col = scrF + lh + 32 * e0 + (e0 >> 1);
-            uint32_t* const row = scrF + 65 * lh + e0;
+            uint32_t* const col = scrI + lh + 32 * e0 + (e0 >> 1);
+            uint32_t* const row = scrI + 65 * lh + e0;
 #pragma unroll
             for (int el = 0; el < kLatE; ++el) col[32 * el + (el >> 1)] = x[el];
             __syncthreads();
@@ -597,7 +605,7 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
             fwd_stage<8, kLatE>(x, fw, p, lh, e0);
             fwd_stage<9, kLatE>(x, fw, p, lh, e0);
             fwd_stage<10, kLatE>(x, fw, p, lh, e0);
-            // products with the GGSW rows
+            // products with the GGSW rows (own digit first, as in the key)
 #pragma unroll
             for (int el = 0; el < kLatE; el += 2) {
                 const uint4 kq = kpre[el >> 1];
@@ -605,11 +613,7 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
                 for (int o = 0; o < 2; ++o) {
                     const uint32_t own = x[el + o];
                     const uint32_t other = swap_halves(own, lane);
-                    const uint32_t d0 = h ? other : own;
-                    const uint32_t d1 = h ? own : other;
-                    const uint32_t k0 = o ? kq.z : kq.x;
-                    const uint32_t k1 = o ? kq.w : kq.y;
-                    x[el + o] = redc(uint64_t(d0) * k0 + uint64_t(d1) * k1, p, mont);
+                    x[el + o] = redc(uint64_t(own) * (o ? kq.z : kq.x) + uint64_t(other) * (o ? kq.w : kq.y), p, mont);
                 }
             }
             // inverse transform, stages 0..9
@@ -618,8 +622,8 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
             inv_stage<2, kLatE>(x, iw, p, q, lh, e0);
             inv_stage<3, kLatE>(x, iw, p, q, lh, e0);
             inv_stage<4, kLatE>(x, iw, p, q, lh, e0);
-            uint32_t* const rowI = scrI + 65 * lh + e0;
-            uint32_t* const colI = scrI + lh + 32 * e0 + (e0 >> 1);
+            uint32_t* const rowI = scrF + 65 * lh + e0;
+            uint32_t* const colI = scrF + lh + 32 * e0 + (e0 >> 1);
 #pragma unroll
             for (int el = 0; el < kLatE; ++el) rowI[el] = x[el];
             __syncthreads();
@@ -630,7 +634,7 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
             inv_stage<7, kLatE>(x, iw, p, q, lh, e0);
             inv_stage<8, kLatE>(x, iw, p, q, lh, e0);
             inv_stage<9, kLatE>(x, iw, p, q, lh, e0);
-            uint32_t* const nat = scrF + lh + 32 * e0;
+            uint32_t* const nat = scrI + lh + 32 * e0;
 #pragma unroll
             for (int el = 0; el < kLatE; ++el) nat[32 * el] = x[el];
             __syncthreads();
@@ -642,8 +646,8 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
 #pragma unroll
                 for (int w = 0; w < kPrimes; ++w) {
                     const uint32_t pw = A.crt.p[w];
-                    const uint32_t u0 = F[w * 2 * kPoly + at];
-                    const uint32_t u1 = F[w * 2 * kPoly + at + kN / 2];
+                    const uint32_t u0 = I[w * 2 * kPoly + at];
+                    const uint32_t u1 = I[w * 2 * kPoly + at + kN / 2];
                     rlo[w] = u0 + u1;                                        // below 16 p_w
                     rhi[w] = mul_shoup(u0 + 8 * pw - u1, wlast[w].x, wlast[w].y, pw);
                 }
@@ -686,8 +690,11 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
 __global__ void __launch_bounds__(64) bsk_convert_kernel(const uint64_t* __restrict__ bsk, uint32_t* __restrict__ out,
                                                         Tw tw, CrtConsts C, const uint32_t* scale,
                                                         const uint32_t* scale_s) {
-    // output order [i][prime][h][e / 2][lh][e % 2][rho]: one 16-byte load gives
-    // both rows' values of two neighbouring positions
+    // output order [i][prime][h][e / 2][lh][e % 2][rho ^ h]: one 16-byte load
+    // gives both rows' values of two neighbouring positions, for lanes of the
+    // body polynomial (h = 1) with the rows swapped, so that every lane
+    // multiplies its own transformed digit by the first value of a pair
+    // (D_h K[h][h]) and the other lane's by the second (D_{1-h} K[1-h][h])
     __shared__ uint32_t scratch[2 * kPoly];
     const int lane = threadIdx.x;
     const int h = lane >> 5, lh = lane & 31;
@@ -706,7 +713,7 @@ __global__ void __launch_bounds__(64) bsk_convert_kernel(const uint64_t* __restr
     ntt_forward<false>(x, scratch + h * kPoly, tw.fwd + size_t(r) * kN, p, lh);
     const uint32_t sc = scale[r], scs = scale_s[r];
     const int i = row >> 1, rho = row & 1;
-    uint32_t* dst = out + ((size_t(i) * kPrimes + r) * 2 + h) * (2 * kN) + lh * 4 + rho;
+    uint32_t* dst = out + ((size_t(i) * kPrimes + r) * 2 + h) * (2 * kN) + lh * 4 + (rho ^ h);
 #pragma unroll
     for (int e = 0; e < kEh; ++e) dst[(e >> 1) * 128 + (e & 1) * 2] = csub(mul_shoup(x[e], sc, scs, p), p);
 }
