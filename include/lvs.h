@@ -318,7 +318,9 @@ int lvs_plan_workspace_bytes(const lvs_query* queries, size_t nq, int encoding, 
 /* Batch of edit distances (batch input matching, Section 6.2): the equality
  * bootstraps of every pair of every query form the first step(s); then step
  * s = 2 .. max(m + n) bootstraps every ready cell (i, s - i) of every query
- * in one key-switch launch and one persistent blind-rotation launch.  The
+ * in one key-switch launch and one blind-rotation launch, together with the
+ * equality bootstraps of the next diagonals (and, to fill the device's last
+ * partial round of the step, of later ones).  The
  * schedule is static (no data-dependent branch exists under encryption), so
  * it is built and uploaded once into d_work and, with LVS_PLAN_GRAPH,
  * captured as one HIP graph.  Query buffers are referenced, not copied: they
@@ -326,6 +328,19 @@ int lvs_plan_workspace_bytes(const lvs_query* queries, size_t nq, int encoding, 
  * computing each query alone. */
 int lvs_plan_create(lvs_context* ctx, const lvs_query* queries, size_t nq, int encoding, int flags, void* d_work,
                     size_t work_bytes, lvs_plan** out);
+
+/* Host-side check of the schedule lvs_plan_create builds for these queries
+ * (no device, nothing dereferenced: the query pointers only name buffers).
+ * round: bootstraps the device runs at once (>= 1); with fill != 0 the
+ * schedule fills the last partial round of each step with equality
+ * bootstraps of later diagonals, as lvs_plan_create does with the device's
+ * round.  Returns the steps, bootstraps, device rounds (sum over steps of
+ * ceil(count / round)) and violations: reads of a word the plan writes
+ * before an earlier step has written it, subtrahend reads or writes of a
+ * word another job of the same step writes, and steps larger than the
+ * workspace bound. */
+int lvs_plan_verify(const lvs_query* queries, size_t nq, int encoding, size_t round, int fill, size_t* steps,
+                    size_t* jobs, size_t* rounds, size_t* violations);
 
 /* Enqueues one execution of the plan on the context's stream. */
 int lvs_plan_run(lvs_plan* plan);

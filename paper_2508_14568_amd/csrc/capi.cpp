@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <set>
 #include <climits>
 #include <cstring>
 #include <new>
@@ -110,6 +112,13 @@ size_t max_step_of(const std::vector<QuerySpec>& qs) {
         step += eq ? (q.encoding == LVS_ENC_ASCII7 ? 3 : 2) * w : w;
     }
     return step;
+}
+
+// Bootstraps the device runs at once for steps of up to cap bootstraps: one
+// per CU in the eight-wave form, two per CU in the four-wave form.
+size_t round_of(const Context* C, size_t cap) {
+    const size_t cus = size_t(std::max(1, C->cus));
+    return cap <= size_t(C->latency_form_max) ? cus : 2 * cus;
 }
 
 size_t plan_ws(const std::vector<QuerySpec>& qs) {
@@ -472,7 +481,8 @@ int lvs_edit_distance(lvs_context* ctx, const uint64_t* d_a, size_t m, const uin
     uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
     assign_buffers(qs, ws);
     Plan P;
-    build_edit_distance_plan(qs, P);
+    const size_t cap = max_step_of(qs);
+    build_edit_distance_plan(qs, P, true, round_of(C, cap), cap);
     return execute(C, P, ws);
 }
 
@@ -504,7 +514,8 @@ int lvs_edit_distance_band(lvs_context* ctx, const uint64_t* d_a, size_t m, cons
     uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
     assign_buffers(qs, ws);
     Plan P;
-    build_edit_distance_plan(qs, P);
+    const size_t cap = max_step_of(qs);
+    build_edit_distance_plan(qs, P, true, round_of(C, cap), cap);
     return execute(C, P, ws);
 }
 
@@ -689,7 +700,8 @@ int lvs_plan_create(lvs_context* ctx, const lvs_query* queries, size_t nq, int e
     H->C = C;
     uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
     assign_buffers(qs, ws);
-    build_edit_distance_plan(qs, H->P);
+    const size_t cap = max_step_of(qs);
+    build_edit_distance_plan(qs, H->P, true, round_of(C, cap), cap);
     hipError_t e = upload_plan(H->P, ws, C->stream);
     if (e == hipSuccess && (flags & LVS_PLAN_GRAPH)) e = capture_plan(C, H->P);
     if (e != hipSuccess) {
@@ -698,6 +710,69 @@ int lvs_plan_create(lvs_context* ctx, const lvs_query* queries, size_t nq, int e
         return LVS_E_DEVICE;
     }
     *out = reinterpret_cast<lvs_plan*>(H);
+    return LVS_OK;
+}
+
+int lvs_plan_verify(const lvs_query* queries, size_t nq, int encoding, size_t round, int fill, size_t* steps,
+                    size_t* jobs, size_t* rounds, size_t* violations) {
+    LVS_REQUIRE(queries || nq == 0, LVS_E_INVAL, "lvs_plan_verify: NULL queries");
+    LVS_REQUIRE(valid_encoding(encoding), LVS_E_INVAL, "unknown encoding");
+    std::vector<QuerySpec> qs;
+    int rc = make_specs(queries, nq, encoding, qs);
+    if (rc) return rc;
+    // workspace buffers at addresses above every caller address; nothing is dereferenced
+    uintptr_t top = 0;
+    for (size_t k = 0; k < nq; ++k)
+        for (uintptr_t a : {uintptr_t(queries[k].d_a), uintptr_t(queries[k].d_b), uintptr_t(queries[k].d_table),
+                            uintptr_t(queries[k].d_h_last), uintptr_t(queries[k].d_path)})
+            top = std::max(top, a);
+    uint8_t* ws = reinterpret_cast<uint8_t*>((top + (uintptr_t(1) << 40)) & ~uintptr_t(255));
+    assign_buffers(qs, ws);
+    Plan P;
+    const size_t cap = max_step_of(qs);
+    build_edit_distance_plan(qs, P, true, fill ? round : 0, cap);
+    // Sweeping the steps in order: a word that some job of the plan writes
+    // may only be read (as a source or a subtrahend) once an earlier step has
+    // written it; within a step the key switch reads every source before the
+    // blind rotation writes, but the blind rotation's subtrahend reads and
+    // writes run together, so a subtrahend that another job of the same step
+    // writes, or a word two jobs of a step write, is a race.  No step may
+    // exceed the workspace's bound.
+    std::set<uintptr_t> produced, seen;
+    for (const Job& J : P.jobs)
+        for (int d = 0; d < 4; ++d)
+            if (J.dst[d]) produced.insert(uintptr_t(J.dst[d]));
+    size_t bad = 0, nrounds = 0;
+    const size_t r = std::max<size_t>(round, 1);
+    for (size_t st = 0; st < P.steps.size(); ++st) {
+        const PlanStep& S = P.steps[st];
+        nrounds += (S.count + r - 1) / r;
+        if (S.count > cap) ++bad;
+        std::map<uintptr_t, size_t> writer;
+        for (size_t x = S.off; x < S.off + S.count; ++x) {
+            const Job& J = P.jobs[x];
+            const void* reads[5] = {J.src[0], J.src[1], J.src[2], J.sub[0], J.sub[1]};
+            for (const void* rd : reads)
+                if (rd && produced.count(uintptr_t(rd)) && !seen.count(uintptr_t(rd))) ++bad;
+            for (int d = 0; d < 4; ++d) {
+                if (!J.dst[d]) continue;
+                auto ins = writer.emplace(uintptr_t(J.dst[d]), x);
+                if (!ins.second && ins.first->second != x) ++bad;
+            }
+        }
+        for (size_t x = S.off; x < S.off + S.count; ++x)
+            for (int k = 0; k < 2; ++k) {
+                const Job& J = P.jobs[x];
+                if (!J.sub[k]) continue;
+                auto it = writer.find(uintptr_t(J.sub[k]));
+                if (it != writer.end() && it->second != x) ++bad;
+            }
+        for (const auto& w : writer) seen.insert(w.first);
+    }
+    if (steps) *steps = P.steps.size();
+    if (jobs) *jobs = P.jobs.size();
+    if (rounds) *rounds = nrounds;
+    if (violations) *violations = bad;
     return LVS_OK;
 }
 

@@ -145,7 +145,7 @@ void for_diagonal(const QuerySpec& q, size_t s, F&& f) {
 
 }  // namespace
 
-void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool with_dp) {
+void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool with_dp, size_t quantum, size_t cap) {
     Builder b(P);
     size_t smax = 0;
     bool any_ascii = false;
@@ -188,20 +188,57 @@ void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool wi
         for (size_t i = q.n + 1; i <= q.m; ++i)
             if (!in_band(q, i, q.n)) P.fills.push_back({q.path + (2 * q.n + (i - q.n - 1)) * W, 1});
     }
-    // Step t bootstraps the cells of anti-diagonal t (t >= 2) together with
-    // the equality of the cells they feed: the last equality stage of
-    // diagonal t + 1 and, for ASCII, the first stage of diagonal t + 2
-    // (Algorithm 4 evaluates equality inside the loop; each result is ready
-    // one step before it is read).
+    // Step t bootstraps the cells of anti-diagonal t (t >= 2).  Equality has
+    // no dependence on the DP (Algorithm 4 evaluates it inside the loop, but
+    // any earlier step will do): each cell's last equality stage must run by
+    // step t - 1 and, for ASCII, its first stage by step t - 2.  Those
+    // deadlines are met exactly; then, when a device round holds `quantum`
+    // bootstraps, the last partial round of a step is filled with equality
+    // jobs of later diagonals, earliest deadline first (a last stage only
+    // once its first stage ran in an earlier step), never past `cap`.
+    struct Diag {
+        std::vector<std::pair<size_t, std::pair<size_t, size_t>>> cells;   // (query, (i, j)) with equality
+        size_t n1 = 0, n1_before = 0, n2 = 0;   // first stages placed (in earlier steps), last stages placed
+    };
+    std::vector<Diag> eqd(smax + 3);
+    for (size_t k = 0; k < qs.size(); ++k) {
+        const QuerySpec& q = qs[k];
+        if (!both_encrypted(q)) continue;
+        for (size_t s = 2; s <= q.m + q.n; ++s)
+            for_diagonal(q, s, [&](size_t i, size_t j) { eqd[s].cells.push_back({k, {i, j}}); });
+    }
+    // ASCII and DNA queries may share a plan: a DNA cell has one stage (eq9,
+    // deadline s - 1), an ASCII cell two; keep them in separate lists
+    std::vector<Diag> eqd2(smax + 3);     // cells with a single stage (DNA)
+    for (size_t s = 0; s < eqd.size(); ++s) {
+        std::vector<std::pair<size_t, std::pair<size_t, size_t>>> two, one;
+        for (const auto& c : eqd[s].cells) (qs[c.first].encoding == LVS_ENC_ASCII7 ? two : one).push_back(c);
+        eqd[s].cells.swap(two);
+        eqd2[s].cells.swap(one);
+    }
+    auto place1 = [&](Diag& d, size_t count) {   // first stages (ASCII eq1, DNA eq9)
+        for (size_t e = 0; e < count && d.n1 < d.cells.size(); ++e, ++d.n1) {
+            const auto& c = d.cells[d.n1];
+            b.add(equality_job(qs[c.first], c.second.first, c.second.second, 1));
+        }
+    };
+    auto place2 = [&](Diag& d, size_t count) {   // ASCII last stages whose first stage ran earlier
+        for (size_t e = 0; e < count && d.n2 < d.n1_before; ++e, ++d.n2) {
+            const auto& c = d.cells[d.n2];
+            b.add(equality_job(qs[c.first], c.second.first, c.second.second, 2));
+        }
+    };
+    const size_t all = size_t(-1);
     const size_t t0 = any_ascii ? 0 : 1;
     for (size_t t = t0; t <= smax; ++t) {
         b.step();
+        // deadlines: last stages of diagonal t + 1, first stages of diagonal t + 2
+        if (t + 1 <= smax) {
+            place2(eqd[t + 1], all);
+            place1(eqd2[t + 1], all);
+        }
+        if (t + 2 <= smax) place1(eqd[t + 2], all);
         for (const auto& q : qs) {
-            if (both_encrypted(q)) {
-                const bool ascii = q.encoding == LVS_ENC_ASCII7;
-                for_diagonal(q, t + 1, [&](size_t i, size_t j) { b.add(equality_job(q, i, j, ascii ? 2 : 1)); });
-                if (ascii) for_diagonal(q, t + 2, [&](size_t i, size_t j) { b.add(equality_job(q, i, j, 1)); });
-            }
             uint64_t* H = (q.h_last ? q.h_last : q.H) - W;   // H[j] = h[latest i, j], j >= 1
             for_diagonal(q, t, [&](size_t i, size_t j) {
                 const uint64_t* eq;
@@ -251,6 +288,20 @@ void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool wi
                 b.add(J);
             });
         }
+        // fill the step's last partial round, earliest deadline first
+        if (quantum > 0) {
+            const size_t count = P.steps.back().count;
+            size_t target = (count + quantum - 1) / quantum * quantum;
+            if (cap > 0) target = std::min(target, cap);
+            for (size_t s = t + 2; s <= smax && P.steps.back().count < target; ++s) {
+                // deadline s - 1: last stages of diagonal s, single stages of s
+                place2(eqd[s], target - P.steps.back().count);
+                place1(eqd2[s], target - P.steps.back().count);
+                // deadline s - 1 as well: first stages of diagonal s + 1
+                if (s + 1 <= smax) place1(eqd[s + 1], target - P.steps.back().count);
+            }
+        }
+        for (auto& d : eqd) d.n1_before = d.n1;
     }
 }
 

@@ -75,7 +75,10 @@ void assign_buffers(std::vector<QuerySpec>& qs, uint8_t*& ws);
 
 // Builds the jobs: equality steps (both encrypted), then one step per
 // anti-diagonal s = 2 .. max(m + n) holding every query's cells on it.
-void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool with_dp = true);
+// quantum: bootstraps the device runs at once (0: no filling); cap: the
+// largest step the workspace was sized for.
+void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool with_dp = true, size_t quantum = 0,
+                              size_t cap = 0);
 
 // Jobs of the Section 5 table: T[c][i] = Enc(9 [a_i = S_c]).
 void build_preprocess_plan(const uint64_t* A, size_t m, int encoding, const std::vector<uint8_t>& syms_lo,

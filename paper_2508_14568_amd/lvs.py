@@ -75,6 +75,8 @@ _SIGS = {
     "lvs_edit_distance_clear_band": (I32, [VP, VP, SZ, VP, SZ, VP, SZ, SZ, VP, VP, SZ]),
     "lvs_plan_workspace_bytes": (I32, [VP, SZ, I32, ctypes.POINTER(SZ)]),
     "lvs_plan_create": (I32, [VP, VP, SZ, I32, I32, VP, SZ, ctypes.POINTER(VP)]),
+    "lvs_plan_verify": (I32, [VP, SZ, I32, SZ, I32, ctypes.POINTER(SZ), ctypes.POINTER(SZ), ctypes.POINTER(SZ),
+                              ctypes.POINTER(SZ)]),
     "lvs_plan_run": (I32, [VP]),
     "lvs_plan_info": (I32, [VP, ctypes.POINTER(SZ), ctypes.POINTER(SZ), ctypes.POINTER(SZ)]),
     "lvs_server_fixed_bytes": (SZ, [SZ]),
@@ -455,6 +457,42 @@ def lvs_plan_create(ctx: Context, items, encoding: int, graph: bool = False, d_w
     _check(lib().lvs_plan_create(ctx, arr, len(items), encoding, LVS_PLAN_GRAPH if graph else 0, _dptr(d_work),
                                  d_work.numel() * d_work.element_size(), ctypes.byref(out)))
     return Plan(out, (arr, keep, d_work, items))
+
+
+def lvs_plan_verify(queries, encoding: int, round_: int, fill: bool = True):
+    """queries: (m, n, kind, ell) tuples with kind 'enc' (both encrypted) or
+    'clear' (cleartext b over alphabet bytes(range(n)) of n distinct symbols);
+    ell None for the full matrix.  Buffers get placeholder addresses.
+    Returns (steps, bootstraps, rounds, violations)."""
+    arr = (lvs_query * max(1, len(queries)))()
+    keep = []
+    addr = 1 << 32
+    for k, (m, n, kind, ell) in enumerate(queries):
+        q = arr[k]
+        q.m, q.n = m, n
+        q.d_a = addr
+        addr += (m + 1) * 2 * CT_WORDS * 8
+        if kind == "enc":
+            q.d_b = addr
+            addr += (n + 1) * 2 * CT_WORDS * 8
+        else:
+            ab = (ctypes.c_uint8 * max(1, n)).from_buffer_copy(bytes(range(n)) or b"\0")
+            keep.append(ab)
+            q.d_table = addr
+            addr += (n + 1) * (m + 1) * CT_WORDS * 8
+            q.alphabet = ctypes.cast(ab, VP)
+            q.alen = n
+            q.b_clear = ctypes.cast(ab, VP)
+        if ell is None:
+            q.d_h_last = addr
+            addr += (n + 1) * CT_WORDS * 8
+        else:
+            q.banded, q.ell, q.d_path = 1, ell, addr
+            addr += (m + n + 1) * CT_WORDS * 8
+    st, jb, rd, bad = SZ(), SZ(), SZ(), SZ()
+    _check(lib().lvs_plan_verify(arr, len(queries), encoding, round_, 1 if fill else 0, ctypes.byref(st),
+                                 ctypes.byref(jb), ctypes.byref(rd), ctypes.byref(bad)))
+    return st.value, jb.value, rd.value, bad.value
 
 
 def lvs_plan_run(plan: Plan):

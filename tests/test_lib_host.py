@@ -115,3 +115,39 @@ def test_band_counts_match_definition():
                 assert L.lvs_band_cells(m, n, ell) == want
             assert L.lvs_band_exact(m, n) == P.exact_band(m, n)
     assert L.lvs_band_cells(40, 40, 7) == P.band_cell_count_formula(40, 7)
+
+
+def test_plan_schedule_is_causal_and_fills_rounds():
+    """lvs_plan_verify (host only): for mixes of ASCII/DNA, both-encrypted
+    and cleartext, full and banded queries, every plan-written word is read
+    only after an earlier step wrote it, no step races or exceeds the
+    workspace bound, every bootstrap is scheduled, and filling the last
+    partial round of each step never adds device rounds."""
+    import numpy as np
+    from paper_2508_14568_amd import lvs as L
+    import workloads as W
+    rng = np.random.default_rng(5)
+    for enc in (L.LVS_ENC_ASCII7, L.LVS_ENC_DNA2):
+        for trial in range(6):
+            qs = []
+            for _ in range(int(rng.integers(1, 40))):
+                m, n = (int(x) for x in rng.integers(1, 50, size=2))
+                kind = "enc" if rng.random() < 0.7 else "clear"
+                ell = None if rng.random() < 0.6 else int(rng.integers(0, 12))
+                qs.append((m, n, kind, ell))
+            want = 0
+            for m, n, kind, ell in qs:
+                cells = L.lvs_band_cells(m, n, ell) if ell is not None else m * n
+                want += cells * ((3 if enc == L.LVS_ENC_ASCII7 else 2) if kind == "enc" else 1)
+            for rnd in (64, 256):
+                _, jobs0, rounds0, bad0 = L.lvs_plan_verify(qs, enc, rnd, fill=False)
+                _, jobs1, rounds1, bad1 = L.lvs_plan_verify(qs, enc, rnd, fill=True)
+                assert bad0 == 0 and bad1 == 0, (enc, trial, rnd)
+                assert jobs0 == jobs1 == want
+                assert rounds1 <= rounds0
+    # the 64-query batched workload: filling removes device rounds
+    qs = [(len(a), len(b), "enc", None) for a, b in W.batched()[:64]]
+    _, jobs, rounds_plain, bad0 = L.lvs_plan_verify(qs, L.LVS_ENC_ASCII7, 256, fill=False)
+    _, _, rounds_filled, bad1 = L.lvs_plan_verify(qs, L.LVS_ENC_ASCII7, 256, fill=True)
+    assert bad0 == bad1 == 0 and jobs == 3 * sum(m * n for m, n, _, _ in qs)
+    assert rounds_filled < 0.97 * rounds_plain
