@@ -156,7 +156,7 @@ def batched_block(L, ck, ctx, nq, plain_sample):
     }
 
 
-def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos):
+def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos, progress=False, arena_gb=4):
     """The serving workload on the first n_names of its 1024 cleartext server
     names: n_sat queries submitted at once (saturated queries/s), then
     n_poisson queries per load factor rho arriving as a Poisson process at
@@ -171,7 +171,7 @@ def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos):
     cts = [L.lvs_encrypt_string(ck, q, L.LVS_ENC_ASCII7, 40000 + k) for k, q in enumerate(queries)]
     max_step = 8192
     per = L.lvs_server_request_bytes(names, len(alpha), max(len(q) for q in queries))
-    cap = max(4, min(128, (4 << 30) // per))
+    cap = max(4, min(128, (arena_gb << 30) // per))
     srv = L.lvs_server_create(ctx, names, alpha, L.lvs_server_fixed_bytes(max_step) + per * cap + 4096,
                               max_step=max_step)
 
@@ -181,6 +181,8 @@ def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos):
             if L.lvs_decrypt_distance(ck, out[row:row + len(nm)], len(q)) != levenshtein(q, nm):
                 raise SystemExit(f"serving: wrong distance for query {k}")
             row += len(nm)
+        if progress:
+            note(f"serving: query {k} done")
 
     S.run(srv, cts[:1], [0.0], on_result=check)            # warm-up
     st0, pbs0 = L.lvs_server_stats(srv)
@@ -192,6 +194,7 @@ def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos):
         "workload": f"serving: first {n_names} of 1024 cleartext names (lengths lognormal, mean 15), "
                     f"alphabet {len(alpha)} letters, encrypted queries of the same length law",
         "names": n_names, "alphabet": len(alpha), "max_requests_resident": cap,
+        "request_bytes": per,
         "saturated": {"queries": n_sat, "seconds": round(wall, 3), "queries_per_s": round(sat_qps, 4),
                       "pbs_per_s": round((pbs1 - pbs0) / wall, 1), "steps": st1 - st0,
                       "pbs_per_query": round((pbs1 - pbs0) / n_sat, 1),
@@ -266,6 +269,121 @@ def band_block(L, ck, ctx, nq, approx_ell):
     return res
 
 
+def full_configs(L, ck, ctx, serving_sat, serving_poisson):
+    """Every workload at its full size (a run of several minutes; not part of
+    the default line).  Returns a dict keyed by workload."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2508_14568_amd import serving as S
+    dev = ctx.device
+    out = {}
+
+    def plain_once(sa, sb, enc):
+        dA = L.to_device(L.lvs_encrypt_string(ck, sa, enc, 70001), dev)
+        dB = L.to_device(L.lvs_encrypt_string(ck, sb, enc, 70002), dev)
+        d_h = torch.zeros(len(sb) * L.CT_WORDS, dtype=torch.int64, device=dev)
+        work = L.device_buffer(L.lvs_edit_distance_workspace_bytes(len(sa), len(sb), enc), dev)
+        L.lvs_edit_distance(ctx, dA, len(sa), dB, len(sb), enc, d_h, work)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.lvs_edit_distance(ctx, dA, len(sa), dB, len(sb), enc, d_h, work)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return dt, L.to_host(d_h).reshape(len(sb), L.CT_WORDS)
+
+    # tiny DNA and the 256-base DNA alignment (plain path, 1 equality bootstrap per cell)
+    for name, (a, b) in (("tiny_dna_6x6", W.tiny_dna()), ("dna_align_256x256", W.dna_align())):
+        note(f"full: {name}")
+        dt, h = plain_once(W.dna_codes(a), W.dna_codes(b), L.LVS_ENC_DNA2)
+        d = L.lvs_decrypt_distance(ck, h, len(a))
+        if d != levenshtein(a, b):
+            raise SystemExit(f"{name}: wrong distance")
+        pbs = 2 * len(a) * len(b)
+        out[name] = {"pbs": pbs, "seconds": round(dt, 3), "pbs_per_s": round(pbs / dt, 1),
+                     "cells_per_s": round(len(a) * len(b) / dt, 1), "distance": d}
+
+    # the batched workload, all 256 pairs, both encrypted (one graph plan)
+    pairs = W.batched()
+    note("full: batched 256 pairs, encrypting")
+    items, keep = [], []
+    for k, (a, b) in enumerate(pairs):
+        dA = L.to_device(L.lvs_encrypt_string(ck, a, L.LVS_ENC_ASCII7, 80000 + 2 * k), dev)
+        dB = L.to_device(L.lvs_encrypt_string(ck, b, L.LVS_ENC_ASCII7, 80001 + 2 * k), dev)
+        items.append({"d_a": dA, "m": len(a), "d_b": dB, "n": len(b),
+                      "d_h_last": torch.zeros(len(b) * L.CT_WORDS, dtype=torch.int64, device=dev)})
+    note("full: batched 256 pairs, plan run")
+    plan = L.lvs_plan_create(ctx, items, L.LVS_ENC_ASCII7, graph=True)
+    steps, pbs, max_step = L.lvs_plan_info(plan)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L.lvs_plan_run(plan)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for (a, b), it in zip(pairs, items):
+        h = L.to_host(it["d_h_last"]).reshape(len(b), L.CT_WORDS)
+        if L.lvs_decrypt_distance(ck, h, len(a)) != levenshtein(a, b):
+            raise SystemExit("batched 256: wrong distance")
+    del plan
+    cells = sum(len(a) * len(b) for a, b in pairs)
+    # the same kind of query through the plain path, a sample of 8
+    note("full: plain path on 8 of the 256 pairs")
+    t_plain = pbs_plain = 0
+    for a, b in pairs[:8]:
+        dtp, _ = plain_once(a, b, L.LVS_ENC_ASCII7)
+        t_plain += dtp
+        pbs_plain += 3 * len(a) * len(b)
+    out["batched_ascii_256"] = {"pbs": pbs, "cells": cells, "steps": steps, "max_step": max_step,
+                                "seconds": round(dt, 3), "pbs_per_s": round(pbs / dt, 1),
+                                "cells_per_s": round(cells / dt, 1), "queries_per_s": round(256 / dt, 3),
+                                "plain_sample_pbs_per_s": round(pbs_plain / t_plain, 1),
+                                "speedup_vs_plain": round((pbs / dt) / (pbs_plain / t_plain), 2)}
+    del items
+
+    # the cleartext-string variant: preprocessing of every a over the 52 letters, then one plan
+    alpha = W.LETTERS
+    note("full: cleartext variant, preprocessing 256 queries")
+    tabs, t_pre, pbs_pre = [], 0.0, 0
+    for k, (a, b) in enumerate(pairs):
+        dA = L.to_device(L.lvs_encrypt_string(ck, a, L.LVS_ENC_ASCII7, 90000 + k), dev)
+        d_tab = torch.zeros(len(alpha) * len(a) * L.CT_WORDS, dtype=torch.int64, device=dev)
+        work = L.device_buffer(L.lvs_preprocess_workspace_bytes(len(a), len(alpha), L.LVS_ENC_ASCII7), dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.lvs_preprocess(ctx, dA, len(a), L.LVS_ENC_ASCII7, alpha, d_tab, work)
+        torch.cuda.synchronize()
+        t_pre += time.perf_counter() - t0
+        pbs_pre += 2 * len(alpha) * len(a)
+        tabs.append(d_tab)
+        del work
+    citems = [{"d_a": None, "m": len(a), "d_table": t, "alphabet": alpha, "b_clear": b,
+               "d_h_last": torch.zeros(len(b) * L.CT_WORDS, dtype=torch.int64, device=dev)}
+              for (a, b), t in zip(pairs, tabs)]
+    note("full: cleartext variant, plan run")
+    plan = L.lvs_plan_create(ctx, citems, L.LVS_ENC_ASCII7, graph=True)
+    steps, cpbs, _ = L.lvs_plan_info(plan)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L.lvs_plan_run(plan)
+    torch.cuda.synchronize()
+    dtc = time.perf_counter() - t0
+    for (a, b), it in zip(pairs, citems):
+        h = L.to_host(it["d_h_last"]).reshape(len(b), L.CT_WORDS)
+        if L.lvs_decrypt_distance(ck, h, len(a)) != levenshtein(a, b):
+            raise SystemExit("cleartext 256: wrong distance")
+    del plan, citems, tabs
+    out["batched_cleartext_256"] = {"pre_pbs": pbs_pre, "pre_seconds": round(t_pre, 3),
+                                    "pre_pbs_per_s": round(pbs_pre / t_pre, 1),
+                                    "main_pbs": cpbs, "main_seconds": round(dtc, 3),
+                                    "main_pbs_per_s": round(cpbs / dtc, 1),
+                                    "main_queries_per_s": round(256 / dtc, 3)}
+
+    # serving against the full list of 1024 names
+    out["serving_1024"] = serving_block(L, ck, ctx, 1024, serving_sat, serving_poisson, [0.8], progress=True,
+                                        arena_gb=32)
+    return out
+
+
 def microbench(L, ctx):
     """Measured ceilings: the butterfly instruction mix from registers on
     every CU, and a 1 GiB device copy."""
@@ -299,6 +417,10 @@ def main():
     ap.add_argument("--no-band", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--no-microbench", action="store_true")
+    ap.add_argument("--full-configs", action="store_true",
+                    help="instead of the default line: every workload at full size (several minutes)")
+    ap.add_argument("--full-serving-queries", type=int, default=8)
+    ap.add_argument("--full-poisson-queries", type=int, default=16)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -320,6 +442,10 @@ def main():
     if not args.no_autotune:
         note("autotune")
         tuning = L.autotune(ctx)
+    if args.full_configs:
+        res = full_configs(L, ck, ctx, args.full_serving_queries, args.full_poisson_queries)
+        print(json.dumps({"full_configs": res, "tuning": tuning and tuning["tuning"]}), flush=True)
+        return
     A = L.lvs_encrypt_string(ck, a, L.LVS_ENC_ASCII7, 1001)
     B = L.lvs_encrypt_string(ck, b, L.LVS_ENC_ASCII7, 1002)
     dA, dB = L.to_device(A, ctx.device), L.to_device(B, ctx.device)
