@@ -19,6 +19,9 @@ of the schoolbook TFHE oracle (``tfhe.py``):
   * Section 3.4 / Algorithm 1 band: only cells with |i - j| <= ell are
     bootstrapped (and only their equality pairs); the result is the sum of
     the differences along the diagonal path (``dp_band``).
+  * Section 3.1 noise refresh: the differences written on every R-th
+    anti-diagonal are bootstrapped again through the identity table
+    (``refresh_every``), which restarts their noise growth.
 """
 import numpy as np
 
@@ -28,13 +31,22 @@ from . import tfhe as T
 ENC_ASCII7 = 0
 ENC_DNA2 = 1
 
-LUT_IDS = {"eq": 0, "eq9": 1, "min": 2}
+LUT_IDS = {"eq": 0, "eq9": 1, "min": 2, "refresh": 3}
 
 
 def lut_polys(N: int) -> np.ndarray:
     """Test polynomials in the order of LUT_IDS."""
     return np.stack([T.test_polynomial(P.LUT_EQ, N), T.test_polynomial(P.LUT_EQ9, N),
-                     T.test_polynomial(P.lut_min_negated(), N)])
+                     T.test_polynomial(P.lut_min_negated(), N), T.test_polynomial(P.LUT_REFRESH, N)])
+
+
+def refresh_due(s: int, m: int, n: int, refresh_every: int) -> bool:
+    """Whether the differences written on anti-diagonal s are bootstrapped
+    again before diagonal s + 1 reads them (every refresh_every-th diagonal;
+    0: never).  Reading of Section 3.1's refresh: every chain of differences
+    passes through each anti-diagonal, so refreshing the outputs of one
+    diagonal restarts the noise growth of all of them."""
+    return refresh_every > 0 and s % refresh_every == 0 and s < m + n
 
 
 def symbols(s, encoding):
@@ -86,11 +98,15 @@ def preprocess(keys: T.Keys, A: np.ndarray, alphabet, encoding: int, nthreads=No
     return np.ascontiguousarray(eq9.transpose(1, 0, 2))
 
 
-def dp(keys: T.Keys, m: int, n: int, eq9_at, order: str = "alg4", nthreads=None, record: bool = False):
+def dp(keys: T.Keys, m: int, n: int, eq9_at, order: str = "alg4", nthreads=None, record: bool = False,
+       refresh_every: int = 0):
     """Main loop of Algorithm 4 over an m x n grid; eq9_at(i, j) returns the
     ciphertext of 9 [a_i = b_j] (1-based indices).  Returns the last-row
     vector h[m, 1..n] (n ciphertexts) and, when record is set, a dict with
-    every key and M ciphertext."""
+    every key and M ciphertext.  refresh_every > 0 (diagonal order only)
+    bootstraps the v and h written on every refresh_every-th anti-diagonal
+    through the identity table (refresh_due)."""
+    assert refresh_every == 0 or order == "diagonal"
     N, W = keys.N, keys.N + 1
     polys = lut_polys(N)
     one = T.trivial(1, N)
@@ -124,6 +140,11 @@ def dp(keys: T.Keys, m: int, n: int, eq9_at, order: str = "alg4", nthreads=None,
                 if record:
                     rec["key"][(i, j)], rec["M"][(i, j)] = key, M
                 update(i, j, M)
+            if refresh_due(s, m, n, refresh_every):
+                fresh = keys.pbs_batch(np.stack([V[i] for i, _ in cells] + [H[j] for _, j in cells]), polys,
+                                       LUT_IDS["refresh"], nthreads)
+                for k, (i, j) in enumerate(cells):
+                    V[i], H[j] = fresh[k], fresh[len(cells) + k]
     else:
         raise ValueError(order)
     h_last = H[1:].copy()
@@ -131,31 +152,32 @@ def dp(keys: T.Keys, m: int, n: int, eq9_at, order: str = "alg4", nthreads=None,
 
 
 def edit_distance(keys: T.Keys, A: np.ndarray, B: np.ndarray, encoding: int, order="diagonal",
-                  nthreads=None, record=False):
+                  nthreads=None, record=False, refresh_every: int = 0):
     """Algorithm 4 on two encrypted strings; returns h[m,1..n] (and records)."""
     m, n = A.shape[0], B.shape[0]
     if m == 0 or n == 0:
         h_last = np.tile(T.trivial(1, keys.N), (n, 1))
         return (h_last, {"eq9": None}) if record else h_last
     eq1, eq9 = equality(keys, A, B, encoding, nthreads)
-    out = dp(keys, m, n, lambda i, j: eq9[i - 1, j - 1], order, nthreads, record)
+    out = dp(keys, m, n, lambda i, j: eq9[i - 1, j - 1], order, nthreads, record, refresh_every)
     if record:
         out[1]["eq1"], out[1]["eq9"] = eq1, eq9
     return out
 
 
 def edit_distance_clear(keys: T.Keys, table: np.ndarray, alphabet, b, encoding: int, order="diagonal",
-                        nthreads=None, record=False):
+                        nthreads=None, record=False, refresh_every: int = 0):
     """Main loop with eq9[i,j] = T[b_j][i] read from the preprocessing table."""
     m, n = table.shape[1], len(b)
     index = {c: k for k, c in enumerate(alphabet)}
     cols = [index[c] for c in b]
     if m == 0 or n == 0:
         return np.tile(T.trivial(1, keys.N), (n, 1))
-    return dp(keys, m, n, lambda i, j: table[cols[j - 1], i - 1], order, nthreads, record)
+    return dp(keys, m, n, lambda i, j: table[cols[j - 1], i - 1], order, nthreads, record, refresh_every)
 
 
-def dp_band(keys: T.Keys, m: int, n: int, eq9_at, ell: int, nthreads=None, record: bool = False):
+def dp_band(keys: T.Keys, m: int, n: int, eq9_at, ell: int, nthreads=None, record: bool = False,
+            refresh_every: int = 0):
     """Algorithm 1 restricted to the band |i - j| <= ell (Section 3.4), cells
     of one anti-diagonal as one batch; neighbours outside the band keep the
     OneMatrix value (a noise-free 1).  Returns the m + n ciphertexts of the
@@ -167,6 +189,7 @@ def dp_band(keys: T.Keys, m: int, n: int, eq9_at, ell: int, nthreads=None, recor
     four = T.trivial(4, N)
     v = {}
     h = {}
+    path_vals = {}     # (v, h) of a refreshed cell as its bootstrap produced them
 
     def v_at(i, j):
         return v.get((i, j), one)
@@ -181,16 +204,31 @@ def dp_band(keys: T.Keys, m: int, n: int, eq9_at, ell: int, nthreads=None, recor
         keys_b = np.stack([(four - v_at(i, j - 1) + T.scale(h_at(i - 1, j), 3) + eq9_at(i, j)).astype(T.U64)
                            for i, j in cells])
         Ms = keys.pbs_batch(keys_b, polys, LUT_IDS["min"], nthreads)
+        fresh_path = {}
         for (i, j), M in zip(cells, Ms):
             v[(i, j)] = (M - h_at(i - 1, j)).astype(T.U64)
             h[(i, j)] = (M - v_at(i, j - 1)).astype(T.U64)
-    path = np.stack([(v_at(i, j) if kind == "v" else h_at(i, j)) for kind, i, j in P.band_path(m, n)]) \
+        if refresh_due(s, m, n, refresh_every):
+            # the path keeps the values as computed; the state is refreshed
+            for i, j in cells:
+                fresh_path[(i, j)] = (v[(i, j)], h[(i, j)])
+            fresh = keys.pbs_batch(np.stack([v[c] for c in cells] + [h[c] for c in cells]), polys,
+                                   LUT_IDS["refresh"], nthreads)
+            for k, c in enumerate(cells):
+                v[c], h[c] = fresh[k], fresh[len(cells) + k]
+            path_vals.update(fresh_path)
+    def path_at(kind, i, j):
+        if (i, j) in path_vals:
+            return path_vals[(i, j)][0 if kind == "v" else 1]
+        return v_at(i, j) if kind == "v" else h_at(i, j)
+
+    path = np.stack([path_at(kind, i, j) for kind, i, j in P.band_path(m, n)]) \
         if m + n else np.zeros((0, N + 1), dtype=T.U64)
     return (path, {"v": v, "h": h}) if record else path
 
 
 def edit_distance_band(keys: T.Keys, A: np.ndarray, B: np.ndarray, encoding: int, ell: int, nthreads=None,
-                       record=False):
+                       record=False, refresh_every: int = 0):
     """Equality for the pairs inside the band only, then the banded loop;
     returns the band path (and records)."""
     m, n, W = A.shape[0], B.shape[0], keys.N + 1
@@ -209,15 +247,16 @@ def edit_distance_band(keys: T.Keys, A: np.ndarray, B: np.ndarray, encoding: int
             z2 = (T.scale(Ai[:, 1, :], 2) - T.scale(Bj[:, 1, :], 2) + T.trivial(1, keys.N)[None, :] - e1)
             e9 = _pbs(keys, z2.astype(T.U64), "eq9", nthreads)
         eq9 = {c: e9[k] for k, c in enumerate(cells)}
-    return dp_band(keys, m, n, lambda i, j: eq9[(i, j)], ell, nthreads, record)
+    return dp_band(keys, m, n, lambda i, j: eq9[(i, j)], ell, nthreads, record, refresh_every)
 
 
-def edit_distance_clear_band(keys: T.Keys, table: np.ndarray, alphabet, b, ell: int, nthreads=None, record=False):
+def edit_distance_clear_band(keys: T.Keys, table: np.ndarray, alphabet, b, ell: int, nthreads=None, record=False,
+                             refresh_every: int = 0):
     """Banded loop with eq9[i,j] = T[b_j][i] from the preprocessing table."""
     m, n = table.shape[1], len(b)
     index = {c: k for k, c in enumerate(alphabet)}
     cols = [index[c] for c in b]
-    return dp_band(keys, m, n, lambda i, j: table[cols[j - 1], i - 1], ell, nthreads, record)
+    return dp_band(keys, m, n, lambda i, j: table[cols[j - 1], i - 1], ell, nthreads, record, refresh_every)
 
 
 def decrypt_path(keys: T.Keys, path: np.ndarray) -> int:

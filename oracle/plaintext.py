@@ -182,6 +182,11 @@ def lut_min_negated():
 LUT_EQ = [1] + [0] * 15          # Eq. (eq_eqlut)
 LUT_EQ9 = [9] + [0] * 15         # Eq. (eq_eqlut9)
 LUT_X_MINUS_4 = [(x - 4) % 16 for x in range(16)]   # Table table_lutrelu
+# Refresh of a difference (Section 3.1: the differences are bootstrapped
+# again before their noise reaches the threshold, Fig. noise5): the identity
+# on {-1, 0, 1}.  In the negacyclic layout an input of -1 (= 31) reads
+# -f(15), so f(15) = 1.
+LUT_REFRESH = [0, 1] + [0] * 13 + [1]
 
 
 def negacyclic_read(lut16, x: int, modulus: int = 32) -> int:

@@ -66,8 +66,8 @@ def test_random_pairs_distance(oracle_toy_keys):
     k = oracle_toy_keys
     rng = np.random.default_rng(9)
     for t in range(4):
-        a = bytes(rng.choice(list(b"ACGT"), size=int(rng.integers(1, 7))))
-        b = bytes(rng.choice(list(b"ACGT"), size=int(rng.integers(1, 7))))
+        a = bytes(int(c) for c in rng.choice(list(b"ACGT"), size=int(rng.integers(1, 7))))
+        b = bytes(int(c) for c in rng.choice(list(b"ACGT"), size=int(rng.integers(1, 7))))
         A = L.encrypt_string(k, a, L.ENC_DNA2, 100 + t)
         B = L.encrypt_string(k, b, L.ENC_DNA2, 200 + t)
         h_last = L.edit_distance(k, A, B, L.ENC_DNA2)
@@ -154,3 +154,77 @@ def test_band_cleartext_equals_encrypted(oracle_toy_keys):
     B = L.encrypt_string(k, b, L.ENC_ASCII7, 14)
     path2 = L.edit_distance_band(k, A, B, L.ENC_ASCII7, 1)
     assert L.decrypt_path(k, path2) == P.band_distance(a, b, 1)
+
+
+class _CountingKeys:
+    """Keys whose bootstraps through the refresh table are logged."""
+
+    def __init__(self, keys):
+        self._k = keys
+        self.refresh_calls = []
+
+    def __getattr__(self, name):
+        return getattr(self._k, name)
+
+    def pbs_batch(self, cts, polys, lut_ids, nthreads=None):
+        out = self._k.pbs_batch(cts, polys, lut_ids, nthreads)
+        if np.isscalar(lut_ids) and lut_ids == L.LUT_IDS["refresh"]:
+            self.refresh_calls.append((np.array(cts), out))
+        return out
+
+
+def test_refresh_table_is_identity_on_differences(oracle_toy_keys):
+    """Section 3.1's refresh: a bootstrap through the refresh table returns
+    -1, 0 and 1 unchanged, with the noise of a fresh bootstrap."""
+    k = oracle_toy_keys
+    tp = L.lut_polys(k.N)
+    cts = []
+    for x, off in [(0, 2**56), (1, -(2**56)), (31, 3 * 2**55), (1, 0)]:
+        ct = k.encrypt(x, 19, x)
+        ct[k.N] = np.uint64((int(ct[k.N]) + off) % 2**64)
+        cts.append(ct)
+    outs = k.pbs_batch(np.stack(cts), tp, L.LUT_IDS["refresh"])
+    assert [k.decrypt_signed(o) for o in outs] == [0, 1, -1, 1]
+    assert all(abs(k.phase_error(o)) < 2**52 for o in outs)
+
+
+def test_refresh_schedule_keeps_distances(oracle_toy_keys):
+    """Refreshing every R-th anti-diagonal changes no plaintext: distances
+    stay the Wagner-Fischer ones; the refresh runs on exactly the diagonals
+    s = R, 2R, ... below m + n, on the v and h of their cells, each output
+    decrypting to its input."""
+    rng = np.random.default_rng(23)
+    for t, R in enumerate((2, 3, 5)):
+        k = _CountingKeys(oracle_toy_keys)
+        m, n = int(rng.integers(4, 9)), int(rng.integers(4, 9))
+        a = bytes(int(c) for c in rng.choice(list(b"ACGT"), size=m))
+        b = bytes(int(c) for c in rng.choice(list(b"ACGT"), size=n))
+        A = L.encrypt_string(k, a, L.ENC_DNA2, 300 + t)
+        B = L.encrypt_string(k, b, L.ENC_DNA2, 400 + t)
+        h_last = L.edit_distance(k, A, B, L.ENC_DNA2, refresh_every=R)
+        assert L.decrypt_distance(k, m, h_last) == P.edit_distance(a, b)
+        diags = [s for s in range(2, m + n) if s % R == 0]
+        assert len(k.refresh_calls) == len(diags)
+        for s, (ins, outs) in zip(diags, k.refresh_calls):
+            cells = min(m, s - 1) - max(1, s - n) + 1
+            assert ins.shape[0] == 2 * cells
+            assert [k.decrypt_signed(c) for c in ins] == [k.decrypt_signed(c) for c in outs]
+            assert {k.decrypt_signed(c) for c in outs} <= {-1, 0, 1}
+
+
+def test_refresh_band_and_cleartext(oracle_toy_keys):
+    """The banded loop and the Section 5 cleartext loop with refresh give the
+    same distances as without."""
+    k = oracle_toy_keys
+    a, b = "ACGTTGCA", "CGTTAGCAT"
+    A = L.encrypt_string(k, a.encode(), L.ENC_DNA2, 15)
+    B = L.encrypt_string(k, b.encode(), L.ENC_DNA2, 16)
+    for ell in (1, P.exact_band(len(a), len(b))):
+        path = L.edit_distance_band(k, A, B, L.ENC_DNA2, ell, refresh_every=3)
+        assert L.decrypt_path(k, path) == P.band_distance(a, b, ell)
+    a2, b2 = b"kitten", b"sitting"
+    A2 = L.encrypt_string(k, a2, L.ENC_ASCII7, 17)
+    alpha = bytes(sorted(set(b2)))
+    Tab = L.preprocess(k, A2, alpha, L.ENC_ASCII7)
+    h_last = L.edit_distance_clear(k, Tab, alpha, b2, L.ENC_ASCII7, refresh_every=4)
+    assert L.decrypt_distance(k, len(a2), h_last) == 3

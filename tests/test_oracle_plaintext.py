@@ -127,6 +127,12 @@ def test_lut_eq_and_eq9_over_all_differences():
         assert P.negacyclic_read(P.LUT_EQ9, z) == (9 if z == 0 else 0)
 
 
+def test_refresh_lut_identity_on_differences():
+    """Section 3.1's refresh of a difference: -1, 0 and 1 read themselves."""
+    for z in (-1, 0, 1):
+        assert P.negacyclic_read(P.LUT_REFRESH, z) == z % 32
+
+
 def test_algorithm3_plaintext_all_ascii_pairs():
     """Algorithm 3/4 equality in the clear over all 128 x 128 characters."""
     for x in range(128):

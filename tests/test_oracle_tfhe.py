@@ -201,10 +201,10 @@ def _exhaustive(keys, lut16, seed):
     return [keys.decrypt(o) for o in outs]
 
 
-@pytest.mark.parametrize("name", ["x-4", "lutmin_plain", "lutmin_negated", "eq", "eq9"])
+@pytest.mark.parametrize("name", ["x-4", "lutmin_plain", "lutmin_negated", "eq", "eq9", "refresh"])
 def test_pbs_exhaustive_toy(oracle_toy_keys, name):
     lut = {"x-4": P.LUT_X_MINUS_4, "lutmin_plain": P.lut_min_plain(), "lutmin_negated": P.lut_min_negated(),
-           "eq": P.LUT_EQ, "eq9": P.LUT_EQ9}[name]
+           "eq": P.LUT_EQ, "eq9": P.LUT_EQ9, "refresh": P.LUT_REFRESH}[name]
     got = _exhaustive(oracle_toy_keys, lut, 77)
     assert got == [P.negacyclic_read(lut, x) for x in range(32)]
 
