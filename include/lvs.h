@@ -35,7 +35,7 @@ enum {
     LVS_OK = 0,
     LVS_E_INVAL = -1,        /* bad argument (NULL, size, alignment)           */
     LVS_E_ALPHABET = -2,     /* symbol outside the alphabet of the encoding   */
-    LVS_E_NOISE_BUDGET = -3, /* strings longer than the no-refresh bound      */
+    LVS_E_NOISE_BUDGET = -3, /* min(m, n) past the bound with refresh off     */
     LVS_E_NOMEM_HOST = -4,   /* host allocation failed                        */
     LVS_E_NOMEM_DEVICE = -5, /* caller-provided device memory too small       */
     LVS_E_DEVICE = -6,       /* HIP runtime error                             */
@@ -46,9 +46,32 @@ typedef enum { LVS_ENC_ASCII7 = 0, LVS_ENC_DNA2 = 1 } lvs_encoding;
 
 /* Lookup-table slots of a context.  EQ = [1,0,..] (Eq. eq_eqlut), EQ9 =
  * [9,0,..] (Eq. eq_eqlut9), MIN = 1 + min(-eq, dv, dh) under the key
- * (1 - dv) + 3 (1 + dh) + 9 eq (Eq. eq_keyeq2, Algorithms 1 and 4).  Slots
- * from LVS_LUT_USER are free for lvs_context_set_lut. */
-enum { LVS_LUT_EQ = 0, LVS_LUT_EQ9 = 1, LVS_LUT_MIN = 2, LVS_LUT_USER = 3, LVS_LUT_SLOTS = 8 };
+ * (1 - dv) + 3 (1 + dh) + 9 eq (Eq. eq_keyeq2, Algorithms 1 and 4), REFRESH =
+ * the identity on the differences -1, 0, 1 ([0,1,0,..,0,1]; -1 reads -f(15)),
+ * the noise refresh of Section 3.1.  Slots from LVS_LUT_USER are free for
+ * lvs_context_set_lut. */
+enum { LVS_LUT_EQ = 0, LVS_LUT_EQ9 = 1, LVS_LUT_MIN = 2, LVS_LUT_REFRESH = 3, LVS_LUT_USER = 4, LVS_LUT_SLOTS = 8 };
+
+/* Noise refresh (Section 3.1: the differences are bootstrapped again before
+ * their noise reaches the decoding threshold, Fig. noise5).  The error of a
+ * difference grows with the number of cell updates since its last bootstrap
+ * through the refresh table, one per two anti-diagonals along the diagonal
+ * of the matrix.  With an interval R, the v and h written on anti-diagonals
+ * s = R, 2R, ... (s < m + n) are refreshed in place before anti-diagonal
+ * s + 1 reads them (2 bootstraps per cell of such a diagonal), which bounds
+ * that count by R / 2.  A context starts at LVS_REFRESH_DEFAULT; R = 0 turns
+ * refresh off, and then every DP entry point returns LVS_E_NOISE_BUDGET when
+ * min(m, n) exceeds LVS_MAX_DEPTH_NO_REFRESH.  Strings are at most
+ * LVS_MAX_LEN symbols long (LVS_E_INVAL past it).  The *_workspace_bytes
+ * functions size for the shortest interval, so one workspace serves every
+ * setting. */
+enum {
+    LVS_REFRESH_DEFAULT = 256,
+    LVS_REFRESH_MIN = 4,
+    LVS_REFRESH_MAX = 512,
+    LVS_MAX_DEPTH_NO_REFRESH = 256,
+    LVS_MAX_LEN = 1 << 20
+};
 
 /* TFHE parameter set; noise standard deviations are given as sigma * 2^64. */
 typedef struct {
@@ -125,6 +148,12 @@ int lvs_context_set_stream(lvs_context* ctx, void* hip_stream);
 /* Installs a 16-entry lookup table f: Z_16 -> Z_32 in slot >= LVS_LUT_USER
  * (inputs 16..31 read -f(x-16), Section 2.2).  Synchronous. */
 int lvs_context_set_lut(lvs_context* ctx, int slot, const int32_t f16[16]);
+
+/* Sets the refresh interval R of the DP entry points (plans built later,
+ * servers created later): 0 (off) or LVS_REFRESH_MIN..LVS_REFRESH_MAX, else
+ * LVS_E_INVAL. */
+int lvs_context_set_refresh(lvs_context* ctx, size_t every);
+int lvs_context_get_refresh(const lvs_context* ctx, size_t* every);
 
 /* Waits for all work enqueued on the context's stream. */
 int lvs_sync(lvs_context* ctx);
@@ -221,7 +250,8 @@ size_t lvs_edit_distance_workspace_bytes(size_t m, size_t n, int encoding);
  * (Section 6.2: cells on one anti-diagonal are independent).  d_a is the
  * encrypted [m][nsym][N+1] string, d_b [n][nsym][N+1]; d_h_last receives the n
  * ciphertexts h[m, 1..n].  m = 0 or n = 0 returns n noise-free encryptions of
- * 1 (distance max(m, n)).  LVS_E_NOISE_BUDGET if min(m, n) exceeds 1024. */
+ * 1 (distance max(m, n)).  The context's refresh interval applies (see
+ * LVS_REFRESH_DEFAULT), as in every DP entry point below. */
 int lvs_edit_distance(lvs_context* ctx, const uint64_t* d_a, size_t m, const uint64_t* d_b, size_t n, int encoding,
                       uint64_t* d_h_last, void* d_work, size_t work_bytes);
 
@@ -338,9 +368,10 @@ int lvs_plan_create(lvs_context* ctx, const lvs_query* queries, size_t nq, int e
  * ceil(count / round)) and violations: reads of a word the plan writes
  * before an earlier step has written it, subtrahend reads or writes of a
  * word another job of the same step writes, and steps larger than the
- * workspace bound. */
-int lvs_plan_verify(const lvs_query* queries, size_t nq, int encoding, size_t round, int fill, size_t* steps,
-                    size_t* jobs, size_t* rounds, size_t* violations);
+ * workspace bound.  refresh: the refresh interval (0 = off; the noise bound
+ * is not checked here). */
+int lvs_plan_verify(const lvs_query* queries, size_t nq, int encoding, size_t round, int fill, size_t refresh,
+                    size_t* steps, size_t* jobs, size_t* rounds, size_t* violations);
 
 /* Enqueues one execution of the plan on the context's stream. */
 int lvs_plan_run(lvs_plan* plan);
@@ -368,15 +399,18 @@ size_t lvs_server_request_bytes(const uint8_t* names, const size_t* name_lens, s
                                 size_t m);
 
 /* Server over n_names cleartext names (concatenated in `names`, lengths in
- * name_lens, every symbol in `alphabet`, 7-bit ASCII).  d_arena is borrowed
- * for the server's lifetime (256-byte aligned). */
+ * name_lens, each at most 4096, every symbol in `alphabet`, 7-bit ASCII).
+ * d_arena is borrowed for the server's lifetime (256-byte aligned).  The
+ * context's refresh interval at creation applies to every request. */
 int lvs_server_create(lvs_context* ctx, const uint8_t* names, const size_t* name_lens, size_t n_names,
                       const uint8_t* alphabet, size_t alen, size_t max_step, void* d_arena, size_t arena_bytes,
                       lvs_server** out);
 
 /* Queues a request: h_query is the encrypted ASCII query ([m][2][N+1], host,
- * copied).  Requests are admitted in arrival order at the next step that
- * has room.  LVS_E_NOMEM_DEVICE if it could never fit. */
+ * copied, 1 <= m <= 4096).  Requests are admitted in arrival order at the
+ * next step that has room.  LVS_E_NOMEM_DEVICE if it could never fit;
+ * LVS_E_NOISE_BUDGET with refresh off and min(m, longest name) above
+ * LVS_MAX_DEPTH_NO_REFRESH. */
 int lvs_server_submit(lvs_server* srv, const uint64_t* h_query, size_t m, uint64_t* ticket);
 
 /* One engine step: admits queued requests while their buffers fit, then runs

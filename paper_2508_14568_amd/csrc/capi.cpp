@@ -24,7 +24,7 @@ namespace {
 thread_local std::string g_error = "no error";
 
 constexpr size_t kAlign = 256;
-constexpr size_t kMaxLen = 4096;            // longest string the no-refresh noise budget admits
+constexpr size_t kMaxLen = LVS_MAX_LEN;
 constexpr size_t W = kCtWords;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -103,16 +103,33 @@ int execute(Context* C, Plan& P, uint8_t* ws) {
 
 // Bound of a wavefront plan's largest step: a diagonal holds at most
 // min(m, n) cells of a query, each step the cells of one diagonal plus one
-// equality stage of each of the next two.
+// equality stage of each of the next two, a refresh step two bootstraps per
+// cell of a diagonal.
 size_t max_step_of(const std::vector<QuerySpec>& qs) {
     size_t step = 0;
     for (const auto& q : qs) {
         const size_t w = std::min(q.m, q.n);
         const bool eq = q.B && !q.eq9_in;
-        step += eq ? (q.encoding == LVS_ENC_ASCII7 ? 3 : 2) * w : w;
+        const size_t k = eq ? (q.encoding == LVS_ENC_ASCII7 ? 3 : 2) : 1;
+        step += std::max<size_t>(k, q.refresh ? 2 : 1) * w;
     }
     return step;
 }
+
+// Section 3.1: with refresh off the differences' noise grows with min(m, n),
+// which is then bounded; the string lengths are bounded in any case.
+int check_lengths(const Context* C, size_t m, size_t n, const char* fn) {
+    LVS_REQUIRE(std::max(m, n) <= kMaxLen, LVS_E_INVAL, std::string(fn) + ": string longer than LVS_MAX_LEN");
+    LVS_REQUIRE(C->refresh_every > 0 || std::min(m, n) <= size_t(LVS_MAX_DEPTH_NO_REFRESH), LVS_E_NOISE_BUDGET,
+                std::string(fn) + ": min(m, n) exceeds the noise budget with refresh off");
+    return LVS_OK;
+}
+
+#define LVS_CHECK_LENGTHS(C, m, n, fn)                  \
+    do {                                                \
+        const int rc_ = check_lengths((C), (m), (n), fn); \
+        if (rc_) return rc_;                            \
+    } while (0)
 
 // Bootstraps the device runs at once for steps of up to cap bootstraps: one
 // per CU in the eight-wave form, two per CU in the four-wave form.
@@ -323,6 +340,9 @@ int lvs_context_create(const lvs_server_key* sk, int device, void* hip_stream, v
     build_test_poly(f_eq, &luts[size_t(LVS_LUT_EQ) * kN]);
     build_test_poly(f_eq9, &luts[size_t(LVS_LUT_EQ9) * kN]);
     build_test_poly(f_min, &luts[size_t(LVS_LUT_MIN) * kN]);
+    // the identity on the differences -1, 0, 1: an input of -1 (= 31) reads -f(15)
+    const int32_t f_refresh[16] = {0, 1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1};
+    build_test_poly(f_refresh, &luts[size_t(LVS_LUT_REFRESH) * kN]);
     if (e == hipSuccess) e = hipMemcpy(C->luts, luts.data(), luts.size() * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -349,6 +369,22 @@ int lvs_context_set_lut(lvs_context* ctx, int slot, const int32_t f16[16]) {
     LVS_HIP(hipSetDevice(C->device));
     LVS_HIP(hipMemcpyAsync(C->luts + size_t(slot) * kN, poly.data(), kN * 8, hipMemcpyHostToDevice, C->stream));
     LVS_HIP(hipStreamSynchronize(C->stream));
+    return LVS_OK;
+}
+
+int lvs_context_set_refresh(lvs_context* ctx, size_t every) {
+    Context* C = as_ctx(ctx);
+    LVS_REQUIRE(C, LVS_E_INVAL, "lvs_context_set_refresh: bad context");
+    LVS_REQUIRE(every == 0 || (every >= LVS_REFRESH_MIN && every <= LVS_REFRESH_MAX), LVS_E_INVAL,
+                "lvs_context_set_refresh: interval must be 0 or LVS_REFRESH_MIN..LVS_REFRESH_MAX");
+    C->refresh_every = every;
+    return LVS_OK;
+}
+
+int lvs_context_get_refresh(const lvs_context* ctx, size_t* every) {
+    Context* C = as_ctx(const_cast<lvs_context*>(ctx));
+    LVS_REQUIRE(C && every, LVS_E_INVAL, "lvs_context_get_refresh: bad argument");
+    *every = C->refresh_every;
     return LVS_OK;
 }
 
@@ -428,11 +464,12 @@ int lvs_equality(lvs_context* ctx, const uint64_t* d_a, size_t m, const uint64_t
 }
 
 size_t lvs_edit_distance_eq9_workspace_bytes(size_t m, size_t n) {
-    QuerySpec q;
-    q.m = m;
-    q.n = n;
-    q.eq9_in = reinterpret_cast<const uint64_t*>(16);
-    return query_buffer_bytes(q) + plan_bytes(m * n, std::min(m, n));
+    std::vector<QuerySpec> qs(1);
+    qs[0].m = m;
+    qs[0].n = n;
+    qs[0].eq9_in = reinterpret_cast<const uint64_t*>(16);
+    qs[0].refresh = LVS_REFRESH_MIN;
+    return plan_ws(qs);
 }
 
 int lvs_edit_distance_eq9(lvs_context* ctx, const uint64_t* d_eq9, size_t m, size_t n, uint64_t* d_h_last,
@@ -440,7 +477,7 @@ int lvs_edit_distance_eq9(lvs_context* ctx, const uint64_t* d_eq9, size_t m, siz
     Context* C = as_ctx(ctx);
     LVS_REQUIRE(C, LVS_E_INVAL, "lvs_edit_distance_eq9: bad context");
     LVS_REQUIRE((d_eq9 || m * n == 0) && (d_h_last || n == 0), LVS_E_INVAL, "lvs_edit_distance_eq9: NULL buffer");
-    LVS_REQUIRE(std::min(m, n) <= kMaxLen, LVS_E_NOISE_BUDGET, "lvs_edit_distance_eq9: noise budget");
+    LVS_CHECK_LENGTHS(C, m, n, "lvs_edit_distance_eq9");
     LVS_HIP(hipSetDevice(C->device));
     if (n == 0) return LVS_OK;
     if (m == 0) return empty_first(C, n, d_h_last);
@@ -452,6 +489,7 @@ int lvs_edit_distance_eq9(lvs_context* ctx, const uint64_t* d_eq9, size_t m, siz
     qs[0].eq9_in = d_eq9;
     qs[0].h_last = d_h_last;
     qs[0].trace = d_trace;
+    qs[0].refresh = C->refresh_every;
     uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
     assign_buffers(qs, ws);
     Plan P;
@@ -461,6 +499,7 @@ int lvs_edit_distance_eq9(lvs_context* ctx, const uint64_t* d_eq9, size_t m, siz
 
 size_t lvs_edit_distance_workspace_bytes(size_t m, size_t n, int encoding) {
     std::vector<QuerySpec> qs{pair_query(nullptr, m, reinterpret_cast<const uint64_t*>(16), n, encoding, nullptr)};
+    qs[0].refresh = LVS_REFRESH_MIN;
     return plan_ws(qs);
 }
 
@@ -471,13 +510,14 @@ int lvs_edit_distance(lvs_context* ctx, const uint64_t* d_a, size_t m, const uin
     LVS_REQUIRE(valid_encoding(encoding), LVS_E_INVAL, "unknown encoding");
     LVS_REQUIRE((d_a || m == 0) && (d_b || n == 0) && (d_h_last || n == 0), LVS_E_INVAL,
                 "lvs_edit_distance: NULL buffer");
-    LVS_REQUIRE(std::min(m, n) <= kMaxLen, LVS_E_NOISE_BUDGET, "lvs_edit_distance: strings exceed the noise budget");
+    LVS_CHECK_LENGTHS(C, m, n, "lvs_edit_distance");
     LVS_HIP(hipSetDevice(C->device));
     if (n == 0) return LVS_OK;
     if (m == 0) return empty_first(C, n, d_h_last);
     LVS_REQUIRE(d_work && work_bytes >= lvs_edit_distance_workspace_bytes(m, n, encoding), LVS_E_NOMEM_DEVICE,
                 "lvs_edit_distance: workspace too small");
     std::vector<QuerySpec> qs{pair_query(d_a, m, d_b, n, encoding, d_h_last)};
+    qs[0].refresh = C->refresh_every;
     uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
     assign_buffers(qs, ws);
     Plan P;
@@ -493,6 +533,7 @@ size_t lvs_band_cells(size_t m, size_t n, size_t ell) { return band_cells(m, n, 
 size_t lvs_edit_distance_band_workspace_bytes(size_t m, size_t n, int encoding, size_t ell) {
     std::vector<QuerySpec> qs{pair_query(nullptr, m, reinterpret_cast<const uint64_t*>(16), n, encoding, nullptr)};
     qs[0].band = long(std::min<size_t>(ell, m + n));
+    qs[0].refresh = LVS_REFRESH_MIN;
     return plan_ws(qs);
 }
 
@@ -503,7 +544,7 @@ int lvs_edit_distance_band(lvs_context* ctx, const uint64_t* d_a, size_t m, cons
     LVS_REQUIRE(valid_encoding(encoding), LVS_E_INVAL, "unknown encoding");
     LVS_REQUIRE((d_a || m == 0) && (d_b || n == 0) && (d_path || m + n == 0), LVS_E_INVAL,
                 "lvs_edit_distance_band: NULL buffer");
-    LVS_REQUIRE(std::min(m, n) <= kMaxLen, LVS_E_NOISE_BUDGET, "lvs_edit_distance_band: strings exceed the noise budget");
+    LVS_CHECK_LENGTHS(C, m, n, "lvs_edit_distance_band");
     if (m + n == 0) return LVS_OK;
     LVS_REQUIRE(d_work && work_bytes >= lvs_edit_distance_band_workspace_bytes(m, n, encoding, ell),
                 LVS_E_NOMEM_DEVICE, "lvs_edit_distance_band: workspace too small");
@@ -511,6 +552,7 @@ int lvs_edit_distance_band(lvs_context* ctx, const uint64_t* d_a, size_t m, cons
     std::vector<QuerySpec> qs{pair_query(d_a, m, d_b, n, encoding, nullptr)};
     qs[0].band = long(std::min<size_t>(ell, m + n));
     qs[0].path = d_path;
+    qs[0].refresh = C->refresh_every;
     uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
     assign_buffers(qs, ws);
     Plan P;
@@ -520,11 +562,12 @@ int lvs_edit_distance_band(lvs_context* ctx, const uint64_t* d_a, size_t m, cons
 }
 
 size_t lvs_edit_distance_clear_band_workspace_bytes(size_t m, size_t n, size_t ell) {
-    QuerySpec q;
-    q.m = m;
-    q.n = n;
-    q.band = long(std::min<size_t>(ell, m + n));
-    return query_buffer_bytes(q) + plan_bytes(band_cells(m, n, q.band), std::min(m, n));
+    std::vector<QuerySpec> qs(1);
+    qs[0].m = m;
+    qs[0].n = n;
+    qs[0].band = long(std::min<size_t>(ell, m + n));
+    qs[0].refresh = LVS_REFRESH_MIN;
+    return plan_ws(qs);
 }
 
 int lvs_edit_distance_clear_band(lvs_context* ctx, const uint64_t* d_table, size_t m, const uint8_t* alphabet,
@@ -534,7 +577,7 @@ int lvs_edit_distance_clear_band(lvs_context* ctx, const uint64_t* d_table, size
     LVS_REQUIRE(C, LVS_E_INVAL, "lvs_edit_distance_clear_band: bad context");
     LVS_REQUIRE((d_table || m == 0) && (alphabet || alen == 0) && (b || n == 0) && (d_path || m + n == 0),
                 LVS_E_INVAL, "lvs_edit_distance_clear_band: NULL buffer");
-    LVS_REQUIRE(std::min(m, n) <= kMaxLen, LVS_E_NOISE_BUDGET, "lvs_edit_distance_clear_band: noise budget");
+    LVS_CHECK_LENGTHS(C, m, n, "lvs_edit_distance_clear_band");
     std::vector<QuerySpec> qs(1);
     qs[0].cols.resize(n);
     for (size_t j = 0; j < n; ++j) {
@@ -551,6 +594,7 @@ int lvs_edit_distance_clear_band(lvs_context* ctx, const uint64_t* d_table, size
     qs[0].table = d_table;
     qs[0].band = long(std::min<size_t>(ell, m + n));
     qs[0].path = d_path;
+    qs[0].refresh = C->refresh_every;
     uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
     assign_buffers(qs, ws);
     Plan P;
@@ -593,10 +637,11 @@ int lvs_preprocess(lvs_context* ctx, const uint64_t* d_a, size_t m, int encoding
 }
 
 size_t lvs_edit_distance_clear_workspace_bytes(size_t m, size_t n) {
-    QuerySpec q;
-    q.m = m;
-    q.n = n;
-    return query_buffer_bytes(q) + plan_bytes(m * n, std::min(m, n));
+    std::vector<QuerySpec> qs(1);
+    qs[0].m = m;
+    qs[0].n = n;
+    qs[0].refresh = LVS_REFRESH_MIN;
+    return plan_ws(qs);
 }
 
 int lvs_edit_distance_clear(lvs_context* ctx, const uint64_t* d_table, size_t m, const uint8_t* alphabet, size_t alen,
@@ -605,7 +650,7 @@ int lvs_edit_distance_clear(lvs_context* ctx, const uint64_t* d_table, size_t m,
     LVS_REQUIRE(C, LVS_E_INVAL, "lvs_edit_distance_clear: bad context");
     LVS_REQUIRE((d_table || m == 0) && (alphabet || alen == 0) && (b || n == 0) && (d_h_last || n == 0),
                 LVS_E_INVAL, "lvs_edit_distance_clear: NULL buffer");
-    LVS_REQUIRE(std::min(m, n) <= kMaxLen, LVS_E_NOISE_BUDGET, "lvs_edit_distance_clear: noise budget");
+    LVS_CHECK_LENGTHS(C, m, n, "lvs_edit_distance_clear");
     std::vector<QuerySpec> qs(1);
     qs[0].cols.resize(n);
     for (size_t j = 0; j < n; ++j) {
@@ -622,6 +667,7 @@ int lvs_edit_distance_clear(lvs_context* ctx, const uint64_t* d_table, size_t m,
     qs[0].n = n;
     qs[0].table = d_table;
     qs[0].h_last = d_h_last;
+    qs[0].refresh = C->refresh_every;
     uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
     assign_buffers(qs, ws);
     Plan P;
@@ -637,7 +683,9 @@ struct PlanHandle : Handle {
     Plan P;
 };
 
-int make_specs(const lvs_query* q, size_t nq, int encoding, std::vector<QuerySpec>& qs) {
+// Queries of a plan; refresh is the interval the plan uses (the workspace
+// bound takes the shortest one).
+int make_specs(const lvs_query* q, size_t nq, int encoding, size_t refresh, std::vector<QuerySpec>& qs) {
     qs.resize(nq);
     for (size_t k = 0; k < nq; ++k) {
         const lvs_query& x = q[k];
@@ -646,7 +694,8 @@ int make_specs(const lvs_query* q, size_t nq, int encoding, std::vector<QuerySpe
         s.m = x.m;
         s.n = x.n;
         s.A = x.d_a;
-        LVS_REQUIRE(std::min(x.m, x.n) <= kMaxLen, LVS_E_NOISE_BUDGET, "lvs_plan: strings exceed the noise budget");
+        s.refresh = refresh;
+        LVS_REQUIRE(std::max(x.m, x.n) <= kMaxLen, LVS_E_INVAL, "lvs_plan: string longer than LVS_MAX_LEN");
         const bool banded = x.banded != 0;
         if (banded) {
             s.band = long(std::min<size_t>(x.ell, x.m + x.n));
@@ -678,7 +727,7 @@ int make_specs(const lvs_query* q, size_t nq, int encoding, std::vector<QuerySpe
 int lvs_plan_workspace_bytes(const lvs_query* queries, size_t nq, int encoding, size_t* bytes) {
     LVS_REQUIRE(bytes && (queries || nq == 0), LVS_E_INVAL, "lvs_plan_workspace_bytes: NULL argument");
     std::vector<QuerySpec> qs;
-    int rc = make_specs(queries, nq, encoding, qs);
+    int rc = make_specs(queries, nq, encoding, LVS_REFRESH_MIN, qs);
     if (rc) return rc;
     *bytes = plan_ws(qs);
     return LVS_OK;
@@ -690,8 +739,9 @@ int lvs_plan_create(lvs_context* ctx, const lvs_query* queries, size_t nq, int e
     LVS_REQUIRE(C && out && (queries || nq == 0), LVS_E_INVAL, "lvs_plan_create: bad argument");
     LVS_REQUIRE(valid_encoding(encoding), LVS_E_INVAL, "unknown encoding");
     std::vector<QuerySpec> qs;
-    int rc = make_specs(queries, nq, encoding, qs);
+    int rc = make_specs(queries, nq, encoding, C->refresh_every, qs);
     if (rc) return rc;
+    for (const auto& q : qs) LVS_CHECK_LENGTHS(C, q.m, q.n, "lvs_plan_create");
     LVS_REQUIRE(d_work && work_bytes >= plan_ws(qs), LVS_E_NOMEM_DEVICE, "lvs_plan_create: workspace too small");
     LVS_HIP(hipSetDevice(C->device));
     PlanHandle* H = new (std::nothrow) PlanHandle();
@@ -713,12 +763,14 @@ int lvs_plan_create(lvs_context* ctx, const lvs_query* queries, size_t nq, int e
     return LVS_OK;
 }
 
-int lvs_plan_verify(const lvs_query* queries, size_t nq, int encoding, size_t round, int fill, size_t* steps,
-                    size_t* jobs, size_t* rounds, size_t* violations) {
+int lvs_plan_verify(const lvs_query* queries, size_t nq, int encoding, size_t round, int fill, size_t refresh,
+                    size_t* steps, size_t* jobs, size_t* rounds, size_t* violations) {
     LVS_REQUIRE(queries || nq == 0, LVS_E_INVAL, "lvs_plan_verify: NULL queries");
     LVS_REQUIRE(valid_encoding(encoding), LVS_E_INVAL, "unknown encoding");
+    LVS_REQUIRE(refresh == 0 || (refresh >= LVS_REFRESH_MIN && refresh <= LVS_REFRESH_MAX), LVS_E_INVAL,
+                "lvs_plan_verify: bad refresh interval");
     std::vector<QuerySpec> qs;
-    int rc = make_specs(queries, nq, encoding, qs);
+    int rc = make_specs(queries, nq, encoding, refresh, qs);
     if (rc) return rc;
     // workspace buffers at addresses above every caller address; nothing is dereferenced
     uintptr_t top = 0;

@@ -26,6 +26,7 @@ struct Context : Handle {
     // launch shape of the blind rotation (lvs_context_set_tuning / lvs_autotune)
     int br_grid = 0;              // persistent grid (0: one workgroup per job)
     int latency_form_max = 0;     // batches up to this size take the eight-wave form
+    size_t refresh_every = LVS_REFRESH_DEFAULT;   // noise-refresh interval in anti-diagonals (0: off)
     // kernel timing (lvs_profile_*): event pairs recorded around launches
     bool profiling = false;
     struct Timed {

@@ -16,7 +16,9 @@ namespace lvs {
 // a cell in the same pass; dst[2] receives M itself and dst[3] a second copy
 // of output copy_of (0 or 1), which collects the differences of a band path.
 // A thread reads every sub[] word before writing the dst[] words of the same
-// index, so dst and sub may alias.
+// index, so dst and sub may alias; dst[2] may alias src[0] (an in-place
+// refresh), since the key switch reads the mask in an earlier launch and the
+// blind rotation reads the body before it writes any output.
 struct Job {
     const uint64_t* src[3];
     int32_t coef[3];

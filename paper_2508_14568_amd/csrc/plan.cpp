@@ -8,7 +8,9 @@
 // difference update are folded into the bootstrap's job (see launch.h).
 // With Algorithm 1's band (Section 3.4) only the pairs and cells with
 // |i - j| <= band get bootstraps, neighbours outside it read as Enc(1), and
-// the result is the diagonal path of differences.
+// the result is the diagonal path of differences.  Section 3.1's noise
+// refresh adds a step after every refresh-th diagonal that bootstraps the
+// differences it wrote through the identity table.
 #include "plan.h"
 
 #include <algorithm>
@@ -56,6 +58,19 @@ size_t band_cells(size_t m, size_t n, long band) {
     return c;
 }
 
+size_t diagonal_cells(const QuerySpec& q, size_t s) {
+    if (!q.m || !q.n || s < 2 || s > q.m + q.n) return 0;
+    size_t lo = (s > q.n + 1) ? s - q.n : 1;
+    size_t hi = std::min(q.m, s - 1);
+    if (q.band >= 0) {
+        // |i - (s - i)| <= band  <=>  (s - band) / 2 <= i <= (s + band) / 2
+        const size_t b = size_t(q.band);
+        if (s > b) lo = std::max(lo, (s - b + 1) / 2);
+        hi = std::min(hi, (s + b) / 2);
+    }
+    return hi >= lo ? hi - lo + 1 : 0;
+}
+
 size_t query_buffer_bytes(const QuerySpec& q) {
     size_t b = align256(sizeof(uint64_t) * (q.m + 1) * W);
     if (!q.h_last) b += align256(sizeof(uint64_t) * std::max<size_t>(q.n, 1) * W);   // row state
@@ -68,8 +83,11 @@ size_t query_buffer_bytes(const QuerySpec& q) {
 
 size_t query_jobs(const QuerySpec& q) {
     const size_t cells = band_cells(q.m, q.n, q.band);
-    if (!both_encrypted(q)) return cells;
-    return cells * (q.encoding == LVS_ENC_ASCII7 ? 3 : 2);
+    size_t refresh = 0;
+    if (q.refresh > 0)
+        for (size_t s = q.refresh; s < q.m + q.n; s += q.refresh) refresh += 2 * diagonal_cells(q, s);
+    if (!both_encrypted(q)) return cells + refresh;
+    return cells * (q.encoding == LVS_ENC_ASCII7 ? 3 : 2) + refresh;
 }
 
 size_t plan_bytes(size_t njobs, size_t max_step) {
@@ -229,6 +247,23 @@ void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool wi
         }
     };
     const size_t all = size_t(-1);
+    // fill the current step's last partial round, earliest deadline first
+    // (the step precedes diagonal t + 1)
+    auto fill = [&](size_t t) {
+        if (quantum > 0) {
+            const size_t count = P.steps.back().count;
+            size_t target = (count + quantum - 1) / quantum * quantum;
+            if (cap > 0) target = std::min(target, cap);
+            for (size_t s = t + 2; s <= smax && P.steps.back().count < target; ++s) {
+                // deadline s - 1: last stages of diagonal s, single stages of s
+                place2(eqd[s], target - P.steps.back().count);
+                place1(eqd2[s], target - P.steps.back().count);
+                // deadline s - 1 as well: first stages of diagonal s + 1
+                if (s + 1 <= smax) place1(eqd[s + 1], target - P.steps.back().count);
+            }
+        }
+        for (auto& d : eqd) d.n1_before = d.n1;
+    };
     const size_t t0 = any_ascii ? 0 : 1;
     for (size_t t = t0; t <= smax; ++t) {
         b.step();
@@ -288,20 +323,29 @@ void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool wi
                 b.add(J);
             });
         }
-        // fill the step's last partial round, earliest deadline first
-        if (quantum > 0) {
-            const size_t count = P.steps.back().count;
-            size_t target = (count + quantum - 1) / quantum * quantum;
-            if (cap > 0) target = std::min(target, cap);
-            for (size_t s = t + 2; s <= smax && P.steps.back().count < target; ++s) {
-                // deadline s - 1: last stages of diagonal s, single stages of s
-                place2(eqd[s], target - P.steps.back().count);
-                place1(eqd2[s], target - P.steps.back().count);
-                // deadline s - 1 as well: first stages of diagonal s + 1
-                if (s + 1 <= smax) place1(eqd[s + 1], target - P.steps.back().count);
-            }
+        fill(t);
+        // Section 3.1's refresh: the v and h just written on diagonal t are
+        // bootstrapped in place through the identity table (the key switch
+        // reads every source before the blind rotation writes)
+        bool refresh = false;
+        for (const auto& q : qs) refresh |= refresh_due(q, t) && diagonal_cells(q, t) > 0;
+        if (!refresh) continue;
+        b.step();
+        for (const auto& q : qs) {
+            if (!refresh_due(q, t)) continue;
+            uint64_t* H = (q.h_last ? q.h_last : q.H) - W;
+            for_diagonal(q, t, [&](size_t i, size_t j) {
+                for (uint64_t* x : {q.V + i * W, H + j * W}) {
+                    Job J = blank_job();
+                    J.src[0] = x;
+                    J.coef[0] = 1;
+                    J.lut = LVS_LUT_REFRESH;
+                    J.dst[2] = x;
+                    b.add(J);
+                }
+            });
         }
-        for (auto& d : eqd) d.n1_before = d.n1;
+        fill(t);
     }
 }
 

@@ -32,6 +32,10 @@ struct QuerySpec {
     // differences of the diagonal path, written to path ([m+n][W]).
     long band = -1;
     uint64_t* path = nullptr;
+    // Section 3.1's noise refresh: the v and h written on anti-diagonals
+    // s = refresh, 2 refresh, ... (s < m + n) are bootstrapped again through
+    // the identity table before diagonal s + 1 reads them (0: never).
+    size_t refresh = 0;
     // workspace buffers assigned by assign_buffers()
     uint64_t* V = nullptr;                  // [m+1][W]
     uint64_t* eq1 = nullptr;                // [m][n][W] (ASCII, both encrypted)
@@ -46,6 +50,14 @@ inline bool in_band(const QuerySpec& q, size_t i, size_t j) {
 
 // Cells of an m x n matrix with |i - j| <= band (every cell if band < 0).
 size_t band_cells(size_t m, size_t n, long band);
+
+// Cells of anti-diagonal s (i + j = s) that the query bootstraps.
+size_t diagonal_cells(const QuerySpec& q, size_t s);
+
+// Whether the differences written on anti-diagonal s are refreshed.
+inline bool refresh_due(const QuerySpec& q, size_t s) {
+    return q.refresh > 0 && s >= 2 && s % q.refresh == 0 && s < q.m + q.n;
+}
 
 struct PlanStep {
     size_t off, count;
@@ -74,7 +86,8 @@ size_t query_jobs(const QuerySpec& q);
 void assign_buffers(std::vector<QuerySpec>& qs, uint8_t*& ws);
 
 // Builds the jobs: equality steps (both encrypted), then one step per
-// anti-diagonal s = 2 .. max(m + n) holding every query's cells on it.
+// anti-diagonal s = 2 .. max(m + n) holding every query's cells on it, each
+// followed by a refresh step when some query's refresh is due after it.
 // quantum: bootstraps the device runs at once (0: no filling); cap: the
 // largest step the workspace was sized for.
 void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool with_dp = true, size_t quantum = 0,

@@ -6,7 +6,8 @@
 // Each request goes through three phases: the preprocessing table's two
 // bootstrap rounds (eq1, then eq9 = T[c][i]), then the anti-diagonals
 // s = 2 .. m + max(n_k) of one DP instance per name, all instances of the
-// request advancing together.  An engine step gathers the ready bootstraps of
+// request advancing together, with a refresh round (Section 3.1) after every
+// refresh-th diagonal.  An engine step gathers the ready bootstraps of
 // every admitted request (any mix of phases and tables) into one key-switch
 // launch and one persistent blind-rotation launch.  Requests are admitted in
 // arrival order when their device buffers fit in the caller's arena, and join
@@ -86,6 +87,7 @@ struct Request {
     std::vector<uint64_t> host_query;   // [m][2][W] until admitted
     Phase phase = kQueued;
     size_t s = 2;                        // current anti-diagonal in the DP phase
+    bool refreshing = false;             // the round refreshes the differences of diagonal s
     size_t off = 0, bytes = 0;           // block in the pool
     uint64_t* A = nullptr;               // [m][2][W]
     uint64_t* eq1 = nullptr;             // [alen][m][W]
@@ -105,6 +107,7 @@ struct Server : Handle {
     std::vector<size_t> name_len, name_start;  // first result row of every name
     std::vector<int32_t> cols;                 // concatenated alphabet index of every name symbol
     size_t total_len = 0, max_len = 0;
+    size_t refresh = 0;                        // noise-refresh interval (anti-diagonals, 0: off)
     std::vector<uint8_t> sym_lo, sym_hi;       // alphabet symbols (4-bit, 3-bit)
     // device regions
     Job* d_jobs = nullptr;
@@ -176,6 +179,20 @@ struct Server : Handle {
             const int32_t* col = cols.data() + name_start[k];
             const size_t i_lo = (s > n + 1) ? s - n : 1;
             const size_t i_hi = std::min(m, s - 1);
+            if (r->refreshing) {
+                // the v and h written on diagonal s, in place through the identity table
+                if (s >= m + n) continue;
+                for (size_t i = i_lo; i <= i_hi; ++i)
+                    for (uint64_t* x : {V + i * W, H + (s - i) * W}) {
+                        Job J{};
+                        J.src[0] = x;
+                        J.coef[0] = 1;
+                        J.lut = LVS_LUT_REFRESH;
+                        J.dst[2] = x;
+                        out.push_back(J);
+                    }
+                continue;
+            }
             for (size_t i = i_lo; i <= i_hi; ++i) {
                 const size_t j = s - i;
                 const uint64_t* v_in = (j == 1) ? nullptr : V + i * W;
@@ -204,6 +221,12 @@ struct Server : Handle {
         if (r->phase == kPre1) r->phase = kPre2;
         else if (r->phase == kPre2) { r->phase = kDp; r->s = 2; }
         else if (r->phase == kDp) {
+            // a refresh round follows diagonal s when some name still has cells past it
+            if (!r->refreshing && refresh > 0 && r->s % refresh == 0 && r->s < r->m + max_len) {
+                r->refreshing = true;
+                return;
+            }
+            r->refreshing = false;
             r->s++;
             if (r->s > r->m + max_len) r->phase = kDone;
         }
@@ -269,6 +292,7 @@ int lvs_server_create(lvs_context* ctx, const uint8_t* names, const size_t* name
     S->arena = reinterpret_cast<uint8_t*>(d_arena);
     S->arena_bytes = arena_bytes;
     S->max_step = max_step;
+    S->refresh = C->refresh_every;
     for (size_t c = 0; c < alen; ++c) {
         if (alphabet[c] >= 128) SRV_FAIL(LVS_E_ALPHABET, "lvs_server_create: alphabet symbol >= 128");
         S->sym_lo.push_back(alphabet[c] & 15);
@@ -277,7 +301,7 @@ int lvs_server_create(lvs_context* ctx, const uint8_t* names, const size_t* name
     size_t pos = 0;
     for (size_t k = 0; k < n_names; ++k) {
         const size_t n = name_lens[k];
-        if (n > 4096) SRV_FAIL(LVS_E_NOISE_BUDGET, "lvs_server_create: name exceeds the noise budget");
+        if (n > 4096) SRV_FAIL(LVS_E_INVAL, "lvs_server_create: name longer than 4096");
         S->name_len.push_back(n);
         S->name_start.push_back(S->total_len);
         for (size_t j = 0; j < n; ++j) {
@@ -301,6 +325,8 @@ int lvs_server_submit(lvs_server* srv, const uint64_t* h_query, size_t m, uint64
     Server* S = as_srv(srv);
     if (!S || !ticket || (!h_query && m)) SRV_FAIL(LVS_E_INVAL, "lvs_server_submit: bad argument");
     if (m == 0 || m > 4096) SRV_FAIL(LVS_E_INVAL, "lvs_server_submit: query length must be 1..4096");
+    if (S->refresh == 0 && std::min(m, S->max_len) > size_t(LVS_MAX_DEPTH_NO_REFRESH))
+        SRV_FAIL(LVS_E_NOISE_BUDGET, "lvs_server_submit: min(m, name length) exceeds the noise budget with refresh off");
     if (S->request_bytes(m) > S->pool.total())
         SRV_FAIL(LVS_E_NOMEM_DEVICE, "lvs_server_submit: the request can never fit in the arena");
     auto r = std::unique_ptr<Request>(new (std::nothrow) Request());

@@ -16,7 +16,9 @@ LIB_PATH = os.path.join(HERE, "liblvs.so")
 
 LVS_ENC_ASCII7 = 0
 LVS_ENC_DNA2 = 1
-LVS_LUT_EQ, LVS_LUT_EQ9, LVS_LUT_MIN, LVS_LUT_USER, LVS_LUT_SLOTS = 0, 1, 2, 3, 8
+LVS_LUT_EQ, LVS_LUT_EQ9, LVS_LUT_MIN, LVS_LUT_REFRESH, LVS_LUT_USER, LVS_LUT_SLOTS = 0, 1, 2, 3, 4, 8
+LVS_REFRESH_DEFAULT, LVS_REFRESH_MIN, LVS_REFRESH_MAX, LVS_MAX_DEPTH_NO_REFRESH = 256, 4, 512, 256
+LVS_MAX_LEN = 1 << 20
 CT_WORDS = 2049
 
 ERRORS = {-1: "LVS_E_INVAL", -2: "LVS_E_ALPHABET", -3: "LVS_E_NOISE_BUDGET", -4: "LVS_E_NOMEM_HOST",
@@ -75,8 +77,10 @@ _SIGS = {
     "lvs_edit_distance_clear_band": (I32, [VP, VP, SZ, VP, SZ, VP, SZ, SZ, VP, VP, SZ]),
     "lvs_plan_workspace_bytes": (I32, [VP, SZ, I32, ctypes.POINTER(SZ)]),
     "lvs_plan_create": (I32, [VP, VP, SZ, I32, I32, VP, SZ, ctypes.POINTER(VP)]),
-    "lvs_plan_verify": (I32, [VP, SZ, I32, SZ, I32, ctypes.POINTER(SZ), ctypes.POINTER(SZ), ctypes.POINTER(SZ),
-                              ctypes.POINTER(SZ)]),
+    "lvs_plan_verify": (I32, [VP, SZ, I32, SZ, I32, SZ, ctypes.POINTER(SZ), ctypes.POINTER(SZ),
+                              ctypes.POINTER(SZ), ctypes.POINTER(SZ)]),
+    "lvs_context_set_refresh": (I32, [VP, SZ]),
+    "lvs_context_get_refresh": (I32, [VP, ctypes.POINTER(SZ)]),
     "lvs_plan_run": (I32, [VP]),
     "lvs_plan_info": (I32, [VP, ctypes.POINTER(SZ), ctypes.POINTER(SZ), ctypes.POINTER(SZ)]),
     "lvs_server_fixed_bytes": (SZ, [SZ]),
@@ -263,6 +267,17 @@ def lvs_context_set_stream(ctx: Context, stream):
 def lvs_context_set_lut(ctx: Context, slot: int, f16):
     arr = (ctypes.c_int32 * 16)(*[int(v) for v in f16])
     _check(lib().lvs_context_set_lut(ctx, slot, arr))
+
+
+def lvs_context_set_refresh(ctx: Context, every: int):
+    """Noise-refresh interval in anti-diagonals (0: off)."""
+    _check(lib().lvs_context_set_refresh(ctx, every))
+
+
+def lvs_context_get_refresh(ctx: Context) -> int:
+    out = SZ()
+    _check(lib().lvs_context_get_refresh(ctx, ctypes.byref(out)))
+    return out.value
 
 
 def lvs_sync(ctx: Context):
@@ -459,10 +474,11 @@ def lvs_plan_create(ctx: Context, items, encoding: int, graph: bool = False, d_w
     return Plan(out, (arr, keep, d_work, items))
 
 
-def lvs_plan_verify(queries, encoding: int, round_: int, fill: bool = True):
+def lvs_plan_verify(queries, encoding: int, round_: int, fill: bool = True, refresh: int = 0):
     """queries: (m, n, kind, ell) tuples with kind 'enc' (both encrypted) or
     'clear' (cleartext b over alphabet bytes(range(n)) of n distinct symbols);
     ell None for the full matrix.  Buffers get placeholder addresses.
+    refresh: the noise-refresh interval (0: off).
     Returns (steps, bootstraps, rounds, violations)."""
     arr = (lvs_query * max(1, len(queries)))()
     keep = []
@@ -490,7 +506,7 @@ def lvs_plan_verify(queries, encoding: int, round_: int, fill: bool = True):
             q.banded, q.ell, q.d_path = 1, ell, addr
             addr += (m + n + 1) * CT_WORDS * 8
     st, jb, rd, bad = SZ(), SZ(), SZ(), SZ()
-    _check(lib().lvs_plan_verify(arr, len(queries), encoding, round_, 1 if fill else 0, ctypes.byref(st),
+    _check(lib().lvs_plan_verify(arr, len(queries), encoding, round_, 1 if fill else 0, refresh, ctypes.byref(st),
                                  ctypes.byref(jb), ctypes.byref(rd), ctypes.byref(bad)))
     return st.value, jb.value, rd.value, bad.value
 

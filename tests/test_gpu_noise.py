@@ -1,5 +1,5 @@
-"""Noise of the DP state along the wavefront (the paper's reason for
-noise-refresh bootstraps past a few thousand additions).  v and h telescope
+"""Noise of the DP state along the wavefront with refresh off (the reason
+for Section 3.1's refresh bootstraps).  v and h telescope
 along the diagonal (v[i,j] = M[i,j] - M[i-1,j] + v[i-1,j-1]), so the error of
 a cell's key grows with min(i, j).  On the 256 x 256 DNA alignment every
 bootstrap output M is recorded; every key 4 - v + 3 h + eq9 is rebuilt on the
@@ -32,8 +32,13 @@ def test_key_noise_dna_256(gpu):
     d_tr = torch.zeros_like(d_eq9)
     d_h = torch.zeros(n * L.CT_WORDS, dtype=torch.int64, device=g.dev)
     L.lvs_equality(g.ctx, dA, m, dB, n, L.LVS_ENC_DNA2, d_eq9)
-    L.lvs_edit_distance_eq9(g.ctx, d_eq9, m, n, d_h, d_trace=d_tr)
-    torch.cuda.synchronize()
+    prev = L.lvs_context_get_refresh(g.ctx)
+    L.lvs_context_set_refresh(g.ctx, 0)          # the growth without refresh
+    try:
+        L.lvs_edit_distance_eq9(g.ctx, d_eq9, m, n, d_h, d_trace=d_tr)
+        torch.cuda.synchronize()
+    finally:
+        L.lvs_context_set_refresh(g.ctx, prev)
     eq9 = L.to_host(d_eq9).reshape(m, n, L.CT_WORDS)
     tr = L.to_host(d_tr).reshape(m, n, L.CT_WORDS)
     del d_eq9, d_tr

@@ -145,6 +145,31 @@ def test_plan_schedule_is_causal_and_fills_rounds():
                 assert bad0 == 0 and bad1 == 0, (enc, trial, rnd)
                 assert jobs0 == jobs1 == want
                 assert rounds1 <= rounds0
+    # Section 3.1 refresh: a step after every R-th diagonal holding two
+    # bootstraps per cell of that diagonal for each query with cells past it
+    for enc in (L.LVS_ENC_ASCII7, L.LVS_ENC_DNA2):
+        for trial, R in enumerate((4, 7, 16)):
+            qs = []
+            for _ in range(int(rng.integers(1, 20))):
+                m, n = (int(x) for x in rng.integers(1, 50, size=2))
+                kind = "enc" if rng.random() < 0.7 else "clear"
+                ell = None if rng.random() < 0.6 else int(rng.integers(0, 12))
+                qs.append((m, n, kind, ell))
+            extra, due = 0, set()
+            for m, n, kind, ell in qs:
+                for s_ in range(R, m + n, R):
+                    c = sum(1 for i in range(1, m + 1) if 1 <= s_ - i <= n and (ell is None or abs(2 * i - s_) <= ell))
+                    extra += 2 * c
+                    if c:
+                        due.add(s_)
+            for rnd in (64, 256):
+                st0, jobs0, _, _ = L.lvs_plan_verify(qs, enc, rnd, fill=True)
+                st1, jobs1, rounds1, bad1 = L.lvs_plan_verify(qs, enc, rnd, fill=True, refresh=R)
+                assert bad1 == 0, (enc, R, rnd)
+                assert jobs1 == jobs0 + extra
+                assert st1 == st0 + len(due)
+    with pytest.raises(L.LvsError):
+        L.lvs_plan_verify([(4, 4, "enc", None)], L.LVS_ENC_DNA2, 64, refresh=3)
     # the 64-query batched workload: filling removes device rounds
     qs = [(len(a), len(b), "enc", None) for a, b in W.batched()[:64]]
     _, jobs, rounds_plain, bad0 = L.lvs_plan_verify(qs, L.LVS_ENC_ASCII7, 256, fill=False)
