@@ -22,6 +22,10 @@ of the schoolbook TFHE oracle (``tfhe.py``):
   * Section 3.1 noise refresh: the differences written on every R-th
     anti-diagonal are bootstrapped again through the identity table
     (``refresh_every``), which restarts their noise growth.
+  * Section 4.2 equality of wide symbols (the hybrid method): a symbol of
+    w bits is encrypted as ceil(w / 4) 4-bit chunks; every chunk pair gives
+    a sub-equality PBS(x_k - y_k; LUT_eq), and Algorithm 2's merging sums
+    groups of at most 15 and bootstraps each sum (``equality_wide``).
 """
 import numpy as np
 
@@ -31,13 +35,14 @@ from . import tfhe as T
 ENC_ASCII7 = 0
 ENC_DNA2 = 1
 
-LUT_IDS = {"eq": 0, "eq9": 1, "min": 2, "refresh": 3}
+LUT_IDS = {"eq": 0, "eq9": 1, "min": 2, "refresh": 3, "max": 4, "max9": 5}
 
 
 def lut_polys(N: int) -> np.ndarray:
     """Test polynomials in the order of LUT_IDS."""
     return np.stack([T.test_polynomial(P.LUT_EQ, N), T.test_polynomial(P.LUT_EQ9, N),
-                     T.test_polynomial(P.lut_min_negated(), N), T.test_polynomial(P.LUT_REFRESH, N)])
+                     T.test_polynomial(P.lut_min_negated(), N), T.test_polynomial(P.LUT_REFRESH, N),
+                     T.test_polynomial(P.LUT_MAX, N), T.test_polynomial(P.LUT_MAX9, N)])
 
 
 def refresh_due(s: int, m: int, n: int, refresh_every: int) -> bool:
@@ -68,6 +73,17 @@ def encrypt_string(keys: T.Keys, s, encoding: int, seed: int) -> np.ndarray:
     return out
 
 
+def encrypt_symbols(keys: T.Keys, syms, width: int, seed: int) -> np.ndarray:
+    """Array (len, c, N+1) of wide symbols, c = ceil(width / 4): chunk k of
+    symbol i is ciphertext number i * c + k under the encryption seed."""
+    c = P.wide_chunk_count(width)
+    out = np.zeros((len(syms), c, keys.N + 1), dtype=T.U64)
+    for i, v in enumerate(syms):
+        for k, x in enumerate(P.wide_chunks(int(v), width)):
+            out[i, k] = keys.encrypt(x, seed, i * c + k)
+    return out
+
+
 def _pbs(keys, cts, lut_name, nthreads):
     polys = lut_polys(keys.N)
     return keys.pbs_batch(cts, polys, LUT_IDS[lut_name], nthreads)
@@ -87,6 +103,48 @@ def equality(keys: T.Keys, A: np.ndarray, B: np.ndarray, encoding: int, nthreads
     z2 = (z2 + one[None, :] - eq1).astype(T.U64)
     eq9 = _pbs(keys, z2, "eq9", nthreads)
     return eq1.reshape(m, n, W), eq9.reshape(m, n, W)
+
+
+def merge_wide(keys: T.Keys, sub: np.ndarray, nthreads=None) -> np.ndarray:
+    """Algorithm 2's merging over the last axis but one of sub (..., c, N+1)
+    holding encryptions of 0/1: groups of at most 15 are summed, offset by
+    15 - g (a noise-free constant) and bootstrapped through LUT_max (LUT_max9
+    at the last level), until one ciphertext is left per leading index."""
+    lead, W = sub.shape[:-2], sub.shape[-1]
+    cur = sub.reshape(-1, sub.shape[-2], W)
+    while cur.shape[1] > 1:
+        c = cur.shape[1]
+        groups = [(k, min(c, k + P.MERGE_GROUP)) for k in range(0, c, P.MERGE_GROUP)]
+        lut = "max9" if len(groups) == 1 else "max"
+        sums = np.stack([(cur[:, a:b].sum(axis=1, dtype=T.U64)
+                          + T.trivial(P.MERGE_GROUP - (b - a), keys.N)[None, :]).astype(T.U64)
+                         for a, b in groups], axis=1)
+        cur = _pbs(keys, sums.reshape(-1, W), lut, nthreads).reshape(cur.shape[0], len(groups), W)
+    return cur[:, 0].reshape(*lead, W)
+
+
+def equality_wide(keys: T.Keys, A: np.ndarray, B: np.ndarray, width: int, nthreads=None) -> np.ndarray:
+    """eq9[i,j] = Enc(9 [a_i = b_j]) for symbols of `width` bits encrypted
+    by encrypt_symbols: one sub-equality PBS per 4-bit chunk pair, then the
+    merging (a single chunk reads LUT_eq9 directly).  Shape (m, n, N+1)."""
+    m, n, W = A.shape[0], B.shape[0], keys.N + 1
+    c = P.wide_chunk_count(width)
+    assert A.shape[1] == c and B.shape[1] == c
+    z = (A[:, None, :, :] - B[None, :, :, :]).astype(T.U64).reshape(m * n * c, W)
+    if c == 1:
+        return _pbs(keys, z, "eq9", nthreads).reshape(m, n, W)
+    sub = _pbs(keys, z, "eq", nthreads).reshape(m * n, c, W)
+    return merge_wide(keys, sub, nthreads).reshape(m, n, W)
+
+
+def edit_distance_wide(keys: T.Keys, A: np.ndarray, B: np.ndarray, width: int, nthreads=None,
+                       refresh_every: int = 0):
+    """Wide-symbol equality of every pair, then the diagonal-order main loop."""
+    m, n = A.shape[0], B.shape[0]
+    if m == 0 or n == 0:
+        return np.tile(T.trivial(1, keys.N), (n, 1))
+    eq9 = equality_wide(keys, A, B, width, nthreads)
+    return dp(keys, m, n, lambda i, j: eq9[i - 1, j - 1], "diagonal", nthreads, False, refresh_every)
 
 
 def preprocess(keys: T.Keys, A: np.ndarray, alphabet, encoding: int, nthreads=None):

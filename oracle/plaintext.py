@@ -13,6 +13,9 @@ The cleartext definitions that the encrypted method must reproduce exactly
   * The 7-bit character split into a 4-bit and a 3-bit symbol (Section 4.3).
   * Skipping irrelevant cells (Section 3.4, Algorithm 1's band |i - j| <= ell)
     with the result summed along the diagonal.
+  * Equality of wide symbols (Section 4.2, the hybrid of the 4-bit
+    subtraction check with Algorithm 2's merging) and the bootstrap counts
+    of the three equality methods the section compares.
 """
 import itertools
 
@@ -206,3 +209,73 @@ def ascii_symbols(c: int):
 
 def dna_code(base) -> int:
     return "ACGT".index(base) if isinstance(base, str) else int(base)
+
+
+# ------------------------------------------------- wide symbols (Section 4.2)
+
+# Merging (Algorithm 2): the sub-equalities are summed in groups of at most
+# t - 1 = 15 (a lookup reads 16 values), and a bootstrap tests whether a
+# group's sum reached the group size.  Here a group of g is offset by 15 - g
+# so that one table serves every group size: the sum reads 15 exactly when
+# all g sub-equalities are 1.
+MERGE_GROUP = 15
+LUT_MAX = [0] * 15 + [1]
+LUT_MAX9 = [0] * 15 + [9]
+
+
+def wide_chunk_count(width: int) -> int:
+    """4-bit chunks of a width-bit symbol (the hybrid encoding, Section 4.2)."""
+    assert width >= 1
+    return (width + 3) // 4
+
+
+def wide_chunks(v: int, width: int):
+    """Chunk k holds bits 4k .. 4k + 3 of v (the last chunk may be narrower)."""
+    assert 0 <= v < 2 ** width
+    return [(v >> (4 * k)) & 15 for k in range(wide_chunk_count(width))]
+
+
+def merge_levels(count: int):
+    """Group counts of the successive merging levels for `count`
+    sub-equalities (empty for one: its own bootstrap gives the result)."""
+    levels = []
+    while count > 1:
+        count = (count + MERGE_GROUP - 1) // MERGE_GROUP
+        levels.append(count)
+    return levels
+
+
+def hybrid_equal_plain(x: int, y: int, width: int) -> int:
+    """The hybrid equality in the clear: sub-equality of every chunk pair
+    (z = x_k - y_k read through LUT_eq), then the merging levels (a group of
+    g reads LUT_max at sum + 15 - g; the last level reads LUT_max9).  Returns
+    the final bootstrap's value, 9 [x = y]."""
+    cx, cy = wide_chunks(x, width), wide_chunks(y, width)
+    if len(cx) == 1:
+        return negacyclic_read(LUT_EQ9, cx[0] - cy[0])
+    sub = [negacyclic_read(LUT_EQ, a - b) for a, b in zip(cx, cy)]
+    while len(sub) > 1:
+        groups = [sub[k:k + MERGE_GROUP] for k in range(0, len(sub), MERGE_GROUP)]
+        lut = LUT_MAX9 if len(groups) == 1 else LUT_MAX
+        sub = [negacyclic_read(lut, sum(g) + MERGE_GROUP - len(g)) for g in groups]
+    return sub[0]
+
+
+def pbs_hybrid(width: int) -> int:
+    """Bootstraps of the hybrid equality: one per 4-bit chunk plus the merges."""
+    c = wide_chunk_count(width)
+    return c + sum(merge_levels(c))
+
+
+def pbs_two_bit(width: int) -> int:
+    """Bootstraps of Algorithm 2 as TFHE-rs runs it: one per 2-bit chunk
+    (key x + 4 y) plus the same merges."""
+    c = (width + 1) // 2
+    return c + sum(merge_levels(c))
+
+
+def pbs_chain(width: int) -> int:
+    """Bootstraps of the Section 4.3 method extended to any width: a 4-bit
+    symbol, then 3-bit symbols, each folded with the previous result as in
+    Algorithm 3 (2 (x - y) + (1 - eq) stays within [-15, 15])."""
+    return 1 + (max(0, width - 4) + 2) // 3

@@ -2,6 +2,8 @@
 preprocessing of arXiv 2508.14568) against the plaintext definitions."""
 import itertools
 
+import pytest
+
 import numpy as np
 
 from conftest import golden
@@ -228,3 +230,56 @@ def test_refresh_band_and_cleartext(oracle_toy_keys):
     Tab = L.preprocess(k, A2, alpha, L.ENC_ASCII7)
     h_last = L.edit_distance_clear(k, Tab, alpha, b2, L.ENC_ASCII7, refresh_every=4)
     assert L.decrypt_distance(k, len(a2), h_last) == 3
+
+
+class _LutCountingKeys(_CountingKeys):
+    """Keys that count bootstraps per table."""
+
+    def __init__(self, keys):
+        super().__init__(keys)
+        self.count = {}
+
+    def pbs_batch(self, cts, polys, lut_ids, nthreads=None):
+        name = {v: k for k, v in L.LUT_IDS.items()}[int(lut_ids)]
+        self.count[name] = self.count.get(name, 0) + np.asarray(cts).reshape(-1, self._k.N + 1).shape[0]
+        return self._k.pbs_batch(cts, polys, lut_ids, nthreads)
+
+
+@pytest.mark.parametrize("width", [4, 7, 21, 64])
+def test_wide_equality_encrypted(oracle_toy_keys, width):
+    """Section 4.2's hybrid on encrypted symbols: eq9 decrypts to 9 [x = y]
+    for equal pairs, pairs differing in one chunk only, and random pairs; the
+    bootstraps per pair match the count of the method (one per chunk, then
+    the merging levels)."""
+    k = _LutCountingKeys(oracle_toy_keys)
+    rng = np.random.default_rng(width)
+    base = [int(rng.integers(0, 2 ** min(width, 62))) % (2 ** width) for _ in range(3)]
+    xs = base + [base[0]]
+    ys = [base[1], base[0] ^ (1 << int(rng.integers(0, width))), int(rng.integers(0, 2 ** min(width, 62))),
+          base[0]]
+    A = L.encrypt_symbols(k, xs, width, 51)
+    B = L.encrypt_symbols(k, ys, width, 52)
+    assert A.shape == (4, P.wide_chunk_count(width), k.N + 1)
+    eq9 = L.equality_wide(k, A, B, width)
+    for i, x in enumerate(xs):
+        for j, y in enumerate(ys):
+            assert k.decrypt(eq9[i, j]) == (9 if x == y else 0), (i, j)
+    assert sum(k.count.values()) == 16 * P.pbs_hybrid(width)
+    c = P.wide_chunk_count(width)
+    if c > 1:
+        assert k.count["eq"] == 16 * c and k.count["max9"] == 16
+
+
+def test_wide_edit_distance(oracle_toy_keys):
+    """Edit distance over 21-bit symbols (Unicode code points) equals
+    Wagner-Fischer on the symbol sequences, with and without refresh."""
+    k = oracle_toy_keys
+    rng = np.random.default_rng(77)
+    alphabet = [int(v) for v in rng.integers(0, 2 ** 21, size=4)]
+    a = [alphabet[int(t)] for t in rng.integers(0, 4, size=5)]
+    b = [alphabet[int(t)] for t in rng.integers(0, 4, size=6)]
+    A = L.encrypt_symbols(k, a, 21, 61)
+    B = L.encrypt_symbols(k, b, 21, 62)
+    for R in (0, 4):
+        h_last = L.edit_distance_wide(k, A, B, 21, refresh_every=R)
+        assert L.decrypt_distance(k, len(a), h_last) == P.edit_distance(a, b)

@@ -220,3 +220,53 @@ def test_full_band_equals_delta_dp():
         v, h = P.delta_dp_band(a, b, max(len(a), len(b)))
         v2, h2, _ = P.delta_dp(a, b)
         assert (v == v2).all() and (h == h2).all()
+
+
+def test_equality_method_counts_section4():
+    """Section 4's counts: an ASCII check costs 2 bootstraps with the
+    Section 4.3 method, 5 with 2-bit chunks and 3 with 4-bit chunks merged;
+    the Section 4.3 method is the cheapest up to 16-bit symbols and the
+    hybrid beyond (Fig. fig_eq); the hybrid roughly halves the 2-bit cost."""
+    assert (P.pbs_chain(7), P.pbs_two_bit(7), P.pbs_hybrid(7)) == (2, 5, 3)
+    for w in range(5, 17):
+        assert P.pbs_chain(w) <= P.pbs_hybrid(w) and P.pbs_chain(w) <= P.pbs_two_bit(w), w
+    for w in range(17, 65):
+        assert P.pbs_hybrid(w) <= P.pbs_chain(w), w
+    assert all(P.pbs_hybrid(w) < P.pbs_chain(w) for w in range(26, 65))
+    for w in range(8, 65):
+        assert 3 * P.pbs_hybrid(w) <= 2 * P.pbs_two_bit(w), w
+        assert w < 32 or P.pbs_hybrid(w) <= 0.55 * P.pbs_two_bit(w), w
+    # the merge of c sub-equalities: groups of at most 15, level by level
+    assert P.merge_levels(1) == [] and P.merge_levels(15) == [1]
+    assert P.merge_levels(16) == [2, 1] and P.merge_levels(226) == [16, 2, 1]
+
+
+def test_hybrid_equality_exhaustive_small_widths():
+    """Every pair of symbols up to 8 bits: the hybrid returns 9 exactly on
+    equal symbols."""
+    for w in range(1, 9):
+        for x in range(2 ** w):
+            for y in range(2 ** w):
+                assert P.hybrid_equal_plain(x, y, w) == (9 if x == y else 0), (w, x, y)
+
+
+def test_hybrid_equality_all_chunk_patterns():
+    """Every pattern of equal / unequal chunks for 2, 15, 16 and 17 chunks,
+    and random patterns over 226 chunks (three merging levels): equal only
+    when every chunk is."""
+    rng = np.random.default_rng(41)
+    for c in (2, 15, 16, 17):
+        w = 4 * c
+        for pattern in range(2 ** c):
+            x = int(rng.integers(0, 2 ** 62)) % (2 ** w) if w <= 62 else \
+                sum(int(rng.integers(0, 16)) << (4 * k) for k in range(c))
+            y = x
+            for k in range(c):
+                if pattern >> k & 1:
+                    y ^= (1 + int(rng.integers(0, 15))) << (4 * k)
+            assert P.hybrid_equal_plain(x, y, w) == (9 if pattern == 0 else 0), (c, pattern)
+    for _ in range(200):
+        x = sum(int(rng.integers(0, 16)) << (4 * k) for k in range(226))
+        k = int(rng.integers(0, 226))
+        y = x ^ ((1 + int(rng.integers(0, 15))) << (4 * k)) if rng.random() < 0.7 else x
+        assert P.hybrid_equal_plain(x, y, 904) == (9 if x == y else 0)
