@@ -48,9 +48,20 @@ typedef enum { LVS_ENC_ASCII7 = 0, LVS_ENC_DNA2 = 1 } lvs_encoding;
  * [9,0,..] (Eq. eq_eqlut9), MIN = 1 + min(-eq, dv, dh) under the key
  * (1 - dv) + 3 (1 + dh) + 9 eq (Eq. eq_keyeq2, Algorithms 1 and 4), REFRESH =
  * the identity on the differences -1, 0, 1 ([0,1,0,..,0,1]; -1 reads -f(15)),
- * the noise refresh of Section 3.1.  Slots from LVS_LUT_USER are free for
- * lvs_context_set_lut. */
-enum { LVS_LUT_EQ = 0, LVS_LUT_EQ9 = 1, LVS_LUT_MIN = 2, LVS_LUT_REFRESH = 3, LVS_LUT_USER = 4, LVS_LUT_SLOTS = 8 };
+ * the noise refresh of Section 3.1.  MAX = [0,..,0,1] and MAX9 = [0,..,0,9]
+ * test whether a merging sum of the wide-symbol equality reached its maximum
+ * (Algorithm 2, with the sum offset so that the maximum reads 15).  Slots from
+ * LVS_LUT_USER are free for lvs_context_set_lut. */
+enum {
+    LVS_LUT_EQ = 0,
+    LVS_LUT_EQ9 = 1,
+    LVS_LUT_MIN = 2,
+    LVS_LUT_REFRESH = 3,
+    LVS_LUT_MAX = 4,
+    LVS_LUT_MAX9 = 5,
+    LVS_LUT_USER = 6,
+    LVS_LUT_SLOTS = 8
+};
 
 /* Noise refresh (Section 3.1: the differences are bootstrapped again before
  * their noise reaches the decoding threshold, Fig. noise5).  The error of a
@@ -311,6 +322,55 @@ size_t lvs_edit_distance_clear_band_workspace_bytes(size_t m, size_t n, size_t e
  * restricted to the band.  Arguments as lvs_edit_distance_clear. */
 int lvs_edit_distance_clear_band(lvs_context* ctx, const uint64_t* d_table, size_t m, const uint8_t* alphabet,
                                  size_t alen, const uint8_t* b, size_t n, size_t ell, uint64_t* d_path, void* d_work,
+                                 size_t work_bytes);
+
+/* ----------------------------------------------------------- wide symbols */
+
+/* Section 4.2's hybrid equality for symbols wider than a character (up to
+ * 64 bits, e.g. 21-bit Unicode code points).  A symbol of `width` bits is
+ * encrypted as c = ceil(width / 4) ciphertexts of its 4-bit chunks (chunk k
+ * holds bits 4k .. 4k + 3).  Equality of two symbols costs one bootstrap per
+ * chunk pair, PBS(x_k - y_k; LUT_eq), then Algorithm 2's merging: groups of
+ * at most 15 sub-equalities are summed, a group of g offset by 15 - g, and
+ * bootstrapped through LUT_max (LUT_max9 at the last level) until one
+ * ciphertext, Enc(9 [x = y]), is left; a single chunk (width <= 4) reads
+ * LUT_eq9 at once.  lvs_wide_pbs_per_pair gives the count: c plus the
+ * merges. */
+size_t lvs_wide_chunks(unsigned width);          /* c, or 0 unless 1 <= width <= 64 */
+size_t lvs_wide_pbs_per_pair(unsigned width);    /* bootstraps per symbol pair, 0 if width is invalid */
+
+/* h_out ([len][c][N+1] words, host): chunk k of syms[i] is ciphertext number
+ * i * c + k under the encryption seed.  LVS_E_ALPHABET if a symbol does not
+ * fit in width bits. */
+int lvs_encrypt_symbols(const lvs_client_key* ck, const uint64_t* syms, size_t len, unsigned width, uint64_t seed,
+                        uint64_t* h_out);
+
+/* Equality of every pair of two encrypted symbol strings ([m][c][N+1] and
+ * [n][c][N+1], device): d_eq9 ([m][n][N+1]) receives Enc(9 [a_i = b_j]). */
+size_t lvs_equality_wide_workspace_bytes(size_t m, size_t n, unsigned width);
+int lvs_equality_wide(lvs_context* ctx, const uint64_t* d_a, size_t m, const uint64_t* d_b, size_t n, unsigned width,
+                      uint64_t* d_eq9, void* d_work, size_t work_bytes);
+
+/* Edit distance of two encrypted symbol strings: the wide equality of every
+ * pair, then the single-bootstrap main loop of Algorithm 1 over the eq9
+ * matrix (with the context's refresh interval); d_h_last as for
+ * lvs_edit_distance. */
+size_t lvs_edit_distance_wide_workspace_bytes(size_t m, size_t n, unsigned width);
+int lvs_edit_distance_wide(lvs_context* ctx, const uint64_t* d_a, size_t m, const uint64_t* d_b, size_t n,
+                           unsigned width, uint64_t* d_h_last, void* d_work, size_t work_bytes);
+
+/* Section 5's preprocessing for wide symbols: d_table[s][i] =
+ * Enc(9 [a_i = alphabet[s]]) ([alen][m][N+1]), c + merges bootstraps per
+ * entry; the main pass is lvs_edit_distance_clear_wide. */
+size_t lvs_preprocess_wide_workspace_bytes(size_t m, size_t alen, unsigned width);
+int lvs_preprocess_wide(lvs_context* ctx, const uint64_t* d_a, size_t m, unsigned width, const uint64_t* alphabet,
+                        size_t alen, uint64_t* d_table, void* d_work, size_t work_bytes);
+
+/* Main pass with a cleartext symbol string b (host, n symbols, each in the
+ * alphabet the table was built for, else LVS_E_ALPHABET): as
+ * lvs_edit_distance_clear.  Workspace: lvs_edit_distance_clear_workspace_bytes. */
+int lvs_edit_distance_clear_wide(lvs_context* ctx, const uint64_t* d_table, size_t m, const uint64_t* alphabet,
+                                 size_t alen, const uint64_t* b, size_t n, uint64_t* d_h_last, void* d_work,
                                  size_t work_bytes);
 
 /* ------------------------------------------------------------ batch plans */

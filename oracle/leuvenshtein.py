@@ -137,6 +137,21 @@ def equality_wide(keys: T.Keys, A: np.ndarray, B: np.ndarray, width: int, nthrea
     return merge_wide(keys, sub, nthreads).reshape(m, n, W)
 
 
+def preprocess_wide(keys: T.Keys, A: np.ndarray, alphabet, width: int, nthreads=None) -> np.ndarray:
+    """Section 5's table for wide symbols: T[s][i] = Enc(9 [a_i = alphabet[s]])
+    by the hybrid equality against the cleartext symbol (a noise-free
+    chunk).  Shape (|alphabet|, m, N+1)."""
+    m, W = A.shape[0], keys.N + 1
+    c = P.wide_chunk_count(width)
+    S = len(alphabet)
+    clear = np.stack([np.stack([T.trivial(x, keys.N) for x in P.wide_chunks(int(v), width)]) for v in alphabet])
+    z = (A[None, :, :, :] - clear[:, None, :, :]).astype(T.U64).reshape(S * m * c, W)
+    if c == 1:
+        return _pbs(keys, z, "eq9", nthreads).reshape(S, m, W)
+    sub = _pbs(keys, z, "eq", nthreads).reshape(S * m, c, W)
+    return merge_wide(keys, sub, nthreads).reshape(S, m, W)
+
+
 def edit_distance_wide(keys: T.Keys, A: np.ndarray, B: np.ndarray, width: int, nthreads=None,
                        refresh_every: int = 0):
     """Wide-symbol equality of every pair, then the diagonal-order main loop."""

@@ -343,6 +343,11 @@ int lvs_context_create(const lvs_server_key* sk, int device, void* hip_stream, v
     // the identity on the differences -1, 0, 1: an input of -1 (= 31) reads -f(15)
     const int32_t f_refresh[16] = {0, 1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1};
     build_test_poly(f_refresh, &luts[size_t(LVS_LUT_REFRESH) * kN]);
+    // Algorithm 2's merging test, with the group sum offset so its maximum reads 15
+    const int32_t f_max[16] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1};
+    const int32_t f_max9[16] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 9};
+    build_test_poly(f_max, &luts[size_t(LVS_LUT_MAX) * kN]);
+    build_test_poly(f_max9, &luts[size_t(LVS_LUT_MAX9) * kN]);
     if (e == hipSuccess) e = hipMemcpy(C->luts, luts.data(), luts.size() * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -644,25 +649,29 @@ size_t lvs_edit_distance_clear_workspace_bytes(size_t m, size_t n) {
     return plan_ws(qs);
 }
 
-int lvs_edit_distance_clear(lvs_context* ctx, const uint64_t* d_table, size_t m, const uint8_t* alphabet, size_t alen,
-                            const uint8_t* b, size_t n, uint64_t* d_h_last, void* d_work, size_t work_bytes) {
+extern "C++" {
+namespace {
+// The cleartext main pass over table rows cols[j] of the b_j (both symbol kinds).
+template <typename Sym>
+int clear_pass(lvs_context* ctx, const uint64_t* d_table, size_t m, const Sym* alphabet, size_t alen, const Sym* b,
+               size_t n, uint64_t* d_h_last, void* d_work, size_t work_bytes, const char* fn) {
     Context* C = as_ctx(ctx);
-    LVS_REQUIRE(C, LVS_E_INVAL, "lvs_edit_distance_clear: bad context");
+    LVS_REQUIRE(C, LVS_E_INVAL, std::string(fn) + ": bad context");
     LVS_REQUIRE((d_table || m == 0) && (alphabet || alen == 0) && (b || n == 0) && (d_h_last || n == 0),
-                LVS_E_INVAL, "lvs_edit_distance_clear: NULL buffer");
-    LVS_CHECK_LENGTHS(C, m, n, "lvs_edit_distance_clear");
+                LVS_E_INVAL, std::string(fn) + ": NULL buffer");
+    LVS_CHECK_LENGTHS(C, m, n, fn);
     std::vector<QuerySpec> qs(1);
     qs[0].cols.resize(n);
     for (size_t j = 0; j < n; ++j) {
-        const uint8_t* hit = std::find(alphabet, alphabet + alen, b[j]);
-        LVS_REQUIRE(hit != alphabet + alen, LVS_E_ALPHABET, "lvs_edit_distance_clear: symbol not in the table");
+        const Sym* hit = std::find(alphabet, alphabet + alen, b[j]);
+        LVS_REQUIRE(hit != alphabet + alen, LVS_E_ALPHABET, std::string(fn) + ": symbol not in the table");
         qs[0].cols[j] = int32_t(hit - alphabet);
     }
     LVS_HIP(hipSetDevice(C->device));
     if (n == 0) return LVS_OK;
     if (m == 0) return empty_first(C, n, d_h_last);
     LVS_REQUIRE(d_work && work_bytes >= lvs_edit_distance_clear_workspace_bytes(m, n), LVS_E_NOMEM_DEVICE,
-                "lvs_edit_distance_clear: workspace too small");
+                std::string(fn) + ": workspace too small");
     qs[0].m = m;
     qs[0].n = n;
     qs[0].table = d_table;
@@ -673,6 +682,20 @@ int lvs_edit_distance_clear(lvs_context* ctx, const uint64_t* d_table, size_t m,
     Plan P;
     build_edit_distance_plan(qs, P);
     return execute(C, P, ws);
+}
+}  // namespace
+}  // extern "C++"
+
+int lvs_edit_distance_clear(lvs_context* ctx, const uint64_t* d_table, size_t m, const uint8_t* alphabet, size_t alen,
+                            const uint8_t* b, size_t n, uint64_t* d_h_last, void* d_work, size_t work_bytes) {
+    return clear_pass(ctx, d_table, m, alphabet, alen, b, n, d_h_last, d_work, work_bytes, "lvs_edit_distance_clear");
+}
+
+int lvs_edit_distance_clear_wide(lvs_context* ctx, const uint64_t* d_table, size_t m, const uint64_t* alphabet,
+                                 size_t alen, const uint64_t* b, size_t n, uint64_t* d_h_last, void* d_work,
+                                 size_t work_bytes) {
+    return clear_pass(ctx, d_table, m, alphabet, alen, b, n, d_h_last, d_work, work_bytes,
+                      "lvs_edit_distance_clear_wide");
 }
 
 // ------------------------------------------------------------ batch plans

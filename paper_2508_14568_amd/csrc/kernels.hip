@@ -766,6 +766,24 @@ __global__ void __launch_bounds__(256) copy_probe_kernel(const uint4* __restrict
     for (size_t i = blockIdx.x * size_t(256) + threadIdx.x; i < n; i += size_t(gridDim.x) * 256) dst[i] = src[i];
 }
 
+// out[item][g] = sum of in[item][k] for k in [g * group, min(cnt, (g + 1) * group)),
+// ciphertext by ciphertext (the merging sums of the wide-symbol equality).
+__global__ void __launch_bounds__(256) group_sum_kernel(const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
+                                                        size_t items, int cnt, int groups, int group) {
+    const size_t total = items * size_t(groups) * kCtWords;
+    for (size_t e = blockIdx.x * size_t(256) + threadIdx.x; e < total; e += size_t(gridDim.x) * 256) {
+        const size_t w = e % kCtWords;
+        const size_t ig = e / kCtWords;
+        const size_t item = ig / size_t(groups);
+        const int g = int(ig % size_t(groups));
+        const int k0 = g * group, k1 = min(cnt, k0 + group);
+        const uint64_t* src = in + (item * size_t(cnt) + size_t(k0)) * kCtWords + w;
+        uint64_t acc = 0;
+        for (int k = k0; k < k1; ++k, src += kCtWords) acc += *src;
+        out[e] = acc;
+    }
+}
+
 }  // namespace dev
 
 // ------------------------------------------------------------- launchers
@@ -874,6 +892,15 @@ hipError_t launch_bsk_convert(const uint64_t* bsk_u64, uint32_t* out, const DevT
     hipLaunchKernelGGL(dev::bsk_convert_kernel, grid, dim3(64), 0, st, bsk_u64, out,
                        dev::Tw{reinterpret_cast<const uint2*>(t.fwd), reinterpret_cast<const uint2*>(t.inv)}, make_crt(),
                        t.scale, t.scale_s);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_sum(const uint64_t* in, uint64_t* out, size_t items, int cnt, int groups, int group,
+                            int cus, hipStream_t st) {
+    const size_t total = items * size_t(groups) * kCtWords;
+    if (!total) return hipSuccess;
+    const int blocks = int(std::min<size_t>((total + 255) / 256, size_t(std::max(1, cus)) * 16));
+    hipLaunchKernelGGL(dev::group_sum_kernel, dim3(blocks), dim3(256), 0, st, in, out, items, cnt, groups, group);
     return hipGetLastError();
 }
 

@@ -51,6 +51,10 @@ hipError_t launch_blind_rotate_jobs(const Job* jobs, int B, const uint64_t* part
 hipError_t prepare_kernels();
 hipError_t launch_bsk_convert(const uint64_t* bsk_u64, uint32_t* out, const DevTables& t, hipStream_t st);
 hipError_t launch_trivial(uint64_t* out, int count, uint32_t mu, hipStream_t st);
+// out[item][g] = sum_{k in group g} in[item][k] for items x cnt ciphertexts in
+// groups of `group` (the last may be shorter); groups = ceil(cnt / group).
+hipError_t launch_group_sum(const uint64_t* in, uint64_t* out, size_t items, int cnt, int groups, int group,
+                            int cus, hipStream_t st);
 // Microbenchmarks: the forward butterfly's instruction mix from registers
 // (blocks of 256 threads, iters rounds) and a 16-byte vector copy.
 hipError_t launch_modmul_probe(uint32_t* out, int blocks, int iters, hipStream_t st);

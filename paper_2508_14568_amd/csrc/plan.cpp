@@ -401,11 +401,87 @@ void build_pbs_plan(const uint64_t* in, const uint8_t* lut_ids, int lut, size_t 
     }
 }
 
+size_t wide_buffer_bytes(size_t pairs, size_t c) {
+    if (c <= 1) return 0;
+    return align256(sizeof(uint64_t) * pairs * c * W) + align256(sizeof(uint64_t) * pairs * ((c + 14) / 15) * W);
+}
+
+size_t wide_jobs(size_t pairs, size_t c) {
+    size_t jobs = pairs * c;
+    for (size_t cnt = c; cnt > 1;) {
+        cnt = (cnt + 14) / 15;
+        jobs += pairs * cnt;
+    }
+    return jobs;
+}
+
+size_t wide_max_step(size_t pairs, size_t c) { return pairs * c; }
+
+void build_wide_equality(Plan& P, size_t pairs, size_t c, WideChunkInput (*chunk)(const void*, size_t, size_t),
+                         const void* ctx, uint64_t* out, uint8_t*& ws) {
+    constexpr size_t kGroup = 15;   // Algorithm 2: groups of at most t - 1 for a 16-value lookup
+    Builder b(P);
+    uint64_t* buf[2] = {nullptr, nullptr};
+    if (c > 1) {
+        buf[0] = reinterpret_cast<uint64_t*>(ws);
+        ws += align256(sizeof(uint64_t) * pairs * c * W);
+        buf[1] = reinterpret_cast<uint64_t*>(ws);
+        ws += align256(sizeof(uint64_t) * pairs * ((c + kGroup - 1) / kGroup) * W);
+    }
+    // sub-equality of every chunk pair: PBS(x_k - y_k; LUT_eq), or LUT_eq9
+    // when one chunk is the whole symbol
+    b.step();
+    for (size_t p = 0; p < pairs; ++p)
+        for (size_t k = 0; k < c; ++k) {
+            const WideChunkInput in = chunk(ctx, p, k);
+            Job J = blank_job();
+            J.src[0] = in.a;
+            J.coef[0] = 1;
+            if (in.b) {
+                J.src[1] = in.b;
+                J.coef[1] = -1;
+            } else {
+                J.delta = uint64_t(0) - uint64_t(in.clear) * kOne;
+            }
+            J.lut = c == 1 ? LVS_LUT_EQ9 : LVS_LUT_EQ;
+            J.dst[2] = c == 1 ? out + p * W : buf[0] + (p * c + k) * W;
+            b.add(J);
+        }
+    // merging: groups of at most 15 summed, a group of g offset by 15 - g, so
+    // that the sum reads 15 exactly when all g are 1; bootstrapped in place
+    int cur = 0;
+    for (size_t cnt = c; cnt > 1;) {
+        const size_t G = (cnt + kGroup - 1) / kGroup;
+        uint64_t* sums = buf[cur ^ 1];
+        P.sums.push_back({buf[cur], sums, pairs, int(cnt), int(G), int(kGroup)});
+        P.steps.push_back({P.jobs.size(), 0, int(P.sums.size() - 1)});
+        b.step();
+        for (size_t p = 0; p < pairs; ++p)
+            for (size_t g = 0; g < G; ++g) {
+                const size_t size = std::min(cnt, (g + 1) * kGroup) - g * kGroup;
+                Job J = blank_job();
+                J.src[0] = sums + (p * G + g) * W;
+                J.coef[0] = 1;
+                J.delta = uint64_t(kGroup - size) * kOne;
+                J.lut = G == 1 ? LVS_LUT_MAX9 : LVS_LUT_MAX;
+                J.dst[2] = G == 1 ? out + p * W : sums + (p * G + g) * W;
+                b.add(J);
+            }
+        cnt = G;
+        cur ^= 1;
+    }
+}
+
 hipError_t upload_plan(Plan& P, uint8_t*& ws, hipStream_t st) {
-    // split oversized steps (their jobs are independent)
+    // split oversized steps (their jobs are independent); linear steps stay
     std::vector<PlanStep> steps;
-    for (const auto& s : P.steps)
+    for (const auto& s : P.steps) {
+        if (s.sum >= 0) {
+            steps.push_back(s);
+            continue;
+        }
         for (size_t o = 0; o < s.count; o += kMaxStep) steps.push_back({s.off + o, std::min(kMaxStep, s.count - o)});
+    }
     P.steps.swap(steps);
     P.max_step = 0;
     for (const auto& s : P.steps) P.max_step = std::max(P.max_step, s.count);
@@ -426,6 +502,12 @@ hipError_t launch_steps(Context* C, const Plan& P, hipStream_t st, bool timed) {
         if (e != hipSuccess) return e;
     }
     for (const auto& s : P.steps) {
+        if (s.sum >= 0) {
+            const SumOp& o = P.sums[size_t(s.sum)];
+            hipError_t e = launch_group_sum(o.in, o.out, o.items, o.cnt, o.groups, o.group, C->cus, st);
+            if (e != hipSuccess) return e;
+            continue;
+        }
         if (!s.count) continue;
         const int B = int(s.count);
         {

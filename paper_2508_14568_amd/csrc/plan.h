@@ -59,14 +59,27 @@ inline bool refresh_due(const QuerySpec& q, size_t s) {
     return q.refresh > 0 && s >= 2 && s % q.refresh == 0 && s < q.m + q.n;
 }
 
+// A step is a batch of bootstraps (jobs off .. off + count), or, with
+// sum >= 0, the linear group sums Plan::sums[sum].
 struct PlanStep {
     size_t off, count;
+    int sum = -1;
+};
+
+// Linear step: out[item][g] = sum of in[item][k] over the g-th group of
+// `group` consecutive k < cnt (launch_group_sum).
+struct SumOp {
+    const uint64_t* in;
+    uint64_t* out;
+    size_t items;
+    int cnt, groups, group;
 };
 
 struct Plan {
     std::vector<std::pair<uint64_t*, size_t>> fills;   // rows set to Enc(1) at the start of every run
     std::vector<Job> jobs;
     std::vector<PlanStep> steps;
+    std::vector<SumOp> sums;
     size_t max_step = 0;
     Job* d_jobs = nullptr;
     uint64_t* d_part = nullptr;
@@ -99,6 +112,21 @@ void build_preprocess_plan(const uint64_t* A, size_t m, int encoding, const std:
 
 // Independent bootstraps d_out[b] = PBS(d_in[b]).
 void build_pbs_plan(const uint64_t* in, const uint8_t* lut_ids, int lut, size_t B, uint64_t* out, Plan& P);
+
+// Section 4.2's hybrid equality of `pairs` symbol pairs of c 4-bit chunks:
+// chunk_input(p, k) returns a job whose inputs form x_k - y_k of pair p; the
+// result Enc(9 [x = y]) of pair p goes to out + p * W.  ws is advanced past
+// the level buffers (wide_buffer_bytes).
+struct WideChunkInput {
+    const uint64_t* a;      // encrypted chunk of x
+    const uint64_t* b;      // encrypted chunk of y, or null: y_k is `clear`
+    uint32_t clear;
+};
+size_t wide_buffer_bytes(size_t pairs, size_t c);
+size_t wide_jobs(size_t pairs, size_t c);
+size_t wide_max_step(size_t pairs, size_t c);
+void build_wide_equality(Plan& P, size_t pairs, size_t c, WideChunkInput (*chunk)(const void*, size_t, size_t),
+                         const void* ctx, uint64_t* out, uint8_t*& ws);
 
 // Splits oversized steps, uploads the jobs into ws (advancing it) and
 // reserves the key-switch partial sums.

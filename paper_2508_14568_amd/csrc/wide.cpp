@@ -1,0 +1,204 @@
+// Wide symbols (Section 4.2 of arXiv 2508.14568): the hybrid of the 4-bit
+// subtraction equality with Algorithm 2's merging, for symbols of up to 64
+// bits, and the edit distances built on it.
+//
+// A symbol of w bits is c = ceil(w / 4) ciphertexts of 4-bit chunks.  The
+// equality of a pair is one plan: a step with the c sub-equality bootstraps
+// of every pair, then per merging level a linear step (group sums) and a
+// step with one bootstrap per group.  The edit distance appends the main
+// loop over the resulting eq9 matrix to the same plan.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "context.h"
+#include "launch.h"
+#include "lvs_internal.h"
+#include "plan.h"
+
+using namespace lvs;
+
+namespace {
+
+constexpr size_t W = kCtWords;
+
+#define WIDE_FAIL(code, msg) \
+    do {                     \
+        set_error(msg);      \
+        return (code);       \
+    } while (0)
+
+#define WIDE_HIP(expr)                                                                                  \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess) WIDE_FAIL(LVS_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+Context* ctx_of(lvs_context* c) {
+    auto* h = reinterpret_cast<Context*>(c);
+    return (h && h->kind == kContext) ? h : nullptr;
+}
+
+size_t chunks_of(unsigned width) { return (width >= 1 && width <= 64) ? (width + 3) / 4 : 0; }
+
+uint32_t chunk_value(uint64_t v, size_t k) { return uint32_t((v >> (4 * k)) & 15u); }
+
+// Both strings encrypted: pair p = i * n + j.
+struct PairSrc {
+    const uint64_t* A;
+    const uint64_t* B;
+    size_t n, c;
+};
+WideChunkInput pair_chunk(const void* ctx, size_t p, size_t k) {
+    const auto* s = static_cast<const PairSrc*>(ctx);
+    const size_t i = p / s->n, j = p % s->n;
+    return {s->A + (i * s->c + k) * W, s->B + (j * s->c + k) * W, 0};
+}
+
+// Preprocessing: entry p = s * m + i against the cleartext alphabet[s].
+struct TableSrc {
+    const uint64_t* A;
+    const uint64_t* alphabet;
+    size_t m, c;
+};
+WideChunkInput table_chunk(const void* ctx, size_t p, size_t k) {
+    const auto* s = static_cast<const TableSrc*>(ctx);
+    const size_t sym = p / s->m, i = p % s->m;
+    return {s->A + (i * s->c + k) * W, nullptr, chunk_value(s->alphabet[sym], k)};
+}
+
+int run(Context* C, Plan& P, uint8_t* ws) {
+    WIDE_HIP(upload_plan(P, ws, C->stream));
+    WIDE_HIP(run_plan(C, P));
+    return LVS_OK;
+}
+
+// The main loop over an eq9 matrix (the same query form as
+// lvs_edit_distance_eq9), with the refresh interval given.
+QuerySpec eq9_query(const uint64_t* eq9, size_t m, size_t n, uint64_t* h_last, size_t refresh) {
+    QuerySpec q;
+    q.m = m;
+    q.n = n;
+    q.eq9_in = eq9 ? eq9 : reinterpret_cast<const uint64_t*>(16);
+    q.h_last = h_last;
+    q.refresh = refresh;
+    return q;
+}
+
+size_t dp_max_step(size_t m, size_t n) { return 2 * std::min(m, n); }   // a refresh step: two per cell
+
+}  // namespace
+
+extern "C" {
+
+size_t lvs_wide_chunks(unsigned width) { return chunks_of(width); }
+
+size_t lvs_wide_pbs_per_pair(unsigned width) {
+    const size_t c = chunks_of(width);
+    return c ? wide_jobs(1, c) : 0;
+}
+
+int lvs_encrypt_symbols(const lvs_client_key* ck, const uint64_t* syms, size_t len, unsigned width, uint64_t seed,
+                        uint64_t* h_out) {
+    auto* c = reinterpret_cast<const ClientKey*>(ck);
+    if (!c || c->kind != kClientKey || (!syms && len) || (!h_out && len))
+        WIDE_FAIL(LVS_E_INVAL, "lvs_encrypt_symbols: bad argument");
+    const size_t nc = chunks_of(width);
+    if (!nc) WIDE_FAIL(LVS_E_INVAL, "lvs_encrypt_symbols: width must be 1..64");
+    for (size_t i = 0; i < len; ++i)
+        if (width < 64 && (syms[i] >> width))
+            WIDE_FAIL(LVS_E_ALPHABET, "lvs_encrypt_symbols: symbol wider than width bits");
+    for (size_t i = 0; i < len; ++i)
+        for (size_t k = 0; k < nc; ++k) encrypt(*c, chunk_value(syms[i], k), seed, i * nc + k, h_out + (i * nc + k) * W);
+    return LVS_OK;
+}
+
+size_t lvs_equality_wide_workspace_bytes(size_t m, size_t n, unsigned width) {
+    const size_t c = chunks_of(width);
+    return wide_buffer_bytes(m * n, c) + plan_bytes(wide_jobs(m * n, c), wide_max_step(m * n, c));
+}
+
+int lvs_equality_wide(lvs_context* ctx, const uint64_t* d_a, size_t m, const uint64_t* d_b, size_t n, unsigned width,
+                      uint64_t* d_eq9, void* d_work, size_t work_bytes) {
+    Context* C = ctx_of(ctx);
+    const size_t c = chunks_of(width);
+    if (!C || !c) WIDE_FAIL(LVS_E_INVAL, "lvs_equality_wide: bad context or width");
+    if (m == 0 || n == 0) return LVS_OK;
+    if (!d_a || !d_b || !d_eq9 || !d_work) WIDE_FAIL(LVS_E_INVAL, "lvs_equality_wide: NULL buffer");
+    if (std::max(m, n) > size_t(LVS_MAX_LEN)) WIDE_FAIL(LVS_E_INVAL, "lvs_equality_wide: string longer than LVS_MAX_LEN");
+    if (work_bytes < lvs_equality_wide_workspace_bytes(m, n, width))
+        WIDE_FAIL(LVS_E_NOMEM_DEVICE, "lvs_equality_wide: workspace too small");
+    WIDE_HIP(hipSetDevice(C->device));
+    uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
+    const PairSrc src{d_a, d_b, n, c};
+    Plan P;
+    build_wide_equality(P, m * n, c, pair_chunk, &src, d_eq9, ws);
+    return run(C, P, ws);
+}
+
+size_t lvs_edit_distance_wide_workspace_bytes(size_t m, size_t n, unsigned width) {
+    const size_t c = chunks_of(width);
+    const QuerySpec q = eq9_query(nullptr, m, n, nullptr, LVS_REFRESH_MIN);
+    return align256(sizeof(uint64_t) * std::max<size_t>(m * n, 1) * W) + wide_buffer_bytes(m * n, c) +
+           query_buffer_bytes(q) +
+           plan_bytes(wide_jobs(m * n, c) + query_jobs(q), std::max(wide_max_step(m * n, c), dp_max_step(m, n)));
+}
+
+int lvs_edit_distance_wide(lvs_context* ctx, const uint64_t* d_a, size_t m, const uint64_t* d_b, size_t n,
+                           unsigned width, uint64_t* d_h_last, void* d_work, size_t work_bytes) {
+    Context* C = ctx_of(ctx);
+    const size_t c = chunks_of(width);
+    if (!C || !c) WIDE_FAIL(LVS_E_INVAL, "lvs_edit_distance_wide: bad context or width");
+    if ((!d_a && m) || (!d_b && n) || (!d_h_last && n)) WIDE_FAIL(LVS_E_INVAL, "lvs_edit_distance_wide: NULL buffer");
+    if (std::max(m, n) > size_t(LVS_MAX_LEN))
+        WIDE_FAIL(LVS_E_INVAL, "lvs_edit_distance_wide: string longer than LVS_MAX_LEN");
+    if (C->refresh_every == 0 && std::min(m, n) > size_t(LVS_MAX_DEPTH_NO_REFRESH))
+        WIDE_FAIL(LVS_E_NOISE_BUDGET, "lvs_edit_distance_wide: min(m, n) exceeds the noise budget with refresh off");
+    WIDE_HIP(hipSetDevice(C->device));
+    if (n == 0) return LVS_OK;
+    if (m == 0) {
+        WIDE_HIP(launch_trivial(d_h_last, int(n), 1, C->stream));
+        return LVS_OK;
+    }
+    if (!d_work || work_bytes < lvs_edit_distance_wide_workspace_bytes(m, n, width))
+        WIDE_FAIL(LVS_E_NOMEM_DEVICE, "lvs_edit_distance_wide: workspace too small");
+    uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
+    uint64_t* eq9 = reinterpret_cast<uint64_t*>(ws);
+    ws += align256(sizeof(uint64_t) * m * n * W);
+    const PairSrc src{d_a, d_b, n, c};
+    Plan P;
+    build_wide_equality(P, m * n, c, pair_chunk, &src, eq9, ws);
+    std::vector<QuerySpec> qs{eq9_query(eq9, m, n, d_h_last, C->refresh_every)};
+    assign_buffers(qs, ws);
+    build_edit_distance_plan(qs, P);
+    return run(C, P, ws);
+}
+
+size_t lvs_preprocess_wide_workspace_bytes(size_t m, size_t alen, unsigned width) {
+    return lvs_equality_wide_workspace_bytes(alen, m, width);
+}
+
+int lvs_preprocess_wide(lvs_context* ctx, const uint64_t* d_a, size_t m, unsigned width, const uint64_t* alphabet,
+                        size_t alen, uint64_t* d_table, void* d_work, size_t work_bytes) {
+    Context* C = ctx_of(ctx);
+    const size_t c = chunks_of(width);
+    if (!C || !c) WIDE_FAIL(LVS_E_INVAL, "lvs_preprocess_wide: bad context or width");
+    if (m == 0 || alen == 0) return LVS_OK;
+    if (!d_a || !alphabet || !d_table || !d_work) WIDE_FAIL(LVS_E_INVAL, "lvs_preprocess_wide: NULL buffer");
+    if (m > size_t(LVS_MAX_LEN)) WIDE_FAIL(LVS_E_INVAL, "lvs_preprocess_wide: string longer than LVS_MAX_LEN");
+    for (size_t s = 0; s < alen; ++s)
+        if (width < 64 && (alphabet[s] >> width))
+            WIDE_FAIL(LVS_E_ALPHABET, "lvs_preprocess_wide: alphabet symbol wider than width bits");
+    if (work_bytes < lvs_preprocess_wide_workspace_bytes(m, alen, width))
+        WIDE_FAIL(LVS_E_NOMEM_DEVICE, "lvs_preprocess_wide: workspace too small");
+    WIDE_HIP(hipSetDevice(C->device));
+    uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
+    const TableSrc src{d_a, alphabet, m, c};
+    Plan P;
+    build_wide_equality(P, alen * m, c, table_chunk, &src, d_table, ws);
+    return run(C, P, ws);
+}
+
+}  // extern "C"

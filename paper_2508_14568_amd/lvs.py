@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "liblvs.so")
 
 LVS_ENC_ASCII7 = 0
 LVS_ENC_DNA2 = 1
-LVS_LUT_EQ, LVS_LUT_EQ9, LVS_LUT_MIN, LVS_LUT_REFRESH, LVS_LUT_USER, LVS_LUT_SLOTS = 0, 1, 2, 3, 4, 8
+LVS_LUT_EQ, LVS_LUT_EQ9, LVS_LUT_MIN, LVS_LUT_REFRESH, LVS_LUT_MAX, LVS_LUT_MAX9 = 0, 1, 2, 3, 4, 5
+LVS_LUT_USER, LVS_LUT_SLOTS = 6, 8
 LVS_REFRESH_DEFAULT, LVS_REFRESH_MIN, LVS_REFRESH_MAX, LVS_MAX_DEPTH_NO_REFRESH = 256, 4, 512, 256
 LVS_MAX_LEN = 1 << 20
 CT_WORDS = 2049
@@ -80,6 +81,16 @@ _SIGS = {
     "lvs_plan_verify": (I32, [VP, SZ, I32, SZ, I32, SZ, ctypes.POINTER(SZ), ctypes.POINTER(SZ),
                               ctypes.POINTER(SZ), ctypes.POINTER(SZ)]),
     "lvs_context_set_refresh": (I32, [VP, SZ]),
+    "lvs_wide_chunks": (SZ, [ctypes.c_uint]),
+    "lvs_wide_pbs_per_pair": (SZ, [ctypes.c_uint]),
+    "lvs_encrypt_symbols": (I32, [VP, VP, SZ, ctypes.c_uint, U64, VP]),
+    "lvs_equality_wide_workspace_bytes": (SZ, [SZ, SZ, ctypes.c_uint]),
+    "lvs_equality_wide": (I32, [VP, VP, SZ, VP, SZ, ctypes.c_uint, VP, VP, SZ]),
+    "lvs_edit_distance_wide_workspace_bytes": (SZ, [SZ, SZ, ctypes.c_uint]),
+    "lvs_edit_distance_wide": (I32, [VP, VP, SZ, VP, SZ, ctypes.c_uint, VP, VP, SZ]),
+    "lvs_preprocess_wide_workspace_bytes": (SZ, [SZ, SZ, ctypes.c_uint]),
+    "lvs_preprocess_wide": (I32, [VP, VP, SZ, ctypes.c_uint, VP, SZ, VP, VP, SZ]),
+    "lvs_edit_distance_clear_wide": (I32, [VP, VP, SZ, VP, SZ, VP, SZ, VP, VP, SZ]),
     "lvs_context_get_refresh": (I32, [VP, ctypes.POINTER(SZ)]),
     "lvs_plan_run": (I32, [VP]),
     "lvs_plan_info": (I32, [VP, ctypes.POINTER(SZ), ctypes.POINTER(SZ), ctypes.POINTER(SZ)]),
@@ -367,6 +378,82 @@ def lvs_edit_distance_clear(ctx: Context, d_table, m: int, alphabet: bytes, b: b
     bb = (ctypes.c_uint8 * max(1, len(b))).from_buffer_copy(bytes(b) or b"\0")
     _check(lib().lvs_edit_distance_clear(ctx, _dptr(d_table), m, ab, len(alphabet), bb, len(b), _dptr(d_h_last),
                                          _dptr(d_work), d_work.numel() * d_work.element_size()))
+    return d_work
+
+
+# ----------------------------------------------------------- wide symbols
+
+def lvs_wide_chunks(width: int) -> int:
+    return lib().lvs_wide_chunks(width)
+
+
+def lvs_wide_pbs_per_pair(width: int) -> int:
+    return lib().lvs_wide_pbs_per_pair(width)
+
+
+def _u64_array(values):
+    arr = np.ascontiguousarray(np.asarray([int(v) for v in values] or [0], dtype=np.uint64))
+    return arr
+
+
+def lvs_encrypt_symbols(ck, syms, width: int, seed: int) -> np.ndarray:
+    """(len, c, N+1) ciphertexts of the 4-bit chunks of each symbol."""
+    c = lvs_wide_chunks(width)
+    if c == 0:
+        raise LvsError(-1, "width must be 1..64")
+    arr = _u64_array(syms)
+    out = np.zeros((len(syms), c, CT_WORDS), dtype=np.uint64)
+    _check(lib().lvs_encrypt_symbols(ck, _np_ptr(arr), len(syms), width, seed, _np_ptr(out)))
+    return out
+
+
+def lvs_equality_wide_workspace_bytes(m: int, n: int, width: int) -> int:
+    return lib().lvs_equality_wide_workspace_bytes(m, n, width)
+
+
+def lvs_equality_wide(ctx: Context, d_a, m: int, d_b, n: int, width: int, d_eq9, d_work=None):
+    need = lvs_equality_wide_workspace_bytes(m, n, width)
+    if d_work is None:
+        d_work = device_buffer(need, ctx.device)
+    _check(lib().lvs_equality_wide(ctx, _dptr(d_a), m, _dptr(d_b), n, width, _dptr(d_eq9), _dptr(d_work),
+                                   d_work.numel() * d_work.element_size()))
+    return d_work
+
+
+def lvs_edit_distance_wide_workspace_bytes(m: int, n: int, width: int) -> int:
+    return lib().lvs_edit_distance_wide_workspace_bytes(m, n, width)
+
+
+def lvs_edit_distance_wide(ctx: Context, d_a, m: int, d_b, n: int, width: int, d_h_last, d_work=None):
+    need = lvs_edit_distance_wide_workspace_bytes(m, n, width)
+    if d_work is None:
+        d_work = device_buffer(need, ctx.device)
+    _check(lib().lvs_edit_distance_wide(ctx, _dptr(d_a), m, _dptr(d_b), n, width, _dptr(d_h_last), _dptr(d_work),
+                                        d_work.numel() * d_work.element_size()))
+    return d_work
+
+
+def lvs_preprocess_wide_workspace_bytes(m: int, alen: int, width: int) -> int:
+    return lib().lvs_preprocess_wide_workspace_bytes(m, alen, width)
+
+
+def lvs_preprocess_wide(ctx: Context, d_a, m: int, width: int, alphabet, d_table, d_work=None):
+    need = lvs_preprocess_wide_workspace_bytes(m, len(alphabet), width)
+    if d_work is None:
+        d_work = device_buffer(need, ctx.device)
+    ab = _u64_array(alphabet)
+    _check(lib().lvs_preprocess_wide(ctx, _dptr(d_a), m, width, _np_ptr(ab), len(alphabet), _dptr(d_table),
+                                     _dptr(d_work), d_work.numel() * d_work.element_size()))
+    return d_work
+
+
+def lvs_edit_distance_clear_wide(ctx: Context, d_table, m: int, alphabet, b, d_h_last, d_work=None):
+    need = lvs_edit_distance_clear_workspace_bytes(m, len(b))
+    if d_work is None:
+        d_work = device_buffer(need, ctx.device)
+    ab, bb = _u64_array(alphabet), _u64_array(b)
+    _check(lib().lvs_edit_distance_clear_wide(ctx, _dptr(d_table), m, _np_ptr(ab), len(alphabet), _np_ptr(bb), len(b),
+                                              _dptr(d_h_last), _dptr(d_work), d_work.numel() * d_work.element_size()))
     return d_work
 
 

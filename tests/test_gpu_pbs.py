@@ -43,19 +43,19 @@ def test_table1_exhaustive_bit_exact(gpu, okeys):
     assert dec == golden("table1_lut_x_minus_4.json")["outputs"]
 
 
-@pytest.mark.parametrize("name", ["eq", "eq9", "min", "refresh", "table2"])
+@pytest.mark.parametrize("name", ["eq", "eq9", "min", "refresh", "max", "max9", "table2"])
 def test_tables_exhaustive(gpu, okeys, name):
     """All 32 inputs through LUT_eq, LUT_eq9, the negated-key LUT_min, the
-    refresh table and the printed Table LUTmin; decryptions exact, 8 sampled
-    outputs bit-exact."""
+    refresh table, the merging tables LUT_max / LUT_max9 and the printed
+    Table LUTmin; decryptions exact, 8 sampled outputs bit-exact."""
     say("tables exhaustive", name)
     g = gpu
     lut = {"eq": P.LUT_EQ, "eq9": P.LUT_EQ9, "min": P.lut_min_negated(), "refresh": P.LUT_REFRESH,
-           "table2": P.lut_min_plain()}[name]
+           "max": P.LUT_MAX, "max9": P.LUT_MAX9, "table2": P.lut_min_plain()}[name]
     slot = {"eq": g.L.LVS_LUT_EQ, "eq9": g.L.LVS_LUT_EQ9, "min": g.L.LVS_LUT_MIN, "refresh": g.L.LVS_LUT_REFRESH,
-            "table2": 5}[name]
+            "max": g.L.LVS_LUT_MAX, "max9": g.L.LVS_LUT_MAX9, "table2": 7}[name]
     if name == "table2":
-        g.L.lvs_context_set_lut(g.ctx, 5, lut)
+        g.L.lvs_context_set_lut(g.ctx, 7, lut)
     cts = np.stack([g.L.lvs_lwe_encrypt(g.ck, x, 600 + slot, x) for x in range(32)])
     out = run_pbs(g, cts, lut_id=slot)
     assert [g.L.lvs_lwe_decrypt(g.ck, o)[0] for o in out] == [P.negacyclic_read(lut, x) for x in range(32)]

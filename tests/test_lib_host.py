@@ -77,6 +77,25 @@ def test_encryption_matches_oracle(L, both_keys):
     assert (L.lvs_encrypt_string(ck, d, L.LVS_ENC_DNA2, 4) == OL.encrypt_string(ok, d, OL.ENC_DNA2, 4)).all()
 
 
+def test_wide_symbols_host(L, both_keys):
+    """Section 4.2 wide symbols on the host: the chunk encryption equals the
+    oracle's, the per-pair bootstrap count equals the method's, and symbols
+    wider than the width are refused."""
+    ck, sk, ok = both_keys
+    from oracle import plaintext as OP
+    for width in (1, 4, 5, 21, 60, 64):
+        assert L.lvs_wide_chunks(width) == OP.wide_chunk_count(width)
+        assert L.lvs_wide_pbs_per_pair(width) == OP.pbs_hybrid(width)
+    assert L.lvs_wide_chunks(0) == 0 and L.lvs_wide_chunks(65) == 0
+    syms = [0x1F600, 0x41, 0x10FFFF, 0]
+    assert (L.lvs_encrypt_symbols(ck, syms, 21, 12) == OL.encrypt_symbols(ok, syms, 21, 12)).all()
+    big = [2 ** 64 - 1, 2 ** 63 + 12345]
+    assert (L.lvs_encrypt_symbols(ck, big, 64, 13) == OL.encrypt_symbols(ok, big, 64, 13)).all()
+    with pytest.raises(L.LvsError) as e:
+        L.lvs_encrypt_symbols(ck, [16], 4, 1)
+    assert e.value.code == -2
+
+
 def test_decrypt(L, both_keys):
     ck, sk, ok = both_keys
     for mu in range(32):

@@ -283,3 +283,19 @@ def test_wide_edit_distance(oracle_toy_keys):
     for R in (0, 4):
         h_last = L.edit_distance_wide(k, A, B, 21, refresh_every=R)
         assert L.decrypt_distance(k, len(a), h_last) == P.edit_distance(a, b)
+
+
+def test_wide_preprocessing_table(oracle_toy_keys):
+    """Section 5's table over wide symbols: one Enc(9) per column at the
+    row of the symbol; the cleartext main pass gives the Wagner-Fischer
+    distance."""
+    k = oracle_toy_keys
+    a = [0x1F600, 0x41, 0x1F600, 0x3042, 0x41]
+    b = [0x41, 0x1F600, 0x3042, 0x3042]
+    alphabet = sorted(set(b)) + [0x10FFFF]
+    A = L.encrypt_symbols(k, a, 21, 71)
+    table = L.preprocess_wide(k, A, alphabet, 21)
+    for s_, v in enumerate(alphabet):
+        assert [k.decrypt(table[s_, i]) for i in range(len(a))] == [9 if x == v else 0 for x in a]
+    h_last = L.edit_distance_clear(k, table, alphabet, b, None)
+    assert L.decrypt_distance(k, len(a), h_last) == P.edit_distance(a, b)
