@@ -269,6 +269,45 @@ def band_block(L, ck, ctx, nq, approx_ell):
     return res
 
 
+def refresh_pbs(m, n, every):
+    """Bootstraps of Section 3.1's refresh steps on an m x n matrix: two per
+    cell of every anti-diagonal s = every, 2 every, ... below m + n."""
+    if every <= 0:
+        return 0
+    return sum(2 * (min(m, s - 1) - max(1, s - n) + 1) for s in range(every, m + n, every))
+
+
+def wide_block(L, ck, ctx):
+    """Section 4.2's wide-symbol path: a 32 x 32 pair of 21-bit symbols
+    (hybrid equality, one bootstrap per 4-bit chunk plus the merges, then the
+    main loop), one edit distance timed after a warm-up run."""
+    import torch
+    import workloads as W
+    width = 21
+    a, b = W.wide_symbols(width=width)
+    m, n = len(a), len(b)
+    dev = ctx.device
+    dA = L.to_device(L.lvs_encrypt_symbols(ck, a, width, 60001), dev)
+    dB = L.to_device(L.lvs_encrypt_symbols(ck, b, width, 60002), dev)
+    d_h = torch.zeros(n * L.CT_WORDS, dtype=torch.int64, device=dev)
+    work = L.device_buffer(L.lvs_edit_distance_wide_workspace_bytes(m, n, width), dev)
+    note("wide: 32 x 32, 21-bit symbols")
+    L.lvs_edit_distance_wide(ctx, dA, m, dB, n, width, d_h, work)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L.lvs_edit_distance_wide(ctx, dA, m, dB, n, width, d_h, work)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    d = L.lvs_decrypt_distance(ck, L.to_host(d_h).reshape(n, L.CT_WORDS), m)
+    if d != levenshtein(a, b):
+        raise SystemExit("wide: wrong distance")
+    per_pair = L.lvs_wide_pbs_per_pair(width)
+    pbs = m * n * (per_pair + 1) + refresh_pbs(m, n, L.lvs_context_get_refresh(ctx))
+    return {"workload": f"wide_symbols {m}x{n}, {width}-bit symbols over 64 code points, 20% copied, seed 7",
+            "equality_pbs_per_pair": per_pair, "pbs": pbs, "seconds": round(dt, 3), "pbs_per_s": round(pbs / dt, 1),
+            "cells_per_s": round(m * n / dt, 1), "distance": d}
+
+
 def full_configs(L, ck, ctx, serving_sat, serving_poisson):
     """Every workload at its full size (a run of several minutes; not part of
     the default line).  Returns a dict keyed by workload."""
@@ -299,9 +338,10 @@ def full_configs(L, ck, ctx, serving_sat, serving_poisson):
         d = L.lvs_decrypt_distance(ck, h, len(a))
         if d != levenshtein(a, b):
             raise SystemExit(f"{name}: wrong distance")
-        pbs = 2 * len(a) * len(b)
+        R = L.lvs_context_get_refresh(ctx)
+        pbs = 2 * len(a) * len(b) + refresh_pbs(len(a), len(b), R)
         out[name] = {"pbs": pbs, "seconds": round(dt, 3), "pbs_per_s": round(pbs / dt, 1),
-                     "cells_per_s": round(len(a) * len(b) / dt, 1), "distance": d}
+                     "cells_per_s": round(len(a) * len(b) / dt, 1), "distance": d, "refresh_every": R}
 
     # the batched workload, all 256 pairs, both encrypted (one graph plan)
     pairs = W.batched()
@@ -415,6 +455,7 @@ def main():
     ap.add_argument("--band-queries", type=int, default=32)
     ap.add_argument("--band-ell", type=int, default=4, help="half-width of the approximate band")
     ap.add_argument("--no-band", action="store_true")
+    ap.add_argument("--no-wide", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--no-microbench", action="store_true")
     ap.add_argument("--full-configs", action="store_true",
@@ -476,7 +517,7 @@ def main():
         print(f"wrong distance {dist} != {levenshtein(a, b)}", file=sys.stderr)
         sys.exit(1)
 
-    pbs_per_step = 3 * m * n
+    pbs_per_step = 3 * m * n + refresh_pbs(m, n, L.lvs_context_get_refresh(ctx))
     ms_per_step = 1000 * elapsed / args.steps
     pbs_s = pbs_per_step * args.steps / elapsed
     # the dominant kernel: the blind-rotation form with the most time
@@ -522,6 +563,8 @@ def main():
                                                                             args.batched_queries))
     if not args.no_band and args.band_queries > 0:
         line["band"] = band_block(L, ck, ctx, args.band_queries, args.band_ell)
+    if not args.no_wide:
+        line["wide"] = wide_block(L, ck, ctx)
     if not args.no_serving and args.serving_names > 0:
         line["serving"] = serving_block(L, ck, ctx, args.serving_names, args.serving_queries,
                                         args.poisson_queries, [float(x) for x in args.rho.split(",") if x])

@@ -4,9 +4,11 @@ along the diagonal (v[i,j] = M[i,j] - M[i-1,j] + v[i-1,j-1]), so the error of
 a cell's key grows with min(i, j).  On the 256 x 256 DNA alignment every
 bootstrap output M is recorded; every key 4 - v + 3 h + eq9 is rebuilt on the
 host from them and decrypted with the client key: each must decode to its
-plaintext key, the error must grow like sqrt(min(i, j)) and stay below the
-decoding threshold (half a box, 2^58) with the key switch's and modulus
-switch's noise still to come."""
+plaintext key, its variance must follow Section 3.1's equation (14 bootstrap
+output variances per level of the diagonal chain, with the output error
+measured on the same bootstraps) and stay below the decoding threshold (half
+a box, 2^58) with the key switch's and modulus switch's noise still to
+come."""
 import numpy as np
 import pytest
 
@@ -70,11 +72,27 @@ def test_key_noise_dna_256(gpu):
     worst = np.abs(err).max()
     lo = err[d <= 8].std()
     hi = err[d >= 192].std()
-    say(f"key error: max 2^{np.log2(worst):.2f}, std 2^{np.log2(lo):.2f} (min(i,j) <= 8), "
-        f"2^{np.log2(hi):.2f} (>= 192)")
-    # a bootstrap's output error is about 2^48 (dominated by the 41 bits the
-    # one-level gadget drops: 742 * 1024 * 2^80 / 12); the key sums about
-    # 20 min(i, j) + 1 of them, so sqrt growth: std ratio ~ sqrt(4481 / 91) ~ 7
-    assert lo < 2.0 ** 52.5
+    # every bootstrap output's own error (the trace holds all m n of them)
+    Mf = tr.reshape(m * n, L.CT_WORDS)
+    ph = Mf[:, -1] - Mf[:, :-1] @ S
+    mv = (ph + np.uint64(DELTA // 2)) >> np.uint64(59)
+    eps = (ph - (mv << np.uint64(59))).astype(np.int64).astype(np.float64).std()
+    # Section 3.1's key noise for the key of Eq. eq_keyeq2: each level of the
+    # diagonal chain adds M[i,j-1], M[i-1,j-1], M[i-1,j] with weights 1, 2, 3
+    # (1 + 4 + 9 = 14 output variances); the chain ends on the top row (one
+    # more output), on the left column (weight 3: nine) or in the corner
+    # (none), and eq9 adds one
+    ii, jj = np.meshgrid(np.arange(1, m + 1), np.arange(1, n + 1), indexing="ij")
+    base = np.where(ii < jj, 1, np.where(ii > jj, 9, 0))
+    model = 14 * (d - 1) + base + 1
+    fit_lo = err[d <= 8].var() / (eps ** 2 * model[d <= 8].mean())
+    fit_hi = err[d >= 192].var() / (eps ** 2 * model[d >= 192].mean())
+    say(f"bootstrap output error std 2^{np.log2(eps):.2f}; key error: max 2^{np.log2(worst):.2f}, "
+        f"std 2^{np.log2(lo):.2f} (min(i,j) <= 8), 2^{np.log2(hi):.2f} (>= 192); "
+        f"measured / model variance {fit_lo:.3f}, {fit_hi:.3f}")
+    # a bootstrap's output error is about 2^48 (mostly the 41 bits the
+    # one-level gadget drops: 742 * 1024 * 2^80 / 12)
+    assert 2.0 ** 47.5 < eps < 2.0 ** 49
+    assert 0.75 < fit_lo < 1.33 and 0.75 < fit_hi < 1.33
     assert 4.0 < hi / lo < 12.0
     assert worst < 2.0 ** 57                # half the decoding threshold (a box is 2^59 wide)

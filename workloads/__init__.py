@@ -20,6 +20,10 @@ recipes below stand in for them:
                 clip(round(LogNormal(ln 15 - s^2/2, s = 0.5)), 2, 64); half the
                 queries copy a server name with 1-2 random edits; Poisson
                 arrivals.
+  wide_symbols  a pair of 32-symbol strings over 64 distinct symbols drawn
+                uniformly below 2^21 (the range of Unicode code points); the
+                second string is uniform except that 20% of its positions,
+                drawn without replacement, copy the first string's symbol.
 """
 import math
 
@@ -140,3 +144,17 @@ def poisson_arrivals(seed: int, rate_per_s: float, count: int):
 
 def alphabet_of(strings) -> bytes:
     return bytes(sorted(set(b"".join(strings))))
+
+
+def wide_symbols(seed: int = 7, length: int = 32, width: int = 21, alphabet: int = 64, copy_frac: float = 0.2):
+    rng = _rng(seed)
+    symbols = []
+    while len(symbols) < alphabet:
+        v = int(rng.integers(0, 2 ** width))
+        if v not in symbols:
+            symbols.append(v)
+    a = [symbols[int(k)] for k in rng.integers(0, alphabet, size=length)]
+    b = [symbols[int(k)] for k in rng.integers(0, alphabet, size=length)]
+    for pos in rng.choice(length, size=int(round(copy_frac * length)), replace=False):
+        b[pos] = a[pos]
+    return a, b
