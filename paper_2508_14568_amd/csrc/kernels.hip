@@ -173,6 +173,111 @@ __device__ __forceinline__ void inv_stage(uint32_t (&x)[NE], const uint2* w, uin
     }
 }
 
+// The per-lane stages (forward S >= 6, inverse U < 5) with their twiddles
+// loaded ahead into registers: a lane holding elements e0 .. e0 + NE - 1 needs
+// NE >> sh distinct twiddles per stage, so that the loads of a whole phase can
+// be issued before the barrier that precedes it and wait there in the memory
+// pipeline instead of stalling each stage.
+template <int S, int NE>
+struct FwdTw {
+    uint2 v[NE >> (11 - S)];
+};
+template <int S, int NE>
+__device__ __forceinline__ void load_fwd_tw(FwdTw<S, NE>& t, const uint2* w, int lh, int e0) {
+    static_assert(S >= 6, "per-lane stages only");
+    constexpr int sh = 11 - S;
+    const uint2* wb = w + (1 << S) + (lh << (S - 5)) + (e0 >> sh);
+#pragma unroll
+    for (int k = 0; k < (NE >> sh); ++k) t.v[k] = wb[k];
+}
+template <int S, int NE>
+__device__ __forceinline__ void fwd_stage_tw(uint32_t (&x)[NE], const FwdTw<S, NE>& t, uint32_t p) {
+    constexpr int half = 1 << (10 - S);
+    constexpr int sh = 11 - S;
+    const uint32_t two_p = 2 * p;
+#pragma unroll
+    for (int el = 0; el < NE; ++el) {
+        if (el & half) continue;
+        const uint2 tw = t.v[el >> sh];
+        const uint32_t b = x[el + half];
+        const uint32_t s = __umulhi(b, tw.y) * p - b * tw.x;
+        const uint32_t a = x[el];
+        x[el] = a - s;
+        x[el + half] = a + two_p + s;
+    }
+}
+template <int U, int NE>
+struct InvTw {
+    uint2 v[NE >> (U + 1)];
+};
+template <int U, int NE>
+__device__ __forceinline__ void load_inv_tw(InvTw<U, NE>& t, const uint2* w, int lh, int e0) {
+    static_assert(U < 5, "per-lane stages only");
+    constexpr int sh = U + 1;
+    const uint2* wb = w + (1 << (10 - U)) + (lh << (5 - U)) + (e0 >> sh);
+#pragma unroll
+    for (int k = 0; k < (NE >> sh); ++k) t.v[k] = wb[k];
+}
+template <int U, int NE>
+__device__ __forceinline__ void inv_stage_tw(uint32_t (&x)[NE], const InvTw<U, NE>& t, uint32_t p, uint32_t q) {
+    constexpr int half = 1 << U;
+    constexpr int since = (U <= 3) ? U : U - 4;
+    constexpr bool reduce = (U == 3);
+    const uint32_t bound = (2 * p) << since;
+    constexpr int sh = U + 1;
+#pragma unroll
+    for (int el = 0; el < NE; ++el) {
+        if (el & half) continue;
+        const uint2 tw = t.v[el >> sh];
+        const uint32_t a = x[el], b = x[el + half];
+        const uint32_t sum = a + b;
+        x[el] = reduce ? reduce2p(sum, q, p) : sum;
+        x[el + half] = mul_shoup(a + bound - b, tw.x, tw.y, p);
+    }
+}
+
+// The stages with wave-uniform twiddles (forward S < 6, inverse U >= 5) read
+// from an LDS copy tl of entries 0 .. 63 of the prime's table: the waits for
+// them then count on the LDS counter, not behind the key loads on the
+// in-order vector memory counter.
+template <int S, int NE>
+__device__ __forceinline__ void fwd_stage_lds(uint32_t (&x)[NE], const uint2* tl, uint32_t p, int e0) {
+    static_assert(S >= 1 && S < 6, "wave-uniform stages only");
+    constexpr int half = 32 >> S;
+    constexpr int sh = 6 - S;
+    const uint2* wb = tl + (1 << S) + (e0 >> sh);
+    const uint32_t two_p = 2 * p;
+#pragma unroll
+    for (int el = 0; el < NE; ++el) {
+        if (el & half) continue;
+        const uint2 tw = wb[el >> sh];
+        const uint32_t b = x[el + half];
+        const uint32_t s = __umulhi(b, tw.y) * p - b * tw.x;
+        const uint32_t a = x[el];
+        x[el] = a - s;
+        x[el + half] = a + two_p + s;
+    }
+}
+template <int U, int NE>
+__device__ __forceinline__ void inv_stage_lds(uint32_t (&x)[NE], const uint2* tl, uint32_t p, uint32_t q, int e0) {
+    static_assert(U >= 5 && U < 10, "wave-uniform stages only");
+    constexpr int half = 1 << (U - 5);
+    constexpr int since = (U <= 7) ? U - 4 : U - 8;
+    constexpr bool reduce = (U == 7);
+    const uint32_t bound = (2 * p) << since;
+    constexpr int sh = U - 4;
+    const uint2* wb = tl + (1 << (10 - U)) + (e0 >> sh);
+#pragma unroll
+    for (int el = 0; el < NE; ++el) {
+        if (el & half) continue;
+        const uint2 tw = wb[el >> sh];
+        const uint32_t a = x[el], b = x[el + half];
+        const uint32_t sum = a + b;
+        x[el] = reduce ? reduce2p(sum, q, p) : sum;
+        x[el + half] = mul_shoup(a + bound - b, tw.x, tw.y, p);
+    }
+}
+
 __device__ __forceinline__ void ntt_inverse(uint32_t (&x)[kEh], uint32_t* scr, const uint2* w, uint32_t p, uint32_t q,
                                             int lh) {
     inv_stage<0>(x, w, p, q, lh);
@@ -477,8 +582,10 @@ __global__ void __launch_bounds__(kBrThreads, 2) blind_rotate_kernel(BrArgs A) {
 constexpr int kLatThreads = 512;
 constexpr int kLatE = kEh / 2;                   // elements per lane and wave
 constexpr int kLatAcc = 2 * kN / kLatThreads;    // accumulator coefficients per thread (8)
+constexpr int kLatTwu = 64;                      // uniform-stage twiddles per prime and direction
 constexpr size_t kLatLds = sizeof(uint32_t) * 2 * kPrimes * 2 * kPoly       // F and I
-                           + sizeof(uint32_t) * (kSmallWords + 1);           // switched mask and body
+                           + sizeof(uint32_t) * (kSmallWords + 1)            // switched mask and body
+                           + sizeof(uint2) * 2 * kPrimes * kLatTwu;          // uniform-stage twiddles
 
 // Coefficient k of thread t: polynomial (k >> 1) & 1, index t + 512 (k >> 2)
 // + 1024 (k & 1), so a thread holds both members (c, c + 1024) of each pair.
@@ -490,6 +597,8 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
     uint32_t* F = reinterpret_cast<uint32_t*>(lds);      // [kPrimes][2][kPoly]
     uint32_t* I = F + kPrimes * 2 * kPoly;               // [kPrimes][2][kPoly]
     uint32_t* abar = I + kPrimes * 2 * kPoly;            // [n+1]
+    // entries 0 .. 63 of every prime's forward and inverse tables
+    uint2* twu = reinterpret_cast<uint2*>(abar + kSmallWords + 1);   // [2][kPrimes][kLatTwu]
     // the accumulator copy sits at the residue slots of primes 0 and 1 that
     // the writing thread alone reads in the CRT step
     uint32_t* acc_lo = I;                                // [2][kPoly]
@@ -516,6 +625,12 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
         wfirst[w] = A.tw.fwd[size_t(w) * kN + 1];
         wlast[w] = A.tw.inv[size_t(w) * kN + 1];
     }
+    for (int t = tid; t < 2 * kPrimes * kLatTwu; t += kLatThreads) {
+        const int dir = t / (kPrimes * kLatTwu), pr = (t / kLatTwu) % kPrimes, idx = t % kLatTwu;
+        twu[t] = (dir ? A.tw.inv : A.tw.fwd)[size_t(pr) * kN + idx];
+    }
+    const uint2* const twf = twu + r * kLatTwu;                       // this wave's prime, forward
+    const uint2* const twi = twu + (kPrimes + r) * kLatTwu;           // and inverse
 
     for (int b = blockIdx.x; b < A.B; b += gridDim.x) {
         const Job& J = A.jobs[b];
@@ -587,11 +702,23 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
             const uint32_t* const nat0 = scrF + lh + 32 * e0;
 #pragma unroll
             for (int el = 0; el < kLatE; ++el) x[el] = nat0[32 * el];
-            fwd_stage<1, kLatE>(x, fw, p, lh, e0);
-            fwd_stage<2, kLatE>(x, fw, p, lh, e0);
-            fwd_stage<3, kLatE>(x, fw, p, lh, e0);
-            fwd_stage<4, kLatE>(x, fw, p, lh, e0);
-            fwd_stage<5, kLatE>(x, fw, p, lh, e0);
+            fwd_stage_lds<1, kLatE>(x, twf, p, e0);
+            fwd_stage_lds<2, kLatE>(x, twf, p, e0);
+            fwd_stage_lds<3, kLatE>(x, twf, p, e0);
+            fwd_stage_lds<4, kLatE>(x, twf, p, e0);
+            fwd_stage_lds<5, kLatE>(x, twf, p, e0);
+            // twiddles of stages 6..10, in flight across the transpose
+            FwdTw<6, kLatE> t6;
+            FwdTw<7, kLatE> t7;
+            FwdTw<8, kLatE> t8;
+            FwdTw<9, kLatE> t9;
+            FwdTw<10, kLatE> t10;
+            load_fwd_tw(t6, fw, lh, e0);
+            load_fwd_tw(t7, fw, lh, e0);
+            load_fwd_tw(t8, fw, lh, e0);
+            load_fwd_tw(t9, fw, lh, e0);
+            load_fwd_tw(t10, fw, lh, e0);
+            asm volatile("" ::: "memory");
             // pad(lh + 32 e) = lh + 32 e + (e >> 1) and pad(64 lh + e) = 65 lh + e (lh < 32, e < 64)
             uint32_t* const col = scrI + lh + 32 * e0 + (e0 >> 1);
             uint32_t* const row = scrI + 65 * lh + e0;
@@ -600,11 +727,11 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
             __syncthreads();
 #pragma unroll
             for (int el = 0; el < kLatE; ++el) x[el] = row[el];
-            fwd_stage<6, kLatE>(x, fw, p, lh, e0);
-            fwd_stage<7, kLatE>(x, fw, p, lh, e0);
-            fwd_stage<8, kLatE>(x, fw, p, lh, e0);
-            fwd_stage<9, kLatE>(x, fw, p, lh, e0);
-            fwd_stage<10, kLatE>(x, fw, p, lh, e0);
+            fwd_stage_tw(x, t6, p);
+            fwd_stage_tw(x, t7, p);
+            fwd_stage_tw(x, t8, p);
+            fwd_stage_tw(x, t9, p);
+            fwd_stage_tw(x, t10, p);
             // products with the GGSW rows (own digit first, as in the key)
 #pragma unroll
             for (int el = 0; el < kLatE; el += 2) {
@@ -616,12 +743,24 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
                     x[el + o] = redc(uint64_t(own) * (o ? kq.z : kq.x) + uint64_t(other) * (o ? kq.w : kq.y), p, mont);
                 }
             }
+            // twiddles of inverse stages 0..4
+            InvTw<0, kLatE> u0;
+            InvTw<1, kLatE> u1;
+            InvTw<2, kLatE> u2;
+            InvTw<3, kLatE> u3;
+            InvTw<4, kLatE> u4;
+            load_inv_tw(u0, iw, lh, e0);
+            load_inv_tw(u1, iw, lh, e0);
+            load_inv_tw(u2, iw, lh, e0);
+            load_inv_tw(u3, iw, lh, e0);
+            load_inv_tw(u4, iw, lh, e0);
+            asm volatile("" ::: "memory");
             // inverse transform, stages 0..9
-            inv_stage<0, kLatE>(x, iw, p, q, lh, e0);
-            inv_stage<1, kLatE>(x, iw, p, q, lh, e0);
-            inv_stage<2, kLatE>(x, iw, p, q, lh, e0);
-            inv_stage<3, kLatE>(x, iw, p, q, lh, e0);
-            inv_stage<4, kLatE>(x, iw, p, q, lh, e0);
+            inv_stage_tw(x, u0, p, q);
+            inv_stage_tw(x, u1, p, q);
+            inv_stage_tw(x, u2, p, q);
+            inv_stage_tw(x, u3, p, q);
+            inv_stage_tw(x, u4, p, q);
             uint32_t* const rowI = scrF + 65 * lh + e0;
             uint32_t* const colI = scrF + lh + 32 * e0 + (e0 >> 1);
 #pragma unroll
@@ -629,11 +768,11 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
             __syncthreads();
 #pragma unroll
             for (int el = 0; el < kLatE; ++el) x[el] = colI[32 * el + (el >> 1)];
-            inv_stage<5, kLatE>(x, iw, p, q, lh, e0);
-            inv_stage<6, kLatE>(x, iw, p, q, lh, e0);
-            inv_stage<7, kLatE>(x, iw, p, q, lh, e0);
-            inv_stage<8, kLatE>(x, iw, p, q, lh, e0);
-            inv_stage<9, kLatE>(x, iw, p, q, lh, e0);
+            inv_stage_lds<5, kLatE>(x, twi, p, q, e0);
+            inv_stage_lds<6, kLatE>(x, twi, p, q, e0);
+            inv_stage_lds<7, kLatE>(x, twi, p, q, e0);
+            inv_stage_lds<8, kLatE>(x, twi, p, q, e0);
+            inv_stage_lds<9, kLatE>(x, twi, p, q, e0);
             uint32_t* const nat = scrI + lh + 32 * e0;
 #pragma unroll
             for (int el = 0; el < kLatE; ++el) nat[32 * el] = x[el];
