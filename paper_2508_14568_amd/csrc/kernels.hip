@@ -653,12 +653,23 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
             acc[k] = lat_poly(k) ? ((src < uint32_t(kN)) ? v : uint64_t(0) - v) : uint64_t(0);
         }
 
+        // the lane's bootstrapping-key values of a CMux: the first half is
+        // issued at the end of the previous CMux's inverse transform (it
+        // arrives during the CRT), the second at the top of the CMux
+        const uint4* const K0 = reinterpret_cast<const uint4*>(A.bsk) + (size_t(r) * 2 + h) * (kN / 2) + lh + 16 * e0;
+        constexpr size_t kKeyStep = size_t(kPrimes) * 2 * (kN / 2);   // uint4 per CMux
+        constexpr int kEarly = kLatE / 4;
+        uint4 kpre[kLatE / 2];
+#pragma unroll
+        for (int k = 0; k < kEarly; ++k) kpre[k] = K0[k * 32];
+
         for (int i = 0; i < kSmallN; ++i) {
             const uint32_t a = abar[i];
-            const uint4* K = reinterpret_cast<const uint4*>(A.bsk) + ((size_t(i) * kPrimes + r) * 2 + h) * (kN / 2) + lh;
-            uint4 kpre[kLatE / 2];
+            {
+                const uint4* K = K0 + size_t(i) * kKeyStep;
 #pragma unroll
-            for (int k = 0; k < kLatE / 2; ++k) kpre[k] = K[(e0 / 2 + k) * 32];
+                for (int k = kEarly; k < kLatE / 2; ++k) kpre[k] = K[k * 32];
+            }
             asm volatile("" ::: "memory");
             // accumulator copy (low and high words)
 #pragma unroll
@@ -776,6 +787,13 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
             uint32_t* const nat = scrI + lh + 32 * e0;
 #pragma unroll
             for (int el = 0; el < kLatE; ++el) nat[32 * el] = x[el];
+            {
+                // the last CMux reloads its own key (in bounds, unused)
+                const uint4* K = K0 + size_t(min(i + 1, kSmallN - 1)) * kKeyStep;
+#pragma unroll
+                for (int k = 0; k < kEarly; ++k) kpre[k] = K[k * 32];
+            }
+            asm volatile("" ::: "memory");
             __syncthreads();
             // last inverse stage (coefficients c and c + 1024), then the CRT
 #pragma unroll
