@@ -508,7 +508,8 @@ def main():
     br_ms, br_launches, br_pbs = L.lvs_profile_read(ctx, L.KERNEL_BLIND_ROTATE)
     forms = {name: L.lvs_profile_read(ctx, k) for name, k in
              (("blind_rotate_latency_kernel", L.KERNEL_BLIND_ROTATE_LATENCY),
-              ("blind_rotate_kernel", L.KERNEL_BLIND_ROTATE_THROUGHPUT))}
+              ("blind_rotate_kernel", L.KERNEL_BLIND_ROTATE_THROUGHPUT),
+              ("blind_rotate_w16_kernel", L.KERNEL_BLIND_ROTATE_W16))}
     ks_ms, ks_launches, _ = L.lvs_profile_read(ctx, L.KERNEL_KEYSWITCH)
     L.lvs_profile_enable(ctx, False)
 

@@ -174,23 +174,26 @@ int lvs_sync(lvs_context* ctx);
 /* Launch shape of the blind rotation kernel (the dominant cost of every
  * bootstrap, Section 2.2).  br_grid: workgroups per launch, each looping over
  * the batch (0: one workgroup per bootstrap).  latency_form_max: batches of
- * at most this many bootstraps use the eight-wave form (one workgroup of 512
- * threads per CU, two waves per prime); larger batches use the four-wave form
- * (two workgroups of 256 threads per CU).  A new context starts at
- * {0, INT32_MAX}: the eight-wave form was the faster one at every batch size
- * measured on MI355X.  Plans captured as graphs keep the shape they were
+ * at most this many bootstraps use the one-workgroup-per-CU form; larger
+ * batches use the four-wave form (two workgroups of 256 threads per CU).
+ * latency_waves picks the one-per-CU form: 8 (512 threads, two waves per
+ * prime) or 16 (1024 threads, four waves per prime, first and last three
+ * transform stages in the digit and CRT steps).  A new context starts at
+ * {0, INT32_MAX, 8}.  Plans captured as graphs keep the shape they were
  * captured with. */
 typedef struct lvs_tuning {
     int32_t br_grid;
     int32_t latency_form_max;
+    int32_t latency_waves;   /* 8 or 16: wavefronts per bootstrap of the one-per-CU form (0 = 8) */
 } lvs_tuning;
 
 int lvs_context_get_tuning(const lvs_context* ctx, lvs_tuning* out);
-/* Rejects negative values (LVS_E_INVAL). */
+/* Rejects negative values and latency_waves other than 0, 8, 16 (LVS_E_INVAL). */
 int lvs_context_set_tuning(lvs_context* ctx, const lvs_tuning* t);
 
 /* One timing of the autotuner: mean duration (ms) of a blind-rotation launch
- * of `batch` bootstraps in `form` (1 or 2) with `grid` workgroups. */
+ * of `batch` bootstraps in `form` (1: eight-wave, 2: four-wave, 3:
+ * sixteen-wave) with `grid` workgroups. */
 typedef struct lvs_tune_sample {
     int32_t batch;
     int32_t form;
@@ -201,10 +204,12 @@ typedef struct lvs_tune_sample {
 /* Device workspace bytes of lvs_autotune (256-byte aligned, caller-owned). */
 size_t lvs_autotune_workspace_bytes(size_t max_batch);
 
-/* Times both forms, and a persistent grid of twice the CU count, on batches
- * from half to four times the CU count (at most max_batch, 1..65536) of zero
- * ciphertexts, installs the fastest shape in the context and returns it in
- * *best.  Up to max_samples timings go to samples (may be NULL); *n_samples
+/* Times the three forms, and a persistent grid of twice the CU count, on
+ * batches from half to four times the CU count (at most max_batch, 1..65536)
+ * of zero ciphertexts, installs the fastest shape in the context (the
+ * one-per-CU form with the smaller total time, used up to the largest batch
+ * at which it is still at least as fast as the four-wave form) and returns it
+ * in *best.  Up to max_samples timings go to samples (may be NULL); *n_samples
  * (may be NULL) receives how many were taken.  Synchronous; uses the
  * context's stream.  Errors: LVS_E_INVAL, LVS_E_NOMEM_DEVICE (workspace too
  * small), LVS_E_DEVICE. */
@@ -491,11 +496,12 @@ int lvs_server_stats(const lvs_server* srv, uint64_t* steps, uint64_t* bootstrap
 
 /* ------------------------------------------------------------ measurement */
 
-#define LVS_KERNEL_BLIND_ROTATE 0            /* both forms together */
+#define LVS_KERNEL_BLIND_ROTATE 0            /* every form together */
 #define LVS_KERNEL_KEYSWITCH 1
 #define LVS_KERNEL_GRAPH 2                   /* a graph-captured plan, whole */
 #define LVS_KERNEL_BLIND_ROTATE_LATENCY 3    /* eight-wave form, one workgroup per CU */
 #define LVS_KERNEL_BLIND_ROTATE_THROUGHPUT 4 /* four-wave form, two workgroups per CU */
+#define LVS_KERNEL_BLIND_ROTATE_W16 5        /* sixteen-wave form, one workgroup per CU */
 
 /* Kernel timing for measurement: while enabled, every launch of the blind
  * rotation, of the key switch and of a plan's graph is bracketed by HIP

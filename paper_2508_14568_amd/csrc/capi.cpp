@@ -889,7 +889,7 @@ int lvs_profile_read(lvs_context* ctx, int kernel, double* total_ms, uint64_t* l
     double ms = 0;
     uint64_t n = 0, u = 0;
     for (auto& t : C->timed) {
-        const bool br = t.kernel == kProfBrLatency || t.kernel == kProfBrThroughput;
+        const bool br = t.kernel == kProfBrLatency || t.kernel == kProfBrThroughput || t.kernel == kProfBrW16;
         if (t.kernel != kernel && !(kernel == kProfBlindRotate && br)) continue;
         LVS_HIP(hipEventSynchronize(t.end));
         float dt = 0;

@@ -25,7 +25,8 @@ struct Context : Handle {
     int cus = 0;                  // compute units of the device
     // launch shape of the blind rotation (lvs_context_set_tuning / lvs_autotune)
     int br_grid = 0;              // persistent grid (0: one workgroup per job)
-    int latency_form_max = 0;     // batches up to this size take the eight-wave form
+    int latency_form_max = 0;     // batches up to this size take the one-workgroup-per-CU form
+    int latency_waves = 8;        // that form's wavefronts per bootstrap: 8 or 16
     size_t refresh_every = LVS_REFRESH_DEFAULT;   // noise-refresh interval in anti-diagonals (0: off)
     // kernel timing (lvs_profile_*): event pairs recorded around launches
     bool profiling = false;
@@ -49,13 +50,15 @@ inline hipEvent_t take_event(Context* C) {
     return e;
 }
 
-// Profile ids (lvs_profile_read): 0 sums the two blind-rotation forms, which
-// are recorded as 3 (eight-wave workgroup, one per CU) and 4 (four-wave
-// workgroups, two per CU).
-constexpr int kProfBlindRotate = 0, kProfKeySwitch = 1, kProfGraph = 2, kProfBrLatency = 3, kProfBrThroughput = 4;
+// Profile ids (lvs_profile_read): 0 sums the blind-rotation forms, which are
+// recorded as 3 (eight-wave workgroup, one per CU), 4 (four-wave workgroups,
+// two per CU) and 5 (sixteen-wave workgroup, one per CU).
+constexpr int kProfBlindRotate = 0, kProfKeySwitch = 1, kProfGraph = 2, kProfBrLatency = 3, kProfBrThroughput = 4,
+              kProfBrW16 = 5;
 
 inline int br_profile_id(const Context* C, int B) {
-    return B <= C->latency_form_max ? kProfBrLatency : kProfBrThroughput;
+    if (B > C->latency_form_max) return kProfBrThroughput;
+    return C->latency_waves == 16 ? kProfBrW16 : kProfBrLatency;
 }
 
 // Brackets one launch with events when profiling is on.

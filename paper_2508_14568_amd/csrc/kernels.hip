@@ -838,6 +838,336 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
     }
 }
 
+// ------------------------------------------ blind rotation, sixteen-wave form
+
+// One workgroup of 16 wavefronts per bootstrap (four per prime), one per CU,
+// four waves per SIMD.  With position bits b10..b0 of a polynomial:
+//  * the digit phase runs the first three forward stages (b10, b9, b8): a
+//    pair of threads holds the eight positions c + 256 k (k = b10 b9 b8) of
+//    a group, each thread the digits' residues for two primes;
+//  * wave (prime r, quarter q = b10 b9) then holds, in element e of lane
+//    (h, l), position q 512 + (l >> 4) 256 + 16 e + (l & 15) and runs the
+//    stages of b7..b4 in the lane; a transpose local to the wave gives lane
+//    l the positions q 512 + 16 l + e' for the stages of b3..b0 and for the
+//    products, which are the key's order (position 64 lh + e with lh = 8 q +
+//    (l >> 2), e = 16 (l & 3) + e');
+//  * the inverse runs the same phases backwards and ends in the CRT step with
+//    the last three stages; the two threads of a group exchange residues by
+//    a lane permutation.
+// Three workgroup barriers per CMux: accumulator copy -> digits, digits ->
+// transform, transform -> CRT.
+constexpr int kW16Threads = 1024;
+constexpr int kW16E = 16;                                  // elements per lane and phase
+constexpr int kW16Stride = kN + kN / 16 + 16;              // padded polynomial in LDS, 16 mod 32 words
+constexpr int kW16Acc = kN + 32;                           // words of one padded accumulator polynomial
+constexpr int kW16Twu = 128;                               // LDS twiddle entries per prime and direction
+constexpr size_t kW16Lds = sizeof(uint32_t) * kPrimes * 2 * kW16Stride      // residues
+                           + sizeof(uint32_t) * 2 * 2 * kW16Acc              // accumulator copy (lo, hi)
+                           + sizeof(uint32_t) * (kSmallWords + 1)            // switched mask and body
+                           + sizeof(uint2) * 2 * kPrimes * kW16Twu;          // twiddles 0..127
+__device__ __forceinline__ int w16pad(int pos) { return pos + (pos >> 4); }
+__device__ __forceinline__ int w16apad(int pos) { return pos + ((pos >> 10) << 4); }
+
+// pick ? a : b for a per-lane pick, as arithmetic (no indexed array access)
+__device__ __forceinline__ uint32_t sel(uint32_t pick_mask, uint32_t a, uint32_t b) {
+    return (a & pick_mask) | (b & ~pick_mask);
+}
+
+// Value of v in lane ^ 1 (the other thread of a group).
+__device__ __forceinline__ uint32_t lane_xor1(uint32_t v) {
+    return uint32_t(__builtin_amdgcn_mov_dpp(int(v), 0xB1, 0xF, 0xF, false));   // quad_perm [1, 0, 3, 2]
+}
+
+__device__ __forceinline__ void fwd_bfly(uint32_t& a, uint32_t& b, uint2 tw, uint32_t p) {
+    const uint32_t s = __umulhi(b, tw.y) * p - b * tw.x;
+    const uint32_t x = a;
+    a = x - s;
+    b = x + 2 * p + s;
+}
+
+__device__ __forceinline__ void inv_bfly(uint32_t& a, uint32_t& b, uint2 tw, uint32_t p, uint32_t bound, bool reduce,
+                                         uint32_t q) {
+    const uint32_t x = a, y = b;
+    const uint32_t sum = x + y;
+    a = reduce ? reduce2p(sum, q, p) : sum;
+    b = mul_shoup(x + bound - y, tw.x, tw.y, p);
+}
+
+__global__ void __launch_bounds__(kW16Threads, 1) blind_rotate_w16_kernel(BrArgs A) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint32_t* F = reinterpret_cast<uint32_t*>(lds);                  // [kPrimes][2][kW16Stride]
+    uint32_t* acc_lo = F + kPrimes * 2 * kW16Stride;                 // [2][kW16Acc]
+    uint32_t* acc_hi = acc_lo + 2 * kW16Acc;
+    uint32_t* abar = acc_hi + 2 * kW16Acc;                           // [n+1]
+    uint2* twl = reinterpret_cast<uint2*>(abar + kSmallWords + 1);   // [2][kPrimes][kW16Twu]
+
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int r = wave >> 2;          // prime of the transform phases
+    const int q = wave & 3;           // position bits b10 b9 of the wave
+    const int lane = tid & 63;
+    const int h = lane >> 5;          // polynomial of the lane
+    const int l = lane & 31;
+    const int b8 = l >> 4;
+    // digit and CRT phases: group (polynomial gh, c = gc), primes 2 pp and 2 pp + 1
+    const int grp = tid >> 1, pp = tid & 1;
+    const int gh = grp >> 8, gc = grp & 255;
+    const uint32_t ppm = 0u - uint32_t(pp);     // all ones for the second thread of a group
+
+    const uint32_t p = pick(A.crt.p, r);
+    const uint32_t mont = pick(A.crt.mont, r);
+    const uint32_t qr = pick(A.crt.red, r);
+    const uint2* fw = A.tw.fwd + size_t(r) * kN;
+    const uint2* iw = A.tw.inv + size_t(r) * kN;
+    uint32_t* Fr = F + (r * 2 + h) * kW16Stride;
+    const uint2* twf = twl + r * kW16Twu;
+    const uint2* twi = twl + (kPrimes + r) * kW16Twu;
+    for (int t = tid; t < 2 * kPrimes * kW16Twu; t += kW16Threads) {
+        const int dir = t / (kPrimes * kW16Twu), pr = (t / kW16Twu) % kPrimes, idx = t % kW16Twu;
+        twl[t] = (dir ? A.tw.inv : A.tw.fwd)[size_t(pr) * kN + idx];
+    }
+    // this thread's primes in the digit and CRT phases
+    uint32_t pj[2], qj[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        pj[j] = pp ? A.crt.p[2 + j] : A.crt.p[j];
+        qj[j] = pp ? A.crt.red[2 + j] : A.crt.red[j];
+    }
+    // B1: element e at position base1 + 16 e; B2: element e' at base2 + e'
+    const int base1 = (q << 9) | (b8 << 8) | (l & 15);
+    const int base2 = (q << 9) | (l << 4);
+    uint32_t* const row1 = Fr + w16pad(base1);      // element e at row1[17 e]
+    uint32_t* const row2 = Fr + w16pad(base2);      // element e' at row2[e']
+    const int ql = (q << 5) | l;                    // position bits b10..b4 in the B2 layout
+    const int qb = (q << 1) | b8;                   // position bits b10..b8 in the B1 layout
+
+    for (int b = blockIdx.x; b < A.B; b += gridDim.x) {
+        const Job& J = A.jobs[b];
+        for (int c = tid; c < kSmallWords; c += kW16Threads) {
+            uint64_t v = 0;
+            for (int sp = 0; sp < A.nsplit; ++sp) v += A.part[(size_t(sp) * A.B + b) * kSmallWords + c];
+            if (c == kSmallN) v += job_word(J, kN) + J.delta;
+            abar[c] = uint32_t((((v >> 51) + 1) >> 1) & (2 * kN - 1));
+        }
+        __syncthreads();
+        const int lut = min(int(J.lut), LVS_LUT_SLOTS - 1);
+        const uint64_t* tp = A.luts + size_t(lut) * kN;
+        const uint32_t bbar = abar[kSmallN];
+        // the thread's accumulator coefficients: polynomial gh, positions gc + 256 (k + 4 pp)
+        uint64_t acc[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t c = uint32_t(gc + 256 * (k + 4 * pp));
+            const uint32_t src = (c + bbar) & (2 * kN - 1);
+            const uint64_t v = tp[src & (kN - 1)];
+            acc[k] = gh ? ((src < uint32_t(kN)) ? v : uint64_t(0) - v) : uint64_t(0);
+        }
+
+        for (int i = 0; i < kSmallN; ++i) {
+            // the loop-invariant twiddle reads stay in the loop (registers are the limit here)
+            asm volatile("" ::: "memory");
+            const uint32_t a = abar[i];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int at = gh * kW16Acc + w16apad(gc + 256 * (k + 4 * pp));
+                acc_lo[at] = uint32_t(acc[k]);
+                acc_hi[at] = uint32_t(acc[k] >> 32);
+            }
+            __syncthreads();
+            // digits of X^a ACC - ACC at the thread's four positions, then the
+            // partner's four by a lane permutation
+            uint32_t mine[4], d[8];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t c = uint32_t(gc + 256 * (k + 4 * pp));
+                const uint32_t src = (c - a) & (2 * kN - 1);
+                const int at = gh * kW16Acc + w16apad(int(src & (kN - 1)));
+                uint64_t rr = uint64_t(acc_lo[at]) | (uint64_t(acc_hi[at]) << 32);
+                if (src >= uint32_t(kN)) rr = uint64_t(0) - rr;
+                const uint64_t t = rr - acc[k];
+                // round(t / 2^41) as a balanced 23-bit digit d, kept as d + 2^22
+                mine[k] = ((((uint32_t(t >> 40) + 1) >> 1) & 0x7FFFFFu) + 0x400000u) & 0x7FFFFFu;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t other = lane_xor1(mine[k]);
+                d[k] = sel(ppm, other, mine[k]);
+                d[k + 4] = sel(ppm, mine[k], other);
+            }
+            // forward stages 0..2 (b10, b9, b8) of the thread's two primes
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const uint32_t pw = pj[j];
+                const uint2* tw = twl + (2 * pp + j) * kW16Twu;
+                uint32_t y[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) y[k] = d[k] + (pw - (1u << 22));   // residue of d below 2p
+                const uint2 t0 = tw[1];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) fwd_bfly(y[k], y[k + 4], t0, pw);
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (!(k & 2)) fwd_bfly(y[k], y[k + 2], tw[2 + (k >> 2)], pw);
+#pragma unroll
+                for (int k = 0; k < 8; k += 2) fwd_bfly(y[k], y[k + 1], tw[4 + (k >> 1)], pw);
+                uint32_t* dst = F + ((2 * pp + j) * 2 + gh) * kW16Stride;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) dst[w16pad(gc + 256 * k)] = y[k];
+            }
+            __syncthreads();
+            // stages 3..6 (b7..b4): partners e and e + (8 >> (s - 3))
+            uint32_t x[kW16E];
+#pragma unroll
+            for (int e = 0; e < kW16E; ++e) x[e] = row1[17 * e];
+#pragma unroll
+            for (int e = 0; e < kW16E; ++e)
+                if (!(e & 8)) fwd_bfly(x[e], x[e + 8], twf[8 + qb], p);
+#pragma unroll
+            for (int e = 0; e < kW16E; ++e)
+                if (!(e & 4)) fwd_bfly(x[e], x[e + 4], twf[16 + (qb << 1) + (e >> 3)], p);
+#pragma unroll
+            for (int e = 0; e < kW16E; ++e)
+                if (!(e & 2)) fwd_bfly(x[e], x[e + 2], twf[32 + (qb << 2) + (e >> 2)], p);
+#pragma unroll
+            for (int e = 0; e < kW16E; ++e)
+                if (!(e & 1)) fwd_bfly(x[e], x[e + 1], twf[64 + (qb << 3) + (e >> 1)], p);
+            // this CMux's key values of the lane (positions base2 + e', e' = 2 k, 2 k + 1)
+            const uint4* K = reinterpret_cast<const uint4*>(A.bsk) + ((size_t(i) * kPrimes + r) * 2 + h) * (kN / 2) +
+                             ((l & 3) << 3) * 32 + (q << 3) + (l >> 2);
+            uint4 kpre[kW16E / 2];
+#pragma unroll
+            for (int k = 0; k < kW16E / 2; ++k) kpre[k] = K[k * 32];
+            // transpose within the wave
+#pragma unroll
+            for (int e = 0; e < kW16E; ++e) row1[17 * e] = x[e];
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int e = 0; e < kW16E; ++e) x[e] = row2[e];
+            __builtin_amdgcn_wave_barrier();
+            // stages 7..10 (b3..b0): partners e' and e' + (8 >> (s - 7))
+            {
+                const uint2 t7 = fw[128 + ql];
+#pragma unroll
+                for (int e = 0; e < kW16E; ++e)
+                    if (!(e & 8)) fwd_bfly(x[e], x[e + 8], t7, p);
+#pragma unroll
+                for (int e = 0; e < kW16E; ++e)
+                    if (!(e & 4)) fwd_bfly(x[e], x[e + 4], fw[256 + (ql << 1) + (e >> 3)], p);
+#pragma unroll
+                for (int e = 0; e < kW16E; ++e)
+                    if (!(e & 2)) fwd_bfly(x[e], x[e + 2], fw[512 + (ql << 2) + (e >> 2)], p);
+#pragma unroll
+                for (int e = 0; e < kW16E; ++e)
+                    if (!(e & 1)) fwd_bfly(x[e], x[e + 1], fw[1024 + (ql << 3) + (e >> 1)], p);
+            }
+            // products with the GGSW rows (own digit first, as in the key)
+#pragma unroll
+            for (int e = 0; e < kW16E; e += 2) {
+                const uint4 kq = kpre[e >> 1];
+#pragma unroll
+                for (int o = 0; o < 2; ++o) {
+                    const uint32_t own = x[e + o];
+                    const uint32_t other = swap_halves(own, lane);
+                    x[e + o] = redc(uint64_t(own) * (o ? kq.z : kq.x) + uint64_t(other) * (o ? kq.w : kq.y), p, mont);
+                }
+            }
+            // inverse stages 0..3 (b0..b3): partners e' and e' + (1 << u); reduce after 3
+            {
+#pragma unroll
+                for (int e = 0; e < kW16E; ++e)
+                    if (!(e & 1)) inv_bfly(x[e], x[e + 1], iw[1024 + (ql << 3) + (e >> 1)], p, 2 * p, false, qr);
+#pragma unroll
+                for (int e = 0; e < kW16E; ++e)
+                    if (!(e & 2)) inv_bfly(x[e], x[e + 2], iw[512 + (ql << 2) + (e >> 2)], p, 4 * p, false, qr);
+#pragma unroll
+                for (int e = 0; e < kW16E; ++e)
+                    if (!(e & 4)) inv_bfly(x[e], x[e + 4], iw[256 + (ql << 1) + (e >> 3)], p, 8 * p, false, qr);
+                const uint2 u3 = iw[128 + ql];
+#pragma unroll
+                for (int e = 0; e < kW16E; ++e)
+                    if (!(e & 8)) inv_bfly(x[e], x[e + 8], u3, p, 16 * p, true, qr);
+            }
+            // transpose back within the wave
+#pragma unroll
+            for (int e = 0; e < kW16E; ++e) row2[e] = x[e];
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int e = 0; e < kW16E; ++e) x[e] = row1[17 * e];
+            __builtin_amdgcn_wave_barrier();
+            // inverse stages 4..7 (b4..b7): partners e and e + (1 << (u - 4)); reduce after 7
+#pragma unroll
+            for (int e = 0; e < kW16E; ++e)
+                if (!(e & 1)) inv_bfly(x[e], x[e + 1], twi[64 + (qb << 3) + (e >> 1)], p, 2 * p, false, qr);
+#pragma unroll
+            for (int e = 0; e < kW16E; ++e)
+                if (!(e & 2)) inv_bfly(x[e], x[e + 2], twi[32 + (qb << 2) + (e >> 2)], p, 4 * p, false, qr);
+#pragma unroll
+            for (int e = 0; e < kW16E; ++e)
+                if (!(e & 4)) inv_bfly(x[e], x[e + 4], twi[16 + (qb << 1) + (e >> 3)], p, 8 * p, false, qr);
+#pragma unroll
+            for (int e = 0; e < kW16E; ++e)
+                if (!(e & 8)) inv_bfly(x[e], x[e + 8], twi[8 + qb], p, 16 * p, true, qr);
+#pragma unroll
+            for (int e = 0; e < kW16E; ++e) row1[17 * e] = x[e];
+            __syncthreads();
+            // inverse stages 8..10 (b8, b9, b10) of the thread's two primes, then
+            // the four primes of four positions by a lane permutation, then the CRT
+            uint32_t y[2][8];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const uint32_t pw = pj[j];
+                const uint2* tw = twl + (kPrimes + 2 * pp + j) * kW16Twu;
+                const uint32_t* src = F + ((2 * pp + j) * 2 + gh) * kW16Stride;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) y[j][k] = src[w16pad(gc + 256 * k)];
+#pragma unroll
+                for (int k = 0; k < 8; k += 2) inv_bfly(y[j][k], y[j][k + 1], tw[4 + (k >> 1)], pw, 2 * pw, false, qj[j]);
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (!(k & 2)) inv_bfly(y[j][k], y[j][k + 2], tw[2 + (k >> 2)], pw, 4 * pw, false, qj[j]);
+                const uint2 t1 = tw[1];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) inv_bfly(y[j][k], y[j][k + 4], t1, pw, 8 * pw, false, qj[j]);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                uint32_t recv[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) recv[j] = lane_xor1(sel(ppm, y[j][k], y[j][k + 4]));
+                uint32_t res[kPrimes];
+                res[0] = sel(ppm, recv[0], y[0][k]);
+                res[1] = sel(ppm, recv[1], y[1][k]);
+                res[2] = sel(ppm, y[0][k + 4], recv[0]);
+                res[3] = sel(ppm, y[1][k + 4], recv[1]);
+                acc[k] += crt_lift(res, A.crt);
+            }
+        }
+        // sample extraction of coefficient 0, then the job's output rule
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int at = gh * kW16Acc + w16apad(gc + 256 * (k + 4 * pp));
+            acc_lo[at] = uint32_t(acc[k]);
+            acc_hi[at] = uint32_t(acc[k] >> 32);
+        }
+        __syncthreads();
+        for (int t = tid; t < kCtWords; t += kW16Threads) {
+            const int at = (t == 0) ? 0 : (t < kN) ? w16apad(kN - t) : kW16Acc;
+            const uint64_t m = uint64_t(acc_lo[at]) | (uint64_t(acc_hi[at]) << 32);
+            const uint64_t v = (t > 0 && t < kN) ? uint64_t(0) - m : m;
+            const uint64_t s0 = J.sub[0] ? J.sub[0][t] : 0;
+            const uint64_t s1 = J.sub[1] ? J.sub[1][t] : 0;
+            const uint64_t c0 = (t == kN) ? J.sub_delta[0] : 0;
+            const uint64_t c1 = (t == kN) ? J.sub_delta[1] : 0;
+            const uint64_t o0 = v - s0 - c0, o1 = v - s1 - c1;
+            if (J.dst[0]) J.dst[0][t] = o0;
+            if (J.dst[1]) J.dst[1][t] = o1;
+            if (J.dst[2]) J.dst[2][t] = v;
+            if (J.dst[3]) J.dst[3][t] = J.copy_of ? o1 : o0;
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------ bootstrapping-key conversion
 
 // One wavefront per (GGSW row, prime): lanes 0-31 take the row's mask
@@ -1020,12 +1350,15 @@ hipError_t prepare_kernels() {
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(dev::blind_rotate_kernel),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(dev::kBrLds));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(dev::blind_rotate_w16_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(dev::kW16Lds));
     return e;
 }
 
 hipError_t launch_blind_rotate_jobs(const Job* jobs, int B, const uint64_t* part, const uint64_t* luts,
                                     const uint32_t* bsk, const DevTables& t, int grid, int latency_form_max,
-                                    hipStream_t st) {
+                                    int latency_waves, hipStream_t st) {
     if (B <= 0) return hipSuccess;
     dev::BrArgs A{};
     A.jobs = jobs;
@@ -1037,7 +1370,9 @@ hipError_t launch_blind_rotate_jobs(const Job* jobs, int B, const uint64_t* part
     A.crt = make_crt();
     A.B = B;
     if (grid <= 0 || grid > B) grid = B;
-    if (B <= latency_form_max)
+    if (B <= latency_form_max && latency_waves == 16)
+        hipLaunchKernelGGL(dev::blind_rotate_w16_kernel, dim3(grid), dim3(dev::kW16Threads), dev::kW16Lds, st, A);
+    else if (B <= latency_form_max)
         hipLaunchKernelGGL(dev::blind_rotate_latency_kernel, dim3(grid), dim3(dev::kLatThreads), dev::kLatLds, st, A);
     else
         hipLaunchKernelGGL(dev::blind_rotate_kernel, dim3(grid), dim3(dev::kBrThreads), dev::kBrLds, st, A);

@@ -44,10 +44,11 @@ int keyswitch_splits(int B);
 size_t keyswitch_part_words(int B);
 hipError_t launch_keyswitch_jobs(const Job* jobs, int B, const uint64_t* ksk, uint64_t* part, hipStream_t st);
 // Batches of at most latency_form_max bootstraps take the one-workgroup-per-CU
-// form of the blind rotation, larger ones the two-per-CU form.
+// form of the blind rotation (latency_waves 8 or 16 wavefronts), larger ones
+// the two-per-CU form.
 hipError_t launch_blind_rotate_jobs(const Job* jobs, int B, const uint64_t* part, const uint64_t* luts,
                                     const uint32_t* bsk, const DevTables& t, int grid, int latency_form_max,
-                                    hipStream_t st);
+                                    int latency_waves, hipStream_t st);
 hipError_t prepare_kernels();
 hipError_t launch_bsk_convert(const uint64_t* bsk_u64, uint32_t* out, const DevTables& t, hipStream_t st);
 hipError_t launch_trivial(uint64_t* out, int count, uint32_t mu, hipStream_t st);

@@ -518,7 +518,7 @@ hipError_t launch_steps(Context* C, const Plan& P, hipStream_t st, bool timed) {
         {
             TimedLaunch t(C, timed ? br_profile_id(C, B) : -1, uint64_t(B));
             hipError_t e = launch_blind_rotate_jobs(P.d_jobs + s.off, B, P.d_part, C->luts, C->bsk, C->tables,
-                                                    C->br_grid, C->latency_form_max, st);
+                                                    C->br_grid, C->latency_form_max, C->latency_waves, st);
             if (e != hipSuccess) return e;
         }
     }

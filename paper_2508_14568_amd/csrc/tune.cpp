@@ -1,9 +1,10 @@
 // Launch-shape tuning of the blind rotation.
 //
-// The blind rotation has two forms (one eight-wave workgroup per CU, or two
-// four-wave workgroups per CU) and an optional persistent grid.  Which is faster depends on how a batch fills the device, so the
-// autotuner times both forms, and a persistent grid, on batches around the
-// CU count and keeps the fastest shape per batch size.  Its inputs are zero
+// The blind rotation has three forms (one eight-wave or one sixteen-wave
+// workgroup per CU, or two four-wave workgroups per CU) and an optional
+// persistent grid.  Which is faster depends on how a batch fills the device,
+// so the autotuner times every form, and a persistent grid, on batches around
+// the CU count and keeps the fastest shape per batch size.  Its inputs are zero
 // ciphertexts: the work of a bootstrap does not depend on the values.
 #include <hip/hip_runtime.h>
 
@@ -65,6 +66,7 @@ int lvs_context_get_tuning(const lvs_context* ctx, lvs_tuning* out) {
     if (!C || !out) TUNE_FAIL(LVS_E_INVAL, "lvs_context_get_tuning: bad argument");
     out->br_grid = C->br_grid;
     out->latency_form_max = C->latency_form_max;
+    out->latency_waves = C->latency_waves;
     return LVS_OK;
 }
 
@@ -72,8 +74,11 @@ int lvs_context_set_tuning(lvs_context* ctx, const lvs_tuning* t) {
     Context* C = ctx_of(ctx);
     if (!C || !t) TUNE_FAIL(LVS_E_INVAL, "lvs_context_set_tuning: bad argument");
     if (t->br_grid < 0 || t->latency_form_max < 0) TUNE_FAIL(LVS_E_INVAL, "lvs_context_set_tuning: negative value");
+    if (t->latency_waves != 0 && t->latency_waves != 8 && t->latency_waves != 16)
+        TUNE_FAIL(LVS_E_INVAL, "lvs_context_set_tuning: latency_waves must be 8 or 16");
     C->br_grid = t->br_grid;
     C->latency_form_max = t->latency_form_max;
+    C->latency_waves = t->latency_waves ? t->latency_waves : 8;
     return LVS_OK;
 }
 
@@ -113,16 +118,18 @@ int lvs_autotune(lvs_context* ctx, size_t max_batch, void* d_work, size_t work_b
         uint8_t* w = ws;
         err = upload_plan(P, w, st);
         if (err == hipSuccess) err = launch_keyswitch_jobs(P.d_jobs, B, C->ksk, P.d_part, st);
-        std::vector<Candidate> cands{{1, B}, {2, B}};
+        std::vector<Candidate> cands{{1, B}, {3, B}, {2, B}};
         if (B >= 2 * cus) cands.push_back({2, 2 * cus});
         for (const Candidate& c : cands) {
             if (err != hipSuccess) break;
-            const int lf = c.form == 1 ? INT_MAX : 0;
+            const int lf = c.form == 2 ? 0 : INT_MAX;
+            const int waves = c.form == 3 ? 16 : 8;
             // one launch to warm caches, then two timed
-            err = launch_blind_rotate_jobs(P.d_jobs, B, P.d_part, C->luts, C->bsk, C->tables, c.grid, lf, st);
+            err = launch_blind_rotate_jobs(P.d_jobs, B, P.d_part, C->luts, C->bsk, C->tables, c.grid, lf, waves, st);
             if (err == hipSuccess) err = hipEventRecord(e0, st);
             for (int r = 0; r < 2 && err == hipSuccess; ++r)
-                err = launch_blind_rotate_jobs(P.d_jobs, B, P.d_part, C->luts, C->bsk, C->tables, c.grid, lf, st);
+                err = launch_blind_rotate_jobs(P.d_jobs, B, P.d_part, C->luts, C->bsk, C->tables, c.grid, lf, waves,
+                                               st);
             if (err == hipSuccess) err = hipEventRecord(e1, st);
             if (err == hipSuccess) err = hipEventSynchronize(e1);
             float ms = 0;
@@ -140,14 +147,22 @@ int lvs_autotune(lvs_context* ctx, size_t max_batch, void* d_work, size_t work_b
             if (r.batch == B && r.form == form && r.grid == grid) return r.ms;
         return -1.0;
     };
-    // the latency form while it is at least as fast, in increasing batch
-    // order; if it is at every size tried, it takes every size
+    // the one-per-CU form with the smaller total time over the batches tried,
+    // then that form while it is at least as fast as the two-per-CU form, in
+    // increasing batch order; if it is at every size tried, it takes every size
     lvs_tuning t{};
-    t.latency_form_max = 0;
     const std::vector<int> tried_b = tune_batches(cus, max_batch);
+    double t8 = 0, t16 = 0;
+    for (int B : tried_b) {
+        t8 += time_of(B, 1, B);
+        t16 += time_of(B, 3, B);
+    }
+    const int lat = t16 < t8 ? 3 : 1;
+    t.latency_waves = lat == 3 ? 16 : 8;
+    t.latency_form_max = 0;
     for (size_t k = 0; k < tried_b.size(); ++k) {
         const int B = tried_b[k];
-        if (time_of(B, 1, B) > time_of(B, 2, B)) break;
+        if (time_of(B, lat, B) > time_of(B, 2, B)) break;
         t.latency_form_max = (k + 1 == tried_b.size()) ? INT_MAX : B;
     }
     // a persistent grid only if it wins by more than 1% at every batch that tried it
@@ -160,6 +175,7 @@ int lvs_autotune(lvs_context* ctx, size_t max_batch, void* d_work, size_t work_b
     t.br_grid = (tried && wins) ? 2 * cus : 0;
     C->br_grid = t.br_grid;
     C->latency_form_max = t.latency_form_max;
+    C->latency_waves = t.latency_waves;
     if (best) *best = t;
     if (n_samples) *n_samples = res.size();
     for (size_t k = 0; k < res.size() && samples && k < max_samples; ++k)

@@ -680,7 +680,7 @@ def lvs_server_stats(srv: Server):
 # ------------------------------------------------------------------ tuning
 
 class lvs_tuning(ctypes.Structure):
-    _fields_ = [("br_grid", ctypes.c_int32), ("latency_form_max", ctypes.c_int32)]
+    _fields_ = [("br_grid", ctypes.c_int32), ("latency_form_max", ctypes.c_int32), ("latency_waves", ctypes.c_int32)]
 
 
 class lvs_tune_sample(ctypes.Structure):
@@ -691,11 +691,11 @@ class lvs_tune_sample(ctypes.Structure):
 def lvs_context_get_tuning(ctx: Context) -> dict:
     t = lvs_tuning()
     _check(lib().lvs_context_get_tuning(ctx, ctypes.byref(t)))
-    return {"br_grid": t.br_grid, "latency_form_max": t.latency_form_max}
+    return {"br_grid": t.br_grid, "latency_form_max": t.latency_form_max, "latency_waves": t.latency_waves}
 
 
 def lvs_context_set_tuning(ctx: Context, tuning: dict):
-    t = lvs_tuning(int(tuning["br_grid"]), int(tuning["latency_form_max"]))
+    t = lvs_tuning(int(tuning["br_grid"]), int(tuning["latency_form_max"]), int(tuning.get("latency_waves", 8)))
     _check(lib().lvs_context_set_tuning(ctx, ctypes.byref(t)))
 
 
@@ -713,7 +713,8 @@ def lvs_autotune(ctx: Context, max_batch: int, d_work=None):
     _check(lib().lvs_autotune(ctx, max_batch, _dptr(d_work), d_work.numel() * d_work.element_size(),
                               ctypes.byref(best), samples, 64, ctypes.byref(n)))
     rows = [{"batch": x.batch, "form": x.form, "grid": x.grid, "ms": round(x.ms, 4)} for x in samples[:n.value]]
-    return {"br_grid": best.br_grid, "latency_form_max": best.latency_form_max}, rows
+    return {"br_grid": best.br_grid, "latency_form_max": best.latency_form_max,
+            "latency_waves": best.latency_waves}, rows
 
 
 def _tuning_key(ctx: Context) -> str:
@@ -765,6 +766,7 @@ KERNEL_KEYSWITCH = 1
 KERNEL_GRAPH = 2
 KERNEL_BLIND_ROTATE_LATENCY = 3      # eight-wave form, one workgroup per CU
 KERNEL_BLIND_ROTATE_THROUGHPUT = 4   # four-wave form, two workgroups per CU
+KERNEL_BLIND_ROTATE_W16 = 5          # sixteen-wave form, one workgroup per CU
 
 
 def lvs_microbench_modmul(ctx: Context, iters: int = 4096):

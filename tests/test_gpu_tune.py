@@ -13,10 +13,12 @@ from oracle import tfhe as T
 pytestmark = pytest.mark.gpu
 
 SHAPES = [
-    {"br_grid": 0, "latency_form_max": 1 << 30},   # eight-wave form, one workgroup per bootstrap
-    {"br_grid": 0, "latency_form_max": 0},         # four-wave form, two per CU
-    {"br_grid": 7, "latency_form_max": 0},         # persistent four-wave form, 7 workgroups loop
-    {"br_grid": 5, "latency_form_max": 1 << 30},   # persistent eight-wave form
+    {"br_grid": 0, "latency_form_max": 1 << 30, "latency_waves": 8},   # eight-wave form, one workgroup per bootstrap
+    {"br_grid": 0, "latency_form_max": 0, "latency_waves": 8},         # four-wave form, two per CU
+    {"br_grid": 7, "latency_form_max": 0, "latency_waves": 8},         # persistent four-wave form, 7 workgroups loop
+    {"br_grid": 5, "latency_form_max": 1 << 30, "latency_waves": 8},   # persistent eight-wave form
+    {"br_grid": 0, "latency_form_max": 1 << 30, "latency_waves": 16},   # sixteen-wave form
+    {"br_grid": 3, "latency_form_max": 1 << 30, "latency_waves": 16},   # persistent sixteen-wave form
 ]
 
 
@@ -51,10 +53,47 @@ def test_every_shape_bit_identical(gpu, okeys):
         assert_same_ct(outs[0][b], ref[b], f"b={b}")
 
 
+def test_sixteen_wave_form_bit_exact(gpu, okeys):
+    """The sixteen-wave form on all 32 inputs of Table table_lutrelu and on an
+    ASCII edit distance: every ciphertext bit-exact with the oracle."""
+    from oracle import leuvenshtein as OL
+    g = gpu
+    L, torch = g.L, g.torch
+    saved = L.lvs_context_get_tuning(g.ctx)
+    try:
+        L.lvs_context_set_tuning(g.ctx, {"br_grid": 0, "latency_form_max": 1 << 30, "latency_waves": 16})
+        say("sixteen-wave: table1 exhaustive")
+        L.lvs_context_set_lut(g.ctx, L.LVS_LUT_USER, P.LUT_X_MINUS_4)
+        cts = np.stack([L.lvs_lwe_encrypt(g.ck, x, 501, x) for x in range(32)])
+        out = run_pbs(g, cts, L.LVS_LUT_USER)
+        ref = okeys.pbs_batch(cts, T.test_polynomial(P.LUT_X_MINUS_4, 2048)[None, :], 0)
+        for x in range(32):
+            assert_same_ct(out[x], ref[x], f"x={x}")
+        say("sixteen-wave: kitten / sitting")
+        a, b = b"kitten", b"sitting"
+        A = L.lvs_encrypt_string(g.ck, a, L.LVS_ENC_ASCII7, 1001)
+        B = L.lvs_encrypt_string(g.ck, b, L.LVS_ENC_ASCII7, 1002)
+        d_h = torch.zeros(len(b) * L.CT_WORDS, dtype=torch.int64, device=g.dev)
+        L.lvs_edit_distance(g.ctx, L.to_device(A, g.dev), len(a), L.to_device(B, g.dev), len(b), L.LVS_ENC_ASCII7,
+                            d_h)
+        torch.cuda.synchronize()
+    finally:
+        L.lvs_context_set_tuning(g.ctx, saved)
+    h = L.to_host(d_h).reshape(len(b), L.CT_WORDS)
+    oh = OL.edit_distance(okeys, OL.encrypt_string(okeys, a, OL.ENC_ASCII7, 1001),
+                          OL.encrypt_string(okeys, b, OL.ENC_ASCII7, 1002), OL.ENC_ASCII7)
+    for j in range(len(b)):
+        assert_same_ct(h[j], oh[j], f"h[m,{j + 1}]")
+    assert L.lvs_decrypt_distance(g.ck, h, len(a)) == 3
+
+
 def test_set_tuning_rejects_negative(gpu):
     L = gpu.L
     with pytest.raises(L.LvsError) as e:
         L.lvs_context_set_tuning(gpu.ctx, {"br_grid": -1, "latency_form_max": 0})
+    assert e.value.code == -1
+    with pytest.raises(L.LvsError) as e:
+        L.lvs_context_set_tuning(gpu.ctx, {"br_grid": 0, "latency_form_max": 0, "latency_waves": 12})
     assert e.value.code == -1
 
 
