@@ -343,7 +343,7 @@ __device__ __forceinline__ uint64_t job_word(const Job& J, int w) {
 // level with a carry (level t weight 2^(64-3t)); the top carry is dropped.
 __global__ void __launch_bounds__(256) keyswitch_jobs_kernel(const Job* __restrict__ jobs, int B,
                                                              const uint64_t* __restrict__ ksk,
-                                                             uint64_t* __restrict__ part, int chunk) {
+                                                             uint64_t* __restrict__ part, int chunk, int sub) {
     __shared__ uint64_t digits[kKsSub * kKsLevel];   // 8 signed bytes per row: one per tile ciphertext
     const int tid = threadIdx.x;
     const int b0 = blockIdx.x * kKsTile;
@@ -354,10 +354,10 @@ __global__ void __launch_bounds__(256) keyswitch_jobs_kernel(const Job* __restri
     for (int bb = 0; bb < kKsTile; ++bb)
 #pragma unroll
         for (int cs = 0; cs < kKsCols; ++cs) acc[bb][cs] = 0;
-    for (int j0 = split * chunk; j0 < (split + 1) * chunk; j0 += kKsSub) {
+    for (int j0 = split * chunk; j0 < (split + 1) * chunk; j0 += sub) {
         __syncthreads();
-        for (int idx = tid; idx < kKsTile * kKsSub; idx += 256) {
-            const int bb = idx / kKsSub, jj = idx % kKsSub;
+        for (int idx = tid; idx < kKsTile * sub; idx += 256) {
+            const int bb = idx / sub, jj = idx % sub;
             uint64_t c = 0;
             if (b0 + bb < B) c = job_word(jobs[b0 + bb], j0 + jj);
             uint64_t r = (((c >> 48) + 1) >> 1) & 0x7FFFu;     // round(c / 2^49) mod 2^15
@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(256) keyswitch_jobs_kernel(const Job* __restri
         }
         __syncthreads();
         const uint64_t* rows = ksk + size_t(j0) * kKsLevel * kSmallWords;
-        for (int rr = 0; rr < kKsSub * kKsLevel; ++rr) {
+        for (int rr = 0; rr < sub * kKsLevel; ++rr) {
             const uint64_t dp = digits[rr];
             uint64_t k[kKsCols];
 #pragma unroll
@@ -1318,10 +1318,11 @@ hipError_t launch_fill_u64(uint64_t* p, size_t count, uint64_t v, hipStream_t st
 }
 
 int keyswitch_splits(int B) {
-    // enough workgroups to fill the chip: tiles x splits >= 1024
+    // enough workgroups to fill the chip: tiles x splits >= 1024, at most 64
+    // splits of 32 input coefficients
     const int tiles = (B + dev::kKsTile - 1) / dev::kKsTile;
     int s = 1;
-    while (s < 16 && tiles * s < 1024) s *= 2;
+    while (s < 64 && tiles * s < 1024) s *= 2;
     return s;
 }
 
@@ -1340,7 +1341,9 @@ hipError_t launch_keyswitch_jobs(const Job* jobs, int B, const uint64_t* ksk, ui
     if (B <= 0) return hipSuccess;
     const int ns = keyswitch_splits(B);
     dim3 grid((B + dev::kKsTile - 1) / dev::kKsTile, ns);
-    hipLaunchKernelGGL(dev::keyswitch_jobs_kernel, grid, dim3(256), 0, st, jobs, B, ksk, part, kN / ns);
+    const int chunk = kN / ns;   // input coefficients per split, a power of two
+    hipLaunchKernelGGL(dev::keyswitch_jobs_kernel, grid, dim3(256), 0, st, jobs, B, ksk, part, chunk,
+                       std::min(chunk, dev::kKsSub));
     return hipGetLastError();
 }
 
