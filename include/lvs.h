@@ -424,6 +424,17 @@ int lvs_plan_workspace_bytes(const lvs_query* queries, size_t nq, int encoding, 
 int lvs_plan_create(lvs_context* ctx, const lvs_query* queries, size_t nq, int encoding, int flags, void* d_work,
                     size_t work_bytes, lvs_plan** out);
 
+/* Batch plan over wide symbols (Section 4.2): every query has both strings
+ * encrypted by lvs_encrypt_symbols with the same width (d_a [m][c][N+1],
+ * d_b [n][c][N+1]; d_table must be NULL).  The plan's first steps run the
+ * hybrid equality of every pair of every query (one step of chunk
+ * bootstraps, then the merging levels), then the main loop of every query as
+ * in lvs_plan_create (full or banded; the context's refresh interval).  Run
+ * and free it like any plan. */
+int lvs_plan_wide_workspace_bytes(const lvs_query* queries, size_t nq, unsigned width, size_t* bytes);
+int lvs_plan_create_wide(lvs_context* ctx, const lvs_query* queries, size_t nq, unsigned width, int flags,
+                         void* d_work, size_t work_bytes, lvs_plan** out);
+
 /* Host-side check of the schedule lvs_plan_create builds for these queries
  * (no device, nothing dereferenced: the query pointers only name buffers).
  * round: bootstraps the device runs at once (>= 1); with fill != 0 the

@@ -701,11 +701,6 @@ int lvs_edit_distance_clear_wide(lvs_context* ctx, const uint64_t* d_table, size
 // ------------------------------------------------------------ batch plans
 
 namespace {
-struct PlanHandle : Handle {
-    Context* C = nullptr;
-    Plan P;
-};
-
 // Queries of a plan; refresh is the interval the plan uses (the workspace
 // bound takes the shortest one).
 int make_specs(const lvs_query* q, size_t nq, int encoding, size_t refresh, std::vector<QuerySpec>& qs) {

@@ -87,6 +87,12 @@ struct Plan {
     size_t pbs() const { return jobs.size(); }
 };
 
+// A plan handle of the C ABI (lvs_plan): the context it runs on and the plan.
+struct PlanHandle : Handle {
+    Context* C = nullptr;
+    Plan P;
+};
+
 // Bytes of per-query workspace (V, eq1, eq9) and of a plan's jobs/partials.
 size_t query_buffer_bytes(const QuerySpec& q);
 size_t plan_bytes(size_t njobs, size_t max_step);

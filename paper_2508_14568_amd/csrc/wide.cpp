@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -88,6 +89,67 @@ QuerySpec eq9_query(const uint64_t* eq9, size_t m, size_t n, uint64_t* h_last, s
 }
 
 size_t dp_max_step(size_t m, size_t n) { return 2 * std::min(m, n); }   // a refresh step: two per cell
+
+// Pairs of several queries: query k's pairs are p = first[k] + i n_k + j.
+struct MultiSrc {
+    std::vector<size_t> first;     // first pair of every query, then the total
+    std::vector<const uint64_t*> A, B;
+    std::vector<size_t> n;
+    size_t c;
+};
+WideChunkInput multi_chunk(const void* ctx, size_t p, size_t k) {
+    const auto* s = static_cast<const MultiSrc*>(ctx);
+    const size_t q = size_t(std::upper_bound(s->first.begin(), s->first.end(), p) - s->first.begin()) - 1;
+    const size_t local = p - s->first[q];
+    const size_t i = local / s->n[q], j = local % s->n[q];
+    return {s->A[q] + (i * s->c + k) * W, s->B[q] + (j * s->c + k) * W, 0};
+}
+
+// The queries of a wide plan; refresh is the interval the plan uses.
+int wide_specs(const lvs_query* x, size_t nq, size_t refresh, std::vector<QuerySpec>& qs, MultiSrc& src,
+               size_t c) {
+    qs.assign(nq, QuerySpec());
+    src.first.assign(1, 0);
+    src.A.clear();
+    src.B.clear();
+    src.n.clear();
+    src.c = c;
+    for (size_t k = 0; k < nq; ++k) {
+        const lvs_query& y = x[k];
+        if (std::max(y.m, y.n) > size_t(LVS_MAX_LEN)) WIDE_FAIL(LVS_E_INVAL, "lvs_plan_wide: string longer than LVS_MAX_LEN");
+        if (y.d_table || (!y.d_a && y.m) || (!y.d_b && y.n))
+            WIDE_FAIL(LVS_E_INVAL, "lvs_plan_wide: every query needs both strings encrypted");
+        QuerySpec& s = qs[k];
+        s.m = y.m;
+        s.n = y.n;
+        s.refresh = refresh;
+        s.eq9_in = reinterpret_cast<const uint64_t*>(16);   // set once the workspace is carved
+        if (y.banded) {
+            s.band = long(std::min<size_t>(y.ell, y.m + y.n));
+            s.path = y.d_path;
+            if (!y.d_path && y.m + y.n) WIDE_FAIL(LVS_E_INVAL, "lvs_plan_wide: NULL band path");
+        } else {
+            s.h_last = y.d_h_last;
+            if (!y.d_h_last && y.n) WIDE_FAIL(LVS_E_INVAL, "lvs_plan_wide: NULL result buffer");
+        }
+        src.A.push_back(y.d_a);
+        src.B.push_back(y.d_b);
+        src.n.push_back(std::max<size_t>(y.n, 1));
+        src.first.push_back(src.first.back() + y.m * y.n);
+    }
+    return LVS_OK;
+}
+
+size_t wide_plan_bytes(const std::vector<QuerySpec>& qs, size_t pairs, size_t c) {
+    size_t b = align256(sizeof(uint64_t) * std::max<size_t>(pairs, 1) * W) + wide_buffer_bytes(pairs, c);
+    size_t jobs = wide_jobs(pairs, c), step = wide_max_step(pairs, c), dp_step = 0;
+    for (const auto& q : qs) {
+        b += query_buffer_bytes(q);
+        jobs += query_jobs(q);
+        dp_step += dp_max_step(q.m, q.n);
+    }
+    return b + plan_bytes(jobs, std::max(step, dp_step));
+}
 
 }  // namespace
 
@@ -174,6 +236,56 @@ int lvs_edit_distance_wide(lvs_context* ctx, const uint64_t* d_a, size_t m, cons
     assign_buffers(qs, ws);
     build_edit_distance_plan(qs, P);
     return run(C, P, ws);
+}
+
+int lvs_plan_wide_workspace_bytes(const lvs_query* queries, size_t nq, unsigned width, size_t* bytes) {
+    const size_t c = chunks_of(width);
+    if (!bytes || (!queries && nq) || !c) WIDE_FAIL(LVS_E_INVAL, "lvs_plan_wide_workspace_bytes: bad argument");
+    std::vector<QuerySpec> qs;
+    MultiSrc src;
+    const int rc = wide_specs(queries, nq, LVS_REFRESH_MIN, qs, src, c);
+    if (rc) return rc;
+    *bytes = wide_plan_bytes(qs, src.first.back(), c);
+    return LVS_OK;
+}
+
+int lvs_plan_create_wide(lvs_context* ctx, const lvs_query* queries, size_t nq, unsigned width, int flags,
+                         void* d_work, size_t work_bytes, lvs_plan** out) {
+    Context* C = ctx_of(ctx);
+    const size_t c = chunks_of(width);
+    if (!C || !out || (!queries && nq) || !c) WIDE_FAIL(LVS_E_INVAL, "lvs_plan_create_wide: bad argument");
+    std::vector<QuerySpec> qs;
+    MultiSrc src;
+    int rc = wide_specs(queries, nq, C->refresh_every, qs, src, c);
+    if (rc) return rc;
+    for (const auto& q : qs)
+        if (C->refresh_every == 0 && std::min(q.m, q.n) > size_t(LVS_MAX_DEPTH_NO_REFRESH))
+            WIDE_FAIL(LVS_E_NOISE_BUDGET, "lvs_plan_create_wide: min(m, n) exceeds the noise budget with refresh off");
+    const size_t pairs = src.first.back();
+    if (!d_work || work_bytes < wide_plan_bytes(qs, pairs, c))
+        WIDE_FAIL(LVS_E_NOMEM_DEVICE, "lvs_plan_create_wide: workspace too small");
+    if (reinterpret_cast<uintptr_t>(d_work) % 256) WIDE_FAIL(LVS_E_INVAL, "lvs_plan_create_wide: misaligned workspace");
+    WIDE_HIP(hipSetDevice(C->device));
+    auto* H = new (std::nothrow) PlanHandle();
+    if (!H) WIDE_FAIL(LVS_E_NOMEM_HOST, "lvs_plan_create_wide: out of host memory");
+    H->kind = kPlan;
+    H->C = C;
+    uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
+    uint64_t* eq9 = reinterpret_cast<uint64_t*>(ws);
+    ws += align256(sizeof(uint64_t) * std::max<size_t>(pairs, 1) * W);
+    for (size_t k = 0; k < qs.size(); ++k) qs[k].eq9_in = eq9 + src.first[k] * W;
+    if (pairs) build_wide_equality(H->P, pairs, c, multi_chunk, &src, eq9, ws);
+    assign_buffers(qs, ws);
+    build_edit_distance_plan(qs, H->P);
+    hipError_t e = upload_plan(H->P, ws, C->stream);
+    if (e == hipSuccess && (flags & LVS_PLAN_GRAPH)) e = capture_plan(C, H->P);
+    if (e != hipSuccess) {
+        if (H->P.graph) (void)hipGraphExecDestroy(H->P.graph);
+        delete H;
+        WIDE_FAIL(LVS_E_DEVICE, std::string("lvs_plan_create_wide: ") + hipGetErrorString(e));
+    }
+    *out = reinterpret_cast<lvs_plan*>(H);
+    return LVS_OK;
 }
 
 size_t lvs_preprocess_wide_workspace_bytes(size_t m, size_t alen, unsigned width) {

@@ -91,6 +91,8 @@ _SIGS = {
     "lvs_preprocess_wide_workspace_bytes": (SZ, [SZ, SZ, ctypes.c_uint]),
     "lvs_preprocess_wide": (I32, [VP, VP, SZ, ctypes.c_uint, VP, SZ, VP, VP, SZ]),
     "lvs_edit_distance_clear_wide": (I32, [VP, VP, SZ, VP, SZ, VP, SZ, VP, VP, SZ]),
+    "lvs_plan_wide_workspace_bytes": (I32, [VP, SZ, ctypes.c_uint, ctypes.POINTER(SZ)]),
+    "lvs_plan_create_wide": (I32, [VP, VP, SZ, ctypes.c_uint, I32, VP, SZ, ctypes.POINTER(VP)]),
     "lvs_context_get_refresh": (I32, [VP, ctypes.POINTER(SZ)]),
     "lvs_plan_run": (I32, [VP]),
     "lvs_plan_info": (I32, [VP, ctypes.POINTER(SZ), ctypes.POINTER(SZ), ctypes.POINTER(SZ)]),
@@ -558,6 +560,26 @@ def lvs_plan_create(ctx: Context, items, encoding: int, graph: bool = False, d_w
     out = VP()
     _check(lib().lvs_plan_create(ctx, arr, len(items), encoding, LVS_PLAN_GRAPH if graph else 0, _dptr(d_work),
                                  d_work.numel() * d_work.element_size(), ctypes.byref(out)))
+    return Plan(out, (arr, keep, d_work, items))
+
+
+def lvs_plan_wide_workspace_bytes(items, width: int) -> int:
+    arr, keep = make_queries(items)
+    n = SZ()
+    _check(lib().lvs_plan_wide_workspace_bytes(arr, len(items), width, ctypes.byref(n)))
+    return n.value
+
+
+def lvs_plan_create_wide(ctx: Context, items, width: int, graph: bool = False, d_work=None) -> Plan:
+    """Batch plan over wide symbols: items as for lvs_plan_create, both strings
+    encrypted by lvs_encrypt_symbols with this width."""
+    arr, keep = make_queries(items)
+    need = lvs_plan_wide_workspace_bytes(items, width)
+    if d_work is None:
+        d_work = device_buffer(need, ctx.device)
+    out = VP()
+    _check(lib().lvs_plan_create_wide(ctx, arr, len(items), width, LVS_PLAN_GRAPH if graph else 0, _dptr(d_work),
+                                      d_work.numel() * d_work.element_size(), ctypes.byref(out)))
     return Plan(out, (arr, keep, d_work, items))
 
 

@@ -132,3 +132,44 @@ def test_wide_larger_pair_distance(gpu):
     with pytest.raises(L.LvsError) as e:
         L.lvs_edit_distance_wide(g.ctx, A, len(a), B, len(b), 65, d_h)
     assert e.value.code == -1
+
+
+def test_wide_batch_plan_equals_alone(gpu):
+    """A graph-captured plan over 21-bit symbols mixing lengths, an empty
+    string and a banded query: every result equals its lone run (the banded
+    one the plaintext banded loop), replayed twice."""
+    say("wide batch plan")
+    g = gpu
+    L, torch = g.L, g.torch
+    rng = np.random.default_rng(33)
+    alphabet = [int(v) for v in rng.integers(0, 2 ** 21, size=5)]
+    lens = [(5, 7), (9, 4), (0, 3), (6, 6), (3, 8)]
+    pairs = [([alphabet[int(t)] for t in rng.integers(0, 5, size=m)], [alphabet[int(t)] for t in rng.integers(0, 5, size=n)])
+             for m, n in lens]
+    items, cts = [], []
+    for k, (a, b) in enumerate(pairs):
+        A = L.lvs_encrypt_symbols(g.ck, a, 21, 950 + 2 * k)
+        B = L.lvs_encrypt_symbols(g.ck, b, 21, 951 + 2 * k)
+        cts.append((A, B))
+        it = {"d_a": L.to_device(A, g.dev) if a else None, "m": len(a), "d_b": L.to_device(B, g.dev), "n": len(b)}
+        if k == 3:
+            it["ell"] = 1
+            it["d_path"] = torch.zeros((len(a) + len(b)) * L.CT_WORDS, dtype=torch.int64, device=g.dev)
+        else:
+            it["d_h_last"] = torch.zeros(len(b) * L.CT_WORDS, dtype=torch.int64, device=g.dev)
+        items.append(it)
+    plan = L.lvs_plan_create_wide(g.ctx, items, 21, graph=True)
+    for rep in range(2):
+        L.lvs_plan_run(plan)
+        torch.cuda.synchronize()
+        for k, ((a, b), (A, B), it) in enumerate(zip(pairs, cts, items)):
+            if k == 3:
+                path = L.to_host(it["d_path"]).reshape(-1, L.CT_WORDS)
+                assert L.lvs_decrypt_distance(g.ck, path, 0) == P.band_distance(a, b, 1), (rep, k)
+                continue
+            h = L.to_host(it["d_h_last"]).reshape(len(b), L.CT_WORDS)
+            d_ref = torch.zeros_like(it["d_h_last"])
+            L.lvs_edit_distance_wide(g.ctx, it["d_a"], len(a), it["d_b"], len(b), 21, d_ref)
+            torch.cuda.synchronize()
+            assert (h == L.to_host(d_ref).reshape(len(b), L.CT_WORDS)).all(), (rep, k)
+            assert L.lvs_decrypt_distance(g.ck, h, len(a)) == P.edit_distance(a, b), (rep, k)
