@@ -32,6 +32,13 @@ INT_MUL_PER_PBS = 3 * MODMUL_PER_PBS
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit multiply per lane per cycle
 # (v_mul_lo_u32 / v_mul_hi_u32 issue at the full VALU rate on gfx950).
 VALU_INT_MUL_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Algorithmic HBM bytes of one blind-rotation launch: the NTT-domain
+# bootstrapping key once (742 GGSW x 4 primes x 2 rows x 2 polynomials x 2048
+# u32 residues), shared by every bootstrap of the launch, plus per bootstrap
+# its key-switched input (743 u64) and its extracted output (2049 u64).
+BSK_BYTES = 742 * 4 * 2 * 2 * 2048 * 4
+IO_BYTES_PER_PBS = (743 + 2049) * 8
+HBM_PEAK_GBS = 8000.0
 
 
 def note(msg):
@@ -56,6 +63,15 @@ def traffic_per_launch(kernel, avg_pbs_per_launch):
     if t.get("kernels_hip_sha256") != kernel_source_digest() or kernel not in t.get("bytes_per_pbs", {}):
         return None
     return round(t["bytes_per_pbs"][kernel] * avg_pbs_per_launch)
+
+
+def hbm_roofline(pbs_per_launch, launch_ms):
+    """The same launches against the HBM peak: algorithmic bytes (key once
+    per launch, inputs and outputs per bootstrap) over the launch time."""
+    nbytes = BSK_BYTES + IO_BYTES_PER_PBS * pbs_per_launch
+    gbs = nbytes / (launch_ms / 1e3) / 1e9
+    return {"achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
+            "bytes_per_launch": round(nbytes)}
 
 
 def cpu_baseline(workload_cts, seconds_hint=20.0):
@@ -536,6 +552,7 @@ def main():
                f"{INT_MUL_PER_PBS} per bootstrap",
         "avg_launch_ms": round(avg_launch_ms, 4), "launches": k_launches,
         "avg_pbs_per_launch": round(avg_pbs_launch, 2),
+        "hbm": hbm_roofline(avg_pbs_launch, avg_launch_ms),
         "other_form": {k: {"ms_per_step": round(v[0] / args.steps, 3), "launches": v[1], "pbs": v[2]}
                        for k, v in forms.items() if k != kname},
         "keyswitch_ms_per_step": round(ks_ms / args.steps, 3),
