@@ -482,8 +482,27 @@ int lvs_server_create(lvs_context* ctx, const uint8_t* names, const size_t* name
                       const uint8_t* alphabet, size_t alen, size_t max_step, void* d_arena, size_t arena_bytes,
                       lvs_server** out);
 
-/* Queues a request: h_query is the encrypted ASCII query ([m][2][N+1], host,
- * copied, 1 <= m <= 4096).  Requests are admitted in arrival order at the
+/* The same engine over wide symbols (Section 4.2): names and alphabet are
+ * symbols of `width` bits (1..64) as uint64_t, and each request's
+ * preprocessing is the table of lvs_preprocess_wide (the chunk
+ * sub-equalities, then one bootstrap round per merging level, each level's
+ * group sums run by the engine just before its round).  Queries are
+ * lvs_encrypt_symbols output of the same width.  Everything else (arena,
+ * admission, the main pass, results) is as for lvs_server_create.
+ * LVS_E_ALPHABET for an alphabet symbol wider than width bits or a name
+ * symbol outside the alphabet; LVS_E_INVAL for a bad width. */
+int lvs_server_create_wide(lvs_context* ctx, const uint64_t* names, const size_t* name_lens, size_t n_names,
+                           const uint64_t* alphabet, size_t alen, unsigned width, size_t max_step, void* d_arena,
+                           size_t arena_bytes, lvs_server** out);
+
+/* Pool bytes of one request of length m on a wide server: its chunk
+ * ciphertexts, the merging levels' buffers, the table, one DP frontier per
+ * name and the result rows.  0 for a bad width. */
+size_t lvs_server_request_bytes_wide(const size_t* name_lens, size_t n_names, size_t alen, size_t m,
+                                     unsigned width);
+
+/* Queues a request: h_query is the encrypted query (ASCII: [m][2][N+1]; a
+ * wide server: [m][ceil(width / 4)][N+1]; host, copied, 1 <= m <= 4096).  Requests are admitted in arrival order at the
  * next step that has room.  LVS_E_NOMEM_DEVICE if it could never fit;
  * LVS_E_NOISE_BUDGET with refresh off and min(m, longest name) above
  * LVS_MAX_DEPTH_NO_REFRESH. */

@@ -4,7 +4,9 @@
 // name).
 //
 // Each request goes through three phases: the preprocessing table's two
-// bootstrap rounds (eq1, then eq9 = T[c][i]), then the anti-diagonals
+// bootstrap rounds (eq1, then eq9 = T[c][i]; over wide symbols, Section
+// 4.2, the chunk sub-equalities and one round per merging level, each level's
+// group sums run just before its round), then the anti-diagonals
 // s = 2 .. m + max(n_k) of one DP instance per name, all instances of the
 // request advancing together, with a refresh round (Section 3.1) after every
 // refresh-th diagonal.  An engine step gathers the ready bootstraps of
@@ -79,7 +81,7 @@ private:
     size_t total_ = 0;
 };
 
-enum Phase { kQueued, kPre1, kPre2, kDp, kDone };
+enum Phase { kQueued, kPre1, kPre2, kPreWide, kDp, kDone };
 
 struct Request {
     uint64_t ticket = 0;
@@ -94,7 +96,33 @@ struct Request {
     uint64_t* T = nullptr;               // [alen][m][W]
     uint64_t* V = nullptr;               // [names][m+1][W]
     uint64_t* H = nullptr;               // [sum n_k][W] results
+    // wide symbols: the table's equality plan (jobs point into the block) and
+    // the next of its steps to run
+    Plan pre;
+    size_t pre_step = 0;
 };
+
+// Pool bytes of one request: the query, the preprocessing buffers (ASCII: the
+// eq1 table; wide: the merging levels), the table T, one DP frontier per name
+// and the result rows.
+size_t request_block_bytes(size_t m, size_t alen, size_t c, size_t n_names, size_t total_len) {
+    const size_t qsyms = c ? c : 2;
+    const size_t pre = c ? wide_buffer_bytes(alen * m, c) : align256(sizeof(uint64_t) * alen * m * W);
+    return align256(sizeof(uint64_t) * m * qsyms * W) + pre + align256(sizeof(uint64_t) * alen * m * W) +
+           align256(sizeof(uint64_t) * n_names * (m + 1) * W) + align256(sizeof(uint64_t) * total_len * W);
+}
+
+// Table entry p = sym * m + i of a wide request against the alphabet.
+struct WideTableSrc {
+    const uint64_t* A;
+    const uint64_t* alphabet;
+    size_t m, c;
+};
+WideChunkInput wide_table_chunk(const void* ctx, size_t p, size_t k) {
+    const auto* s = static_cast<const WideTableSrc*>(ctx);
+    const size_t sym = p / s->m, i = p % s->m;
+    return {s->A + (i * s->c + k) * W, nullptr, uint32_t((s->alphabet[sym] >> (4 * k)) & 15u)};
+}
 
 }  // namespace
 
@@ -109,6 +137,9 @@ struct Server : Handle {
     size_t total_len = 0, max_len = 0;
     size_t refresh = 0;                        // noise-refresh interval (anti-diagonals, 0: off)
     std::vector<uint8_t> sym_lo, sym_hi;       // alphabet symbols (4-bit, 3-bit)
+    size_t alen = 0;
+    size_t c = 0;                              // chunks of a wide symbol (0: ASCII)
+    std::vector<uint64_t> alpha_wide;          // wide alphabet
     // device regions
     Job* d_jobs = nullptr;
     uint64_t* d_part = nullptr;
@@ -122,48 +153,67 @@ struct Server : Handle {
     std::vector<Job> jobs;
     uint64_t steps = 0, bootstraps = 0;
 
-    size_t request_bytes(size_t m) const {
-        const size_t alen = sym_lo.size();
-        return align256(sizeof(uint64_t) * m * 2 * W) + 2 * align256(sizeof(uint64_t) * alen * m * W) +
-               align256(sizeof(uint64_t) * name_len.size() * (m + 1) * W) +
-               align256(sizeof(uint64_t) * total_len * W);
-    }
+    size_t query_syms() const { return c ? c : 2; }
+
+    size_t request_bytes(size_t m) const { return request_block_bytes(m, alen, c, name_len.size(), total_len); }
 
     void carve(Request* r) {
         uint8_t* p = pool_base + r->off;
-        const size_t alen = sym_lo.size(), m = r->m;
+        const size_t m = r->m;
         r->A = reinterpret_cast<uint64_t*>(p);
-        p += align256(sizeof(uint64_t) * m * 2 * W);
-        r->eq1 = reinterpret_cast<uint64_t*>(p);
-        p += align256(sizeof(uint64_t) * alen * m * W);
-        r->T = reinterpret_cast<uint64_t*>(p);
+        p += align256(sizeof(uint64_t) * m * query_syms() * W);
+        if (c) {
+            // the merging levels, then T, which the plan's last round writes
+            uint8_t* levels = p;
+            p += wide_buffer_bytes(alen * m, c);
+            r->T = reinterpret_cast<uint64_t*>(p);
+            const WideTableSrc src{r->A, alpha_wide.data(), m, c};
+            r->pre = Plan();
+            r->pre_step = 0;
+            build_wide_equality(r->pre, alen * m, c, wide_table_chunk, &src, r->T, levels);
+        } else {
+            r->eq1 = reinterpret_cast<uint64_t*>(p);
+            p += align256(sizeof(uint64_t) * alen * m * W);
+            r->T = reinterpret_cast<uint64_t*>(p);
+        }
         p += align256(sizeof(uint64_t) * alen * m * W);
         r->V = reinterpret_cast<uint64_t*>(p);
         p += align256(sizeof(uint64_t) * name_len.size() * (m + 1) * W);
         r->H = reinterpret_cast<uint64_t*>(p);
     }
 
-    // Jobs of one request's current phase.
-    void gather(Request* r, std::vector<Job>& out) const {
-        const size_t alen = sym_lo.size(), m = r->m;
+    // Jobs of one request's current phase; *sum receives the group sums
+    // that must run before them (wide merging levels), if any.
+    void gather(Request* r, std::vector<Job>& out, const SumOp** sum) const {
+        const size_t m = r->m;
+        *sum = nullptr;
+        if (r->phase == kPreWide) {
+            const PlanStep* st = &r->pre.steps[r->pre_step];
+            if (st->sum >= 0) {
+                *sum = &r->pre.sums[size_t(st->sum)];
+                st = &r->pre.steps[r->pre_step + 1];
+            }
+            out.insert(out.end(), r->pre.jobs.begin() + long(st->off), r->pre.jobs.begin() + long(st->off + st->count));
+            return;
+        }
         if (r->phase == kPre1 || r->phase == kPre2) {
-            for (size_t c = 0; c < alen; ++c)
+            for (size_t a = 0; a < alen; ++a)
                 for (size_t i = 0; i < m; ++i) {
                     Job J{};
                     if (r->phase == kPre1) {     // z1 = x1 - c1, eq1 = PBS(z1; LUT_eq)
                         J.src[0] = r->A + (i * 2) * W;
                         J.coef[0] = 1;
-                        J.delta = uint64_t(0) - uint64_t(sym_lo[c]) * kOne;
+                        J.delta = uint64_t(0) - uint64_t(sym_lo[a]) * kOne;
                         J.lut = LVS_LUT_EQ;
-                        J.dst[0] = r->eq1 + (c * m + i) * W;
+                        J.dst[0] = r->eq1 + (a * m + i) * W;
                     } else {                     // z2 = 2 (x2 - c2) + 1 - eq1, T = PBS(z2; LUT_eq9)
                         J.src[0] = r->A + (i * 2 + 1) * W;
-                        J.src[1] = r->eq1 + (c * m + i) * W;
+                        J.src[1] = r->eq1 + (a * m + i) * W;
                         J.coef[0] = 2;
                         J.coef[1] = -1;
-                        J.delta = kOne - 2 * uint64_t(sym_hi[c]) * kOne;
+                        J.delta = kOne - 2 * uint64_t(sym_hi[a]) * kOne;
                         J.lut = LVS_LUT_EQ9;
-                        J.dst[0] = r->T + (c * m + i) * W;
+                        J.dst[0] = r->T + (a * m + i) * W;
                     }
                     out.push_back(J);
                 }
@@ -218,7 +268,14 @@ struct Server : Handle {
     }
 
     void advance(Request* r) const {
-        if (r->phase == kPre1) r->phase = kPre2;
+        if (r->phase == kPreWide) {
+            r->pre_step += (r->pre.steps[r->pre_step].sum >= 0) ? 2 : 1;
+            if (r->pre_step >= r->pre.steps.size()) {
+                r->pre = Plan();
+                r->phase = kDp;
+                r->s = 2;
+            }
+        } else if (r->phase == kPre1) r->phase = kPre2;
         else if (r->phase == kPre2) { r->phase = kDp; r->s = 2; }
         else if (r->phase == kDp) {
             // a refresh round follows diagonal s when some name still has cells past it
@@ -271,42 +328,61 @@ size_t lvs_server_request_bytes(const uint8_t* names, const size_t* name_lens, s
     (void)names;
     size_t total = 0;
     for (size_t k = 0; k < n_names; ++k) total += name_lens[k];
-    return align256(sizeof(uint64_t) * m * 2 * W) + 2 * align256(sizeof(uint64_t) * alen * m * W) +
-           align256(sizeof(uint64_t) * n_names * (m + 1) * W) + align256(sizeof(uint64_t) * total * W);
+    return request_block_bytes(m, alen, 0, n_names, total);
 }
 
-int lvs_server_create(lvs_context* ctx, const uint8_t* names, const size_t* name_lens, size_t n_names,
-                      const uint8_t* alphabet, size_t alen, size_t max_step, void* d_arena, size_t arena_bytes,
-                      lvs_server** out) {
+size_t lvs_server_request_bytes_wide(const size_t* name_lens, size_t n_names, size_t alen, size_t m,
+                                     unsigned width) {
+    if (width < 1 || width > 64) return 0;
+    size_t total = 0;
+    for (size_t k = 0; k < n_names; ++k) total += name_lens[k];
+    return request_block_bytes(m, alen, (width + 3) / 4, n_names, total);
+}
+
+}  // extern "C"
+
+namespace {
+
+// The part of server creation shared by the ASCII and the wide form: checks,
+// arena layout and the name table (every name symbol's alphabet index).
+template <typename Sym>
+int create_server(lvs_context* ctx, const Sym* names, const size_t* name_lens, size_t n_names, const Sym* alphabet,
+                  size_t alen, size_t max_step, void* d_arena, size_t arena_bytes, size_t chunks, const char* fn,
+                  lvs_server** out) {
     auto* C = reinterpret_cast<Context*>(ctx);
     if (!C || C->kind != kContext || !out || (!names && n_names) || (!name_lens && n_names) || !alphabet || !alen)
-        SRV_FAIL(LVS_E_INVAL, "lvs_server_create: bad argument");
-    if (max_step == 0 || max_step > kMaxStep) SRV_FAIL(LVS_E_INVAL, "lvs_server_create: max_step out of range");
+        SRV_FAIL(LVS_E_INVAL, std::string(fn) + ": bad argument");
+    if (max_step == 0 || max_step > kMaxStep) SRV_FAIL(LVS_E_INVAL, std::string(fn) + ": max_step out of range");
     const size_t fixed = lvs_server_fixed_bytes(max_step);
     if (!d_arena || arena_bytes < fixed || reinterpret_cast<uintptr_t>(d_arena) % 256)
-        SRV_FAIL(LVS_E_NOMEM_DEVICE, "lvs_server_create: arena too small or misaligned");
+        SRV_FAIL(LVS_E_NOMEM_DEVICE, std::string(fn) + ": arena too small or misaligned");
     auto S = std::unique_ptr<Server>(new (std::nothrow) Server());
-    if (!S) SRV_FAIL(LVS_E_NOMEM_HOST, "lvs_server_create: out of host memory");
+    if (!S) SRV_FAIL(LVS_E_NOMEM_HOST, std::string(fn) + ": out of host memory");
     S->kind = kServer;
     S->C = C;
     S->arena = reinterpret_cast<uint8_t*>(d_arena);
     S->arena_bytes = arena_bytes;
     S->max_step = max_step;
     S->refresh = C->refresh_every;
-    for (size_t c = 0; c < alen; ++c) {
-        if (alphabet[c] >= 128) SRV_FAIL(LVS_E_ALPHABET, "lvs_server_create: alphabet symbol >= 128");
-        S->sym_lo.push_back(alphabet[c] & 15);
-        S->sym_hi.push_back(alphabet[c] >> 4);
+    S->alen = alen;
+    S->c = chunks;
+    if (chunks) {
+        S->alpha_wide.assign(alphabet, alphabet + alen);
+    } else {
+        for (size_t a = 0; a < alen; ++a) {
+            S->sym_lo.push_back(uint8_t(alphabet[a] & 15));
+            S->sym_hi.push_back(uint8_t(alphabet[a] >> 4));
+        }
     }
     size_t pos = 0;
     for (size_t k = 0; k < n_names; ++k) {
         const size_t n = name_lens[k];
-        if (n > 4096) SRV_FAIL(LVS_E_INVAL, "lvs_server_create: name longer than 4096");
+        if (n > 4096) SRV_FAIL(LVS_E_INVAL, std::string(fn) + ": name longer than 4096");
         S->name_len.push_back(n);
         S->name_start.push_back(S->total_len);
         for (size_t j = 0; j < n; ++j) {
-            const uint8_t* hit = std::find(alphabet, alphabet + alen, names[pos + j]);
-            if (hit == alphabet + alen) SRV_FAIL(LVS_E_ALPHABET, "lvs_server_create: name symbol not in the alphabet");
+            const Sym* hit = std::find(alphabet, alphabet + alen, names[pos + j]);
+            if (hit == alphabet + alen) SRV_FAIL(LVS_E_ALPHABET, std::string(fn) + ": name symbol not in the alphabet");
             S->cols.push_back(int32_t(hit - alphabet));
         }
         pos += n;
@@ -321,6 +397,30 @@ int lvs_server_create(lvs_context* ctx, const uint8_t* names, const size_t* name
     return LVS_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int lvs_server_create(lvs_context* ctx, const uint8_t* names, const size_t* name_lens, size_t n_names,
+                      const uint8_t* alphabet, size_t alen, size_t max_step, void* d_arena, size_t arena_bytes,
+                      lvs_server** out) {
+    for (size_t a = 0; alphabet && a < alen; ++a)
+        if (alphabet[a] >= 128) SRV_FAIL(LVS_E_ALPHABET, "lvs_server_create: alphabet symbol >= 128");
+    return create_server(ctx, names, name_lens, n_names, alphabet, alen, max_step, d_arena, arena_bytes, 0,
+                         "lvs_server_create", out);
+}
+
+int lvs_server_create_wide(lvs_context* ctx, const uint64_t* names, const size_t* name_lens, size_t n_names,
+                           const uint64_t* alphabet, size_t alen, unsigned width, size_t max_step, void* d_arena,
+                           size_t arena_bytes, lvs_server** out) {
+    if (width < 1 || width > 64) SRV_FAIL(LVS_E_INVAL, "lvs_server_create_wide: width must be 1..64");
+    for (size_t a = 0; alphabet && a < alen; ++a)
+        if (width < 64 && (alphabet[a] >> width))
+            SRV_FAIL(LVS_E_ALPHABET, "lvs_server_create_wide: alphabet symbol wider than width bits");
+    return create_server(ctx, names, name_lens, n_names, alphabet, alen, max_step, d_arena, arena_bytes,
+                         (width + 3) / 4, "lvs_server_create_wide", out);
+}
+
 int lvs_server_submit(lvs_server* srv, const uint64_t* h_query, size_t m, uint64_t* ticket) {
     Server* S = as_srv(srv);
     if (!S || !ticket || (!h_query && m)) SRV_FAIL(LVS_E_INVAL, "lvs_server_submit: bad argument");
@@ -333,7 +433,7 @@ int lvs_server_submit(lvs_server* srv, const uint64_t* h_query, size_t m, uint64
     if (!r) SRV_FAIL(LVS_E_NOMEM_HOST, "lvs_server_submit: out of host memory");
     r->ticket = S->next_ticket++;
     r->m = m;
-    r->host_query.assign(h_query, h_query + m * 2 * W);
+    r->host_query.assign(h_query, h_query + m * S->query_syms() * W);
     S->queue.push_back(r.get());
     *ticket = r->ticket;
     S->all[r->ticket] = std::move(r);
@@ -355,23 +455,29 @@ int lvs_server_step(lvs_server* srv, size_t* active, size_t* queued, size_t* ste
         S->carve(r);
         SRV_HIP(hipMemcpyAsync(r->A, r->host_query.data(), r->host_query.size() * 8, hipMemcpyHostToDevice,
                                C->stream));
-        r->phase = kPre1;
+        r->phase = S->c ? kPreWide : kPre1;
         S->queue.pop_front();
         S->active.push_back(r);
     }
     // gather every admitted request's ready bootstraps, within the step cap
     S->jobs.clear();
     std::vector<Request*> stepped;
+    std::vector<const SumOp*> sums;
     for (Request* r : S->active) {
         if (r->phase == kDone) continue;
         const size_t before = S->jobs.size();
-        S->gather(r, S->jobs);
+        const SumOp* sum = nullptr;
+        S->gather(r, S->jobs, &sum);
         if (S->jobs.size() > S->max_step && before > 0) {   // defer this request (and keep order)
             S->jobs.resize(before);
             break;
         }
         stepped.push_back(r);
+        if (sum) sums.push_back(sum);
     }
+    // the merging levels' group sums feed this step's bootstraps
+    for (const SumOp* o : sums)
+        SRV_HIP(launch_group_sum(o->in, o->out, o->items, o->cnt, o->groups, o->group, C->cus, C->stream));
     // a single request larger than the cap runs in several launches
     if (!S->jobs.empty()) {
         SRV_HIP(hipMemcpyAsync(S->d_jobs, S->jobs.data(), sizeof(Job) * std::min(S->jobs.size(), S->max_step),

@@ -99,6 +99,8 @@ _SIGS = {
     "lvs_server_fixed_bytes": (SZ, [SZ]),
     "lvs_server_request_bytes": (SZ, [VP, VP, SZ, SZ, SZ]),
     "lvs_server_create": (I32, [VP, VP, VP, SZ, VP, SZ, SZ, VP, SZ, ctypes.POINTER(VP)]),
+    "lvs_server_create_wide": (I32, [VP, VP, VP, SZ, VP, SZ, ctypes.c_uint, SZ, VP, SZ, ctypes.POINTER(VP)]),
+    "lvs_server_request_bytes_wide": (SZ, [VP, SZ, SZ, SZ, ctypes.c_uint]),
     "lvs_server_submit": (I32, [VP, VP, SZ, ctypes.POINTER(U64)]),
     "lvs_server_step": (I32, [VP, ctypes.POINTER(SZ), ctypes.POINTER(SZ), ctypes.POINTER(SZ)]),
     "lvs_server_poll": (I32, [VP, U64, VP, ctypes.POINTER(ctypes.c_int)]),
@@ -664,6 +666,31 @@ def lvs_server_create(ctx: Context, names, alphabet: bytes, arena_bytes: int, ma
     out = VP()
     _check(lib().lvs_server_create(ctx, buf, lens, len(names), ab, len(alphabet), max_step, _dptr(arena),
                                    arena.numel() * arena.element_size(), ctypes.byref(out)))
+    return Server(out, (buf, lens, ab, arena, ctx), sum(len(x) for x in names))
+
+
+def _wide_names_buf(names):
+    cat = [int(v) for x in names for v in x]
+    buf = _u64_array(cat or [0])
+    lens = (SZ * max(1, len(names)))(*[len(x) for x in names])
+    return buf, lens
+
+
+def lvs_server_request_bytes_wide(names, alen: int, m: int, width: int) -> int:
+    _, lens = _wide_names_buf(names)
+    return lib().lvs_server_request_bytes_wide(lens, len(names), alen, m, width)
+
+
+def lvs_server_create_wide(ctx: Context, names, alphabet, width: int, arena_bytes: int,
+                           max_step: int = 65536) -> Server:
+    """names: sequences of symbols below 2^width; alphabet: their symbols."""
+    buf, lens = _wide_names_buf(names)
+    ab = _u64_array(list(alphabet))
+    arena = device_buffer(arena_bytes, ctx.device)
+    out = VP()
+    _check(lib().lvs_server_create_wide(ctx, _np_ptr(buf), lens, len(names), _np_ptr(ab), len(alphabet), width,
+                                        max_step, _dptr(arena), arena.numel() * arena.element_size(),
+                                        ctypes.byref(out)))
     return Server(out, (buf, lens, ab, arena, ctx), sum(len(x) for x in names))
 
 

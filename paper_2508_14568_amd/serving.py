@@ -13,7 +13,8 @@ from . import lvs as L
 
 
 def run(srv, queries_ct, arrivals, on_result=None):
-    """queries_ct: list of encrypted queries ([m][2][N+1] arrays); arrivals:
+    """queries_ct: list of encrypted queries ([m][2][N+1] arrays, [m][c][N+1]
+    chunk ciphertexts on a wide server); arrivals:
     non-decreasing arrival times in seconds.  Returns (latencies in seconds,
     wall seconds, results)."""
     order = np.argsort(np.asarray(arrivals, dtype=float), kind="stable")

@@ -173,3 +173,62 @@ def test_wide_batch_plan_equals_alone(gpu):
             torch.cuda.synchronize()
             assert (h == L.to_host(d_ref).reshape(len(b), L.CT_WORDS)).all(), (rep, k)
             assert L.lvs_decrypt_distance(g.ck, h, len(a)) == P.edit_distance(a, b), (rep, k)
+
+
+def test_wide_server_mix_equals_alone(gpu, okeys):
+    """The serving engine over 21-bit symbols: three queries submitted at
+    different step boundaries against five names, in an arena that holds two
+    requests (the third waits for memory); every request's rows equal its
+    lone run (the wide Section 5 table, then the cleartext pass per name),
+    every distance equals Wagner-Fischer, and one name's rows are bit-exact
+    with the oracle."""
+    say("wide server")
+    g = gpu
+    L, torch = g.L, g.torch
+    width = 21
+    rng = np.random.default_rng(34)
+    alphabet = sorted({int(v) for v in rng.integers(0, 2 ** width, size=6)})
+    names = [[alphabet[int(t)] for t in rng.integers(0, len(alphabet), size=n)] for n in (4, 7, 1, 9, 5)]
+    queries = [[alphabet[int(t)] for t in rng.integers(0, len(alphabet), size=m)] for m in (5, 3, 8)]
+    cts = [L.lvs_encrypt_symbols(g.ck, q, width, 960 + k) for k, q in enumerate(queries)]
+    per = max(L.lvs_server_request_bytes_wide(names, len(alphabet), len(q), width) for q in queries)
+    max_step = 4096
+    srv = L.lvs_server_create_wide(g.ctx, names, alphabet, width, L.lvs_server_fixed_bytes(max_step) + 2 * per + 4096,
+                                   max_step=max_step)
+    arrivals = {0: [0], 1: [1], 4: [2]}
+    tickets, outs = {}, {}
+    for step in range(2000):
+        for k in arrivals.get(step, []):
+            tickets[k] = L.lvs_server_submit(srv, cts[k])
+        L.lvs_server_step(srv)
+        for k, t in tickets.items():
+            if k not in outs:
+                o = L.lvs_server_poll(srv, t)
+                if o is not None:
+                    outs[k] = o
+        if len(outs) == len(queries):
+            break
+    assert len(outs) == len(queries)
+    starts = np.cumsum([0] + [len(nm) for nm in names])
+    for k, q in enumerate(queries):
+        m = len(q)
+        d_tab = torch.zeros(len(alphabet) * m * L.CT_WORDS, dtype=torch.int64, device=g.dev)
+        L.lvs_preprocess_wide(g.ctx, L.to_device(cts[k], g.dev), m, width, alphabet, d_tab)
+        for j, nm in enumerate(names):
+            rows = outs[k][starts[j]:starts[j + 1]]
+            d_h = torch.zeros(len(nm) * L.CT_WORDS, dtype=torch.int64, device=g.dev)
+            L.lvs_edit_distance_clear_wide(g.ctx, d_tab, m, alphabet, nm, d_h)
+            torch.cuda.synchronize()
+            assert (L.to_host(d_h).reshape(len(nm), L.CT_WORDS) == rows).all(), (k, j)
+            assert L.lvs_decrypt_distance(g.ck, rows, m) == P.edit_distance(q, nm), (k, j)
+    # name 0 against query 0 through the oracle, table rows of its own symbols
+    nm = names[0]
+    sub_alpha = sorted(set(nm))
+    otab = OL.preprocess_wide(okeys, OL.encrypt_symbols(okeys, queries[0], width, 960), sub_alpha, width)
+    oh = OL.edit_distance_clear(okeys, otab, sub_alpha, nm, None)
+    for j in range(len(nm)):
+        assert_same_ct(outs[0][j], oh[j], f"name 0 h[m,{j + 1}]")
+    with pytest.raises(L.LvsError) as e:
+        L.lvs_server_create_wide(g.ctx, [[2 ** width]], [2 ** width], width, L.lvs_server_fixed_bytes(16) + 4096,
+                                 max_step=16)
+    assert e.value.code == -2
