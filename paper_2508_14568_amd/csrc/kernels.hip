@@ -341,19 +341,54 @@ __device__ __forceinline__ uint64_t job_word(const Job& J, int w) {
 // input of job b (mask coefficients only; the body is added later).  Digits:
 // round to 15 bits, then balanced base-8 digits from the least significant
 // level with a carry (level t weight 2^(64-3t)); the top carry is dropped.
+// One KSK row's words of a thread's columns; a column past the last reads
+// the last column (its sums are never stored).
+__device__ __forceinline__ void ks_load_row(uint64_t (&k)[kKsCols], const uint64_t* row, int tid) {
+#pragma unroll
+    for (int cs = 0; cs < kKsCols; ++cs) k[cs] = row[min(tid + 256 * cs, kSmallWords - 1)];
+}
+
+// The products of one row with the tile's biased digits (dp: 8 bytes, one
+// per ciphertext): sum (d + 4) k = sum (d + 4) k_lo + 2^32 sum (d + 4) k_hi
+// (mod 2^64), the first sum kept in 64 bits (a 32 x 32 + 64 multiply-add per
+// product), the second in 32 bits; ksum collects the rows for the bias.
+__device__ __forceinline__ void ks_row_products(uint64_t dp, const uint64_t (&k)[kKsCols],
+                                                uint64_t (&acc_lo)[kKsTile][kKsCols],
+                                                uint32_t (&acc_hi)[kKsTile][kKsCols], uint64_t (&ksum)[kKsCols]) {
+#pragma unroll
+    for (int cs = 0; cs < kKsCols; ++cs) ksum[cs] += k[cs];
+#pragma unroll
+    for (int bb = 0; bb < kKsTile; ++bb) {
+        const uint32_t d = uint32_t(dp >> (8 * bb)) & 0xFFu;
+#pragma unroll
+        for (int cs = 0; cs < kKsCols; ++cs) {
+            acc_lo[bb][cs] += uint64_t(d) * uint32_t(k[cs]);
+            acc_hi[bb][cs] += d * uint32_t(k[cs] >> 32);
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256) keyswitch_jobs_kernel(const Job* __restrict__ jobs, int B,
                                                              const uint64_t* __restrict__ ksk,
                                                              uint64_t* __restrict__ part, int chunk, int sub) {
-    __shared__ uint64_t digits[kKsSub * kKsLevel];   // 8 signed bytes per row: one per tile ciphertext
+    // 8 bytes per row, one per tile ciphertext: the balanced digit d in
+    // [-4, 4) stored as d + 4.  The products then take unsigned 32 x 64-bit
+    // multiply-adds, and the bias comes off once per split:
+    // sum (d + 4) k - 4 sum k = sum d k (mod 2^64).
+    __shared__ uint64_t digits[kKsSub * kKsLevel];
     const int tid = threadIdx.x;
     const int b0 = blockIdx.x * kKsTile;
     const int split = blockIdx.y;
     uint8_t* dig8 = reinterpret_cast<uint8_t*>(digits);
-    uint64_t acc[kKsTile][kKsCols];
+    uint64_t acc_lo[kKsTile][kKsCols];
+    uint32_t acc_hi[kKsTile][kKsCols];
+    uint64_t ksum[kKsCols];
+#pragma unroll
+    for (int cs = 0; cs < kKsCols; ++cs) ksum[cs] = 0;
 #pragma unroll
     for (int bb = 0; bb < kKsTile; ++bb)
 #pragma unroll
-        for (int cs = 0; cs < kKsCols; ++cs) acc[bb][cs] = 0;
+        for (int cs = 0; cs < kKsCols; ++cs) acc_lo[bb][cs] = acc_hi[bb][cs] = 0;
     for (int j0 = split * chunk; j0 < (split + 1) * chunk; j0 += sub) {
         __syncthreads();
         for (int idx = tid; idx < kKsTile * sub; idx += 256) {
@@ -366,25 +401,15 @@ __global__ void __launch_bounds__(256) keyswitch_jobs_kernel(const Job* __restri
                 int d = int(r & 7u);
                 r >>= 3;
                 if (d >= 4) { d -= 8; r += 1; }
-                dig8[(jj * kKsLevel + lev) * 8 + bb] = uint8_t(int8_t(d));
+                dig8[(jj * kKsLevel + lev) * 8 + bb] = uint8_t(d + 4);
             }
         }
         __syncthreads();
         const uint64_t* rows = ksk + size_t(j0) * kKsLevel * kSmallWords;
         for (int rr = 0; rr < sub * kKsLevel; ++rr) {
-            const uint64_t dp = digits[rr];
             uint64_t k[kKsCols];
-#pragma unroll
-            for (int cs = 0; cs < kKsCols; ++cs) {
-                const int col = tid + 256 * cs;
-                k[cs] = (col < kSmallWords) ? rows[size_t(rr) * kSmallWords + col] : 0;
-            }
-#pragma unroll
-            for (int bb = 0; bb < kKsTile; ++bb) {
-                const int64_t d = int8_t(uint8_t(dp >> (8 * bb)));
-#pragma unroll
-                for (int cs = 0; cs < kKsCols; ++cs) acc[bb][cs] -= uint64_t(d) * k[cs];
-            }
+            ks_load_row(k, rows + size_t(rr) * kSmallWords, tid);
+            ks_row_products(digits[rr], k, acc_lo, acc_hi, ksum);
         }
     }
 #pragma unroll
@@ -393,7 +418,9 @@ __global__ void __launch_bounds__(256) keyswitch_jobs_kernel(const Job* __restri
 #pragma unroll
         for (int cs = 0; cs < kKsCols; ++cs) {
             const int col = tid + 256 * cs;
-            if (col < kSmallWords) part[(size_t(split) * B + b0 + bb) * kSmallWords + col] = acc[bb][cs];
+            // -sum d k over this split's rows
+            const uint64_t acc = acc_lo[bb][cs] + (uint64_t(acc_hi[bb][cs]) << 32);
+            if (col < kSmallWords) part[(size_t(split) * B + b0 + bb) * kSmallWords + col] = 4 * ksum[cs] - acc;
         }
     }
 }
