@@ -172,7 +172,7 @@ def batched_block(L, ck, ctx, nq, plain_sample):
     }
 
 
-def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos, progress=False, arena_gb=4):
+def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos, progress=False, arena_gb=4, max_step=1024):
     """The serving workload on the first n_names of its 1024 cleartext server
     names: n_sat queries submitted at once (saturated queries/s), then
     n_poisson queries per load factor rho arriving as a Poisson process at
@@ -185,7 +185,6 @@ def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos, progress=False, a
     names = server[:n_names]
     alpha = W.alphabet_of(names)
     cts = [L.lvs_encrypt_string(ck, q, L.LVS_ENC_ASCII7, 40000 + k) for k, q in enumerate(queries)]
-    max_step = 8192
     per = L.lvs_server_request_bytes(names, len(alpha), max(len(q) for q in queries))
     cap = max(4, min(128, (arena_gb << 30) // per))
     srv = L.lvs_server_create(ctx, names, alpha, L.lvs_server_fixed_bytes(max_step) + per * cap + 4096,
@@ -209,7 +208,7 @@ def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos, progress=False, a
     res = {
         "workload": f"serving: first {n_names} of 1024 cleartext names (lengths lognormal, mean 15), "
                     f"alphabet {len(alpha)} letters, encrypted queries of the same length law",
-        "names": n_names, "alphabet": len(alpha), "max_requests_resident": cap,
+        "names": n_names, "alphabet": len(alpha), "max_requests_resident": cap, "max_step": max_step,
         "request_bytes": per,
         "saturated": {"queries": n_sat, "seconds": round(wall, 3), "queries_per_s": round(sat_qps, 4),
                       "pbs_per_s": round((pbs1 - pbs0) / wall, 1), "steps": st1 - st0,
@@ -465,6 +464,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-names", type=int, default=32)
     ap.add_argument("--serving-queries", type=int, default=16, help="queries of the saturated run")
+    ap.add_argument("--serving-max-step", type=int, default=1024,
+                    help="bootstraps per engine step at most (admitted requests beyond it wait a step)")
     ap.add_argument("--poisson-queries", type=int, default=40, help="queries per load factor")
     ap.add_argument("--rho", type=str, default="0.8", help="comma-separated load factors")
     ap.add_argument("--no-serving", action="store_true")
@@ -585,7 +586,8 @@ def main():
         line["wide"] = wide_block(L, ck, ctx)
     if not args.no_serving and args.serving_names > 0:
         line["serving"] = serving_block(L, ck, ctx, args.serving_names, args.serving_queries,
-                                        args.poisson_queries, [float(x) for x in args.rho.split(",") if x])
+                                        args.poisson_queries, [float(x) for x in args.rho.split(",") if x],
+                                        max_step=args.serving_max_step)
     if not args.no_cpu_baseline:
         z1 = (A[:, None, 0, :] - B[None, :, 0, :]).reshape(m * n, L.CT_WORDS).astype(np.uint64)
         line["cpu_baseline"] = cpu_baseline(z1)

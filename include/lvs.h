@@ -509,10 +509,17 @@ size_t lvs_server_request_bytes_wide(const size_t* name_lens, size_t n_names, si
 int lvs_server_submit(lvs_server* srv, const uint64_t* h_query, size_t m, uint64_t* ticket);
 
 /* One engine step: admits queued requests while their buffers fit, then runs
- * one batched launch over the ready bootstraps of every admitted request
+ * one batched launch over the ready bootstraps of the admitted requests
  * (preprocessing rounds of new requests and the current anti-diagonal of
- * every running one), and advances them.  Waits for the step to finish.
- * Reports the requests still running, still queued, and the step's
+ * running ones), taken in arrival order up to max_step bootstraps, and
+ * advances every request whose round is complete.  The bootstraps of one
+ * round are independent, so the last request taken may run part of its
+ * round (the rest runs in the next step first); a step larger than one device
+ * round (one bootstrap per CU, two in the four-wave form) is trimmed to a
+ * whole number of rounds, the trimmed bootstraps taken off the latest
+ * requests.  A smaller max_step shortens the steps and so the latency of the
+ * requests in front, at some cost in throughput.  Waits for the step to
+ * finish.  Reports the requests still running, still queued, and the step's
  * bootstraps (any may be NULL). */
 int lvs_server_step(lvs_server* srv, size_t* active, size_t* queued, size_t* step_jobs);
 

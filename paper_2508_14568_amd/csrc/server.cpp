@@ -10,8 +10,10 @@
 // s = 2 .. m + max(n_k) of one DP instance per name, all instances of the
 // request advancing together, with a refresh round (Section 3.1) after every
 // refresh-th diagonal.  An engine step gathers the ready bootstraps of
-// every admitted request (any mix of phases and tables) into one key-switch
-// launch and one persistent blind-rotation launch.  Requests are admitted in
+// the admitted requests in arrival order (any mix of phases and tables, the
+// last one possibly with part of its round, the step trimmed to whole device
+// rounds) into one key-switch launch and one blind-rotation launch.
+// Requests are admitted in
 // arrival order when their device buffers fit in the caller's arena, and join
 // at the next step boundary.
 #include <hip/hip_runtime.h>
@@ -100,6 +102,9 @@ struct Request {
     // the next of its steps to run
     Plan pre;
     size_t pre_step = 0;
+    // bootstraps of the current phase already run (a phase's bootstraps are
+    // independent, so a step may run part of them)
+    size_t taken = 0;
 };
 
 // Pool bytes of one request: the query, the preprocessing buffers (ASCII: the
@@ -150,7 +155,7 @@ struct Server : Handle {
     std::deque<Request*> queue;                // arrival order, not admitted yet
     std::vector<Request*> active;              // admitted, arrival order
     std::map<uint64_t, std::unique_ptr<Request>> all;
-    std::vector<Job> jobs;
+    std::vector<Job> jobs, phase_jobs;
     uint64_t steps = 0, bootstraps = 0;
 
     size_t query_syms() const { return c ? c : 2; }
@@ -459,51 +464,71 @@ int lvs_server_step(lvs_server* srv, size_t* active, size_t* queued, size_t* ste
         S->queue.pop_front();
         S->active.push_back(r);
     }
-    // gather every admitted request's ready bootstraps, within the step cap
+    // gather the admitted requests' ready bootstraps in arrival order, within
+    // the step cap; the last request may contribute part of its phase
+    struct Take {
+        Request* r;
+        size_t count, total;
+        const SumOp* sum;
+    };
+    std::vector<Take> takes;
     S->jobs.clear();
-    std::vector<Request*> stepped;
-    std::vector<const SumOp*> sums;
     for (Request* r : S->active) {
         if (r->phase == kDone) continue;
-        const size_t before = S->jobs.size();
+        if (S->jobs.size() >= S->max_step) break;
+        S->phase_jobs.clear();
         const SumOp* sum = nullptr;
-        S->gather(r, S->jobs, &sum);
-        if (S->jobs.size() > S->max_step && before > 0) {   // defer this request (and keep order)
-            S->jobs.resize(before);
-            break;
-        }
-        stepped.push_back(r);
-        if (sum) sums.push_back(sum);
+        S->gather(r, S->phase_jobs, &sum);
+        const size_t total = S->phase_jobs.size();
+        const size_t n = std::min(total - r->taken, S->max_step - S->jobs.size());
+        S->jobs.insert(S->jobs.end(), S->phase_jobs.begin() + long(r->taken), S->phase_jobs.begin() + long(r->taken + n));
+        takes.push_back({r, n, total, r->taken == 0 ? sum : nullptr});
     }
-    // the merging levels' group sums feed this step's bootstraps
-    for (const SumOp* o : sums)
-        SRV_HIP(launch_group_sum(o->in, o->out, o->items, o->cnt, o->groups, o->group, C->cus, C->stream));
-    // a single request larger than the cap runs in several launches
-    if (!S->jobs.empty()) {
-        SRV_HIP(hipMemcpyAsync(S->d_jobs, S->jobs.data(), sizeof(Job) * std::min(S->jobs.size(), S->max_step),
-                               hipMemcpyHostToDevice, C->stream));
-        for (size_t o = 0; o < S->jobs.size(); o += S->max_step) {
-            const int B = int(std::min(S->max_step, S->jobs.size() - o));
-            if (o) {
-                SRV_HIP(hipStreamSynchronize(C->stream));
-                SRV_HIP(hipMemcpyAsync(S->d_jobs, S->jobs.data() + o, sizeof(Job) * size_t(B), hipMemcpyHostToDevice,
-                                       C->stream));
-            }
-            {
-                TimedLaunch t(C, kProfKeySwitch, uint64_t(B));
-                SRV_HIP(launch_keyswitch_jobs(S->d_jobs, B, C->ksk, S->d_part, C->stream));
-            }
-            {
-                TimedLaunch t(C, br_profile_id(C, B), uint64_t(B));
-                SRV_HIP(launch_blind_rotate_jobs(S->d_jobs, B, S->d_part, C->luts, C->bsk, C->tables, C->br_grid,
-                                                 C->latency_form_max, C->latency_waves, C->stream));
-            }
+    // end the step on a whole device round (one bootstrap per CU, two in the
+    // four-wave form): the bootstraps of a partial last round wait for the
+    // next step, taken off the latest requests
+    const size_t cus = size_t(std::max(1, C->cus));
+    const size_t round = S->jobs.size() <= size_t(C->latency_form_max) ? cus : 2 * cus;
+    if (S->jobs.size() > round) {
+        size_t cut = S->jobs.size() % round;
+        while (cut > 0 && !takes.empty()) {
+            Take& t = takes.back();
+            const size_t d = std::min(cut, t.count);
+            t.count -= d;
+            cut -= d;
+            S->jobs.resize(S->jobs.size() - d);
+            if (t.count == 0) takes.pop_back();
         }
-        SRV_HIP(hipStreamSynchronize(C->stream));   // job list is reused by the next step
+    }
+    // the merging levels' group sums feed this step's bootstraps (once, with
+    // the first part of their round)
+    for (const Take& t : takes)
+        if (t.sum)
+            SRV_HIP(launch_group_sum(t.sum->in, t.sum->out, t.sum->items, t.sum->cnt, t.sum->groups, t.sum->group,
+                                     C->cus, C->stream));
+    if (!S->jobs.empty()) {
+        const int B = int(S->jobs.size());
+        SRV_HIP(hipMemcpyAsync(S->d_jobs, S->jobs.data(), sizeof(Job) * S->jobs.size(), hipMemcpyHostToDevice,
+                               C->stream));
+        {
+            TimedLaunch t(C, kProfKeySwitch, uint64_t(B));
+            SRV_HIP(launch_keyswitch_jobs(S->d_jobs, B, C->ksk, S->d_part, C->stream));
+        }
+        {
+            TimedLaunch t(C, br_profile_id(C, B), uint64_t(B));
+            SRV_HIP(launch_blind_rotate_jobs(S->d_jobs, B, S->d_part, C->luts, C->bsk, C->tables, C->br_grid,
+                                             C->latency_form_max, C->latency_waves, C->stream));
+        }
+        SRV_HIP(hipStreamSynchronize(C->stream));   // the job list is reused by the next step
         S->steps++;
         S->bootstraps += S->jobs.size();
     }
-    for (Request* r : stepped) S->advance(r);
+    for (const Take& t : takes) {
+        t.r->taken += t.count;
+        if (t.r->taken < t.total) continue;
+        t.r->taken = 0;
+        S->advance(t.r);
+    }
     // requests with no name work left are done as well
     for (Request* r : S->active)
         if (r->phase == kDp && r->s > r->m + S->max_len) r->phase = kDone;

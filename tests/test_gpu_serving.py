@@ -33,10 +33,9 @@ def enc_queries(g):
     return [g.L.lvs_encrypt_string(g.ck, q, g.L.LVS_ENC_ASCII7, 31000 + k) for k, q in enumerate(QUERIES)]
 
 
-def new_server(g, requests_that_fit=None):
+def new_server(g, requests_that_fit=None, max_step=4096):
     L = g.L
     alpha = alphabet()
-    max_step = 4096
     fixed = L.lvs_server_fixed_bytes(max_step)
     per = L.lvs_server_request_bytes(NAMES, len(alpha), max(len(q) for q in QUERIES))
     pool = per * (requests_that_fit or 16) + 4096
@@ -58,8 +57,12 @@ def check_distances(g, q, out):
         assert g.L.lvs_decrypt_distance(g.ck, rows, len(q)) == P.edit_distance(q, nm), (q, nm)
 
 
-def test_alone_vs_mix(gpu):
-    say("serving alone vs mix")
+@pytest.mark.parametrize("max_step", [4096, 37])
+def test_alone_vs_mix(gpu, max_step):
+    """Every request's rows are bit-identical alone and in a mix whose
+    requests join at different step boundaries; with a cap of 37 bootstraps
+    per step every phase runs in parts over several steps."""
+    say("serving alone vs mix, cap", max_step)
     g = gpu
     L = g.L
     cts = enc_queries(g)
@@ -67,7 +70,7 @@ def test_alone_vs_mix(gpu):
     for q, out in zip(QUERIES, alone):
         check_distances(g, q, out)
     # the mix: requests join at different step boundaries
-    srv = new_server(g)
+    srv = new_server(g, max_step=max_step)
     tickets = {L.lvs_server_submit(srv, cts[0]): 0}
     got = {}
     step = 0
