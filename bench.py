@@ -464,6 +464,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-names", type=int, default=32)
     ap.add_argument("--serving-queries", type=int, default=16, help="queries of the saturated run")
+    ap.add_argument("--serving-progress", action="store_true", help="a progress line per finished query")
     ap.add_argument("--serving-max-step", type=int, default=1024,
                     help="bootstraps per engine step at most (admitted requests beyond it wait a step)")
     ap.add_argument("--poisson-queries", type=int, default=40, help="queries per load factor")
@@ -562,6 +563,9 @@ def main():
     if not args.no_microbench:
         note("microbenchmarks")
         roofline["measured"] = microbench(L, ctx)
+        # the same achieved rate against the measured ceiling of the
+        # butterfly's instruction mix (what the kernel's arithmetic can reach)
+        roofline["frac_of_measured_peak"] = round(achieved / roofline["measured"]["modmul_probe_tops"], 4)
     line = {
         "metric": "PBS/s & DP cells/s; batched vs plain queries/s; p50/p99 query latency",
         "value": round(pbs_s, 2), "unit": "PBS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -580,6 +584,9 @@ def main():
     if not args.no_batched and args.batched_queries > 0:
         line["batched"] = batched_block(L, ck, ctx, args.batched_queries, min(args.plain_sample,
                                                                             args.batched_queries))
+        if "measured" in roofline:
+            rg = line["batched"]["roofline_graph"]
+            rg["frac_of_measured_peak"] = round(rg["achieved"] / roofline["measured"]["modmul_probe_tops"], 4)
     if not args.no_band and args.band_queries > 0:
         line["band"] = band_block(L, ck, ctx, args.band_queries, args.band_ell)
     if not args.no_wide:
@@ -587,7 +594,7 @@ def main():
     if not args.no_serving and args.serving_names > 0:
         line["serving"] = serving_block(L, ck, ctx, args.serving_names, args.serving_queries,
                                         args.poisson_queries, [float(x) for x in args.rho.split(",") if x],
-                                        max_step=args.serving_max_step)
+                                        max_step=args.serving_max_step, progress=args.serving_progress)
     if not args.no_cpu_baseline:
         z1 = (A[:, None, 0, :] - B[None, :, 0, :]).reshape(m * n, L.CT_WORDS).astype(np.uint64)
         line["cpu_baseline"] = cpu_baseline(z1)
