@@ -103,6 +103,29 @@ def levenshtein(a, b) -> int:
     return prev[-1]
 
 
+def plain_path_time(L, ctx, items, label):
+    """Every query of items (dicts with d_a, m, d_b, n; ASCII, both
+    encrypted) once through the plain per-diagonal path, after one warm-up
+    call: (seconds, bootstraps).  Buffers are set up outside the timing."""
+    import torch
+    dev = ctx.device
+    t_plain, pbs_plain = 0.0, 0
+    for k, it in enumerate([items[0]] + list(items)):
+        work = L.device_buffer(L.lvs_edit_distance_workspace_bytes(it["m"], it["n"], L.LVS_ENC_ASCII7), dev)
+        d_h = torch.zeros(max(1, it["n"]) * L.CT_WORDS, dtype=torch.int64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.lvs_edit_distance(ctx, it["d_a"], it["m"], it["d_b"], it["n"], L.LVS_ENC_ASCII7, d_h, work)
+        torch.cuda.synchronize()
+        if k == 0:
+            continue                  # warm-up
+        t_plain += time.perf_counter() - t0
+        pbs_plain += 3 * it["m"] * it["n"]
+        if k % 16 == 0:
+            note(f"{label}: {k} of {len(items)} queries through the plain path")
+    return t_plain, pbs_plain
+
+
 def batched_block(L, ck, ctx, nq, plain_sample):
     """The batched workload's first nq pairs (ASCII, lengths 8..64, both
     encrypted) as one graph-captured plan, against the same kind of query run
@@ -136,20 +159,11 @@ def batched_block(L, ck, ctx, nq, plain_sample):
         h = L.to_host(d_h).reshape(len(b), L.CT_WORDS)
         if L.lvs_decrypt_distance(ck, h, len(a)) != levenshtein(a, b):
             raise SystemExit("batched: wrong distance")
-    note(f"batched: {plain_sample} queries through the plain path")
-    # plain path: the first queries one at a time
-    t_plain, pbs_plain = 0.0, 0
-    for k in range(plain_sample):
-        it = items[k]
-        work = L.device_buffer(L.lvs_edit_distance_workspace_bytes(it["m"], it["n"], L.LVS_ENC_ASCII7), dev)
-        d_h = torch.zeros_like(outs[k])
-        L.lvs_edit_distance(ctx, it["d_a"], it["m"], it["d_b"], it["n"], L.LVS_ENC_ASCII7, d_h, work)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        L.lvs_edit_distance(ctx, it["d_a"], it["m"], it["d_b"], it["n"], L.LVS_ENC_ASCII7, d_h, work)
-        torch.cuda.synchronize()
-        t_plain += time.perf_counter() - t0
-        pbs_plain += 3 * it["m"] * it["n"]
+    # the same queries one at a time through the plain path (identical work;
+    # plain_sample < nq times only the first ones)
+    n_plain = nq if plain_sample <= 0 else min(plain_sample, nq)
+    note(f"batched: {n_plain} queries through the plain path")
+    t_plain, pbs_plain = plain_path_time(L, ctx, items[:n_plain], "batched")
     cells = sum(len(a) * len(b) for a, b in pairs)
     batched_pbs_s = pbs / t_batch
     plain_pbs_s = pbs_plain / t_plain
@@ -158,8 +172,8 @@ def batched_block(L, ck, ctx, nq, plain_sample):
         "queries": nq, "pbs": pbs, "cells": cells, "steps": steps, "max_step": max_step,
         "seconds": round(t_batch, 3), "pbs_per_s": round(batched_pbs_s, 1),
         "cells_per_s": round(cells / t_batch, 1), "queries_per_s": round(nq / t_batch, 3),
-        "plain_sample_queries": plain_sample, "plain_pbs_per_s": round(plain_pbs_s, 1),
-        "plain_queries_per_s": round(plain_sample / t_plain, 4),
+        "plain_queries": n_plain, "plain_seconds": round(t_plain, 3), "plain_pbs_per_s": round(plain_pbs_s, 1),
+        "plain_queries_per_s": round(n_plain / t_plain, 4),
         "plain_queries_per_s_same_work": round(nq / (pbs / plain_pbs_s), 4),
         "speedup_vs_plain": round(batched_pbs_s / plain_pbs_s, 2),
         # the whole graph (key switches and launch gaps included) against the
@@ -381,17 +395,13 @@ def full_configs(L, ck, ctx, serving_sat, serving_poisson):
             raise SystemExit("batched 256: wrong distance")
     del plan
     cells = sum(len(a) * len(b) for a, b in pairs)
-    # the same kind of query through the plain path, a sample of 8
-    note("full: plain path on 8 of the 256 pairs")
-    t_plain = pbs_plain = 0
-    for a, b in pairs[:8]:
-        dtp, _ = plain_once(a, b, L.LVS_ENC_ASCII7)
-        t_plain += dtp
-        pbs_plain += 3 * len(a) * len(b)
+    # the same 256 queries one at a time through the plain path (identical work)
+    note("full: plain path on the 256 pairs")
+    t_plain, pbs_plain = plain_path_time(L, ctx, items, "full")
     out["batched_ascii_256"] = {"pbs": pbs, "cells": cells, "steps": steps, "max_step": max_step,
                                 "seconds": round(dt, 3), "pbs_per_s": round(pbs / dt, 1),
                                 "cells_per_s": round(cells / dt, 1), "queries_per_s": round(256 / dt, 3),
-                                "plain_sample_pbs_per_s": round(pbs_plain / t_plain, 1),
+                                "plain_seconds": round(t_plain, 3), "plain_pbs_per_s": round(pbs_plain / t_plain, 1),
                                 "speedup_vs_plain": round((pbs / dt) / (pbs_plain / t_plain), 2)}
     del items
 
@@ -459,7 +469,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batched-queries", type=int, default=64)
-    ap.add_argument("--plain-sample", type=int, default=4)
+    ap.add_argument("--plain-sample", type=int, default=0,
+                    help="batched queries also timed through the plain path (0: all of them)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-names", type=int, default=32)
@@ -582,8 +593,9 @@ def main():
     if tuning is not None:
         line["tuning"] = dict(tuning["tuning"], cached=tuning["cached"])
     if not args.no_batched and args.batched_queries > 0:
-        line["batched"] = batched_block(L, ck, ctx, args.batched_queries, min(args.plain_sample,
-                                                                            args.batched_queries))
+        line["batched"] = batched_block(L, ck, ctx, args.batched_queries, args.plain_sample)
+        # against the default line's plain workload as well (PBS/s over PBS/s)
+        line["batched"]["vs_plain_line"] = round(line["batched"]["pbs_per_s"] / line["value"], 2)
         if "measured" in roofline:
             rg = line["batched"]["roofline_graph"]
             rg["frac_of_measured_peak"] = round(rg["achieved"] / roofline["measured"]["modmul_probe_tops"], 4)
@@ -595,6 +607,8 @@ def main():
         line["serving"] = serving_block(L, ck, ctx, args.serving_names, args.serving_queries,
                                         args.poisson_queries, [float(x) for x in args.rho.split(",") if x],
                                         max_step=args.serving_max_step, progress=args.serving_progress)
+        sv = line["serving"]
+        sv["saturated"]["vs_plain_line"] = round(sv["saturated"]["pbs_per_s"] / line["value"], 2)
     if not args.no_cpu_baseline:
         z1 = (A[:, None, 0, :] - B[None, :, 0, :]).reshape(m * n, L.CT_WORDS).astype(np.uint64)
         line["cpu_baseline"] = cpu_baseline(z1)

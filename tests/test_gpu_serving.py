@@ -155,8 +155,9 @@ def test_request_that_never_fits(gpu):
 
 def test_step_below_cap_with_more_splits(gpu):
     """A step smaller than the cap can split the key switch more ways than a
-    step at the cap (600 preprocessing bootstraps under a 8192 cap): the
-    partial sums must still fit the server's fixed region."""
+    step at the cap (about 600 preprocessing bootstraps under a 8192 cap):
+    the partial sums must still fit the server's fixed region.  Steps end on
+    whole device rounds and run every bootstrap once."""
     say("serving step below cap")
     g = gpu
     L = g.L
@@ -169,7 +170,14 @@ def test_step_below_cap_with_more_splits(gpu):
                               max_step=max_step)
     t = L.lvs_server_submit(srv, ct)
     out = None
+    sizes = []
     while out is None:
-        L.lvs_server_step(srv)
+        sizes.append(L.lvs_server_step(srv)[2])
         out = L.lvs_server_poll(srv, t)
     check_distances(g, q, out)
+    # steps past one device round end on whole rounds (one bootstrap per CU):
+    # the first preprocessing round (17 letters x 36 = 612 bootstraps) runs
+    # as 512 + 100
+    cus = g.torch.cuda.get_device_properties(g.dev).multi_processor_count
+    assert all(n <= cus or n % cus == 0 for n in sizes), sizes
+    assert sum(sizes) == 2 * len(alpha) * len(q) + sum(len(q) * len(nm) for nm in NAMES)
