@@ -99,7 +99,8 @@ const char* lvs_last_error(void);
 
 /* The parameter set the kernels implement: n = 742, k = 1, N = 2048,
  * bootstrap gadget 2^23 x 1, key switch 2^3 x 5, noise 7.0698e-6 / 2.9404e-16
- * of q (the TFHE "4-bit message" set the paper's Section 6.1 runs on). */
+ * of q (the TFHE parameter set for 4-bit messages that the paper's Section
+ * 6.1 runs on). */
 int lvs_params_default(lvs_params* out);
 
 /* Words per ciphertext (N + 1). */

@@ -1,7 +1,7 @@
 // Serving: continuous batching of encrypted name queries against a cleartext
-// list of names (Section 5's "encrypted query against a large unencrypted
-// database": preprocess the query once, then one bootstrap per cell for every
-// name).
+// list of names (Section 5's setting of one encrypted query against a large
+// cleartext database: preprocess the query once, then one bootstrap per cell
+// for every name).
 //
 // Each request goes through three phases: the preprocessing table's two
 // bootstrap rounds (eq1, then eq9 = T[c][i]; over wide symbols, Section

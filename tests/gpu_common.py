@@ -9,7 +9,7 @@ KEY_SEED = 1
 
 
 def say(*args):
-    """Name the case before each GPU step (flushed, so a lost box still shows it)."""
+    """Name the case before each GPU step (flushed, so the output names it even if the process dies)."""
     print("[gpu-test]", *args, flush=True)
     sys.stdout.flush()
 
