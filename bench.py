@@ -591,7 +591,7 @@ def main():
         "roofline": roofline,
     }
     if tuning is not None:
-        line["tuning"] = dict(tuning["tuning"], cached=tuning["cached"])
+        line["tuning"] = dict(tuning["tuning"], cached=tuning["cached"], samples=tuning.get("samples"))
     if not args.no_batched and args.batched_queries > 0:
         line["batched"] = batched_block(L, ck, ctx, args.batched_queries, args.plain_sample)
         # against the default line's plain workload as well (PBS/s over PBS/s)
