@@ -357,10 +357,10 @@ size_t lvs_equality_wide_workspace_bytes(size_t m, size_t n, unsigned width);
 int lvs_equality_wide(lvs_context* ctx, const uint64_t* d_a, size_t m, const uint64_t* d_b, size_t n, unsigned width,
                       uint64_t* d_eq9, void* d_work, size_t work_bytes);
 
-/* Edit distance of two encrypted symbol strings: the wide equality of every
- * pair, then the single-bootstrap main loop of Algorithm 1 over the eq9
- * matrix (with the context's refresh interval); d_h_last as for
- * lvs_edit_distance. */
+/* Edit distance of two encrypted symbol strings: the single-bootstrap main
+ * loop of Algorithm 1 over the wide equality of every pair (with the
+ * context's refresh interval), the equality bootstraps running inside the
+ * loop as in lvs_plan_create_wide; d_h_last as for lvs_edit_distance. */
 size_t lvs_edit_distance_wide_workspace_bytes(size_t m, size_t n, unsigned width);
 int lvs_edit_distance_wide(lvs_context* ctx, const uint64_t* d_a, size_t m, const uint64_t* d_b, size_t n,
                            unsigned width, uint64_t* d_h_last, void* d_work, size_t work_bytes);
@@ -427,14 +427,27 @@ int lvs_plan_create(lvs_context* ctx, const lvs_query* queries, size_t nq, int e
 
 /* Batch plan over wide symbols (Section 4.2): every query has both strings
  * encrypted by lvs_encrypt_symbols with the same width (d_a [m][c][N+1],
- * d_b [n][c][N+1]; d_table must be NULL).  The plan's first steps run the
- * hybrid equality of every pair of every query (one step of chunk
- * bootstraps, then the merging levels), then the main loop of every query as
- * in lvs_plan_create (full or banded; the context's refresh interval).  Run
- * and free it like any plan. */
+ * d_b [n][c][N+1]; d_table must be NULL).  Step t runs the cells of
+ * anti-diagonal t of every query, as in lvs_plan_create (full or banded; the
+ * context's refresh interval), together with the hybrid equality of the
+ * in-band pairs of later diagonals: a pair's chunk bootstraps by step
+ * s - 1 - levels, each merging level one step later (its group sums run just
+ * before the step), so the pair's eq9 is ready a step before its cell; chunk
+ * bootstraps of later diagonals fill each step's last partial device round.
+ * Run and free it like any plan. */
 int lvs_plan_wide_workspace_bytes(const lvs_query* queries, size_t nq, unsigned width, size_t* bytes);
 int lvs_plan_create_wide(lvs_context* ctx, const lvs_query* queries, size_t nq, unsigned width, int flags,
                          void* d_work, size_t work_bytes, lvs_plan** out);
+
+/* Host-side check of the schedule lvs_plan_create_wide builds for these
+ * queries (no device, nothing dereferenced), as lvs_plan_verify does for
+ * lvs_plan_create: round is the device's round (the schedule fills partial
+ * rounds with chunk sub-equalities of later diagonals), refresh the interval
+ * (0 = off).  Violations count reads of a word the plan writes (by a
+ * bootstrap or a group sum) before an earlier step wrote it, in-step races
+ * and steps above the workspace's bound. */
+int lvs_plan_verify_wide(const lvs_query* queries, size_t nq, unsigned width, size_t round, size_t refresh,
+                         size_t* steps, size_t* jobs, size_t* rounds, size_t* violations);
 
 /* Host-side check of the schedule lvs_plan_create builds for these queries
  * (no device, nothing dereferenced: the query pointers only name buffers).

@@ -801,44 +801,8 @@ int lvs_plan_verify(const lvs_query* queries, size_t nq, int encoding, size_t ro
     Plan P;
     const size_t cap = max_step_of(qs);
     build_edit_distance_plan(qs, P, true, fill ? round : 0, cap);
-    // Sweeping the steps in order: a word that some job of the plan writes
-    // may only be read (as a source or a subtrahend) once an earlier step has
-    // written it; within a step the key switch reads every source before the
-    // blind rotation writes, but the blind rotation's subtrahend reads and
-    // writes run together, so a subtrahend that another job of the same step
-    // writes, or a word two jobs of a step write, is a race.  No step may
-    // exceed the workspace's bound.
-    std::set<uintptr_t> produced, seen;
-    for (const Job& J : P.jobs)
-        for (int d = 0; d < 4; ++d)
-            if (J.dst[d]) produced.insert(uintptr_t(J.dst[d]));
-    size_t bad = 0, nrounds = 0;
-    const size_t r = std::max<size_t>(round, 1);
-    for (size_t st = 0; st < P.steps.size(); ++st) {
-        const PlanStep& S = P.steps[st];
-        nrounds += (S.count + r - 1) / r;
-        if (S.count > cap) ++bad;
-        std::map<uintptr_t, size_t> writer;
-        for (size_t x = S.off; x < S.off + S.count; ++x) {
-            const Job& J = P.jobs[x];
-            const void* reads[5] = {J.src[0], J.src[1], J.src[2], J.sub[0], J.sub[1]};
-            for (const void* rd : reads)
-                if (rd && produced.count(uintptr_t(rd)) && !seen.count(uintptr_t(rd))) ++bad;
-            for (int d = 0; d < 4; ++d) {
-                if (!J.dst[d]) continue;
-                auto ins = writer.emplace(uintptr_t(J.dst[d]), x);
-                if (!ins.second && ins.first->second != x) ++bad;
-            }
-        }
-        for (size_t x = S.off; x < S.off + S.count; ++x)
-            for (int k = 0; k < 2; ++k) {
-                const Job& J = P.jobs[x];
-                if (!J.sub[k]) continue;
-                auto it = writer.find(uintptr_t(J.sub[k]));
-                if (it != writer.end() && it->second != x) ++bad;
-            }
-        for (const auto& w : writer) seen.insert(w.first);
-    }
+    size_t nrounds = 0;
+    const size_t bad = verify_plan(P, round, cap, &nrounds);
     if (steps) *steps = P.steps.size();
     if (jobs) *jobs = P.jobs.size();
     if (rounds) *rounds = nrounds;

@@ -14,6 +14,8 @@
 #include "plan.h"
 
 #include <algorithm>
+#include <map>
+#include <set>
 
 #include "context.h"
 
@@ -470,6 +472,208 @@ void build_wide_equality(Plan& P, size_t pairs, size_t c, WideChunkInput (*chunk
         cnt = G;
         cur ^= 1;
     }
+}
+
+size_t wide_levels(size_t c) {
+    size_t L = 0;
+    for (size_t cnt = c; cnt > 1; cnt = (cnt + 14) / 15) ++L;
+    return L;
+}
+
+size_t wide_interleaved_bytes(size_t pairs, size_t c) {
+    if (c <= 1) return 0;
+    size_t b = align256(sizeof(uint64_t) * pairs * c * W);
+    for (size_t cnt = c; cnt > 1;) {
+        cnt = (cnt + 14) / 15;
+        b += align256(sizeof(uint64_t) * pairs * cnt * W);
+    }
+    return b;
+}
+
+size_t wide_step_bound(const std::vector<QuerySpec>& qs, size_t c) {
+    size_t per = 1 + c;   // a cell, its chunk sub-equalities and its merges
+    for (size_t cnt = c; cnt > 1;) {
+        cnt = (cnt + 14) / 15;
+        per += cnt;
+    }
+    size_t width = 0;
+    for (const auto& q : qs) width += std::min(q.m, q.n);
+    return width * per + 1024;
+}
+
+void build_wide_edit_distance_plan(const std::vector<QuerySpec>& qs, const std::vector<WideQuery>& wq, size_t c,
+                                   size_t quantum, size_t cap, uint8_t*& ws, Plan& P) {
+    constexpr size_t kGroup = 15;   // Algorithm 2: groups of at most t - 1 for a 16-value lookup
+    // the main loop alone: one step per anti-diagonal t = 1 .. smax, each
+    // followed by a refresh step when one is due
+    Plan Pd;
+    build_edit_distance_plan(qs, Pd);
+    size_t smax = 0;
+    for (const auto& q : qs)
+        if (q.m && q.n) smax = std::max(smax, q.m + q.n);
+    std::vector<size_t> dp_step(smax + 1, size_t(-1)), refresh_step(smax + 1, size_t(-1));
+    {
+        size_t idx = 0;
+        for (size_t t = 1; t <= smax; ++t) {
+            dp_step[t] = idx++;
+            bool refresh = false;
+            for (const auto& q : qs) refresh |= refresh_due(q, t) && diagonal_cells(q, t) > 0;
+            if (refresh) refresh_step[t] = idx++;
+        }
+    }
+    // the pairs that need equality, in anti-diagonal order (so that the
+    // pairs of one diagonal are one range of every level buffer)
+    struct Pair {
+        size_t k, i, j;
+    };
+    std::vector<Pair> pairs;
+    std::vector<size_t> first(smax + 2, 0), count(smax + 2, 0);
+    for (size_t s = 2; s <= smax; ++s) {
+        first[s] = pairs.size();
+        for (size_t k = 0; k < qs.size(); ++k)
+            for_diagonal(qs[k], s, [&](size_t i, size_t j) { pairs.push_back({k, i, j}); });
+        count[s] = pairs.size() - first[s];
+    }
+    const size_t D = pairs.size();
+    // merging levels: level l sums groups of cnt[l - 1] into G[l] = cnt[l]
+    const size_t L = wide_levels(c);
+    std::vector<size_t> cnt(L + 1);
+    cnt[0] = c;
+    for (size_t l = 1; l <= L; ++l) cnt[l] = (cnt[l - 1] + kGroup - 1) / kGroup;
+    std::vector<uint64_t*> buf(L + 1, nullptr);   // [D][cnt[l]]: chunk outputs (l = 0), level-l sums
+    if (c > 1)
+        for (size_t l = 0; l <= L; ++l) {
+            buf[l] = reinterpret_cast<uint64_t*>(ws);
+            ws += align256(sizeof(uint64_t) * D * cnt[l] * W);
+        }
+    auto eq9_of = [&](const Pair& x) {
+        return wq[x.k].eq9 + ((x.i - 1) * qs[x.k].n + (x.j - 1)) * W;
+    };
+    // stage 0 of diagonal s: the chunk sub-equalities PBS(x_k - y_k; LUT_eq)
+    // (LUT_eq9 into eq9 when one chunk is the whole symbol), placed in order
+    std::vector<size_t> placed0(smax + 2, 0);
+    Builder b(P);
+    auto place0 = [&](size_t s, size_t n) {
+        const size_t total = count[s] * c;
+        for (size_t e = 0; e < n && placed0[s] < total; ++e, ++placed0[s]) {
+            const size_t d = first[s] + placed0[s] / c, kk = placed0[s] % c;
+            const Pair& x = pairs[d];
+            Job J = blank_job();
+            J.src[0] = wq[x.k].A + ((x.i - 1) * c + kk) * W;
+            J.src[1] = wq[x.k].B + ((x.j - 1) * c + kk) * W;
+            J.coef[0] = 1;
+            J.coef[1] = -1;
+            J.lut = c == 1 ? LVS_LUT_EQ9 : LVS_LUT_EQ;
+            J.dst[2] = c == 1 ? eq9_of(x) : buf[0] + (d * c + kk) * W;
+            b.add(J);
+        }
+    };
+    // Slot t holds the cells of anti-diagonal t and, for diagonal s, stage 0
+    // at slot s - (L + 1) and merging level l at slot s - (L + 1) + l (its
+    // group sums as a linear step just before), so every eq9 of diagonal s is
+    // written at slot s - 1.  Stage 0 may run earlier: the last partial
+    // device round of a slot is filled with stage-0 jobs of later diagonals,
+    // earliest first.
+    const long S = long(L) + 1;
+    for (long t = 2 - S; t <= long(smax); ++t) {
+        for (size_t l = 1; l <= L; ++l) {
+            const long s = t + S - long(l);
+            if (s < 2 || s > long(smax) || count[size_t(s)] == 0) continue;
+            const size_t f = first[size_t(s)];
+            P.sums.push_back({buf[l - 1] + f * cnt[l - 1] * W, buf[l] + f * cnt[l] * W, count[size_t(s)],
+                              int(cnt[l - 1]), int(cnt[l]), int(kGroup)});
+            P.steps.push_back({P.jobs.size(), 0, int(P.sums.size() - 1)});
+        }
+        b.step();
+        if (t >= 1) {
+            const PlanStep& st = Pd.steps[dp_step[size_t(t)]];
+            for (size_t x = st.off; x < st.off + st.count; ++x) b.add(Pd.jobs[x]);
+        }
+        for (size_t l = 1; l <= L; ++l) {
+            const long s = t + S - long(l);
+            if (s < 2 || s > long(smax)) continue;
+            for (size_t d = first[size_t(s)]; d < first[size_t(s)] + count[size_t(s)]; ++d)
+                for (size_t g = 0; g < cnt[l]; ++g) {
+                    const size_t size = std::min(cnt[l - 1], (g + 1) * kGroup) - g * kGroup;
+                    uint64_t* sum = buf[l] + (d * cnt[l] + g) * W;
+                    Job J = blank_job();
+                    J.src[0] = sum;
+                    J.coef[0] = 1;
+                    J.delta = uint64_t(kGroup - size) * kOne;
+                    J.lut = cnt[l] == 1 ? LVS_LUT_MAX9 : LVS_LUT_MAX;
+                    J.dst[2] = cnt[l] == 1 ? eq9_of(pairs[d]) : sum;
+                    b.add(J);
+                }
+        }
+        const long s0 = t + S;
+        if (s0 >= 2 && s0 <= long(smax)) place0(size_t(s0), size_t(-1));
+        if (quantum > 0) {
+            size_t target = (P.steps.back().count + quantum - 1) / quantum * quantum;
+            if (cap > 0) target = std::min(target, cap);
+            for (long s = std::max<long>(s0 + 1, 2); s <= long(smax) && P.steps.back().count < target; ++s)
+                place0(size_t(s), target - P.steps.back().count);
+        }
+        if (t >= 1 && refresh_step[size_t(t)] != size_t(-1)) {
+            b.step();
+            const PlanStep& st = Pd.steps[refresh_step[size_t(t)]];
+            for (size_t x = st.off; x < st.off + st.count; ++x) b.add(Pd.jobs[x]);
+        }
+    }
+    P.fills.insert(P.fills.end(), Pd.fills.begin(), Pd.fills.end());
+}
+
+size_t verify_plan(const Plan& P, size_t round, size_t cap, size_t* rounds) {
+    // Sweeping the steps in order: a word that some job or group sum of the
+    // plan writes may only be read (as a source or a subtrahend) once an
+    // earlier step has written it; within a step the key switch reads every
+    // source before the blind rotation writes, but the blind rotation's
+    // subtrahend reads and writes run together, so a subtrahend that another
+    // job of the same step writes, or a word two jobs of a step write, is a
+    // race.  No step may exceed cap (0: no bound).
+    auto sum_words = [](const SumOp& o, bool out, auto&& f) {
+        const size_t per = size_t(out ? o.groups : o.cnt);
+        const uint64_t* base = out ? o.out : o.in;
+        for (size_t x = 0; x < o.items * per; ++x) f(uintptr_t(base + x * W));
+    };
+    std::set<uintptr_t> produced, seen;
+    for (const Job& J : P.jobs)
+        for (int d = 0; d < 4; ++d)
+            if (J.dst[d]) produced.insert(uintptr_t(J.dst[d]));
+    for (const SumOp& o : P.sums) sum_words(o, true, [&](uintptr_t a) { produced.insert(a); });
+    size_t bad = 0, nrounds = 0;
+    const size_t r = std::max<size_t>(round, 1);
+    for (const PlanStep& S : P.steps) {
+        if (S.sum >= 0) {
+            const SumOp& o = P.sums[size_t(S.sum)];
+            sum_words(o, false, [&](uintptr_t a) { bad += produced.count(a) && !seen.count(a); });
+            sum_words(o, true, [&](uintptr_t a) { seen.insert(a); });
+            continue;
+        }
+        nrounds += (S.count + r - 1) / r;
+        if (cap && S.count > cap) ++bad;
+        std::map<uintptr_t, size_t> writer;
+        for (size_t x = S.off; x < S.off + S.count; ++x) {
+            const Job& J = P.jobs[x];
+            const void* reads[5] = {J.src[0], J.src[1], J.src[2], J.sub[0], J.sub[1]};
+            for (const void* rd : reads)
+                if (rd && produced.count(uintptr_t(rd)) && !seen.count(uintptr_t(rd))) ++bad;
+            for (int d = 0; d < 4; ++d) {
+                if (!J.dst[d]) continue;
+                auto ins = writer.emplace(uintptr_t(J.dst[d]), x);
+                if (!ins.second && ins.first->second != x) ++bad;
+            }
+        }
+        for (size_t x = S.off; x < S.off + S.count; ++x)
+            for (int k = 0; k < 2; ++k) {
+                const Job& J = P.jobs[x];
+                if (!J.sub[k]) continue;
+                auto it = writer.find(uintptr_t(J.sub[k]));
+                if (it != writer.end() && it->second != x) ++bad;
+            }
+        for (const auto& w : writer) seen.insert(w.first);
+    }
+    if (rounds) *rounds = nrounds;
+    return bad;
 }
 
 hipError_t upload_plan(Plan& P, uint8_t*& ws, hipStream_t st) {

@@ -134,6 +134,35 @@ size_t wide_max_step(size_t pairs, size_t c);
 void build_wide_equality(Plan& P, size_t pairs, size_t c, WideChunkInput (*chunk)(const void*, size_t, size_t),
                          const void* ctx, uint64_t* out, uint8_t*& ws);
 
+// Wide-symbol edit distances as one plan: the hybrid equality of every
+// in-band pair interleaved with the main loop.  qs are main-loop queries
+// (eq9_in = wq[k].eq9, buffers assigned); wq[k] gives query k's chunk
+// ciphertexts ([m][c][W], [n][c][W]) and its writable eq9 matrix.  Slot t
+// runs the cells of anti-diagonal t; diagonal s's chunk sub-equalities run by
+// slot s - 1 - levels, merging level l at slot s - 1 - levels + l (group
+// sums first), so its eq9 is ready at slot s - 1.  quantum > 0 fills each
+// slot's last partial device round with chunk sub-equalities of later
+// diagonals, never past cap (0: no bound); no step exceeds
+// wide_step_bound(qs, c) when cap is that bound.  ws is advanced past the
+// level buffers (wide_interleaved_bytes(pairs, c), pairs = every query's m n
+// at most).
+struct WideQuery {
+    const uint64_t* A;
+    const uint64_t* B;
+    uint64_t* eq9;
+};
+size_t wide_levels(size_t c);
+size_t wide_interleaved_bytes(size_t pairs, size_t c);
+size_t wide_step_bound(const std::vector<QuerySpec>& qs, size_t c);
+void build_wide_edit_distance_plan(const std::vector<QuerySpec>& qs, const std::vector<WideQuery>& wq, size_t c,
+                                   size_t quantum, size_t cap, uint8_t*& ws, Plan& P);
+
+// Host-side schedule check (nothing dereferenced): the number of reads of a
+// word the plan writes before any earlier step wrote it, of in-step races
+// (two writers, or a subtrahend another job writes) and of steps above cap
+// (0: no bound); *rounds = sum over bootstrap steps of ceil(count / round).
+size_t verify_plan(const Plan& P, size_t round, size_t cap, size_t* rounds);
+
 // Splits oversized steps, uploads the jobs into ws (advancing it) and
 // reserves the key-switch partial sums.
 hipError_t upload_plan(Plan& P, uint8_t*& ws, hipStream_t st);

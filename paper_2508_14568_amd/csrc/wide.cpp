@@ -5,8 +5,10 @@
 // A symbol of w bits is c = ceil(w / 4) ciphertexts of 4-bit chunks.  The
 // equality of a pair is one plan: a step with the c sub-equality bootstraps
 // of every pair, then per merging level a linear step (group sums) and a
-// step with one bootstrap per group.  The edit distance appends the main
-// loop over the resulting eq9 matrix to the same plan.
+// step with one bootstrap per group.  The edit distances run the same
+// bootstraps inside the main loop instead, each diagonal's equality just in
+// time for it (and earlier where a step has room), as Algorithm 4 runs the
+// equality inside its loop.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -88,23 +90,13 @@ QuerySpec eq9_query(const uint64_t* eq9, size_t m, size_t n, uint64_t* h_last, s
     return q;
 }
 
-size_t dp_max_step(size_t m, size_t n) { return 2 * std::min(m, n); }   // a refresh step: two per cell
-
-// Pairs of several queries: query k's pairs are p = first[k] + i n_k + j.
+// Several queries: query k's eq9 matrix starts at pair first[k].
 struct MultiSrc {
     std::vector<size_t> first;     // first pair of every query, then the total
     std::vector<const uint64_t*> A, B;
     std::vector<size_t> n;
     size_t c;
 };
-WideChunkInput multi_chunk(const void* ctx, size_t p, size_t k) {
-    const auto* s = static_cast<const MultiSrc*>(ctx);
-    const size_t q = size_t(std::upper_bound(s->first.begin(), s->first.end(), p) - s->first.begin()) - 1;
-    const size_t local = p - s->first[q];
-    const size_t i = local / s->n[q], j = local % s->n[q];
-    return {s->A[q] + (i * s->c + k) * W, s->B[q] + (j * s->c + k) * W, 0};
-}
-
 // The queries of a wide plan; refresh is the interval the plan uses.
 int wide_specs(const lvs_query* x, size_t nq, size_t refresh, std::vector<QuerySpec>& qs, MultiSrc& src,
                size_t c) {
@@ -141,14 +133,27 @@ int wide_specs(const lvs_query* x, size_t nq, size_t refresh, std::vector<QueryS
 }
 
 size_t wide_plan_bytes(const std::vector<QuerySpec>& qs, size_t pairs, size_t c) {
-    size_t b = align256(sizeof(uint64_t) * std::max<size_t>(pairs, 1) * W) + wide_buffer_bytes(pairs, c);
-    size_t jobs = wide_jobs(pairs, c), step = wide_max_step(pairs, c), dp_step = 0;
+    size_t b = align256(sizeof(uint64_t) * std::max<size_t>(pairs, 1) * W) + wide_interleaved_bytes(pairs, c);
+    size_t jobs = wide_jobs(pairs, c);
     for (const auto& q : qs) {
         b += query_buffer_bytes(q);
         jobs += query_jobs(q);
-        dp_step += dp_max_step(q.m, q.n);
     }
-    return b + plan_bytes(jobs, std::max(step, dp_step));
+    return b + plan_bytes(jobs, wide_step_bound(qs, c));
+}
+
+// The interleaved plan of qs (eq9 matrices carved from ws at first[k]).
+void build_wide_plan(std::vector<QuerySpec>& qs, const MultiSrc& src, size_t c, size_t quantum, uint8_t*& ws,
+                     Plan& P) {
+    uint64_t* eq9 = reinterpret_cast<uint64_t*>(ws);
+    ws += align256(sizeof(uint64_t) * std::max<size_t>(src.first.back(), 1) * W);
+    std::vector<WideQuery> wq;
+    for (size_t k = 0; k < qs.size(); ++k) {
+        qs[k].eq9_in = eq9 + src.first[k] * W;
+        wq.push_back({src.A[k], src.B[k], eq9 + src.first[k] * W});
+    }
+    assign_buffers(qs, ws);
+    build_wide_edit_distance_plan(qs, wq, c, quantum, wide_step_bound(qs, c), ws, P);
 }
 
 }  // namespace
@@ -202,10 +207,8 @@ int lvs_equality_wide(lvs_context* ctx, const uint64_t* d_a, size_t m, const uin
 
 size_t lvs_edit_distance_wide_workspace_bytes(size_t m, size_t n, unsigned width) {
     const size_t c = chunks_of(width);
-    const QuerySpec q = eq9_query(nullptr, m, n, nullptr, LVS_REFRESH_MIN);
-    return align256(sizeof(uint64_t) * std::max<size_t>(m * n, 1) * W) + wide_buffer_bytes(m * n, c) +
-           query_buffer_bytes(q) +
-           plan_bytes(wide_jobs(m * n, c) + query_jobs(q), std::max(wide_max_step(m * n, c), dp_max_step(m, n)));
+    const std::vector<QuerySpec> qs{eq9_query(nullptr, m, n, nullptr, LVS_REFRESH_MIN)};
+    return wide_plan_bytes(qs, m * n, c);
 }
 
 int lvs_edit_distance_wide(lvs_context* ctx, const uint64_t* d_a, size_t m, const uint64_t* d_b, size_t n,
@@ -227,14 +230,15 @@ int lvs_edit_distance_wide(lvs_context* ctx, const uint64_t* d_a, size_t m, cons
     if (!d_work || work_bytes < lvs_edit_distance_wide_workspace_bytes(m, n, width))
         WIDE_FAIL(LVS_E_NOMEM_DEVICE, "lvs_edit_distance_wide: workspace too small");
     uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
-    uint64_t* eq9 = reinterpret_cast<uint64_t*>(ws);
-    ws += align256(sizeof(uint64_t) * m * n * W);
-    const PairSrc src{d_a, d_b, n, c};
+    std::vector<QuerySpec> qs{eq9_query(nullptr, m, n, d_h_last, C->refresh_every)};
+    MultiSrc src;
+    src.first = {0, m * n};
+    src.A = {d_a};
+    src.B = {d_b};
+    src.n = {n};
+    src.c = c;
     Plan P;
-    build_wide_equality(P, m * n, c, pair_chunk, &src, eq9, ws);
-    std::vector<QuerySpec> qs{eq9_query(eq9, m, n, d_h_last, C->refresh_every)};
-    assign_buffers(qs, ws);
-    build_edit_distance_plan(qs, P);
+    build_wide_plan(qs, src, c, size_t(std::max(1, C->cus)), ws, P);
     return run(C, P, ws);
 }
 
@@ -271,12 +275,7 @@ int lvs_plan_create_wide(lvs_context* ctx, const lvs_query* queries, size_t nq, 
     H->kind = kPlan;
     H->C = C;
     uint8_t* ws = reinterpret_cast<uint8_t*>(d_work);
-    uint64_t* eq9 = reinterpret_cast<uint64_t*>(ws);
-    ws += align256(sizeof(uint64_t) * std::max<size_t>(pairs, 1) * W);
-    for (size_t k = 0; k < qs.size(); ++k) qs[k].eq9_in = eq9 + src.first[k] * W;
-    if (pairs) build_wide_equality(H->P, pairs, c, multi_chunk, &src, eq9, ws);
-    assign_buffers(qs, ws);
-    build_edit_distance_plan(qs, H->P);
+    build_wide_plan(qs, src, c, size_t(std::max(1, C->cus)), ws, H->P);
     hipError_t e = upload_plan(H->P, ws, C->stream);
     if (e == hipSuccess && (flags & LVS_PLAN_GRAPH)) e = capture_plan(C, H->P);
     if (e != hipSuccess) {
@@ -285,6 +284,34 @@ int lvs_plan_create_wide(lvs_context* ctx, const lvs_query* queries, size_t nq, 
         WIDE_FAIL(LVS_E_DEVICE, std::string("lvs_plan_create_wide: ") + hipGetErrorString(e));
     }
     *out = reinterpret_cast<lvs_plan*>(H);
+    return LVS_OK;
+}
+
+int lvs_plan_verify_wide(const lvs_query* queries, size_t nq, unsigned width, size_t round, size_t refresh,
+                         size_t* steps, size_t* jobs, size_t* rounds, size_t* violations) {
+    const size_t c = chunks_of(width);
+    if ((!queries && nq) || !c) WIDE_FAIL(LVS_E_INVAL, "lvs_plan_verify_wide: bad argument");
+    if (refresh != 0 && (refresh < LVS_REFRESH_MIN || refresh > LVS_REFRESH_MAX))
+        WIDE_FAIL(LVS_E_INVAL, "lvs_plan_verify_wide: bad refresh interval");
+    std::vector<QuerySpec> qs;
+    MultiSrc src;
+    const int rc = wide_specs(queries, nq, refresh, qs, src, c);
+    if (rc) return rc;
+    // workspace buffers at addresses above every caller address; nothing is dereferenced
+    uintptr_t top = 0;
+    for (size_t k = 0; k < nq; ++k)
+        for (uintptr_t a : {uintptr_t(queries[k].d_a), uintptr_t(queries[k].d_b), uintptr_t(queries[k].d_h_last),
+                            uintptr_t(queries[k].d_path)})
+            top = std::max(top, a);
+    uint8_t* ws = reinterpret_cast<uint8_t*>((top + (uintptr_t(1) << 40)) & ~uintptr_t(255));
+    Plan P;
+    build_wide_plan(qs, src, c, std::max<size_t>(round, 1), ws, P);
+    size_t nr = 0;
+    const size_t bad = verify_plan(P, round, wide_step_bound(qs, c), &nr);
+    if (steps) *steps = P.steps.size();
+    if (jobs) *jobs = P.jobs.size();
+    if (rounds) *rounds = nr;
+    if (violations) *violations = bad;
     return LVS_OK;
 }
 

@@ -78,6 +78,8 @@ _SIGS = {
     "lvs_edit_distance_clear_band": (I32, [VP, VP, SZ, VP, SZ, VP, SZ, SZ, VP, VP, SZ]),
     "lvs_plan_workspace_bytes": (I32, [VP, SZ, I32, ctypes.POINTER(SZ)]),
     "lvs_plan_create": (I32, [VP, VP, SZ, I32, I32, VP, SZ, ctypes.POINTER(VP)]),
+    "lvs_plan_verify_wide": (I32, [VP, SZ, ctypes.c_uint, SZ, SZ, ctypes.POINTER(SZ), ctypes.POINTER(SZ),
+                                   ctypes.POINTER(SZ), ctypes.POINTER(SZ)]),
     "lvs_plan_verify": (I32, [VP, SZ, I32, SZ, I32, SZ, ctypes.POINTER(SZ), ctypes.POINTER(SZ),
                               ctypes.POINTER(SZ), ctypes.POINTER(SZ)]),
     "lvs_context_set_refresh": (I32, [VP, SZ]),
@@ -621,6 +623,32 @@ def lvs_plan_verify(queries, encoding: int, round_: int, fill: bool = True, refr
                                  ctypes.byref(jb), ctypes.byref(rd), ctypes.byref(bad)))
     return st.value, jb.value, rd.value, bad.value
 
+
+
+def lvs_plan_verify_wide(queries, width: int, round_: int, refresh: int = 0):
+    """queries: (m, n, ell) tuples of wide-symbol queries (both strings
+    encrypted), ell None for the full matrix.  Buffers get placeholder
+    addresses.  Returns (steps, bootstraps, rounds, violations)."""
+    c = lvs_wide_chunks(width)
+    arr = (lvs_query * max(1, len(queries)))()
+    addr = 1 << 32
+    for k, (m, n, ell) in enumerate(queries):
+        q = arr[k]
+        q.m, q.n = m, n
+        q.d_a = addr
+        addr += (m + 1) * max(c, 1) * CT_WORDS * 8
+        q.d_b = addr
+        addr += (n + 1) * max(c, 1) * CT_WORDS * 8
+        if ell is None:
+            q.d_h_last = addr
+            addr += (n + 1) * CT_WORDS * 8
+        else:
+            q.banded, q.ell, q.d_path = 1, ell, addr
+            addr += (m + n + 1) * CT_WORDS * 8
+    st, jb, rd, bad = SZ(), SZ(), SZ(), SZ()
+    _check(lib().lvs_plan_verify_wide(arr, len(queries), width, round_, refresh, ctypes.byref(st), ctypes.byref(jb),
+                                      ctypes.byref(rd), ctypes.byref(bad)))
+    return st.value, jb.value, rd.value, bad.value
 
 def lvs_plan_run(plan: Plan):
     _check(lib().lvs_plan_run(plan))

@@ -195,3 +195,45 @@ def test_plan_schedule_is_causal_and_fills_rounds():
     _, _, rounds_filled, bad1 = L.lvs_plan_verify(qs, L.LVS_ENC_ASCII7, 256, fill=True)
     assert bad0 == bad1 == 0 and jobs == 3 * sum(m * n for m, n, _, _ in qs)
     assert rounds_filled < 0.97 * rounds_plain
+
+
+def test_wide_plan_schedule_is_causal():
+    """lvs_plan_verify_wide (host only): the wide-symbol plans that run the
+    hybrid equality (Section 4.2) inside the main loop read every word that
+    a bootstrap or a group sum writes only after an earlier step wrote it,
+    have no in-step races, stay within the workspace bound and schedule
+    every bootstrap: (chunks + merges) per in-band pair, one per cell, two
+    per cell of a refreshed diagonal.  Widths cover one chunk (no merging),
+    one merging level and two; a 32 x 32 pair of 21-bit symbols takes one
+    device round per anti-diagonal plus two lead-in rounds."""
+    import numpy as np
+    from paper_2508_14568_amd import lvs as L
+
+    def want(qs, width, R):
+        per = L.lvs_wide_pbs_per_pair(width)
+        tot = 0
+        for m, n, ell in qs:
+            cells = L.lvs_band_cells(m, n, ell) if ell is not None else m * n
+            tot += cells * (per + 1)
+            for s in range(R, m + n, R) if R else ():
+                tot += 2 * sum(1 for i in range(max(1, s - n), min(m, s - 1) + 1)
+                               if ell is None or abs(2 * i - s) <= ell)
+        return tot
+
+    rng = np.random.default_rng(9)
+    for width in (4, 21, 64):
+        for trial in range(4):
+            qs = []
+            for _ in range(int(rng.integers(1, 8))):
+                m, n = (int(x) for x in rng.integers(0, 30, size=2))
+                ell = None if rng.random() < 0.7 else int(rng.integers(0, 6))
+                qs.append((m, n, ell))
+            for R in (0, 4, 7):
+                for rnd in (64, 256):
+                    _, jobs, _, bad = L.lvs_plan_verify_wide(qs, width, rnd, refresh=R)
+                    assert bad == 0, (width, trial, R, rnd)
+                    assert jobs == want(qs, width, R), (width, trial, R)
+    _, jobs, rounds, bad = L.lvs_plan_verify_wide([(32, 32, None)], 21, 256)
+    assert bad == 0 and jobs == 32 * 32 * 8 and rounds == 65
+    with pytest.raises(L.LvsError):
+        L.lvs_plan_verify_wide([(4, 4, None)], 65, 256)
