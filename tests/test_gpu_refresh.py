@@ -243,3 +243,30 @@ def test_refresh_lowers_bottom_row_noise_dna_256(gpu):
     say(f"bottom-row error std (j >= 192): 2^{np.log2(std[0]):.2f} without refresh, "
         f"2^{np.log2(std[64]):.2f} with refresh every 64")
     assert std[0] > 1.8 * std[64]
+
+
+def test_past_the_no_refresh_length_dna_400(gpu):
+    """A 400 x 400 DNA alignment (5% edits, the DNA workload's recipe at a
+    length the noise budget refuses without refresh) with the default
+    refresh interval (anti-diagonals 256 and 512 refreshed): the exact
+    distance, every h[m, j] decoding to its plaintext difference with a
+    phase error below half the decoding threshold."""
+    say("past the no-refresh length: dna 400 x 400, default refresh")
+    g = gpu
+    L = g.L
+    a, b = W.dna_align(seed=41, length=400)
+    sa, sb = W.dna_codes(a), W.dna_codes(b)
+    m, n = len(a), len(b)
+    A = L.lvs_encrypt_string(g.ck, sa, L.LVS_ENC_DNA2, 841)
+    B = L.lvs_encrypt_string(g.ck, sb, L.LVS_ENC_DNA2, 842)
+    assert L.lvs_context_get_refresh(g.ctx) == L.LVS_REFRESH_DEFAULT
+    h = one_shot(g, A, m, B, n, L.LVS_ENC_DNA2)
+    assert L.lvs_decrypt_distance(g.ck, h, m) == P.edit_distance(a, b)
+    _, h_pl, _ = P.delta_dp(a, b)
+    err = bottom_row_error(g, h, [int(h_pl[m, j]) for j in range(1, n + 1)])
+    say(f"dna 400: bottom-row error max 2^{np.log2(np.abs(err).max()):.2f}, std 2^{np.log2(err.std()):.2f}")
+    assert np.abs(err).max() < 2.0 ** 57
+    with refresh_interval(g, 0):
+        with pytest.raises(L.LvsError) as e:
+            one_shot(g, A, m, B, n, L.LVS_ENC_DNA2)
+        assert e.value.code == -3
