@@ -422,6 +422,7 @@ int lvs_pbs_batch(lvs_context* ctx, const uint64_t* d_in, const uint8_t* lut_ids
     return execute(C, P, reinterpret_cast<uint8_t*>(d_work));
 }
 
+extern "C++" {
 namespace {
 QuerySpec pair_query(const uint64_t* d_a, size_t m, const uint64_t* d_b, size_t n, int encoding, uint64_t* h) {
     QuerySpec q;
@@ -440,6 +441,7 @@ int empty_first(Context* C, size_t n, uint64_t* d_h_last) {
     return LVS_OK;
 }
 }  // namespace
+}  // extern "C++"
 
 size_t lvs_equality_workspace_bytes(size_t m, size_t n, int encoding) {
     const size_t eq1 = encoding == LVS_ENC_ASCII7 ? align256(sizeof(uint64_t) * m * n * W) : 0;
@@ -873,18 +875,18 @@ void lvs_free(void* handle) {
         case kServer: lvs_server_free_impl(handle); break;
         case kPlan: {
             auto* H = reinterpret_cast<PlanHandle*>(handle);
-            if (H->P.graph) hipGraphExecDestroy(H->P.graph);
+            if (H->P.graph) (void)hipGraphExecDestroy(H->P.graph);   // teardown: nothing to report to
             delete H;
             break;
         }
         case kContext: {
             Context* C = reinterpret_cast<Context*>(handle);
             for (auto& t : C->timed) {
-                hipEventDestroy(t.start);
-                hipEventDestroy(t.end);
+                (void)hipEventDestroy(t.start);
+                (void)hipEventDestroy(t.end);
             }
-            for (auto e : C->spare) hipEventDestroy(e);
-            if (C->capture_stream) hipStreamDestroy(C->capture_stream);
+            for (auto e : C->spare) (void)hipEventDestroy(e);
+            if (C->capture_stream) (void)hipStreamDestroy(C->capture_stream);
             delete C;
             break;
         }

@@ -67,14 +67,22 @@ struct TimedLaunch {
     hipEvent_t a = nullptr;
     int kernel;
     uint64_t units;
+    // an event that cannot be recorded goes back to the spares and the launch
+    // is left untimed
     TimedLaunch(Context* c, int k, uint64_t u) : C(c), kernel(k), units(u) {
-        if (k >= 0 && C->profiling && (a = take_event(C))) hipEventRecord(a, C->stream);
+        if (k >= 0 && C->profiling && (a = take_event(C)) && hipEventRecord(a, C->stream) != hipSuccess) {
+            C->spare.push_back(a);
+            a = nullptr;
+        }
     }
     ~TimedLaunch() {
         if (!a) return;
         hipEvent_t b = take_event(C);
-        if (!b) return;
-        hipEventRecord(b, C->stream);
+        if (!b || hipEventRecord(b, C->stream) != hipSuccess) {
+            C->spare.push_back(a);
+            if (b) C->spare.push_back(b);
+            return;
+        }
         C->timed.push_back({a, b, kernel, units});
     }
 };

@@ -753,13 +753,13 @@ hipError_t capture_plan(Context* C, Plan& P) {
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(C->capture_stream, &g);
     if (le != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);   // the capture's own error is the one to report
         return le;
     }
     if (e != hipSuccess) return e;
     e = hipGraphInstantiate(&P.graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
-    return e;
+    const hipError_t d = hipGraphDestroy(g);   // the executable does not need the graph
+    return e != hipSuccess ? e : d;
 }
 
 }  // namespace lvs

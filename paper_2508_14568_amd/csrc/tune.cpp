@@ -102,7 +102,7 @@ int lvs_autotune(lvs_context* ctx, size_t max_batch, void* d_work, size_t work_b
     hipEvent_t e0 = nullptr, e1 = nullptr;
     TUNE_HIP(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         TUNE_FAIL(LVS_E_DEVICE, "lvs_autotune: hipEventCreate failed");
     }
     struct Result {
@@ -138,8 +138,8 @@ int lvs_autotune(lvs_context* ctx, size_t max_batch, void* d_work, size_t work_b
         }
         if (err != hipSuccess) break;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);   // a failed measurement is reported below
+    (void)hipEventDestroy(e1);
     if (err != hipSuccess) TUNE_FAIL(LVS_E_DEVICE, std::string("lvs_autotune: ") + hipGetErrorString(err));
 
     auto time_of = [&](int B, int form, int grid) {
@@ -207,8 +207,8 @@ int lvs_microbench_modmul(lvs_context* ctx, int iters, void* d_work, size_t work
     if (err == hipSuccess) err = hipEventSynchronize(e1);
     float t = 0;
     if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
-    hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     if (err != hipSuccess) TUNE_FAIL(LVS_E_DEVICE, std::string("lvs_microbench_modmul: ") + hipGetErrorString(err));
     *ms = t;
     *int_muls = double(blocks) * 256.0 * double(iters) * modmul_probe_muls_per_thread_iter();
@@ -232,8 +232,8 @@ int lvs_microbench_copy(lvs_context* ctx, const void* d_src, void* d_dst, size_t
     if (err == hipSuccess) err = hipEventSynchronize(e1);
     float t = 0;
     if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
-    hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     if (err != hipSuccess) TUNE_FAIL(LVS_E_DEVICE, std::string("lvs_microbench_copy: ") + hipGetErrorString(err));
     *ms = double(t) / reps;
     return LVS_OK;
