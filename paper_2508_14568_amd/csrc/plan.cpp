@@ -165,7 +165,8 @@ void for_diagonal(const QuerySpec& q, size_t s, F&& f) {
 
 }  // namespace
 
-void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool with_dp, size_t quantum, size_t cap) {
+void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool with_dp, size_t quantum, size_t cap,
+                              std::vector<long>* step_diag) {
     Builder b(P);
     size_t smax = 0;
     bool any_ascii = false;
@@ -269,6 +270,7 @@ void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool wi
     const size_t t0 = any_ascii ? 0 : 1;
     for (size_t t = t0; t <= smax; ++t) {
         b.step();
+        if (step_diag) step_diag->push_back(long(t));
         // deadlines: last stages of diagonal t + 1, first stages of diagonal t + 2
         if (t + 1 <= smax) {
             place2(eqd[t + 1], all);
@@ -333,6 +335,7 @@ void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool wi
         for (const auto& q : qs) refresh |= refresh_due(q, t) && diagonal_cells(q, t) > 0;
         if (!refresh) continue;
         b.step();
+        if (step_diag) step_diag->push_back(-long(t) - 1);
         for (const auto& q : qs) {
             if (!refresh_due(q, t)) continue;
             uint64_t* H = (q.h_last ? q.h_last : q.H) - W;
@@ -507,19 +510,16 @@ void build_wide_edit_distance_plan(const std::vector<QuerySpec>& qs, const std::
     // the main loop alone: one step per anti-diagonal t = 1 .. smax, each
     // followed by a refresh step when one is due
     Plan Pd;
-    build_edit_distance_plan(qs, Pd);
+    std::vector<long> step_diag;
+    build_edit_distance_plan(qs, Pd, true, 0, 0, &step_diag);
     size_t smax = 0;
     for (const auto& q : qs)
         if (q.m && q.n) smax = std::max(smax, q.m + q.n);
     std::vector<size_t> dp_step(smax + 1, size_t(-1)), refresh_step(smax + 1, size_t(-1));
-    {
-        size_t idx = 0;
-        for (size_t t = 1; t <= smax; ++t) {
-            dp_step[t] = idx++;
-            bool refresh = false;
-            for (const auto& q : qs) refresh |= refresh_due(q, t) && diagonal_cells(q, t) > 0;
-            if (refresh) refresh_step[t] = idx++;
-        }
+    for (size_t k = 0; k < step_diag.size(); ++k) {
+        const long d = step_diag[k];
+        if (d >= 0 && size_t(d) <= smax) dp_step[size_t(d)] = k;
+        else if (d < 0 && size_t(-d - 1) <= smax) refresh_step[size_t(-d - 1)] = k;
     }
     // the pairs that need equality, in anti-diagonal order (so that the
     // pairs of one diagonal are one range of every level buffer)
@@ -585,7 +585,7 @@ void build_wide_edit_distance_plan(const std::vector<QuerySpec>& qs, const std::
             P.steps.push_back({P.jobs.size(), 0, int(P.sums.size() - 1)});
         }
         b.step();
-        if (t >= 1) {
+        if (t >= 0 && dp_step[size_t(t)] != size_t(-1)) {
             const PlanStep& st = Pd.steps[dp_step[size_t(t)]];
             for (size_t x = st.off; x < st.off + st.count; ++x) b.add(Pd.jobs[x]);
         }
@@ -613,7 +613,7 @@ void build_wide_edit_distance_plan(const std::vector<QuerySpec>& qs, const std::
             for (long s = std::max<long>(s0 + 1, 2); s <= long(smax) && P.steps.back().count < target; ++s)
                 place0(size_t(s), target - P.steps.back().count);
         }
-        if (t >= 1 && refresh_step[size_t(t)] != size_t(-1)) {
+        if (t >= 0 && refresh_step[size_t(t)] != size_t(-1)) {
             b.step();
             const PlanStep& st = Pd.steps[refresh_step[size_t(t)]];
             for (size_t x = st.off; x < st.off + st.count; ++x) b.add(Pd.jobs[x]);

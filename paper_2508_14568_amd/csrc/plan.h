@@ -108,9 +108,11 @@ void assign_buffers(std::vector<QuerySpec>& qs, uint8_t*& ws);
 // anti-diagonal s = 2 .. max(m + n) holding every query's cells on it, each
 // followed by a refresh step when some query's refresh is due after it.
 // quantum: bootstraps the device runs at once (0: no filling); cap: the
-// largest step the workspace was sized for.
+// largest step the workspace was sized for.  step_diag, if given, receives
+// per main-loop step its anti-diagonal t, or -t - 1 for the refresh step
+// after diagonal t.
 void build_edit_distance_plan(const std::vector<QuerySpec>& qs, Plan& P, bool with_dp = true, size_t quantum = 0,
-                              size_t cap = 0);
+                              size_t cap = 0, std::vector<long>* step_diag = nullptr);
 
 // Jobs of the Section 5 table: T[c][i] = Enc(9 [a_i = S_c]).
 void build_preprocess_plan(const uint64_t* A, size_t m, int encoding, const std::vector<uint8_t>& syms_lo,
