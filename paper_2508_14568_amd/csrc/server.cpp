@@ -103,8 +103,11 @@ struct Request {
     Plan pre;
     size_t pre_step = 0;
     // bootstraps of the current phase already run (a phase's bootstraps are
-    // independent, so a step may run part of them)
+    // independent, so a step may run part of them), and the phase's jobs,
+    // generated when its first part is taken
     size_t taken = 0;
+    std::vector<Job> phase_jobs;
+    const SumOp* phase_sum = nullptr;
 };
 
 // Pool bytes of one request: the query, the preprocessing buffers (ASCII: the
@@ -155,7 +158,7 @@ struct Server : Handle {
     std::deque<Request*> queue;                // arrival order, not admitted yet
     std::vector<Request*> active;              // admitted, arrival order
     std::map<uint64_t, std::unique_ptr<Request>> all;
-    std::vector<Job> jobs, phase_jobs;
+    std::vector<Job> jobs;
     uint64_t steps = 0, bootstraps = 0;
 
     size_t query_syms() const { return c ? c : 2; }
@@ -476,13 +479,15 @@ int lvs_server_step(lvs_server* srv, size_t* active, size_t* queued, size_t* ste
     for (Request* r : S->active) {
         if (r->phase == kDone) continue;
         if (S->jobs.size() >= S->max_step) break;
-        S->phase_jobs.clear();
-        const SumOp* sum = nullptr;
-        S->gather(r, S->phase_jobs, &sum);
-        const size_t total = S->phase_jobs.size();
+        if (r->taken == 0) {                 // a new phase (or one no step has run yet)
+            r->phase_jobs.clear();
+            S->gather(r, r->phase_jobs, &r->phase_sum);
+        }
+        const size_t total = r->phase_jobs.size();
         const size_t n = std::min(total - r->taken, S->max_step - S->jobs.size());
-        S->jobs.insert(S->jobs.end(), S->phase_jobs.begin() + long(r->taken), S->phase_jobs.begin() + long(r->taken + n));
-        takes.push_back({r, n, total, r->taken == 0 ? sum : nullptr});
+        S->jobs.insert(S->jobs.end(), r->phase_jobs.begin() + long(r->taken),
+                       r->phase_jobs.begin() + long(r->taken + n));
+        takes.push_back({r, n, total, r->taken == 0 ? r->phase_sum : nullptr});
     }
     // end the step on a whole device round (one bootstrap per CU, two in the
     // four-wave form): the bootstraps of a partial last round wait for the
