@@ -62,6 +62,10 @@ def lib():
         L.orc_gaussian.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
         L.orc_negacyclic_mac.restype = None
         L.orc_negacyclic_mac.argtypes = [u64p, u64p, i64p, ctypes.c_int]
+        L.orc_negacyclic_mac_karatsuba.restype = None
+        L.orc_negacyclic_mac_karatsuba.argtypes = [u64p, u64p, i64p, ctypes.c_int]
+        L.orc_keys_set_karatsuba.restype = None
+        L.orc_keys_set_karatsuba.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.orc_monomial_mul.restype = None
         L.orc_monomial_mul.argtypes = [u64p, u64p, ctypes.c_int, ctypes.c_int]
         L.orc_decompose.restype = None
@@ -134,6 +138,17 @@ def negacyclic_mul(a: np.ndarray, d: np.ndarray) -> np.ndarray:
     return out
 
 
+def negacyclic_mul_karatsuba(a: np.ndarray, d: np.ndarray) -> np.ndarray:
+    """The same product through Karatsuba's recursion (exact in Z/2^64; N a
+    power of two)."""
+    a = np.ascontiguousarray(a, dtype=U64)
+    d = np.ascontiguousarray(d, dtype=np.int64)
+    out = np.zeros_like(a)
+    lib().orc_negacyclic_mac_karatsuba(_p(out, ctypes.c_uint64), _p(a, ctypes.c_uint64), _p(d, ctypes.c_int64),
+                                       a.size)
+    return out
+
+
 def monomial_mul(a: np.ndarray, e: int) -> np.ndarray:
     a = np.ascontiguousarray(a, dtype=U64)
     out = np.zeros_like(a)
@@ -165,13 +180,25 @@ def test_polynomial(f16, N: int) -> np.ndarray:
 class Keys:
     """Client and server keys drawn from one seed (see tfhe_ref.c)."""
 
-    def __init__(self, params: Params = None, seed: int = 0, nthreads: int = None):
+    def __init__(self, params: Params = None, seed: int = 0, nthreads: int = None, karatsuba: bool = False):
         self.params = params or default_params()
         self.seed = seed
         self.n, self.N = self.params.n, self.params.N
         self._h = lib().orc_keygen(ctypes.byref(self.params), seed, nthreads or default_threads())
         if not self._h:
             raise MemoryError("oracle keygen failed")
+        self.karatsuba = karatsuba
+
+    @property
+    def karatsuba(self) -> bool:
+        """Whether the blind rotation multiplies through Karatsuba's recursion
+        instead of the schoolbook sum (same words; about 4x faster)."""
+        return self._kara
+
+    @karatsuba.setter
+    def karatsuba(self, on: bool):
+        self._kara = bool(on)
+        lib().orc_keys_set_karatsuba(self._h, int(self._kara))
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -10,6 +10,9 @@
  * Everything is integer arithmetic in Z/2^64 (unsigned wrap-around).  The
  * negacyclic polynomial products are written out as the schoolbook sum that
  * defines them: (a*d)[k] = sum_{i+j=k} a_i d_j - sum_{i+j=k+N} a_i d_j.
+ * A key set may instead select Karatsuba's recursion for the blind rotation's
+ * products (orc_keys_set_karatsuba): exact in Z/2^64 as well, pinned against
+ * the schoolbook sum, about three times faster, for the full-size workloads.
  *
  * Conventions the paper leaves open (each is listed with its reading in the
  * design notes and pinned by tests):
@@ -51,6 +54,7 @@ typedef struct {
     uint8_t* S;   /* GLWE key polynomial, N bits (also the big LWE key)      */
     u64* bsk;     /* [n][2*pbs_level][2][N]: GGSW(s_i) rows, (mask, body)    */
     u64* ksk;     /* [N*ks_level][n+1]: LWE_s(S_j * 2^(64 - B*t))            */
+    int karatsuba; /* blind rotation's products: 0 schoolbook, 1 Karatsuba   */
 } orc_keys;
 
 /* ---------------------------------------------------------------- PRNG */
@@ -122,6 +126,60 @@ void orc_negacyclic_mac(u64* out, const u64* a, const i64* d, int N) {
     if (isa == 2) negacyclic_mac_avx512(out, a, d, N);
     else if (isa == 1) negacyclic_mac_avx2(out, a, d, N);
     else negacyclic_mac_plain(out, a, d, N);
+}
+
+/* Karatsuba's product of two polynomials of n coefficients (n a power of
+ * two), without reduction: c[0 .. 2n) = a * b over Z/2^64 (c[2n-1] = 0).
+ * Writing a = a0 + X^h a1 and b = b0 + X^h b1 (h = n/2),
+ *   a*b = a0 b0 + X^h ((a0 + a1)(b0 + b1) - a0 b0 - a1 b1) + X^n a1 b1,
+ * which uses only the ring's additions, subtractions and products, so the
+ * result is exact in Z/2^64.  Products of ORC_KARA_BASE coefficients (or of
+ * fewer, for a shorter polynomial) are the schoolbook double sum.  work holds
+ * at least 4n words. */
+#define ORC_KARA_BASE 8
+static void kara_full(u64* restrict c, const u64* restrict a, const u64* restrict b, int n, u64* restrict work) {
+    if (n == ORC_KARA_BASE) {          /* the base case with constant bounds */
+        u64 acc[2 * ORC_KARA_BASE] = {0};
+        for (int i = 0; i < ORC_KARA_BASE; ++i)
+            for (int j = 0; j < ORC_KARA_BASE; ++j) acc[i + j] += a[i] * b[j];
+        for (int t = 0; t < 2 * ORC_KARA_BASE; ++t) c[t] = acc[t];
+        return;
+    }
+    if (n < ORC_KARA_BASE) {
+        for (int t = 0; t < 2 * n; ++t) c[t] = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) c[i + j] += a[i] * b[j];
+        return;
+    }
+    const int h = n / 2;
+    u64* sa = work;              /* a0 + a1                         */
+    u64* sb = work + h;          /* b0 + b1                         */
+    u64* mid = work + n;         /* (a0 + a1)(b0 + b1), n words     */
+    kara_full(c, a, b, h, work + 2 * n);             /* a0 b0 -> c[0 .. n)   */
+    kara_full(c + n, a + h, b + h, h, work + 2 * n); /* a1 b1 -> c[n .. 2n)  */
+    for (int t = 0; t < h; ++t) { sa[t] = a[t] + a[h + t]; sb[t] = b[t] + b[h + t]; }
+    kara_full(mid, sa, sb, h, work + 2 * n);
+    for (int t = 0; t < n; ++t) mid[t] -= c[t] + c[n + t];
+    for (int t = 0; t < n; ++t) c[h + t] += mid[t];
+}
+
+/* out += a * d in Z_{2^64}[X]/(X^N + 1) through Karatsuba's full product,
+ * then the reduction X^N = -1: out[k] += c[k] - c[k + N].  Same words as
+ * orc_negacyclic_mac for every input (N a power of two).  buf holds 7N
+ * words of scratch. */
+static void negacyclic_mac_karatsuba_buf(u64* out, const u64* a, const i64* d, int N, u64* buf) {
+    u64* du = buf;               /* d as words of Z/2^64 (two's complement)  */
+    u64* c = buf + N;            /* the full product, 2N words               */
+    u64* work = buf + 3 * N;     /* Karatsuba's scratch, 4N words            */
+    for (int t = 0; t < N; ++t) du[t] = (u64)d[t];
+    kara_full(c, a, du, N, work);
+    for (int k = 0; k < N; ++k) out[k] += c[k] - c[k + N];
+}
+
+void orc_negacyclic_mac_karatsuba(u64* out, const u64* a, const i64* d, int N) {
+    u64* buf = (u64*)malloc(sizeof(u64) * (size_t)(7 * N));
+    negacyclic_mac_karatsuba_buf(out, a, d, N, buf);
+    free(buf);
 }
 
 /* out = X^e * a for e in [0, 2N): coefficient t takes a[(t - e) mod 2N] when
@@ -219,6 +277,10 @@ orc_keys* orc_keygen(const orc_params* p, u64 seed, int nthreads) {
     return k;
 }
 
+/* Selects how the blind rotation multiplies polynomials: 0 the schoolbook
+ * sum (the default), 1 Karatsuba's product.  Both give the same words. */
+void orc_keys_set_karatsuba(orc_keys* k, int on) { k->karatsuba = on ? 1 : 0; }
+
 void orc_keys_free(orc_keys* k) {
     if (!k) return;
     free(k->s); free(k->S); free(k->bsk); free(k->ksk); free(k);
@@ -298,6 +360,7 @@ void orc_blind_rotate(const orc_keys* k, const u64* testpoly, const u32* ms, u64
     u64* rot = (u64*)malloc(sizeof(u64) * 2 * N);
     i64* D = (i64*)malloc(sizeof(i64) * (size_t)R * N);   /* [c*L + lev][N] */
     i64 dig[64];
+    u64* kbuf = k->karatsuba ? (u64*)malloc(sizeof(u64) * 7 * (size_t)N) : NULL;
     for (int i = 0; i < n; ++i) {
         orc_monomial_mul(rot, A, (int)ms[i], N);
         orc_monomial_mul(rot + N, B, (int)ms[i], N);
@@ -310,11 +373,16 @@ void orc_blind_rotate(const orc_keys* k, const u64* testpoly, const u32* ms, u64
         for (int rho = 0; rho < R; ++rho) {
             const u64* rowA = k->bsk + (((size_t)i * R + rho) * 2 + 0) * N;
             const u64* rowB = k->bsk + (((size_t)i * R + rho) * 2 + 1) * N;
-            orc_negacyclic_mac(A, rowA, D + (size_t)rho * N, N);
-            orc_negacyclic_mac(B, rowB, D + (size_t)rho * N, N);
+            if (kbuf) {
+                negacyclic_mac_karatsuba_buf(A, rowA, D + (size_t)rho * N, N, kbuf);
+                negacyclic_mac_karatsuba_buf(B, rowB, D + (size_t)rho * N, N, kbuf);
+            } else {
+                orc_negacyclic_mac(A, rowA, D + (size_t)rho * N, N);
+                orc_negacyclic_mac(B, rowB, D + (size_t)rho * N, N);
+            }
         }
     }
-    free(rot); free(D);
+    free(rot); free(D); free(kbuf);
 }
 
 /* Sample extraction of coefficient 0 into a big-key LWE ciphertext. */

@@ -69,6 +69,67 @@ def test_negacyclic_mul_full_size_against_convolution():
     assert T.negacyclic_mul(a, d).tolist() == folded
 
 
+@pytest.mark.parametrize("N", [1, 2, 4, 8, 16, 32, 64])
+def test_negacyclic_mul_karatsuba_brute_force(N):
+    """Karatsuba's product against the big-integer double sum: below, at and
+    above its 8-coefficient schoolbook blocks (one to three recursion levels)."""
+    rng = np.random.default_rng(100 + N)
+    for _ in range(6):
+        a = rng.integers(0, 2**64 - 1, size=N, dtype=np.uint64, endpoint=True)
+        d = rng.integers(-2**22, 2**22, size=N).astype(np.int64)
+        assert T.negacyclic_mul_karatsuba(a, d).tolist() == brute_negacyclic(a, d, N)
+
+
+def test_negacyclic_mul_karatsuba_full_size_against_convolution():
+    """N = 2048 (eight recursion levels): the folded integer convolution, on
+    random operands and on the extremes (every key word 2^64 - 1 or 2^63,
+    every digit -2^22 or 2^22 - 1), where any carry or sign slip shows."""
+    N = 2048
+    rng = np.random.default_rng(6)
+    cases = [(rng.integers(0, 2**64 - 1, size=N, dtype=np.uint64, endpoint=True),
+              rng.integers(-2**22, 2**22, size=N).astype(np.int64)),
+             (np.full(N, 2**64 - 1, dtype=np.uint64), np.full(N, -2**22, dtype=np.int64)),
+             (np.full(N, 2**63, dtype=np.uint64), np.full(N, 2**22 - 1, dtype=np.int64))]
+    for a, d in cases:
+        full = np.convolve(np.array([int(x) for x in a], dtype=object), np.array([int(x) for x in d], dtype=object))
+        folded = [(full[k] - (full[k + N] if k + N < len(full) else 0)) % M64 for k in range(N)]
+        assert T.negacyclic_mul_karatsuba(a, d).tolist() == folded
+
+
+def test_negacyclic_mul_karatsuba_equals_schoolbook():
+    for N in (128, 512, 2048):
+        rng = np.random.default_rng(N)
+        for _ in range(3):
+            a = rng.integers(0, 2**64 - 1, size=N, dtype=np.uint64, endpoint=True)
+            d = rng.integers(-2**22, 2**22, size=N).astype(np.int64)
+            assert (T.negacyclic_mul_karatsuba(a, d) == T.negacyclic_mul(a, d)).all()
+
+
+def test_pbs_karatsuba_equals_schoolbook(oracle_keys):
+    """The blind rotation with Karatsuba's products gives the same words as
+    with the schoolbook sums: three bootstraps at the benchmark parameters
+    (one with a large input error) and all 32 inputs at toy parameters."""
+    k = oracle_keys
+    tp = np.stack([T.test_polynomial(P.lut_min_negated(), k.N), T.test_polynomial(P.LUT_EQ9, k.N)])
+    cts = np.stack([k.encrypt(x, 31, x) for x in (0, 7, 19)])
+    cts[2, k.N] = np.uint64((int(cts[2, k.N]) + 3 * 2**55) % M64)
+    ids = [0, 1, 0]
+    assert not k.karatsuba
+    school = k.pbs_batch(cts, tp, ids)
+    k.karatsuba = True
+    try:
+        kara = k.pbs_batch(cts, tp, ids)
+    finally:
+        k.karatsuba = False
+    assert (school == kara).all()
+    toy = T.Keys(T.toy_params(), seed=12)
+    tpt = T.test_polynomial(P.LUT_X_MINUS_4, toy.N)
+    cts = np.stack([toy.encrypt(x, 5, x) for x in range(32)])
+    school = toy.pbs_batch(cts, tpt[None], 0)
+    toy.karatsuba = True
+    assert (toy.pbs_batch(cts, tpt[None], 0) == school).all()
+
+
 def test_monomial_identities():
     N = 64
     rng = np.random.default_rng(2)
