@@ -247,7 +247,7 @@ def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos, progress=False, a
 
 
 def band_block(L, ck, ctx, nq, approx_ell):
-    """Section 3.4's skipping on the batched workload's first nq pairs: the
+    """Section 3.2's skipping on the batched workload's first nq pairs: the
     exact band (max(m, n) - floor(min(m, n) / 2), the whole matrix when the
     lengths are far apart) and a fixed half-width, each as one graph plan,
     against the full-matrix plan of the same queries."""

@@ -99,8 +99,8 @@ const char* lvs_last_error(void);
 
 /* The parameter set the kernels implement: n = 742, k = 1, N = 2048,
  * bootstrap gadget 2^23 x 1, key switch 2^3 x 5, noise 7.0698e-6 / 2.9404e-16
- * of q (the TFHE parameter set for 4-bit messages that the paper's Section
- * 6.1 runs on). */
+ * of q (the TFHE parameter set for 4-bit messages that the paper's
+ * implementation runs on, Section 6.2). */
 int lvs_params_default(lvs_params* out);
 
 /* Words per ciphertext (N + 1). */
@@ -108,18 +108,23 @@ size_t lvs_ct_words(void);
 
 /* ----------------------------------------------------------- host crypto */
 
-/* Key generation from one seed (the client draws the small LWE key, the GLWE
+/* Key generation from one seed (Section 2.2: TFHE's keys; the client keeps
+ * the secret keys, the server gets the bootstrapping and key-switching keys
+ * that let it evaluate blind).  The client draws the small LWE key, the GLWE
  * key, the bootstrapping key GGSW(s_i) and the key-switching key with a
- * counter-based SplitMix64 stream per object).  Both handles are owned by the
+ * counter-based SplitMix64 stream per object.  Both handles are owned by the
  * caller.  Cost: about a second of host time. */
 int lvs_keygen(const lvs_params* params, uint64_t seed, lvs_client_key** ck, lvs_server_key** sk);
 
 /* Encrypts symbol value mu (0..31) as ciphertext number `index` of the
- * encryption seed `seed` into h_ct (N+1 words). */
+ * encryption seed `seed` into h_ct (N+1 words): Section 2.2's plaintext space
+ * of 4 message bits and a padding bit, mu encoded as mu * 2^59 under the big
+ * key, with Gaussian noise. */
 int lvs_lwe_encrypt(const lvs_client_key* ck, uint32_t mu, uint64_t seed, uint64_t index, uint64_t* h_ct);
 
-/* Decrypts h_ct: *mu in 0..31 and, if phase_err is not NULL, the signed
- * distance of the phase from mu * 2^59. */
+/* Decrypts h_ct (Section 2.2): the phase rounded to the nearest multiple of
+ * 2^59 gives *mu in 0..31 and, if phase_err is not NULL, the signed distance
+ * of the phase from mu * 2^59. */
 int lvs_lwe_decrypt(const lvs_client_key* ck, const uint64_t* h_ct, uint32_t* mu, int64_t* phase_err);
 
 /* Encrypts a string (Section 2.1 notation a_1..a_m, split into symbols
@@ -293,7 +298,7 @@ int lvs_edit_distance_clear(lvs_context* ctx, const uint64_t* d_table, size_t m,
 
 /* ------------------------------------------------------------ band modes */
 
-/* Skipping irrelevant cells (Section 3.4, Algorithm 1): only the cells with
+/* Skipping irrelevant cells (Section 3.2, Algorithm 1): only the cells with
  * |i - j| <= ell are bootstrapped (and, with both strings encrypted, only
  * their character pairs get equality bootstraps); a neighbour outside the
  * band reads as the noise-free 1 of Algorithm 1's set-up.  The last row is
@@ -304,7 +309,7 @@ int lvs_edit_distance_clear(lvs_context* ctx, const uint64_t* d_table, size_t m,
  * lvs_decrypt_distance(ck, path, 0, m + n, &d).
  *
  * With ell >= lvs_band_exact(m, n) the result is the exact distance
- * (ceil(m / 2) for m = n, Section 3.4; for m != n the band has to reach the
+ * (ceil(m / 2) for m = n, Section 3.2; for m != n the band has to reach the
  * corner: max(m, n) - floor(min(m, n) / 2)).  For m = n, a smaller ell gives
  * a value never below the distance and equal to it whenever the distance is
  * at most 2 ell + 1 (approximate mode).  ell past m + n is clamped. */
@@ -388,7 +393,13 @@ int lvs_edit_distance_clear_wide(lvs_context* ctx, const uint64_t* d_table, size
  * h[m, 1..n] ([n][N+1]).  banded != 0 restricts the query to the band
  * |i - j| <= ell (see lvs_edit_distance_band); its result goes to d_path
  * ([m+n][N+1]) and d_h_last is not used.  A zero-initialised query is the
- * full matrix. */
+ * full matrix.  Optional outputs, for checking (NULL: not kept): d_trace
+ * receives every cell's bootstrap output M as an [m][n][N+1] matrix; with
+ * both strings encrypted, d_eq9 receives the [m][n][N+1] matrix of
+ * Enc(9 [a_i = b_j]) and (ASCII) d_eq1 the first-stage outputs
+ * Enc([x1_i = y1_j]) of Algorithm 3, and the plan then needs no workspace for
+ * them.  Entries outside a band are left untouched.  d_eq1 and d_eq9 must be
+ * NULL for a cleartext query and for wide-symbol plans. */
 typedef struct {
     const uint64_t* d_a;
     size_t m;
@@ -402,6 +413,9 @@ typedef struct {
     int32_t banded;
     size_t ell;
     uint64_t* d_path;
+    uint64_t* d_trace;
+    uint64_t* d_eq1;
+    uint64_t* d_eq9;
 } lvs_query;
 
 typedef struct lvs_plan lvs_plan;

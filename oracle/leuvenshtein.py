@@ -5,7 +5,7 @@ of the schoolbook TFHE oracle (``tfhe.py``):
   * Algorithm 3 / Algorithm 4 equality: z1 = x1 - y1, eq1 = PBS(z1; LUT_eq),
     z2 = 2 (x2 - y2) + (1 - eq1), eq9 = PBS(z2; LUT_eq9) for 7-bit characters
     split into a 4-bit and a 3-bit symbol (Section 4.3); one PBS on x - y for
-    2-bit DNA bases (Section 6.4 uses a single equality PBS for DNA).
+    2-bit DNA bases (Section 6.3 uses a single equality PBS for DNA).
   * Algorithm 4 main loop (j outer, i inner): key = (1 - v[i,j-1]) +
     3 (1 + h[i-1,j]) + eq9[i,j] (Eq. eq_keyeq2), M = PBS(key; LUT_min),
     v[i,j] = M - h[i-1,j], h[i,j] = M - v[i,j-1], boundary v[i,0] = h[0,j] = 1.
@@ -16,7 +16,7 @@ of the schoolbook TFHE oracle (``tfhe.py``):
     S; the main loop then reads eq9[i,j] = T[b_j][i] with no bootstrap.
   * Section 6.2 (parallelism over cells): cells on one anti-diagonal are
     independent; ``dp(..., order="diagonal")`` evaluates them as one batch.
-  * Section 3.4 / Algorithm 1 band: only cells with |i - j| <= ell are
+  * Section 3.2 / Algorithm 1 band: only cells with |i - j| <= ell are
     bootstrapped (and only their equality pairs); the result is the sum of
     the differences along the diagonal path (``dp_band``).
   * Section 3.1 noise refresh: the differences written on every R-th
@@ -251,7 +251,7 @@ def edit_distance_clear(keys: T.Keys, table: np.ndarray, alphabet, b, encoding: 
 
 def dp_band(keys: T.Keys, m: int, n: int, eq9_at, ell: int, nthreads=None, record: bool = False,
             refresh_every: int = 0):
-    """Algorithm 1 restricted to the band |i - j| <= ell (Section 3.4), cells
+    """Algorithm 1 restricted to the band |i - j| <= ell (Section 3.2), cells
     of one anti-diagonal as one batch; neighbours outside the band keep the
     OneMatrix value (a noise-free 1).  Returns the m + n ciphertexts of the
     band path (plaintext.band_path; v[1,0] is the noise-free boundary 1) and,

@@ -11,7 +11,7 @@ The cleartext definitions that the encrypted method must reproduce exactly
     (1-dv) + 3(1+dh) + 9eq of Eq. (eq_keyeq2) that Algorithms 1 and 4 use.
   * Equality tables LUT_eq and LUT_eq9, Eqs. (eq_eqlut) and (eq_eqlut9).
   * The 7-bit character split into a 4-bit and a 3-bit symbol (Section 4.3).
-  * Skipping irrelevant cells (Section 3.4, Algorithm 1's band |i - j| <= ell)
+  * Skipping irrelevant cells (Section 3.2, Algorithm 1's band |i - j| <= ell)
     with the result summed along the diagonal.
   * Equality of wide symbols (Section 4.2, the hybrid of the 4-bit
     subtraction check with Algorithm 2's merging) and the bootstrap counts
@@ -81,7 +81,7 @@ def delta_dp(a, b):
 
 
 def band_contains(i: int, j: int, ell: int) -> bool:
-    """Algorithm 1 computes cell (i, j) only when |i - j| <= ell (Section 3.4,
+    """Algorithm 1 computes cell (i, j) only when |i - j| <= ell (Section 3.2,
     skipping irrelevant cells; Algorithm 4 prints '<', Algorithm 1 and the
     cell count of Eq. (eq_skip) use '<=')."""
     return abs(i - j) <= ell
@@ -93,7 +93,7 @@ def band_cell_count_formula(m: int, ell: int) -> int:
 
 
 def exact_band(m: int, n: int) -> int:
-    """Band half-width whose result is the exact distance.  Section 3.4 gives
+    """Band half-width whose result is the exact distance.  Section 3.2 gives
     ceil(max(m, n) / 2) for m = n; for m != n the band must also reach the
     corner (m, n), and max(m, n) - floor(min(m, n) / 2) covers every cell of
     an optimal path (equal to ceil(m / 2) when m = n)."""
@@ -117,7 +117,7 @@ def delta_dp_band(a, b, ell: int):
 
 
 def band_path(m: int, n: int):
-    """The differences whose sum is the banded result (Section 3.4: the
+    """The differences whose sum is the banded result (Section 3.2: the
     final row is no longer available, so the score is summed along the
     diagonal): D[k,k] - D[k-1,k-1] = v[k,k-1] + h[k,k] for k = 1..min(m, n),
     then the rest of the last row (h[m,j], j > m) or column (v[i,n], i > n).

@@ -715,6 +715,7 @@ int make_specs(const lvs_query* q, size_t nq, int encoding, size_t refresh, std:
         s.n = x.n;
         s.A = x.d_a;
         s.refresh = refresh;
+        s.trace = x.d_trace;
         LVS_REQUIRE(std::max(x.m, x.n) <= kMaxLen, LVS_E_INVAL, "lvs_plan: string longer than LVS_MAX_LEN");
         const bool banded = x.banded != 0;
         if (banded) {
@@ -728,7 +729,10 @@ int make_specs(const lvs_query* q, size_t nq, int encoding, size_t refresh, std:
         if (x.d_b) {
             s.B = x.d_b;
             LVS_REQUIRE(x.d_a || x.m == 0, LVS_E_INVAL, "lvs_plan: NULL buffer");
+            s.eq9_out = x.d_eq9;
+            s.eq1_out = encoding == LVS_ENC_ASCII7 ? x.d_eq1 : nullptr;
         } else {
+            LVS_REQUIRE(!x.d_eq1 && !x.d_eq9, LVS_E_INVAL, "lvs_plan: d_eq1 / d_eq9 given for a cleartext query");
             LVS_REQUIRE((x.d_table || x.m == 0) && (x.b_clear || x.n == 0) && (x.alphabet || x.alen == 0),
                         LVS_E_INVAL, "lvs_plan: NULL buffer (cleartext query)");
             s.table = x.d_table;
@@ -796,7 +800,8 @@ int lvs_plan_verify(const lvs_query* queries, size_t nq, int encoding, size_t ro
     uintptr_t top = 0;
     for (size_t k = 0; k < nq; ++k)
         for (uintptr_t a : {uintptr_t(queries[k].d_a), uintptr_t(queries[k].d_b), uintptr_t(queries[k].d_table),
-                            uintptr_t(queries[k].d_h_last), uintptr_t(queries[k].d_path)})
+                            uintptr_t(queries[k].d_h_last), uintptr_t(queries[k].d_path),
+                            uintptr_t(queries[k].d_trace), uintptr_t(queries[k].d_eq1), uintptr_t(queries[k].d_eq9)})
             top = std::max(top, a);
     uint8_t* ws = reinterpret_cast<uint8_t*>((top + (uintptr_t(1) << 40)) & ~uintptr_t(255));
     assign_buffers(qs, ws);

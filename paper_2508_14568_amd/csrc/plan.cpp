@@ -6,7 +6,7 @@
 // Algorithm 4) is independent of the DP; as in Algorithm 4 it runs inside
 // the loop, each stage one step ahead of the cells that read it.  The key of a cell and the
 // difference update are folded into the bootstrap's job (see launch.h).
-// With Algorithm 1's band (Section 3.4) only the pairs and cells with
+// With Algorithm 1's band (Section 3.2) only the pairs and cells with
 // |i - j| <= band get bootstraps, neighbours outside it read as Enc(1), and
 // the result is the diagonal path of differences.  Section 3.1's noise
 // refresh adds a step after every refresh-th diagonal that bootstraps the
@@ -77,8 +77,8 @@ size_t query_buffer_bytes(const QuerySpec& q) {
     size_t b = align256(sizeof(uint64_t) * (q.m + 1) * W);
     if (!q.h_last) b += align256(sizeof(uint64_t) * std::max<size_t>(q.n, 1) * W);   // row state
     if (both_encrypted(q)) {
-        b += align256(sizeof(uint64_t) * q.m * q.n * W);                     // eq9
-        if (q.encoding == LVS_ENC_ASCII7) b += align256(sizeof(uint64_t) * q.m * q.n * W);   // eq1
+        if (!q.eq9_out) b += align256(sizeof(uint64_t) * q.m * q.n * W);                     // eq9
+        if (q.encoding == LVS_ENC_ASCII7 && !q.eq1_out) b += align256(sizeof(uint64_t) * q.m * q.n * W);   // eq1
     }
     return b;
 }
@@ -107,11 +107,19 @@ void assign_buffers(std::vector<QuerySpec>& qs, uint8_t*& ws) {
             ws += align256(sizeof(uint64_t) * std::max<size_t>(q.n, 1) * W);
         }
         if (both_encrypted(q)) {
-            q.eq9 = reinterpret_cast<uint64_t*>(ws);
-            ws += align256(sizeof(uint64_t) * q.m * q.n * W);
-            if (q.encoding == LVS_ENC_ASCII7) {
-                q.eq1 = reinterpret_cast<uint64_t*>(ws);
+            if (q.eq9_out) {
+                q.eq9 = q.eq9_out;
+            } else {
+                q.eq9 = reinterpret_cast<uint64_t*>(ws);
                 ws += align256(sizeof(uint64_t) * q.m * q.n * W);
+            }
+            if (q.encoding == LVS_ENC_ASCII7) {
+                if (q.eq1_out) {
+                    q.eq1 = q.eq1_out;
+                } else {
+                    q.eq1 = reinterpret_cast<uint64_t*>(ws);
+                    ws += align256(sizeof(uint64_t) * q.m * q.n * W);
+                }
             }
         }
     }
@@ -625,11 +633,13 @@ void build_wide_edit_distance_plan(const std::vector<QuerySpec>& qs, const std::
 size_t verify_plan(const Plan& P, size_t round, size_t cap, size_t* rounds) {
     // Sweeping the steps in order: a word that some job or group sum of the
     // plan writes may only be read (as a source or a subtrahend) once an
-    // earlier step has written it; within a step the key switch reads every
-    // source before the blind rotation writes, but the blind rotation's
-    // subtrahend reads and writes run together, so a subtrahend that another
-    // job of the same step writes, or a word two jobs of a step write, is a
-    // race.  No step may exceed cap (0: no bound).
+    // earlier step has written it.  Within a step the key switch reads the
+    // sources' masks in a launch of its own, but the blind rotation reads
+    // every source's body word and every subtrahend while other workgroups
+    // of the same launch write their outputs, so a source or subtrahend that
+    // another job of the same step writes, or a word two jobs of a step
+    // write, is a race (a job may read what it writes itself: an in-place
+    // refresh).  No step may exceed cap (0: no bound).
     auto sum_words = [](const SumOp& o, bool out, auto&& f) {
         const size_t per = size_t(out ? o.groups : o.cnt);
         const uint64_t* base = out ? o.out : o.in;
@@ -663,13 +673,15 @@ size_t verify_plan(const Plan& P, size_t round, size_t cap, size_t* rounds) {
                 if (!ins.second && ins.first->second != x) ++bad;
             }
         }
-        for (size_t x = S.off; x < S.off + S.count; ++x)
-            for (int k = 0; k < 2; ++k) {
-                const Job& J = P.jobs[x];
-                if (!J.sub[k]) continue;
-                auto it = writer.find(uintptr_t(J.sub[k]));
+        for (size_t x = S.off; x < S.off + S.count; ++x) {
+            const Job& J = P.jobs[x];
+            const void* reads[5] = {J.src[0], J.src[1], J.src[2], J.sub[0], J.sub[1]};
+            for (const void* rd : reads) {
+                if (!rd) continue;
+                auto it = writer.find(uintptr_t(rd));
                 if (it != writer.end() && it->second != x) ++bad;
             }
+        }
         for (const auto& w : writer) seen.insert(w.first);
     }
     if (rounds) *rounds = nrounds;

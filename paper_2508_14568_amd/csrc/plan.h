@@ -27,7 +27,9 @@ struct QuerySpec {
     const uint64_t* eq9_in = nullptr;       // [m][n][W] given equality matrix (Algorithm 1)
     uint64_t* h_last = nullptr;             // [n][W] result; doubles as H[1..n]
     uint64_t* trace = nullptr;              // optional [m][n][W] record of every M
-    // Algorithm 1's band (Section 3.4): only cells with |i - j| <= band are
+    uint64_t* eq1_out = nullptr;            // optional caller buffers for eq1 / eq9 (both encrypted):
+    uint64_t* eq9_out = nullptr;            //   used instead of workspace when set
+    // Algorithm 1's band (Section 3.2): only cells with |i - j| <= band are
     // bootstrapped (band < 0: every cell); the result is then the m + n
     // differences of the diagonal path, written to path ([m+n][W]).
     long band = -1;

@@ -111,10 +111,12 @@ int wide_specs(const lvs_query* x, size_t nq, size_t refresh, std::vector<QueryS
         if (std::max(y.m, y.n) > size_t(LVS_MAX_LEN)) WIDE_FAIL(LVS_E_INVAL, "lvs_plan_wide: string longer than LVS_MAX_LEN");
         if (y.d_table || (!y.d_a && y.m) || (!y.d_b && y.n))
             WIDE_FAIL(LVS_E_INVAL, "lvs_plan_wide: every query needs both strings encrypted");
+        if (y.d_eq1 || y.d_eq9) WIDE_FAIL(LVS_E_INVAL, "lvs_plan_wide: d_eq1 / d_eq9 are not kept for wide symbols");
         QuerySpec& s = qs[k];
         s.m = y.m;
         s.n = y.n;
         s.refresh = refresh;
+        s.trace = y.d_trace;
         s.eq9_in = reinterpret_cast<const uint64_t*>(16);   // set once the workspace is carved
         if (y.banded) {
             s.band = long(std::min<size_t>(y.ell, y.m + y.n));
@@ -301,7 +303,7 @@ int lvs_plan_verify_wide(const lvs_query* queries, size_t nq, unsigned width, si
     uintptr_t top = 0;
     for (size_t k = 0; k < nq; ++k)
         for (uintptr_t a : {uintptr_t(queries[k].d_a), uintptr_t(queries[k].d_b), uintptr_t(queries[k].d_h_last),
-                            uintptr_t(queries[k].d_path)})
+                            uintptr_t(queries[k].d_path), uintptr_t(queries[k].d_trace)})
             top = std::max(top, a);
     uint8_t* ws = reinterpret_cast<uint8_t*>((top + (uintptr_t(1) << 40)) & ~uintptr_t(255));
     Plan P;

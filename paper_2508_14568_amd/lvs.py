@@ -509,7 +509,8 @@ LVS_PLAN_GRAPH = 1
 
 class lvs_query(ctypes.Structure):
     _fields_ = [("d_a", VP), ("m", SZ), ("d_b", VP), ("n", SZ), ("d_table", VP), ("alphabet", VP), ("alen", SZ),
-                ("b_clear", VP), ("d_h_last", VP), ("banded", ctypes.c_int32), ("ell", SZ), ("d_path", VP)]
+                ("b_clear", VP), ("d_h_last", VP), ("banded", ctypes.c_int32), ("ell", SZ), ("d_path", VP),
+                ("d_trace", VP), ("d_eq1", VP), ("d_eq9", VP)]
 
 
 class Plan(_Handle):
@@ -522,7 +523,8 @@ class Plan(_Handle):
 
 def make_queries(items):
     """items: dicts with d_a, m, d_h_last and either d_b, n or d_table,
-    alphabet (bytes), b_clear (bytes); optionally ell and d_path (band)."""
+    alphabet (bytes), b_clear (bytes); optionally ell and d_path (band) and
+    the checking outputs d_trace, d_eq1, d_eq9 ([m][n][N+1] device buffers)."""
     arr = (lvs_query * max(1, len(items)))()
     keep = []
     for k, it in enumerate(items):
@@ -530,6 +532,9 @@ def make_queries(items):
         q.d_a = _dptr(it.get("d_a"))
         q.m = it["m"]
         q.d_h_last = _dptr(it.get("d_h_last"))
+        q.d_trace = _dptr(it.get("d_trace"))
+        q.d_eq1 = _dptr(it.get("d_eq1"))
+        q.d_eq9 = _dptr(it.get("d_eq9"))
         if it.get("ell") is not None:
             q.banded = 1
             q.ell = it["ell"]

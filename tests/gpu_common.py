@@ -39,6 +39,21 @@ def okeys():
     return T.Keys(T.default_params(), seed=KEY_SEED)
 
 
+@pytest.fixture(scope="session")
+def okeys_kara():
+    """The oracle's keys with Karatsuba's products in the blind rotation (the
+    same words as the schoolbook sums, pinned by the oracle's tests; faster
+    for the live runs of hundreds of bootstraps)."""
+    from oracle import tfhe as T
+    return T.Keys(T.default_params(), seed=KEY_SEED, karatsuba=True)
+
+
+def oracle_threads():
+    """Host threads for live oracle runs (the GPU machine grants 16 per GPU)."""
+    import os
+    return max(1, min(16, os.cpu_count() or 1))
+
+
 def assert_same_ct(gpu_ct, oracle_ct, what=""):
     g = np.asarray(gpu_ct, dtype=np.uint64)
     o = np.asarray(oracle_ct, dtype=np.uint64)

@@ -1,4 +1,4 @@
-"""Band modes (Section 3.4, Algorithm 1's |i - j| <= ell): the path
+"""Band modes (Section 3.2, Algorithm 1's |i - j| <= ell): the path
 ciphertexts bit-exact with the oracle's banded loop, exact distances with the
 exact half-width, the approximate mode equal to the plaintext banded loop,
 the cleartext-table variant, and batch plans mixing banded and full queries

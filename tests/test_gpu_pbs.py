@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from conftest import golden
-from gpu_common import assert_same_ct, gpu, okeys, say  # noqa: F401
+from gpu_common import assert_same_ct, gpu, okeys, okeys_kara, oracle_threads, say  # noqa: F401
 from oracle import plaintext as P
 from oracle import tfhe as T
 
@@ -44,10 +44,10 @@ def test_table1_exhaustive_bit_exact(gpu, okeys):
 
 
 @pytest.mark.parametrize("name", ["eq", "eq9", "min", "refresh", "max", "max9", "table2"])
-def test_tables_exhaustive(gpu, okeys, name):
+def test_tables_exhaustive(gpu, okeys_kara, name):
     """All 32 inputs through LUT_eq, LUT_eq9, the negated-key LUT_min, the
     refresh table, the merging tables LUT_max / LUT_max9 and the printed
-    Table LUTmin; decryptions exact, 8 sampled outputs bit-exact."""
+    Table LUTmin; decryptions exact, every output bit-exact with the oracle."""
     say("tables exhaustive", name)
     g = gpu
     lut = {"eq": P.LUT_EQ, "eq9": P.LUT_EQ9, "min": P.lut_min_negated(), "refresh": P.LUT_REFRESH,
@@ -61,10 +61,9 @@ def test_tables_exhaustive(gpu, okeys, name):
     assert [g.L.lvs_lwe_decrypt(g.ck, o)[0] for o in out] == [P.negacyclic_read(lut, x) for x in range(32)]
     if name == "table2":
         assert [g.L.lvs_lwe_decrypt(g.ck, o)[0] % 16 for o in out] == golden("table2_lutmin.json")["outputs"]
-    pick = np.random.default_rng(slot).choice(32, size=8, replace=False)
-    ref = okeys.pbs_batch(cts[pick], T.test_polynomial(lut, 2048)[None, :], 0)
-    for k, x in enumerate(pick):
-        assert_same_ct(out[x], ref[k], f"{name} x={x}")
+    ref = okeys_kara.pbs_batch(cts, T.test_polynomial(lut, 2048)[None, :], 0, nthreads=oracle_threads())
+    for x in range(32):
+        assert_same_ct(out[x], ref[x], f"{name} x={x}")
 
 
 def test_mixed_luts_ragged_batch(gpu, okeys):

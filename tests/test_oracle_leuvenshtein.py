@@ -122,7 +122,7 @@ def test_small_dna_full_parameters(oracle_keys):
 
 
 def test_band_encrypted_matches_plaintext(oracle_toy_keys):
-    """Algorithm 1's band (Section 3.4) on encrypted DNA: every computed
+    """Algorithm 1's band (Section 3.2) on encrypted DNA: every computed
     difference decrypts to the plaintext banded loop's value, cells outside
     the band are never bootstrapped, and the path decrypts to the banded
     distance (exact band: the Wagner-Fischer distance)."""

@@ -178,7 +178,7 @@ def test_band_cell_count_eq_skip():
 
 
 def test_band_path_sums_wf_differences():
-    """The diagonal path of Section 3.4 telescopes: the WF matrix's own
+    """The diagonal path of Section 3.2 telescopes: the WF matrix's own
     differences along it sum to D[m, n] (independent of the banded loop)."""
     for a, b in _random_pairs(21, 300, 12):
         D = P.wagner_fischer(a, b)
@@ -189,7 +189,7 @@ def test_band_path_sums_wf_differences():
 
 
 def test_exact_band_equals_wf():
-    """Section 3.4: with ell = ceil(max(m, n) / 2) (m = n) the banded result is
+    """Section 3.2: with ell = ceil(max(m, n) / 2) (m = n) the banded result is
     the exact distance; for m != n with ell = max(m, n) - floor(min / 2)."""
     for a, b in _random_pairs(22, 1500, 14):
         assert P.band_distance(a, b, P.exact_band(len(a), len(b))) == P.edit_distance(a, b), (a, b)
@@ -199,7 +199,7 @@ def test_exact_band_equals_wf():
 def test_approximate_band_bounds():
     """m = n: the band of half-width w never returns less than the distance,
     and returns it exactly whenever D <= 2w + 1 (an optimal path with cost D
-    stays within floor(D / 2) of the diagonal, Section 3.4)."""
+    stays within floor(D / 2) of the diagonal, Section 3.2)."""
     seen_over = 0
     for a, b in _random_pairs(23, 1500, 12):
         if len(a) != len(b):

@@ -5,7 +5,7 @@ the method's arithmetic and is the one piece of code that both the HIP
 library's tests/benchmark and the CPU oracle use.
 
 The paper (arXiv 2508.14568) names no dataset: its timings use ASCII strings
-(Section 6) and a 210-base DNA pair for the MPC comparison (Section 6.4).  The
+(Section 6) and a 210-base DNA pair for the MPC comparison (Section 6.3).  The
 recipes below stand in for them:
 
   tiny_dna      2 DNA strings of 6 bases, uniform over ACGT.
@@ -140,6 +140,19 @@ def poisson_arrivals(seed: int, rate_per_s: float, count: int):
     """Arrival times (seconds from 0) of a Poisson process."""
     rng = _rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate_per_s, size=count))
+
+
+def batched_sample(seed: int = 33, count: int = 8, total: int = 256):
+    """Indices of the batched pairs whose every ciphertext is checked."""
+    return sorted(int(k) for k in _rng(seed).choice(total, size=count, replace=False))
+
+
+def serving_sample(seed: int = 55, queries: int = 2, names: int = 32, n_queries: int = 200, n_server: int = 1024):
+    """Queries and server names whose every ciphertext is checked."""
+    rng = _rng(seed)
+    q = sorted(int(k) for k in rng.choice(n_queries, size=queries, replace=False))
+    nm = sorted(int(k) for k in rng.choice(n_server, size=names, replace=False))
+    return q, nm
 
 
 def alphabet_of(strings) -> bytes:
