@@ -21,6 +21,17 @@ def golden(name):
         return json.load(f)
 
 
+def oracle_vectors(name):
+    """The oracle's stored expected values of a full-size workload
+    (tests/golden/oracle_<name>.json).  They take hours of host time to
+    write; a test whose vectors are not written yet is skipped with the
+    command that writes them."""
+    path = os.path.join(GOLDEN, f"oracle_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"oracle vectors not written: python tests/golden/make_oracle_vectors.py {name}")
+    return golden(f"oracle_{name}.json")
+
+
 @pytest.fixture(scope="session")
 def oracle_toy_keys():
     from oracle import tfhe as T

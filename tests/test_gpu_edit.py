@@ -13,7 +13,7 @@ import os
 import numpy as np
 import pytest
 
-from conftest import GOLDEN
+from conftest import GOLDEN, oracle_vectors
 from gpu_common import KEY_SEED, assert_same_ct, gpu, okeys, say  # noqa: F401
 from oracle import leuvenshtein as OL
 from oracle import plaintext as P
@@ -156,7 +156,7 @@ def test_dna_256_alignment(gpu):
     say("dna 256")
     g = gpu
     a, b = W.dna_align()
-    meta = json.load(open(os.path.join(GOLDEN, "oracle_dna_align.json")))
+    meta = oracle_vectors("dna_align")
     assert meta["a"] == a.decode() and meta["b"] == b.decode() and meta["key_seed"] == KEY_SEED
     assert (meta["seed_a"], meta["seed_b"]) == (SEED_A, SEED_B)
     refresh = g.L.lvs_context_get_refresh(g.ctx)

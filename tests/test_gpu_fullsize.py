@@ -13,13 +13,11 @@ sampled names' result rows equal the oracle's, and so do the query's
 Section 5 table and the sampled names' M ciphertexts (single-query
 preprocessing, then a cleartext plan keeping M)."""
 import hashlib
-import json
-import os
 
 import numpy as np
 import pytest
 
-from conftest import GOLDEN
+from conftest import oracle_vectors
 from gpu_common import assert_same_ct, gpu, okeys_kara, oracle_threads, say  # noqa: F401
 from oracle import leuvenshtein as OL
 from oracle import plaintext as P
@@ -64,7 +62,7 @@ def test_batched_256_pairs_full_plan(gpu, okeys_kara):
     L, torch = g.L, g.torch
     Wd = L.CT_WORDS
     pairs = W.batched()
-    meta = json.load(open(os.path.join(GOLDEN, "oracle_batched_sample.json")))
+    meta = oracle_vectors("batched_sample")
     sample = W.batched_sample()
     assert [q["index"] for q in meta["queries"]] == sample
     assert max(len(a) + len(b) for a, b in pairs) < L.lvs_context_get_refresh(g.ctx)   # no refresh step
@@ -172,7 +170,7 @@ def test_serving_sampled_queries_against_1024_names(gpu):
     L, torch = g.L, g.torch
     Wd = L.CT_WORDS
     server, queries = W.serving()
-    meta = json.load(open(os.path.join(GOLDEN, "oracle_serving_sample.json")))
+    meta = oracle_vectors("serving_sample")
     qidx, nidx = W.serving_sample()
     alpha = W.alphabet_of(server)
     assert meta["alphabet"] == alpha.decode() and [q["query"] for q in meta["queries"]] == qidx
