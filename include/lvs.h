@@ -146,6 +146,37 @@ int lvs_decrypt_distance(const lvs_client_key* ck, const uint64_t* h_last, size_
  * buf == NULL only *len (bytes) is set. */
 int lvs_key_export(const lvs_client_key* ck, const lvs_server_key* sk, int kind, void* buf, size_t* len);
 
+/* ------------------------------------------------------------ wire format */
+
+/* Records for moving keys and ciphertexts between the client, which encrypts
+ * and alone holds the secret key, and the server, which computes on the
+ * ciphertexts with the server key (the outsourcing setting of the paper's
+ * introduction).  A record is self-describing and little-endian: "LVS1", the
+ * kind, the parameter set (lvs_params), a count, the payload length, the
+ * payload and an FNV-1a checksum of the payload.  Payloads: client key = n
+ * small-key bits then N GLWE-key bits, one byte each; server key = the
+ * bootstrapping key then the key-switching key, as u64 words; ciphertexts =
+ * count x (N+1) u64 words (an encrypted string, [len][nsym], or result rows). */
+enum { LVS_WIRE_CLIENT_KEY = 1, LVS_WIRE_SERVER_KEY = 2, LVS_WIRE_CIPHERTEXTS = 3 };
+
+/* Writes the record of obj: a client key (lvs_client_key*), a server key
+ * (lvs_server_key*) or `count` host ciphertexts (const uint64_t*, [count][N+1];
+ * count is ignored for keys).  buf == NULL: only *len is set to the record's
+ * size; otherwise *len is the capacity on entry and the record's size on
+ * return (LVS_E_INVAL if the buffer is too small). */
+int lvs_export(int kind, const void* obj, size_t count, uint8_t* buf, size_t* len);
+
+/* Reads a key record into a new handle (*out: lvs_client_key* or
+ * lvs_server_key*, as *kind says; release with lvs_free).  LVS_E_INVAL for a
+ * malformed record (magic, length, checksum, payload size, key bits outside
+ * {0, 1}); LVS_E_PARAMS for a parameter set the kernels do not support. */
+int lvs_import_key(const uint8_t* buf, size_t len, int* kind, void** out);
+
+/* Reads a ciphertext record: out == NULL sets *count to the number of
+ * ciphertexts; otherwise *count is the capacity of out (in ciphertexts) on
+ * entry and the number written on return.  Errors as for lvs_import_key. */
+int lvs_import_ciphertexts(const uint8_t* buf, size_t len, uint64_t* out, size_t* count);
+
 /* --------------------------------------------------------- device context */
 
 /* Bytes of device memory lvs_context_create needs (bootstrapping key in NTT
@@ -482,6 +513,61 @@ int lvs_plan_run(lvs_plan* plan);
 
 /* Steps, bootstraps and the largest step of a plan (any may be NULL). */
 int lvs_plan_info(const lvs_plan* plan, size_t* steps, size_t* bootstraps, size_t* max_step);
+
+/* ------------------------------------------ continuous batching of queries */
+
+/* Continuous batching of general queries (Section 6.2: the cells at one
+ * distance from the first cell are independent, so the ready cells of many
+ * queries form one batch): lvs_submit queues lvs_query items (both strings
+ * encrypted, or one cleartext string with its Section 5 table; full or
+ * banded) and returns at once; a worker thread of the engine admits them in
+ * arrival order while their device state (what lvs_plan_create would carve
+ * from its workspace for the query: V, the row state, eq1, eq9) fits a
+ * first-fit pool in the caller's arena (admission by device memory), and at
+ * every engine step runs the next plan step of every admitted query, in
+ * arrival order up to max_step bootstraps and trimmed to whole device rounds,
+ * as one key-switch launch and one blind-rotation launch on the engine's own
+ * stream.  A query runs the steps its lone lvs_plan_create would run, one
+ * after the other, so its results are bit-identical alone and in any mix.
+ * The arena holds lvs_engine_fixed_bytes(max_step) bytes of job list and
+ * key-switch partials, then the pool.
+ *
+ * Buffers: every device buffer of a query (d_a, d_b, d_table, d_h_last,
+ * d_path) must be ready when lvs_submit is called (the engine's stream does
+ * not wait for the caller's stream) and stay valid, untouched, until lvs_poll
+ * reports the query done; then its results are complete in d_h_last (d_path
+ * for a banded query).  d_trace, d_eq1 and d_eq9 must be NULL.  Host buffers
+ * (alphabet, b_clear) are read during lvs_submit.  The context's refresh
+ * interval at submission applies. */
+typedef struct lvs_engine lvs_engine;
+
+/* Job list and key-switch partials for at most max_step bootstraps per step. */
+size_t lvs_engine_fixed_bytes(size_t max_step);
+
+/* Pool bytes the engine keeps for query q while it runs. */
+int lvs_engine_query_bytes(const lvs_query* q, int encoding, size_t* bytes);
+
+/* Engine for queries of one encoding; d_arena (256-byte aligned) is borrowed
+ * for the engine's lifetime.  Starts the worker thread and a stream of the
+ * context's device.  Released with lvs_free, which finishes the step in
+ * flight and stops the worker (queries not yet done are abandoned). */
+int lvs_engine_create(lvs_context* ctx, int encoding, size_t max_step, void* d_arena, size_t arena_bytes,
+                      lvs_engine** out);
+
+/* Queues nq queries (non-blocking) and writes one ticket per query.
+ * LVS_E_NOMEM_DEVICE if a query could never fit in the pool; LVS_E_ALPHABET,
+ * LVS_E_INVAL and LVS_E_NOISE_BUDGET as for lvs_plan_create; nothing is queued
+ * when any query is refused.  May be called from any thread. */
+int lvs_submit(lvs_engine* eng, const lvs_query* q, size_t nq, uint64_t* tickets);
+
+/* *done = 1 once the query's results are complete (wait != 0 blocks until
+ * then); a done ticket is released and its pool space returns to the engine.
+ * An error of the worker's device work is returned by every later call. */
+int lvs_poll(lvs_engine* eng, uint64_t ticket, int wait, int* done);
+
+/* Engine steps and bootstraps run so far, queries running and queued (any
+ * pointer may be NULL). */
+int lvs_engine_stats(lvs_engine* eng, uint64_t* steps, uint64_t* bootstraps, size_t* active, size_t* queued);
 
 /* --------------------------------------------------------------- serving */
 

@@ -10,7 +10,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblvs.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["host_crypto.cpp", "ntt_consts.cpp", "capi.cpp", "plan.cpp", "server.cpp", "tune.cpp", "wide.cpp",
+SOURCES = ["host_crypto.cpp", "ntt_consts.cpp", "wire.cpp", "capi.cpp", "plan.cpp", "server.cpp", "engine.cpp", "tune.cpp",
+           "wide.cpp",
            "kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]
@@ -21,7 +22,7 @@ DEVICE = ["-x", "hip", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-
 def _compile(src: str) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(OBJDIR, src + ".o")
-    if src.endswith(".hip") or src in ("capi.cpp", "plan.cpp", "server.cpp", "tune.cpp", "wide.cpp"):
+    if src.endswith(".hip") or src in ("capi.cpp", "plan.cpp", "server.cpp", "engine.cpp", "tune.cpp", "wide.cpp"):
         cmd = [HIPCC] + DEVICE + COMMON + ["-c", path, "-o", obj]
     else:
         cmd = [HIPCC] + COMMON + ["-c", path, "-o", obj]

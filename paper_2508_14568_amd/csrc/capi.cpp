@@ -149,6 +149,8 @@ size_t plan_ws(const std::vector<QuerySpec>& qs) {
 
 }  // namespace
 
+int check_query_lengths(const Context* C, size_t m, size_t n, const char* fn) { return check_lengths(C, m, n, fn); }
+
 void set_error(const std::string& msg) { g_error = msg; }
 
 bool params_supported(const lvs_params& p) {
@@ -702,10 +704,11 @@ int lvs_edit_distance_clear_wide(lvs_context* ctx, const uint64_t* d_table, size
 
 // ------------------------------------------------------------ batch plans
 
-namespace {
+extern "C++" {
+namespace lvs {
 // Queries of a plan; refresh is the interval the plan uses (the workspace
 // bound takes the shortest one).
-int make_specs(const lvs_query* q, size_t nq, int encoding, size_t refresh, std::vector<QuerySpec>& qs) {
+int make_query_specs(const lvs_query* q, size_t nq, int encoding, size_t refresh, std::vector<QuerySpec>& qs) {
     qs.resize(nq);
     for (size_t k = 0; k < nq; ++k) {
         const lvs_query& x = q[k];
@@ -746,12 +749,13 @@ int make_specs(const lvs_query* q, size_t nq, int encoding, size_t refresh, std:
     }
     return LVS_OK;
 }
-}  // namespace
+}  // namespace lvs
+}  // extern "C++"
 
 int lvs_plan_workspace_bytes(const lvs_query* queries, size_t nq, int encoding, size_t* bytes) {
     LVS_REQUIRE(bytes && (queries || nq == 0), LVS_E_INVAL, "lvs_plan_workspace_bytes: NULL argument");
     std::vector<QuerySpec> qs;
-    int rc = make_specs(queries, nq, encoding, LVS_REFRESH_MIN, qs);
+    int rc = make_query_specs(queries, nq, encoding, LVS_REFRESH_MIN, qs);
     if (rc) return rc;
     *bytes = plan_ws(qs);
     return LVS_OK;
@@ -763,7 +767,7 @@ int lvs_plan_create(lvs_context* ctx, const lvs_query* queries, size_t nq, int e
     LVS_REQUIRE(C && out && (queries || nq == 0), LVS_E_INVAL, "lvs_plan_create: bad argument");
     LVS_REQUIRE(valid_encoding(encoding), LVS_E_INVAL, "unknown encoding");
     std::vector<QuerySpec> qs;
-    int rc = make_specs(queries, nq, encoding, C->refresh_every, qs);
+    int rc = make_query_specs(queries, nq, encoding, C->refresh_every, qs);
     if (rc) return rc;
     for (const auto& q : qs) LVS_CHECK_LENGTHS(C, q.m, q.n, "lvs_plan_create");
     LVS_REQUIRE(d_work && work_bytes >= plan_ws(qs), LVS_E_NOMEM_DEVICE, "lvs_plan_create: workspace too small");
@@ -794,7 +798,7 @@ int lvs_plan_verify(const lvs_query* queries, size_t nq, int encoding, size_t ro
     LVS_REQUIRE(refresh == 0 || (refresh >= LVS_REFRESH_MIN && refresh <= LVS_REFRESH_MAX), LVS_E_INVAL,
                 "lvs_plan_verify: bad refresh interval");
     std::vector<QuerySpec> qs;
-    int rc = make_specs(queries, nq, encoding, refresh, qs);
+    int rc = make_query_specs(queries, nq, encoding, refresh, qs);
     if (rc) return rc;
     // workspace buffers at addresses above every caller address; nothing is dereferenced
     uintptr_t top = 0;
@@ -871,6 +875,7 @@ int lvs_profile_read(lvs_context* ctx, int kernel, double* total_ms, uint64_t* l
 }
 
 void lvs_server_free_impl(void* h);
+void lvs_engine_free_impl(void* h);
 
 void lvs_free(void* handle) {
     if (!handle) return;
@@ -878,6 +883,7 @@ void lvs_free(void* handle) {
         case kClientKey: delete reinterpret_cast<ClientKey*>(handle); break;
         case kServerKey: delete reinterpret_cast<ServerKey*>(handle); break;
         case kServer: lvs_server_free_impl(handle); break;
+        case kEngine: lvs_engine_free_impl(handle); break;
         case kPlan: {
             auto* H = reinterpret_cast<PlanHandle*>(handle);
             if (H->P.graph) (void)hipGraphExecDestroy(H->P.graph);   // teardown: nothing to report to

@@ -26,7 +26,7 @@ constexpr int kPrimeBits = 26;     // every prime is below 2^26
 
 // Every handle starts with a tag so lvs_free can dispatch.
 enum HandleKind : uint32_t { kClientKey = 0x4C565301, kServerKey = 0x4C565302, kContext = 0x4C565303, kPlan = 0x4C565304,
-                             kServer = 0x4C565305 };
+                             kServer = 0x4C565305, kEngine = 0x4C565306 };
 
 struct Handle {
     uint32_t kind;

@@ -177,4 +177,11 @@ hipError_t run_plan(Context* C, const Plan& P);
 // Captures the plan's launches into a graph executable.
 hipError_t capture_plan(Context* C, Plan& P);
 
+// Query specs of C-ABI queries, checking buffers, lengths and alphabets
+// (capi.cpp); refresh is the interval the queries use.
+int make_query_specs(const lvs_query* q, size_t nq, int encoding, size_t refresh, std::vector<QuerySpec>& qs);
+// LVS_E_INVAL past LVS_MAX_LEN, LVS_E_NOISE_BUDGET past the no-refresh depth
+// when the context's refresh is off (capi.cpp).
+int check_query_lengths(const Context* C, size_t m, size_t n, const char* fn);
+
 }  // namespace lvs

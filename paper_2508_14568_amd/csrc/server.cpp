@@ -31,6 +31,7 @@
 #include "launch.h"
 #include "lvs_internal.h"
 #include "plan.h"
+#include "pool.h"
 
 namespace lvs {
 
@@ -38,50 +39,6 @@ namespace {
 
 constexpr size_t W = kCtWords;
 constexpr uint64_t kOne = uint64_t(1) << kDeltaLog;
-
-// First-fit allocator over a byte range of the arena (offsets, 256-aligned).
-class Pool {
-public:
-    void init(size_t bytes) {
-        free_.clear();
-        if (bytes) free_[0] = bytes;
-        total_ = bytes;
-    }
-    bool alloc(size_t bytes, size_t* off) {
-        bytes = align256(bytes);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < bytes) continue;
-            *off = it->first;
-            const size_t rest = it->second - bytes;
-            const size_t at = it->first + bytes;
-            free_.erase(it);
-            if (rest) free_[at] = rest;
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        bytes = align256(bytes);
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    size_t total() const { return total_; }
-
-private:
-    std::map<size_t, size_t> free_;
-    size_t total_ = 0;
-};
 
 enum Phase { kQueued, kPre1, kPre2, kPreWide, kDp, kDone };
 

@@ -53,6 +53,9 @@ _SIGS = {
     "lvs_encrypt_string": (I32, [VP, VP, SZ, I32, U64, VP]),
     "lvs_decrypt_distance": (I32, [VP, VP, SZ, SZ, ctypes.POINTER(ctypes.c_int64)]),
     "lvs_key_export": (I32, [VP, VP, I32, VP, ctypes.POINTER(SZ)]),
+    "lvs_export": (I32, [I32, VP, SZ, VP, ctypes.POINTER(SZ)]),
+    "lvs_import_key": (I32, [VP, SZ, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(VP)]),
+    "lvs_import_ciphertexts": (I32, [VP, SZ, VP, ctypes.POINTER(SZ)]),
     "lvs_context_bytes": (I32, [ctypes.POINTER(lvs_params), ctypes.POINTER(SZ)]),
     "lvs_context_create": (I32, [VP, I32, VP, VP, SZ, ctypes.POINTER(VP)]),
     "lvs_context_set_stream": (I32, [VP, VP]),
@@ -107,6 +110,13 @@ _SIGS = {
     "lvs_server_step": (I32, [VP, ctypes.POINTER(SZ), ctypes.POINTER(SZ), ctypes.POINTER(SZ)]),
     "lvs_server_poll": (I32, [VP, U64, VP, ctypes.POINTER(ctypes.c_int)]),
     "lvs_server_stats": (I32, [VP, ctypes.POINTER(U64), ctypes.POINTER(U64)]),
+    "lvs_engine_fixed_bytes": (SZ, [SZ]),
+    "lvs_engine_query_bytes": (I32, [VP, I32, ctypes.POINTER(SZ)]),
+    "lvs_engine_create": (I32, [VP, I32, SZ, VP, SZ, ctypes.POINTER(VP)]),
+    "lvs_submit": (I32, [VP, VP, SZ, VP]),
+    "lvs_poll": (I32, [VP, U64, I32, ctypes.POINTER(ctypes.c_int)]),
+    "lvs_engine_stats": (I32, [VP, ctypes.POINTER(U64), ctypes.POINTER(U64), ctypes.POINTER(SZ),
+                               ctypes.POINTER(SZ)]),
     "lvs_context_get_tuning": (I32, [VP, VP]),
     "lvs_context_set_tuning": (I32, [VP, VP]),
     "lvs_autotune_workspace_bytes": (SZ, [SZ]),
@@ -226,6 +236,45 @@ def lvs_key_export(ck, sk, kind: int) -> np.ndarray:
     out = np.zeros(n.value, dtype=np.uint8)
     _check(lib().lvs_key_export(ck, sk, kind, _np_ptr(out), ctypes.byref(n)))
     return out if kind < 2 else out.view(np.uint64)
+
+
+# ------------------------------------------------------------ wire format
+
+LVS_WIRE_CLIENT_KEY, LVS_WIRE_SERVER_KEY, LVS_WIRE_CIPHERTEXTS = 1, 2, 3
+
+
+def lvs_export(kind: int, obj) -> bytes:
+    """Record of a key handle (LVS_WIRE_CLIENT_KEY / _SERVER_KEY) or of host
+    ciphertexts (LVS_WIRE_CIPHERTEXTS: an array of [..][N+1] words)."""
+    count, arr = 0, None
+    if kind == LVS_WIRE_CIPHERTEXTS:
+        arr = np.ascontiguousarray(obj, dtype=np.uint64).reshape(-1, CT_WORDS)
+        count, ptr = arr.shape[0], _np_ptr(arr)
+    else:
+        ptr = obj
+    n = SZ()
+    _check(lib().lvs_export(kind, ptr, count, None, ctypes.byref(n)))
+    buf = (ctypes.c_uint8 * n.value)()
+    _check(lib().lvs_export(kind, ptr, count, buf, ctypes.byref(n)))
+    return bytes(buf)
+
+
+def lvs_import_key(record: bytes):
+    """(kind, key handle) from a key record."""
+    buf = (ctypes.c_uint8 * max(1, len(record))).from_buffer_copy(record or b"\0")
+    kind, out = ctypes.c_int(), VP()
+    _check(lib().lvs_import_key(buf, len(record), ctypes.byref(kind), ctypes.byref(out)))
+    return kind.value, _Handle(out)
+
+
+def lvs_import_ciphertexts(record: bytes) -> np.ndarray:
+    """[count][N+1] words from a ciphertext record."""
+    buf = (ctypes.c_uint8 * max(1, len(record))).from_buffer_copy(record or b"\0")
+    n = SZ()
+    _check(lib().lvs_import_ciphertexts(buf, len(record), None, ctypes.byref(n)))
+    out = np.zeros((n.value, CT_WORDS), dtype=np.uint64)
+    _check(lib().lvs_import_ciphertexts(buf, len(record), _np_ptr(out) if n.value else None, ctypes.byref(n)))
+    return out
 
 
 # ------------------------------------------------------------ device side
@@ -757,6 +806,67 @@ def lvs_server_stats(srv: Server):
     st, pb = U64(), U64()
     _check(lib().lvs_server_stats(srv, ctypes.byref(st), ctypes.byref(pb)))
     return st.value, pb.value
+
+
+# ------------------------------------------------- continuous batching
+
+class Engine(_Handle):
+    """A continuous-batching engine over lvs_query items; keeps its arena and
+    the submitted queries' buffers alive until their tickets are polled done."""
+
+    def __init__(self, ptr, keep):
+        super().__init__(ptr)
+        self._keep = keep
+        self._inflight = {}
+
+
+def lvs_engine_fixed_bytes(max_step: int) -> int:
+    return lib().lvs_engine_fixed_bytes(max_step)
+
+
+def lvs_engine_query_bytes(item, encoding: int) -> int:
+    arr, keep = make_queries([item])
+    n = SZ()
+    _check(lib().lvs_engine_query_bytes(arr, encoding, ctypes.byref(n)))
+    return n.value
+
+
+def lvs_engine_create(ctx: Context, encoding: int, arena_bytes: int, max_step: int = 4096) -> Engine:
+    arena = device_buffer(arena_bytes, ctx.device)
+    out = VP()
+    _check(lib().lvs_engine_create(ctx, encoding, max_step, _dptr(arena), arena.numel() * arena.element_size(),
+                                   ctypes.byref(out)))
+    return Engine(out, (arena, ctx))
+
+
+def lvs_submit(eng: Engine, items):
+    """Queues query dicts (as for lvs_plan_create); returns their tickets.
+    The caller's current stream is synchronised first: the engine runs on a
+    stream of its own and reads the queries' device buffers as they are."""
+    _torch().cuda.current_stream().synchronize()
+    arr, keep = make_queries(items)
+    tickets = (U64 * max(1, len(items)))()
+    _check(lib().lvs_submit(eng, arr, len(items), tickets))
+    out = [int(tickets[k]) for k in range(len(items))]
+    for t, it in zip(out, items):
+        eng._inflight[t] = it
+    return out
+
+
+def lvs_poll(eng: Engine, ticket: int, wait: bool = False) -> bool:
+    """True once the query's results are complete in its d_h_last (d_path)."""
+    done = ctypes.c_int()
+    _check(lib().lvs_poll(eng, ticket, 1 if wait else 0, ctypes.byref(done)))
+    if done.value:
+        eng._inflight.pop(ticket, None)
+    return bool(done.value)
+
+
+def lvs_engine_stats(eng: Engine):
+    """(steps, bootstraps, running queries, queued queries)."""
+    st, pb, a, q = U64(), U64(), SZ(), SZ()
+    _check(lib().lvs_engine_stats(eng, ctypes.byref(st), ctypes.byref(pb), ctypes.byref(a), ctypes.byref(q)))
+    return st.value, pb.value, a.value, q.value
 
 
 # ------------------------------------------------------------------ tuning

@@ -237,3 +237,55 @@ def test_wide_plan_schedule_is_causal():
     assert bad == 0 and jobs == 32 * 32 * 8 and rounds == 65
     with pytest.raises(L.LvsError):
         L.lvs_plan_verify_wide([(4, 4, None)], 65, 256)
+
+
+def test_wire_round_trip(L, both_keys):
+    """Client key, server key and ciphertexts survive export and import word
+    for word; the imported client key encrypts and decrypts as the original."""
+    ck, sk, _ = both_keys
+    rec_ck = L.lvs_export(L.LVS_WIRE_CLIENT_KEY, ck)
+    kind, ck2 = L.lvs_import_key(rec_ck)
+    assert kind == L.LVS_WIRE_CLIENT_KEY
+    assert len(rec_ck) == 4 + 4 + 28 + 16 + 16 + 742 + 2048 + 8
+    for k in (0, 1):
+        assert np.array_equal(L.lvs_key_export(ck, sk, k), L.lvs_key_export(ck2, sk, k))
+    ct = L.lvs_encrypt_string(ck, b"kitten", L.LVS_ENC_ASCII7, 77)
+    assert np.array_equal(ct, L.lvs_encrypt_string(ck2, b"kitten", L.LVS_ENC_ASCII7, 77))
+    rec_sk = L.lvs_export(L.LVS_WIRE_SERVER_KEY, sk)
+    kind, sk2 = L.lvs_import_key(rec_sk)
+    assert kind == L.LVS_WIRE_SERVER_KEY
+    for k in (2, 3):
+        assert np.array_equal(L.lvs_key_export(ck, sk, k), L.lvs_key_export(ck, sk2, k))
+    rec_ct = L.lvs_export(L.LVS_WIRE_CIPHERTEXTS, ct)
+    back = L.lvs_import_ciphertexts(rec_ct)
+    assert back.shape == (12, L.CT_WORDS) and np.array_equal(back, ct.reshape(12, L.CT_WORDS))
+    assert [L.lvs_lwe_decrypt(ck2, c)[0] for c in back[0::2]] == [c & 15 for c in b"kitten"]
+    assert L.lvs_import_ciphertexts(L.lvs_export(L.LVS_WIRE_CIPHERTEXTS, ct[:0])).shape == (0, L.CT_WORDS)
+
+
+def test_wire_rejects_malformed(L, both_keys):
+    ck, _, _ = both_keys
+    ct = L.lvs_encrypt_string(ck, b"abc", L.LVS_ENC_ASCII7, 5)
+    rec = bytearray(L.lvs_export(L.LVS_WIRE_CIPHERTEXTS, ct))
+    bad = bytearray(rec)
+    bad[100] ^= 1                                   # a payload byte: checksum mismatch
+    with pytest.raises(L.LvsError, match="checksum") as e:
+        L.lvs_import_ciphertexts(bytes(bad))
+    assert e.value.code == -1
+    with pytest.raises(L.LvsError, match="length"):
+        L.lvs_import_ciphertexts(bytes(rec[:-1]))
+    with pytest.raises(L.LvsError, match="not an lvs record"):
+        L.lvs_import_ciphertexts(b"XXXX" + bytes(rec[4:]))
+    with pytest.raises(L.LvsError, match="no key"):
+        L.lvs_import_key(bytes(rec))
+    kd = bytearray(L.lvs_export(L.LVS_WIRE_CLIENT_KEY, ck))
+    with pytest.raises(L.LvsError, match="no ciphertexts"):
+        L.lvs_import_ciphertexts(bytes(kd))
+    kd[16] ^= 1                                     # poly_N: a parameter set the kernels lack
+    with pytest.raises(L.LvsError) as e:
+        L.lvs_import_key(bytes(kd))
+    assert e.value.code == -7
+    with pytest.raises(L.LvsError, match="unknown kind"):
+        L.lvs_export(9, ck)
+    with pytest.raises(L.LvsError, match="not a server key"):
+        L.lvs_export(L.LVS_WIRE_SERVER_KEY, ck)
