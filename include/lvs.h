@@ -268,6 +268,23 @@ size_t lvs_pbs_workspace_bytes(size_t B);
 int lvs_pbs_batch(lvs_context* ctx, const uint64_t* d_in, const uint8_t* lut_ids, int lut_id, size_t B,
                   uint64_t* d_out, void* d_work, size_t work_bytes);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid allocation): lvs_pbs_batch without a
+ * workspace, bit-identical to it.  The job list and the key switch's partial
+ * sums live in a device array of the library (about 12.3 MB per device, held
+ * by every device a context was created on until the process ends); the call
+ * allocates no memory, stages nothing through the host and does not wait on
+ * the stream.  B is at most LVS_PBS_STATIC_MAX (LVS_E_INVAL past it); d_in
+ * and d_out as for lvs_pbs_batch.  All calls on one device share the array:
+ * calls that overlap on a device (other streams, other threads, other
+ * contexts of the device) race and must be serialised by the caller.  The
+ * array needs no clearing: each call writes every word it reads.  Errors:
+ * LVS_E_INVAL, LVS_E_DEVICE (HIP error, or no context created on the
+ * device). */
+enum { LVS_PBS_STATIC_MAX = 1024 };
+int lvs_pbs_batch_static(lvs_context* ctx, const uint64_t* d_in, const uint8_t* lut_ids, int lut_id, size_t B,
+                         uint64_t* d_out);
+
 /* --------------------------------------------------------- edit distance */
 
 /* Workspace bytes for lvs_equality. */

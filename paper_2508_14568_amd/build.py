@@ -12,7 +12,7 @@ OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["host_crypto.cpp", "ntt_consts.cpp", "wire.cpp", "capi.cpp", "plan.cpp", "server.cpp", "engine.cpp", "tune.cpp",
            "wide.cpp",
-           "kernels.hip"]
+           "kernels.hip", "static_pbs.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]
 # Packed fp32 instructions stay off (no floating point is used anyway).

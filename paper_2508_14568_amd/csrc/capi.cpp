@@ -327,6 +327,7 @@ int lvs_context_create(const lvs_server_key* sk, int device, void* hip_stream, v
     hipError_t e = hipDeviceGetAttribute(&C->cus, hipDeviceAttributeMultiprocessorCount, device);
     C->latency_form_max = INT_MAX;     // the eight-wave form: faster at every batch size measured
     if (e == hipSuccess) e = prepare_kernels();
+    if (e == hipSuccess) e = static_scratch_setup(device);
     if (e == hipSuccess) e = hipMemcpy(C->tw, tw.data(), tw.size() * 4, hipMemcpyHostToDevice);
     // the 64-bit bootstrapping key is staged in the key-switching key's slot
     if (e == hipSuccess) e = hipMemcpy(C->ksk, s->bsk.data(), s->bsk.size() * 8, hipMemcpyHostToDevice);

@@ -1364,9 +1364,11 @@ size_t keyswitch_part_words(int B) {
     return most * kSmallWords;
 }
 
-hipError_t launch_keyswitch_jobs(const Job* jobs, int B, const uint64_t* ksk, uint64_t* part, hipStream_t st) {
+hipError_t launch_keyswitch_jobs(const Job* jobs, int B, const uint64_t* ksk, uint64_t* part, hipStream_t st,
+                                 int nsplit) {
     if (B <= 0) return hipSuccess;
-    const int ns = keyswitch_splits(B);
+    if (nsplit < 0 || nsplit > 64 || (nsplit & (nsplit - 1))) return hipErrorInvalidValue;
+    const int ns = nsplit ? nsplit : keyswitch_splits(B);
     dim3 grid((B + dev::kKsTile - 1) / dev::kKsTile, ns);
     const int chunk = kN / ns;   // input coefficients per split, a power of two
     hipLaunchKernelGGL(dev::keyswitch_jobs_kernel, grid, dim3(256), 0, st, jobs, B, ksk, part, chunk,
@@ -1388,12 +1390,13 @@ hipError_t prepare_kernels() {
 
 hipError_t launch_blind_rotate_jobs(const Job* jobs, int B, const uint64_t* part, const uint64_t* luts,
                                     const uint32_t* bsk, const DevTables& t, int grid, int latency_form_max,
-                                    int latency_waves, hipStream_t st) {
+                                    int latency_waves, hipStream_t st, int nsplit) {
     if (B <= 0) return hipSuccess;
+    if (nsplit < 0 || nsplit > 64 || (nsplit & (nsplit - 1))) return hipErrorInvalidValue;
     dev::BrArgs A{};
     A.jobs = jobs;
     A.part = part;
-    A.nsplit = keyswitch_splits(B);
+    A.nsplit = nsplit ? nsplit : keyswitch_splits(B);
     A.luts = luts;
     A.bsk = bsk;
     A.tw = dev::Tw{reinterpret_cast<const uint2*>(t.fwd), reinterpret_cast<const uint2*>(t.inv)};

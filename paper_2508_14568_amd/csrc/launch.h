@@ -42,14 +42,21 @@ hipError_t launch_fill_u64(uint64_t* p, size_t count, uint64_t v, hipStream_t st
 // the number of splits used (they are summed by the blind rotation).
 int keyswitch_splits(int B);
 size_t keyswitch_part_words(int B);
-hipError_t launch_keyswitch_jobs(const Job* jobs, int B, const uint64_t* ksk, uint64_t* part, hipStream_t st);
+// nsplit > 0 overrides keyswitch_splits(B) (a power of two, at most 64); the
+// blind rotation that sums the partials must be given the same count.
+hipError_t launch_keyswitch_jobs(const Job* jobs, int B, const uint64_t* ksk, uint64_t* part, hipStream_t st,
+                                 int nsplit = 0);
 // Batches of at most latency_form_max bootstraps take the one-workgroup-per-CU
 // form of the blind rotation (latency_waves 8 or 16 wavefronts), larger ones
 // the two-per-CU form.
 hipError_t launch_blind_rotate_jobs(const Job* jobs, int B, const uint64_t* part, const uint64_t* luts,
                                     const uint32_t* bsk, const DevTables& t, int grid, int latency_form_max,
-                                    int latency_waves, hipStream_t st);
+                                    int latency_waves, hipStream_t st, int nsplit = 0);
 hipError_t prepare_kernels();
+// Records the address of the no-allocation entry point's device array on
+// `device`, which must be current (static_pbs.hip); once per device.
+hipError_t static_scratch_setup(int device);
+size_t static_scratch_bytes();
 hipError_t launch_bsk_convert(const uint64_t* bsk_u64, uint32_t* out, const DevTables& t, hipStream_t st);
 hipError_t launch_trivial(uint64_t* out, int count, uint32_t mu, hipStream_t st);
 // out[item][g] = sum_{k in group g} in[item][k] for items x cnt ciphertexts in

@@ -63,6 +63,7 @@ _SIGS = {
     "lvs_sync": (I32, [VP]),
     "lvs_pbs_workspace_bytes": (SZ, [SZ]),
     "lvs_pbs_batch": (I32, [VP, VP, VP, I32, SZ, VP, VP, SZ]),
+    "lvs_pbs_batch_static": (I32, [VP, VP, VP, I32, SZ, VP]),
     "lvs_equality_workspace_bytes": (SZ, [SZ, SZ, I32]),
     "lvs_equality": (I32, [VP, VP, SZ, VP, SZ, I32, VP, VP, SZ]),
     "lvs_edit_distance_eq9_workspace_bytes": (SZ, [SZ, SZ]),
@@ -366,6 +367,20 @@ def lvs_pbs_batch(ctx: Context, d_in, B: int, d_out, lut_id: int = 0, lut_ids=No
     _check(lib().lvs_pbs_batch(ctx, _dptr(d_in), None if ids is None else _np_ptr(ids), lut_id, B, _dptr(d_out),
                                _dptr(d_work), d_work.numel() * d_work.element_size()))
     return d_work
+
+
+LVS_PBS_STATIC_MAX = 1024
+
+
+def lvs_pbs_batch_static(ctx: Context, d_in, B: int, d_out, lut_id: int = 0, lut_ids=None):
+    """lvs_pbs_batch without a workspace (the library's device array); B at
+    most LVS_PBS_STATIC_MAX.  lut_ids: optional host sequence of slots."""
+    ids = None
+    if lut_ids is not None:
+        ids = np.ascontiguousarray(np.asarray(lut_ids, dtype=np.uint8))
+        assert ids.size == B
+    _check(lib().lvs_pbs_batch_static(ctx, _dptr(d_in), None if ids is None else _np_ptr(ids), lut_id, B,
+                                      _dptr(d_out)))
 
 
 def lvs_equality_workspace_bytes(m: int, n: int, encoding: int) -> int:
