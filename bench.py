@@ -1,17 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark of the Leuvenshtein hot path on one MI355X.
 
-A step is one encrypted edit distance of the plain workload: one pair of
-32-character ASCII strings (uniform letters, 20% of positions copied),
-both encrypted -- 2 equality bootstraps per character pair (Algorithm 3) and
-one bootstrap per cell (Algorithm 1/4), 3 * 32 * 32 = 3072 bootstraps, with
-the encrypted strings resident in HBM when the timed region starts.
+Workload: the batched configuration -- 256 pairs of ASCII strings, lengths
+uniform in [8, 64] (uniform letters), both strings encrypted, as one batch
+plan: step t bootstraps every ready cell of anti-diagonal t of every query
+(one bootstrap per cell, Algorithm 1/4) together with the equality
+bootstraps of the next diagonals (2 per character pair, Algorithm 3), in one
+key-switch launch and one blind-rotation launch (Section 6.2: the cells of
+one anti-diagonal are independent).  A benchmark step is one such plan step;
+the W warm-up steps start an execution of the plan, the K timed steps
+continue it, and the execution is then completed untimed and every distance
+checked.  The encrypted strings are resident in HBM when the timed region
+starts.
 
-Prints one JSON line.  value = bootstraps per second of the whole step;
-roofline = the blind-rotation kernel's integer-multiply throughput (HIP
-events around its launches over the timed region) against the chip's
-32-bit VALU multiply peak; cpu_baseline = the oracle's bootstraps per second
-on the host cores for a bounded sample of the same bootstraps.
+Prints one JSON line.  value = bootstraps per second over the K timed
+steps; full_pass = the whole plan as one HIP graph replay (all 256 queries);
+plain = the same 256 queries one at a time through the plain per-diagonal
+path (identical work); roofline = the blind-rotation kernel's integer
+multiplies per second over the timed region (HIP events around its launches
+on the context's stream) against the chip's 32-bit VALU multiply peak; the
+other configurations follow (the 256 x 256 DNA alignment, the tiny DNA pair,
+the 32 x 32 plain pair, serving against 1024 cleartext names);
+cpu_baseline = the oracle's bootstraps per second on the host cores for a
+bounded sample of the same workload's bootstraps.
 """
 import argparse
 import hashlib
@@ -74,7 +85,7 @@ def hbm_roofline(pbs_per_launch, launch_ms):
             "bytes_per_launch": round(nbytes)}
 
 
-def cpu_baseline(workload_cts, seconds_hint=20.0):
+def cpu_baseline(workload_cts, source):
     """Oracle bootstraps per second on this host's cores (bounded sample)."""
     from oracle import leuvenshtein as OL
     from oracle import tfhe as OT
@@ -85,11 +96,19 @@ def cpu_baseline(workload_cts, seconds_hint=20.0):
     polys = OL.lut_polys(keys.N)
     sample = workload_cts[: 2 * threads]
     t0 = time.perf_counter()
-    keys.pbs_batch(sample, polys, OL.LUT_IDS["eq"], threads)
+    ref = keys.pbs_batch(sample, polys, OL.LUT_IDS["eq"], threads)
     dt = time.perf_counter() - t0
+    # the same bootstraps with the oracle's Karatsuba products (same words)
+    kkeys = OT.Keys(OT.default_params(), seed=1, nthreads=threads, karatsuba=True)
+    t0 = time.perf_counter()
+    kref = kkeys.pbs_batch(sample, polys, OL.LUT_IDS["eq"], threads)
+    dtk = time.perf_counter() - t0
+    if not np.array_equal(ref, kref):
+        raise SystemExit("cpu baseline: the oracle's two products disagree")
     return {"value": round(len(sample) / dt, 3), "unit": "PBS/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(sample)} equality bootstraps of the plain 32x32 ASCII workload "
-                      f"(z1 = x1_i - y1_j, LUT_eq), {threads} threads, {dt:.1f} s wall"}
+            "sample": f"{len(sample)} equality bootstraps of {source} "
+                      f"(z1 = x1_i - y1_j, LUT_eq), {threads} threads, {dt:.1f} s wall, schoolbook products",
+            "karatsuba": {"value": round(len(sample) / dtk, 3), "unit": "PBS/s", "seconds": round(dtk, 2)}}
 
 
 def levenshtein(a, b) -> int:
@@ -104,15 +123,17 @@ def levenshtein(a, b) -> int:
 
 
 def plain_path_time(L, ctx, items, label):
-    """Every query of items (dicts with d_a, m, d_b, n; ASCII, both
-    encrypted) once through the plain per-diagonal path, after one warm-up
-    call: (seconds, bootstraps).  Buffers are set up outside the timing."""
+    """Every query of items (dicts with d_a, m, d_b, n, d_h_last; ASCII,
+    both encrypted) once through the plain per-diagonal path into its
+    d_h_last, after one warm-up call: (seconds, bootstraps).  Buffers are set
+    up outside the timing."""
     import torch
     dev = ctx.device
     t_plain, pbs_plain = 0.0, 0
     for k, it in enumerate([items[0]] + list(items)):
         work = L.device_buffer(L.lvs_edit_distance_workspace_bytes(it["m"], it["n"], L.LVS_ENC_ASCII7), dev)
-        d_h = torch.zeros(max(1, it["n"]) * L.CT_WORDS, dtype=torch.int64, device=dev)
+        d_h = it["d_h_last"]
+        d_h.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         L.lvs_edit_distance(ctx, it["d_a"], it["m"], it["d_b"], it["n"], L.LVS_ENC_ASCII7, d_h, work)
@@ -126,64 +147,181 @@ def plain_path_time(L, ctx, items, label):
     return t_plain, pbs_plain
 
 
-def batched_block(L, ck, ctx, nq, plain_sample):
-    """The batched workload's first nq pairs (ASCII, lengths 8..64, both
-    encrypted) as one graph-captured plan, against the same kind of query run
-    one at a time through the plain per-diagonal path."""
+def encrypt_pairs(L, ck, pairs, seed0, dev, enc=None):
+    """Device items (d_a, m, d_b, n, d_h_last) of encrypted string pairs."""
+    import torch
+    enc = L.LVS_ENC_ASCII7 if enc is None else enc
+    items = []
+    for k, (a, b) in enumerate(pairs):
+        dA = L.to_device(L.lvs_encrypt_string(ck, a, enc, seed0 + 2 * k), dev)
+        dB = L.to_device(L.lvs_encrypt_string(ck, b, enc, seed0 + 2 * k + 1), dev)
+        items.append({"d_a": dA, "m": len(a), "d_b": dB, "n": len(b),
+                      "d_h_last": torch.zeros(max(1, len(b)) * L.CT_WORDS, dtype=torch.int64, device=dev)})
+    return items
+
+
+def check_distances(L, ck, pairs, items, what):
+    for k, ((a, b), it) in enumerate(zip(pairs, items)):
+        h = L.to_host(it["d_h_last"]).reshape(-1, L.CT_WORDS)[:len(b)]
+        if L.lvs_decrypt_distance(ck, h, len(a)) != levenshtein(a, b):
+            raise SystemExit(f"{what}: wrong distance for pair {k}")
+
+
+def kernel_roofline(L, ctx, steps):
+    """The blind-rotation form with the most time among the launches profiled
+    since lvs_profile_enable: its integer multiplies per second (HIP events
+    around each launch on the context's stream) against the multiply peak."""
+    forms = {name: L.lvs_profile_read(ctx, k) for name, k in
+             (("blind_rotate_latency_kernel", L.KERNEL_BLIND_ROTATE_LATENCY),
+              ("blind_rotate_kernel", L.KERNEL_BLIND_ROTATE_THROUGHPUT),
+              ("blind_rotate_w16_kernel", L.KERNEL_BLIND_ROTATE_W16),
+              ("blind_rotate_pair_kernel", L.KERNEL_BLIND_ROTATE_PAIR))}
+    br_ms, _, _ = L.lvs_profile_read(ctx, L.KERNEL_BLIND_ROTATE)
+    ks_ms, _, _ = L.lvs_profile_read(ctx, L.KERNEL_KEYSWITCH)
+    kname = max(forms, key=lambda k: forms[k][0])
+    k_ms, k_launches, k_pbs = forms[kname]
+    if k_launches == 0 or k_ms <= 0:
+        raise SystemExit("no blind-rotation launch was timed")
+    avg_launch_ms = k_ms / max(1, k_launches)
+    avg_pbs_launch = k_pbs / max(1, k_launches)
+    achieved = INT_MUL_PER_PBS * avg_pbs_launch / (avg_launch_ms / 1000) / 1e12
+    return {
+        "bound": "alu", "kernel": kname,
+        "achieved": round(achieved, 3), "peak": round(VALU_INT_MUL_PEAK_TOPS, 3), "unit": "TOP/s",
+        "frac": round(achieved / VALU_INT_MUL_PEAK_TOPS, 4),
+        "traffic": traffic_per_launch(kname, avg_pbs_launch),
+        "ops": "32-bit integer multiplies, 3 per modular multiplication, "
+               f"{INT_MUL_PER_PBS} per bootstrap",
+        "avg_launch_ms": round(avg_launch_ms, 4), "launches": k_launches,
+        "avg_pbs_per_launch": round(avg_pbs_launch, 2),
+        "hbm": hbm_roofline(avg_pbs_launch, avg_launch_ms),
+        "other_form": {k: {"ms_per_step": round(v[0] / steps, 3), "launches": v[1], "pbs": v[2]}
+                       for k, v in forms.items() if k != kname},
+        "keyswitch_ms_per_step": round(ks_ms / steps, 3),
+        "blind_rotate_ms_per_step": round(br_ms / steps, 3),
+    }
+
+
+def run_global_steps(L, plan, nsteps, g0, g1):
+    """Plan steps g0 .. g1 - 1 of a sequence of executions (global step g is
+    step g % nsteps of execution g // nsteps)."""
+    g = g0
+    while g < g1:
+        first = g % nsteps
+        count = min(nsteps - first, g1 - g)
+        L.lvs_plan_run_steps(plan, first, count)
+        g += count
+
+
+def batched_headline(L, ck, ctx, warmup, steps, plain_sample, only_timed=False):
+    """The 256-pair batched workload: K timed plan steps after W warm-up
+    steps (the value), the whole plan as one graph replay, and the same
+    queries through the plain per-diagonal path."""
     import torch
     import workloads as W
-    pairs = W.batched()[:nq]
+    pairs = W.batched()
     dev = ctx.device
-    items, outs, keep = [], [], []
-    for k, (a, b) in enumerate(pairs):
-        dA = L.to_device(L.lvs_encrypt_string(ck, a, L.LVS_ENC_ASCII7, 20000 + 2 * k), dev)
-        dB = L.to_device(L.lvs_encrypt_string(ck, b, L.LVS_ENC_ASCII7, 20001 + 2 * k), dev)
-        d_h = torch.zeros(len(b) * L.CT_WORDS, dtype=torch.int64, device=dev)
-        keep += [dA, dB]
-        outs.append(d_h)
-        items.append({"d_a": dA, "m": len(a), "d_b": dB, "n": len(b), "d_h_last": d_h})
-    note(f"batched: {nq} queries as one graph plan")
+    note("batched: encrypting 256 pairs")
+    items = encrypt_pairs(L, ck, pairs, 20000, dev)
+    note("batched: plan (256 queries, graph captured)")
     plan = L.lvs_plan_create(ctx, items, L.LVS_ENC_ASCII7, graph=True)
-    steps, pbs, max_step = L.lvs_plan_info(plan)
-    L.lvs_plan_run(plan)                       # warm-up
+    nsteps, pbs, max_step = L.lvs_plan_info(plan)
+    sizes = L.lvs_plan_step_bootstraps(plan)
+    cells = sum(len(a) * len(b) for a, b in pairs)
+    # warm-up steps, then the timed steps, continuing the same execution
+    note(f"batched: {warmup} warm-up plan steps, {steps} timed")
+    run_global_steps(L, plan, nsteps, 0, warmup)
+    torch.cuda.synchronize()
+    L.lvs_profile_enable(ctx, True)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    assert stream.cuda_stream == ctx.stream_handle, "the context runs on torch's current stream"
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    run_global_steps(L, plan, nsteps, warmup, warmup + steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    timed_ms = start.elapsed_time(end)
+    roofline = kernel_roofline(L, ctx, steps)
+    L.lvs_profile_enable(ctx, False)
+    timed_pbs = sum(sizes[g % nsteps] for g in range(warmup, warmup + steps))
+    if only_timed:
+        return {"timed_pbs": timed_pbs, "timed_ms": round(timed_ms, 3), "roofline": roofline}, None, None
+    # complete the execution the timed steps belong to, then check it
+    g_end = warmup + steps
+    run_global_steps(L, plan, nsteps, g_end, -(-g_end // nsteps) * nsteps)
+    torch.cuda.synchronize()
+    check_distances(L, ck, pairs, items, "batched (steps)")
+    head = {"timed_pbs": timed_pbs, "timed_ms": round(timed_ms, 3), "wall_s": round(wall, 3),
+            "plan_steps": nsteps, "plan_pbs": pbs, "max_step": max_step, "cells": cells,
+            "timed_step_range": [warmup % nsteps, (warmup + steps - 1) % nsteps],
+            "roofline": roofline}
+    # the whole plan as one graph replay
+    note("batched: whole plan, one graph replay")
+    for it in items:
+        it["d_h_last"].zero_()
+    L.lvs_profile_enable(ctx, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     L.lvs_plan_run(plan)
     torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    L.lvs_profile_enable(ctx, True)
-    L.lvs_plan_run(plan)
+    dt = time.perf_counter() - t0
     g_ms, g_runs, _ = L.lvs_profile_read(ctx, L.KERNEL_GRAPH)
     L.lvs_profile_enable(ctx, False)
-    for (a, b), d_h in zip(pairs, outs):
-        h = L.to_host(d_h).reshape(len(b), L.CT_WORDS)
-        if L.lvs_decrypt_distance(ck, h, len(a)) != levenshtein(a, b):
-            raise SystemExit("batched: wrong distance")
-    # the same queries one at a time through the plain path (identical work;
-    # plain_sample < nq times only the first ones)
-    n_plain = nq if plain_sample <= 0 else min(plain_sample, nq)
+    check_distances(L, ck, pairs, items, "batched (graph)")
+    del plan
+    full = {"queries": 256, "pbs": pbs, "cells": cells, "steps": nsteps, "seconds": round(dt, 3),
+            "graph_ms": round(g_ms / max(1, g_runs), 3), "pbs_per_s": round(pbs / dt, 1),
+            "cells_per_s": round(cells / dt, 1), "queries_per_s": round(256 / dt, 3),
+            "roofline_graph": {"bound": "alu",
+                               "achieved": round(INT_MUL_PER_PBS * pbs / (g_ms / g_runs / 1e3) / 1e12, 3),
+                               "peak": round(VALU_INT_MUL_PEAK_TOPS, 3), "unit": "TOP/s",
+                               "frac": round(INT_MUL_PER_PBS * pbs / (g_ms / g_runs / 1e3) / 1e12
+                                             / VALU_INT_MUL_PEAK_TOPS, 4)}}
+    # the same 256 queries one at a time through the plain path
+    n_plain = 256 if plain_sample <= 0 else min(plain_sample, 256)
     note(f"batched: {n_plain} queries through the plain path")
-    t_plain, pbs_plain = plain_path_time(L, ctx, items[:n_plain], "batched")
-    cells = sum(len(a) * len(b) for a, b in pairs)
-    batched_pbs_s = pbs / t_batch
+    t_plain, pbs_plain = plain_path_time(L, ctx, items[:n_plain], "plain")
+    check_distances(L, ck, pairs[:n_plain], items[:n_plain], "plain path")
     plain_pbs_s = pbs_plain / t_plain
-    return {
-        "workload": f"batched_ascii first {nq} of 256 pairs, lengths 8..64",
-        "queries": nq, "pbs": pbs, "cells": cells, "steps": steps, "max_step": max_step,
-        "seconds": round(t_batch, 3), "pbs_per_s": round(batched_pbs_s, 1),
-        "cells_per_s": round(cells / t_batch, 1), "queries_per_s": round(nq / t_batch, 3),
-        "plain_queries": n_plain, "plain_seconds": round(t_plain, 3), "plain_pbs_per_s": round(plain_pbs_s, 1),
-        "plain_queries_per_s": round(n_plain / t_plain, 4),
-        "plain_queries_per_s_same_work": round(nq / (pbs / plain_pbs_s), 4),
-        "speedup_vs_plain": round(batched_pbs_s / plain_pbs_s, 2),
-        # the whole graph (key switches and launch gaps included) against the
-        # blind rotation's multiply peak: a lower bound of the kernel's fraction
-        "roofline_graph": {"bound": "alu", "achieved": round(INT_MUL_PER_PBS * pbs / (g_ms / g_runs / 1e3) / 1e12, 3),
-                           "peak": round(VALU_INT_MUL_PEAK_TOPS, 3), "unit": "TOP/s",
-                           "frac": round(INT_MUL_PER_PBS * pbs / (g_ms / g_runs / 1e3) / 1e12
-                                         / VALU_INT_MUL_PEAK_TOPS, 4),
-                           "graph_ms": round(g_ms / g_runs, 3)},
-    }
+    plain = {"queries": n_plain, "identical_work": n_plain == 256, "pbs": pbs_plain, "seconds": round(t_plain, 3),
+             "pbs_per_s": round(plain_pbs_s, 1), "queries_per_s": round(n_plain / t_plain, 4),
+             "batched_speedup": round(full["pbs_per_s"] / plain_pbs_s, 2)}
+    return head, full, plain
+
+
+def plain_config(L, ck, ctx, a, b, enc, seed, reps=1):
+    """One pair through the plain per-diagonal path, after a warm-up run:
+    bootstraps per second over reps runs and the checked distance."""
+    import torch
+    dev = ctx.device
+    sa, sb = (W_codes(a), W_codes(b)) if enc == L.LVS_ENC_DNA2 else (a, b)
+    dA = L.to_device(L.lvs_encrypt_string(ck, sa, enc, seed), dev)
+    dB = L.to_device(L.lvs_encrypt_string(ck, sb, enc, seed + 1), dev)
+    d_h = torch.zeros(len(b) * L.CT_WORDS, dtype=torch.int64, device=dev)
+    work = L.device_buffer(L.lvs_edit_distance_workspace_bytes(len(a), len(b), enc), dev)
+    L.lvs_edit_distance(ctx, dA, len(a), dB, len(b), enc, d_h, work)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        L.lvs_edit_distance(ctx, dA, len(a), dB, len(b), enc, d_h, work)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    d = L.lvs_decrypt_distance(ck, L.to_host(d_h).reshape(len(b), L.CT_WORDS), len(a))
+    if d != levenshtein(a, b):
+        raise SystemExit("plain config: wrong distance")
+    per_cell = 3 if enc == L.LVS_ENC_ASCII7 else 2
+    R = L.lvs_context_get_refresh(ctx)
+    pbs = per_cell * len(a) * len(b) + refresh_pbs(len(a), len(b), R)
+    return {"m": len(a), "n": len(b), "pbs": pbs, "seconds": round(dt, 4), "pbs_per_s": round(pbs / dt, 1),
+            "cells_per_s": round(len(a) * len(b) / dt, 1), "distance": d, "runs": reps, "refresh_every": R}
+
+
+def W_codes(s):
+    import workloads as W
+    return W.dna_codes(s)
 
 
 def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos, progress=False, arena_gb=4, max_step=1024):
@@ -228,10 +366,11 @@ def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos, progress=False, a
                       "pbs_per_s": round((pbs1 - pbs0) / wall, 1), "steps": st1 - st0,
                       "pbs_per_query": round((pbs1 - pbs0) / n_sat, 1),
                       **{k: round(v, 3) for k, v in S.percentiles(lat).items()}},
+        "latency_note": "seconds from submission to results on the host; with few samples p99 is the maximum",
         "poisson": [],
     }
     base = 1 + n_sat
-    for r, rho in enumerate(rhos):
+    for r, rho in enumerate(rhos if n_poisson > 0 else []):
         idx = range(base + r * n_poisson, base + (r + 1) * n_poisson)
         arr = W.poisson_arrivals(6 + r, rho * sat_qps, n_poisson)
         note(f"serving: Poisson arrivals at rho={rho}, {n_poisson} queries")
@@ -338,8 +477,10 @@ def wide_block(L, ck, ctx):
 
 
 def full_configs(L, ck, ctx, serving_sat, serving_poisson):
-    """Every workload at its full size (a run of several minutes; not part of
-    the default line).  Returns a dict keyed by workload."""
+    """The workloads the default line leaves out, at full size (a run of
+    several minutes): the cleartext-string variant of the batched workload
+    (Section 5 preprocessing of every query, then one plan) and longer
+    serving runs against the 1024 names.  Returns a dict keyed by workload."""
     import numpy as np
     import torch
     import workloads as W
@@ -347,63 +488,7 @@ def full_configs(L, ck, ctx, serving_sat, serving_poisson):
     dev = ctx.device
     out = {}
 
-    def plain_once(sa, sb, enc):
-        dA = L.to_device(L.lvs_encrypt_string(ck, sa, enc, 70001), dev)
-        dB = L.to_device(L.lvs_encrypt_string(ck, sb, enc, 70002), dev)
-        d_h = torch.zeros(len(sb) * L.CT_WORDS, dtype=torch.int64, device=dev)
-        work = L.device_buffer(L.lvs_edit_distance_workspace_bytes(len(sa), len(sb), enc), dev)
-        L.lvs_edit_distance(ctx, dA, len(sa), dB, len(sb), enc, d_h, work)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        L.lvs_edit_distance(ctx, dA, len(sa), dB, len(sb), enc, d_h, work)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        return dt, L.to_host(d_h).reshape(len(sb), L.CT_WORDS)
-
-    # tiny DNA and the 256-base DNA alignment (plain path, 1 equality bootstrap per cell)
-    for name, (a, b) in (("tiny_dna_6x6", W.tiny_dna()), ("dna_align_256x256", W.dna_align())):
-        note(f"full: {name}")
-        dt, h = plain_once(W.dna_codes(a), W.dna_codes(b), L.LVS_ENC_DNA2)
-        d = L.lvs_decrypt_distance(ck, h, len(a))
-        if d != levenshtein(a, b):
-            raise SystemExit(f"{name}: wrong distance")
-        R = L.lvs_context_get_refresh(ctx)
-        pbs = 2 * len(a) * len(b) + refresh_pbs(len(a), len(b), R)
-        out[name] = {"pbs": pbs, "seconds": round(dt, 3), "pbs_per_s": round(pbs / dt, 1),
-                     "cells_per_s": round(len(a) * len(b) / dt, 1), "distance": d, "refresh_every": R}
-
-    # the batched workload, all 256 pairs, both encrypted (one graph plan)
     pairs = W.batched()
-    note("full: batched 256 pairs, encrypting")
-    items, keep = [], []
-    for k, (a, b) in enumerate(pairs):
-        dA = L.to_device(L.lvs_encrypt_string(ck, a, L.LVS_ENC_ASCII7, 80000 + 2 * k), dev)
-        dB = L.to_device(L.lvs_encrypt_string(ck, b, L.LVS_ENC_ASCII7, 80001 + 2 * k), dev)
-        items.append({"d_a": dA, "m": len(a), "d_b": dB, "n": len(b),
-                      "d_h_last": torch.zeros(len(b) * L.CT_WORDS, dtype=torch.int64, device=dev)})
-    note("full: batched 256 pairs, plan run")
-    plan = L.lvs_plan_create(ctx, items, L.LVS_ENC_ASCII7, graph=True)
-    steps, pbs, max_step = L.lvs_plan_info(plan)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    L.lvs_plan_run(plan)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    for (a, b), it in zip(pairs, items):
-        h = L.to_host(it["d_h_last"]).reshape(len(b), L.CT_WORDS)
-        if L.lvs_decrypt_distance(ck, h, len(a)) != levenshtein(a, b):
-            raise SystemExit("batched 256: wrong distance")
-    del plan
-    cells = sum(len(a) * len(b) for a, b in pairs)
-    # the same 256 queries one at a time through the plain path (identical work)
-    note("full: plain path on the 256 pairs")
-    t_plain, pbs_plain = plain_path_time(L, ctx, items, "full")
-    out["batched_ascii_256"] = {"pbs": pbs, "cells": cells, "steps": steps, "max_step": max_step,
-                                "seconds": round(dt, 3), "pbs_per_s": round(pbs / dt, 1),
-                                "cells_per_s": round(cells / dt, 1), "queries_per_s": round(256 / dt, 3),
-                                "plain_seconds": round(t_plain, 3), "plain_pbs_per_s": round(pbs_plain / t_plain, 1),
-                                "speedup_vs_plain": round((pbs / dt) / (pbs_plain / t_plain), 2)}
-    del items
 
     # the cleartext-string variant: preprocessing of every a over the 52 letters, then one plan
     alpha = W.LETTERS
@@ -466,29 +551,30 @@ def microbench(L, ctx):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batched-queries", type=int, default=64)
+    ap.add_argument("--steps", type=int, default=20, help="timed plan steps of the batched workload")
+    ap.add_argument("--warmup", type=int, default=5, help="plan steps run before the timed ones")
     ap.add_argument("--plain-sample", type=int, default=0,
-                    help="batched queries also timed through the plain path (0: all of them)")
-    ap.add_argument("--no-batched", action="store_true")
+                    help="batched queries also timed through the plain path (0: all 256, identical work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serving-names", type=int, default=32)
-    ap.add_argument("--serving-queries", type=int, default=16, help="queries of the saturated run")
+    ap.add_argument("--serving-names", type=int, default=1024)
+    ap.add_argument("--serving-queries", type=int, default=2, help="queries of the saturated run")
     ap.add_argument("--serving-progress", action="store_true", help="a progress line per finished query")
     ap.add_argument("--serving-max-step", type=int, default=1024,
                     help="bootstraps per engine step at most (admitted requests beyond it wait a step)")
-    ap.add_argument("--poisson-queries", type=int, default=40, help="queries per load factor")
+    ap.add_argument("--poisson-queries", type=int, default=0, help="queries per load factor")
     ap.add_argument("--rho", type=str, default="0.8", help="comma-separated load factors")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--band-queries", type=int, default=32)
+    ap.add_argument("--band-queries", type=int, default=0, help="the band modes on this many batched pairs")
     ap.add_argument("--band-ell", type=int, default=4, help="half-width of the approximate band")
-    ap.add_argument("--no-band", action="store_true")
-    ap.add_argument("--no-wide", action="store_true")
+    ap.add_argument("--wide", action="store_true", help="also the 32 x 32 wide-symbol pair")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--tuning", type=str, default=None,
+                    help="launch shape as JSON (lvs_tuning fields) instead of the autotuner's")
     ap.add_argument("--no-microbench", action="store_true")
+    ap.add_argument("--timed-only", action="store_true",
+                    help="only the warm-up and timed plan steps (for profiling their launches)")
     ap.add_argument("--full-configs", action="store_true",
-                    help="instead of the default line: every workload at full size (several minutes)")
+                    help="instead of the default line: the cleartext-string variant and longer serving runs")
     ap.add_argument("--full-serving-queries", type=int, default=8)
     ap.add_argument("--full-poisson-queries", type=int, default=16)
     args = ap.parse_args()
@@ -497,121 +583,92 @@ def main():
         print("bench.py measures one GPU only: the library runs on a single MI355X "
               f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
         sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        raise SystemExit("--steps must be positive and --warmup not negative")
 
     import numpy as np
     import torch
     from paper_2508_14568_amd import lvs as L
     import workloads as W
 
-    a, b = W.plain_ascii()
-    m, n = len(a), len(b)
     params = L.lvs_params_default()
     ck, sk = L.lvs_keygen(params, 1)
     ctx = L.lvs_context_create(sk, params, 0)
     tuning = None
-    if not args.no_autotune:
+    if args.tuning:
+        L.lvs_context_set_tuning(ctx, dict(L.lvs_context_get_tuning(ctx), **json.loads(args.tuning)))
+        tuning = {"tuning": L.lvs_context_get_tuning(ctx), "cached": False, "given": True}
+    elif not args.no_autotune:
         note("autotune")
         tuning = L.autotune(ctx)
     if args.full_configs:
         res = full_configs(L, ck, ctx, args.full_serving_queries, args.full_poisson_queries)
         print(json.dumps({"full_configs": res, "tuning": tuning and tuning["tuning"]}), flush=True)
         return
-    A = L.lvs_encrypt_string(ck, a, L.LVS_ENC_ASCII7, 1001)
-    B = L.lvs_encrypt_string(ck, b, L.LVS_ENC_ASCII7, 1002)
-    dA, dB = L.to_device(A, ctx.device), L.to_device(B, ctx.device)
-    d_h = torch.zeros(n * L.CT_WORDS, dtype=torch.int64, device=ctx.device)
-    d_work = L.device_buffer(L.lvs_edit_distance_workspace_bytes(m, n, L.LVS_ENC_ASCII7), ctx.device)
-    torch.cuda.synchronize()
 
-    for _ in range(args.warmup):
-        L.lvs_edit_distance(ctx, dA, m, dB, n, L.LVS_ENC_ASCII7, d_h, d_work)
-    torch.cuda.synchronize()
-    L.lvs_profile_enable(ctx, True)
-    torch.cuda.synchronize()
-    note(f"plain: {args.steps} timed steps")
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        L.lvs_edit_distance(ctx, dA, m, dB, n, L.LVS_ENC_ASCII7, d_h, d_work)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    br_ms, br_launches, br_pbs = L.lvs_profile_read(ctx, L.KERNEL_BLIND_ROTATE)
-    forms = {name: L.lvs_profile_read(ctx, k) for name, k in
-             (("blind_rotate_latency_kernel", L.KERNEL_BLIND_ROTATE_LATENCY),
-              ("blind_rotate_kernel", L.KERNEL_BLIND_ROTATE_THROUGHPUT),
-              ("blind_rotate_w16_kernel", L.KERNEL_BLIND_ROTATE_W16))}
-    ks_ms, ks_launches, _ = L.lvs_profile_read(ctx, L.KERNEL_KEYSWITCH)
-    L.lvs_profile_enable(ctx, False)
-
-    dist = L.lvs_decrypt_distance(ck, L.to_host(d_h).reshape(n, L.CT_WORDS), m)
-    if dist != levenshtein(a, b):
-        print(f"wrong distance {dist} != {levenshtein(a, b)}", file=sys.stderr)
-        sys.exit(1)
-
-    pbs_per_step = 3 * m * n + refresh_pbs(m, n, L.lvs_context_get_refresh(ctx))
-    ms_per_step = 1000 * elapsed / args.steps
-    pbs_s = pbs_per_step * args.steps / elapsed
-    # the dominant kernel: the blind-rotation form with the most time
-    kname = max(forms, key=lambda k: forms[k][0])
-    k_ms, k_launches, k_pbs = forms[kname]
-    avg_launch_ms = k_ms / max(1, k_launches)
-    avg_pbs_launch = k_pbs / max(1, k_launches)
-    achieved = INT_MUL_PER_PBS * avg_pbs_launch / (avg_launch_ms / 1000) / 1e12
-    roofline = {
-        "bound": "alu", "kernel": kname,
-        "achieved": round(achieved, 3), "peak": round(VALU_INT_MUL_PEAK_TOPS, 3), "unit": "TOP/s",
-        "frac": round(achieved / VALU_INT_MUL_PEAK_TOPS, 4),
-        "traffic": traffic_per_launch(kname, avg_pbs_launch),
-        "ops": "32-bit integer multiplies, 3 per modular multiplication, "
-               f"{INT_MUL_PER_PBS} per bootstrap",
-        "avg_launch_ms": round(avg_launch_ms, 4), "launches": k_launches,
-        "avg_pbs_per_launch": round(avg_pbs_launch, 2),
-        "hbm": hbm_roofline(avg_pbs_launch, avg_launch_ms),
-        "other_form": {k: {"ms_per_step": round(v[0] / args.steps, 3), "launches": v[1], "pbs": v[2]}
-                       for k, v in forms.items() if k != kname},
-        "keyswitch_ms_per_step": round(ks_ms / args.steps, 3),
-        "blind_rotate_ms_per_step": round(br_ms / args.steps, 3),
-    }
+    head, full, plain = batched_headline(L, ck, ctx, args.warmup, args.steps, args.plain_sample, args.timed_only)
+    if args.timed_only:
+        if not args.no_microbench:
+            head["roofline"]["measured"] = microbench(L, ctx)     # the copy kernel calibrates traffic counters
+        pbs_s = head["timed_pbs"] / (head["timed_ms"] / 1e3)
+        print(json.dumps({"workload": "batched_ascii_256_pairs", "steps": args.steps, "warmup": args.warmup,
+                          "value": round(pbs_s, 2), "unit": "PBS/s", **head}), flush=True)
+        return
+    timed_s = head["timed_ms"] / 1e3
+    roofline = head.pop("roofline")
+    pbs_s = head["timed_pbs"] / timed_s
     if not args.no_microbench:
         note("microbenchmarks")
         roofline["measured"] = microbench(L, ctx)
         # the same achieved rate against the measured ceiling of the
         # butterfly's instruction mix (what the kernel's arithmetic can reach)
-        roofline["frac_of_measured_peak"] = round(achieved / roofline["measured"]["modmul_probe_tops"], 4)
+        roofline["frac_of_measured_peak"] = round(roofline["achieved"] / roofline["measured"]["modmul_probe_tops"], 4)
+        full["roofline_graph"]["frac_of_measured_peak"] = round(
+            full["roofline_graph"]["achieved"] / roofline["measured"]["modmul_probe_tops"], 4)
     line = {
         "metric": "PBS/s & DP cells/s; batched vs plain queries/s; p50/p99 query latency",
         "value": round(pbs_s, 2), "unit": "PBS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": round(head["timed_ms"] / args.steps, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": "plain_ascii_32x32", "m": m, "n": n, "encoding": "ascii7",
-                   "pbs_per_step": pbs_per_step, "cells_per_step": m * n,
-                   "params": "n=742 k=1 N=2048 q=2^64 pbs 2^23x1 ks 2^3x5", "path": "plain per-diagonal"},
-        "cells_per_s": round(m * n * args.steps / elapsed, 2),
-        "queries_per_s": round(args.steps / elapsed, 4),
-        "distance": dist,
+        "config": {"workload": "batched_ascii_256_pairs", "queries": 256, "lengths": "uniform 8..64",
+                   "encoding": "ascii7", "both_encrypted": True,
+                   "step": "one plan step: every ready cell of one anti-diagonal of every query plus the "
+                           "equality bootstraps of the next ones, one key-switch and one blind-rotation launch",
+                   "params": "n=742 k=1 N=2048 q=2^64 pbs 2^23x1 ks 2^3x5", "path": "batch plan"},
+        "cells_per_s": full["cells_per_s"],
+        "queries_per_s": full["queries_per_s"],
+        "timed": head,
         "roofline": roofline,
+        "full_pass": full,
+        "plain_same_queries": plain,
     }
     if tuning is not None:
         line["tuning"] = dict(tuning["tuning"], cached=tuning["cached"], samples=tuning.get("samples"))
-    if not args.no_batched and args.batched_queries > 0:
-        line["batched"] = batched_block(L, ck, ctx, args.batched_queries, args.plain_sample)
-        # against the default line's plain workload as well (PBS/s over PBS/s)
-        line["batched"]["vs_plain_line"] = round(line["batched"]["pbs_per_s"] / line["value"], 2)
-        if "measured" in roofline:
-            rg = line["batched"]["roofline_graph"]
-            rg["frac_of_measured_peak"] = round(rg["achieved"] / roofline["measured"]["modmul_probe_tops"], 4)
-    if not args.no_band and args.band_queries > 0:
-        line["band"] = band_block(L, ck, ctx, args.band_queries, args.band_ell)
-    if not args.no_wide:
-        line["wide"] = wide_block(L, ck, ctx)
+    # the other configurations
+    note("configs: dna 256 x 256, tiny dna, plain 32 x 32")
+    a, b = W.dna_align()
+    line["dna_align_256x256"] = plain_config(L, ck, ctx, a, b, L.LVS_ENC_DNA2, 70001)
+    a, b = W.tiny_dna()
+    line["tiny_dna_6x6"] = plain_config(L, ck, ctx, a, b, L.LVS_ENC_DNA2, 70011, reps=5)
+    a, b = W.plain_ascii()
+    line["plain_ascii_32x32"] = plain_config(L, ck, ctx, a, b, L.LVS_ENC_ASCII7, 1001, reps=3)
+    line["plain_same_queries"]["vs_plain_32x32_pbs_per_s"] = round(
+        full["pbs_per_s"] / line["plain_ascii_32x32"]["pbs_per_s"], 2)
     if not args.no_serving and args.serving_names > 0:
         line["serving"] = serving_block(L, ck, ctx, args.serving_names, args.serving_queries,
                                         args.poisson_queries, [float(x) for x in args.rho.split(",") if x],
-                                        max_step=args.serving_max_step, progress=args.serving_progress)
-        sv = line["serving"]
-        sv["saturated"]["vs_plain_line"] = round(sv["saturated"]["pbs_per_s"] / line["value"], 2)
+                                        max_step=args.serving_max_step, progress=args.serving_progress,
+                                        arena_gb=32 if args.serving_names > 256 else 4)
+    if args.band_queries > 0:
+        line["band"] = band_block(L, ck, ctx, args.band_queries, args.band_ell)
+    if args.wide:
+        line["wide"] = wide_block(L, ck, ctx)
     if not args.no_cpu_baseline:
-        z1 = (A[:, None, 0, :] - B[None, :, 0, :]).reshape(m * n, L.CT_WORDS).astype(np.uint64)
-        line["cpu_baseline"] = cpu_baseline(z1)
+        pairs = W.batched()
+        A = L.lvs_encrypt_string(ck, pairs[0][0], L.LVS_ENC_ASCII7, 20000)
+        B = L.lvs_encrypt_string(ck, pairs[0][1], L.LVS_ENC_ASCII7, 20001)
+        z1 = (A[:, None, 0, :] - B[None, :, 0, :]).reshape(-1, L.CT_WORDS).astype(np.uint64)
+        line["cpu_baseline"] = cpu_baseline(z1, "the first pair of the batched workload")
     print(json.dumps(line), flush=True)
 
 

@@ -211,21 +211,25 @@ int lvs_sync(lvs_context* ctx);
 /* Launch shape of the blind rotation kernel (the dominant cost of every
  * bootstrap, Section 2.2).  br_grid: workgroups per launch, each looping over
  * the batch (0: one workgroup per bootstrap).  latency_form_max: batches of
- * at most this many bootstraps use the one-workgroup-per-CU form; larger
- * batches use the four-wave form (two workgroups of 256 threads per CU).
- * latency_waves picks the one-per-CU form: 8 (512 threads, two waves per
- * prime) or 16 (1024 threads, four waves per prime, first and last three
- * transform stages in the digit and CRT steps).  A new context starts at
- * {0, INT32_MAX, 8}.  Plans captured as graphs keep the shape they were
+ * at most this many bootstraps use a one-workgroup-per-CU form; larger
+ * batches use a two-workgroups-per-CU form.  latency_waves picks the
+ * one-per-CU form: 8 (512 threads, two waves per prime) or 16 (1024 threads,
+ * four waves per prime, first and last three transform stages in the digit
+ * and CRT steps).  throughput_waves picks the two-per-CU form: 8 (the
+ * eight-wave form with one LDS buffer and at most 128 registers per thread)
+ * or 4 (256 threads, one wave per prime).  A new context starts at
+ * {0, INT32_MAX, 8, 8}.  Plans captured as graphs keep the shape they were
  * captured with. */
 typedef struct lvs_tuning {
     int32_t br_grid;
     int32_t latency_form_max;
-    int32_t latency_waves;   /* 8 or 16: wavefronts per bootstrap of the one-per-CU form (0 = 8) */
+    int32_t latency_waves;      /* 8 or 16: wavefronts per bootstrap of the one-per-CU form (0 = 8) */
+    int32_t throughput_waves;   /* 8 or 4: wavefronts per bootstrap of the two-per-CU form (0 = 8) */
 } lvs_tuning;
 
 int lvs_context_get_tuning(const lvs_context* ctx, lvs_tuning* out);
-/* Rejects negative values and latency_waves other than 0, 8, 16 (LVS_E_INVAL). */
+/* Rejects negative values, latency_waves other than 0, 8, 16 and
+ * throughput_waves other than 0, 4, 8 (LVS_E_INVAL). */
 int lvs_context_set_tuning(lvs_context* ctx, const lvs_tuning* t);
 
 /* One timing of the autotuner: mean duration (ms) of a blind-rotation launch
@@ -241,12 +245,14 @@ typedef struct lvs_tune_sample {
 /* Device workspace bytes of lvs_autotune (256-byte aligned, caller-owned). */
 size_t lvs_autotune_workspace_bytes(size_t max_batch);
 
-/* Times the three forms, and a persistent grid of twice the CU count, on
- * batches from half to four times the CU count (at most max_batch, 1..65536)
- * of zero ciphertexts, installs the fastest shape in the context (the
- * one-per-CU form with the smaller total time, used up to the largest batch
- * at which it is still at least as fast as the four-wave form) and returns it
- * in *best.  Up to max_samples timings go to samples (may be NULL); *n_samples
+/* Times the four forms (form 1 / 3: one eight- / sixteen-wave workgroup per
+ * CU; 2 / 4: two four- / eight-wave workgroups per CU), and the two-per-CU
+ * forms with a persistent grid of twice the CU count, on batches from half
+ * to four times the CU count (at most max_batch, 1..65536) of zero
+ * ciphertexts, installs the fastest shape in the context (of each kind the
+ * form with the smaller total time; the one-per-CU form up to the batch
+ * before the first one at which the two-per-CU form is more than 1% faster)
+ * and returns it in *best.  Up to max_samples timings go to samples (may be NULL); *n_samples
  * (may be NULL) receives how many were taken.  Synchronous; uses the
  * context's stream.  Errors: LVS_E_INVAL, LVS_E_NOMEM_DEVICE (workspace too
  * small), LVS_E_DEVICE. */
@@ -530,6 +536,17 @@ int lvs_plan_run(lvs_plan* plan);
 
 /* Steps, bootstraps and the largest step of a plan (any may be NULL). */
 int lvs_plan_info(const lvs_plan* plan, size_t* steps, size_t* bootstraps, size_t* max_step);
+
+/* Enqueues steps first .. first + count - 1 of one execution of the plan as
+ * separate launches (never the captured graph), so that a caller can time a
+ * range of steps; an execution starts at step 0 (which also resets the
+ * plan's boundary rows) and must run its steps in order.  LVS_E_INVAL past
+ * the last step. */
+int lvs_plan_run_steps(lvs_plan* plan, size_t first, size_t count);
+
+/* Bootstraps of each of the plan's first n steps (0 for a step of linear
+ * group sums) into counts[]. */
+int lvs_plan_step_bootstraps(const lvs_plan* plan, size_t* counts, size_t n);
 
 /* ------------------------------------------ continuous batching of queries */
 

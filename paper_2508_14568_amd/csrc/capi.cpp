@@ -830,6 +830,25 @@ int lvs_plan_run(lvs_plan* plan) {
     return LVS_OK;
 }
 
+int lvs_plan_run_steps(lvs_plan* plan, size_t first, size_t count) {
+    auto* H = reinterpret_cast<PlanHandle*>(plan);
+    LVS_REQUIRE(H && H->kind == kPlan, LVS_E_INVAL, "lvs_plan_run_steps: bad plan");
+    LVS_REQUIRE(first <= H->P.steps.size() && count <= H->P.steps.size() - first, LVS_E_INVAL,
+                "lvs_plan_run_steps: steps past the end of the plan");
+    LVS_HIP(hipSetDevice(H->C->device));
+    LVS_HIP(run_plan_steps(H->C, H->P, first, count));
+    return LVS_OK;
+}
+
+int lvs_plan_step_bootstraps(const lvs_plan* plan, size_t* counts, size_t n) {
+    auto* H = reinterpret_cast<const PlanHandle*>(plan);
+    LVS_REQUIRE(H && H->kind == kPlan, LVS_E_INVAL, "lvs_plan_step_bootstraps: bad plan");
+    LVS_REQUIRE(counts || n == 0, LVS_E_INVAL, "lvs_plan_step_bootstraps: NULL counts");
+    for (size_t k = 0; k < n && k < H->P.steps.size(); ++k)
+        counts[k] = H->P.steps[k].sum >= 0 ? 0 : H->P.steps[k].count;
+    return LVS_OK;
+}
+
 int lvs_plan_info(const lvs_plan* plan, size_t* steps, size_t* bootstraps, size_t* max_step) {
     auto* H = reinterpret_cast<const PlanHandle*>(plan);
     LVS_REQUIRE(H && H->kind == kPlan, LVS_E_INVAL, "lvs_plan_info: bad plan");
@@ -860,7 +879,8 @@ int lvs_profile_read(lvs_context* ctx, int kernel, double* total_ms, uint64_t* l
     double ms = 0;
     uint64_t n = 0, u = 0;
     for (auto& t : C->timed) {
-        const bool br = t.kernel == kProfBrLatency || t.kernel == kProfBrThroughput || t.kernel == kProfBrW16;
+        const bool br = t.kernel == kProfBrLatency || t.kernel == kProfBrThroughput || t.kernel == kProfBrW16 ||
+                        t.kernel == kProfBrPair;
         if (t.kernel != kernel && !(kernel == kProfBlindRotate && br)) continue;
         LVS_HIP(hipEventSynchronize(t.end));
         float dt = 0;

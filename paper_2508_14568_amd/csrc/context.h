@@ -27,6 +27,7 @@ struct Context : Handle {
     int br_grid = 0;              // persistent grid (0: one workgroup per job)
     int latency_form_max = 0;     // batches up to this size take the one-workgroup-per-CU form
     int latency_waves = 8;        // that form's wavefronts per bootstrap: 8 or 16
+    int throughput_waves = 8;     // larger batches: two workgroups per CU of 8 (or 4) wavefronts
     size_t refresh_every = LVS_REFRESH_DEFAULT;   // noise-refresh interval in anti-diagonals (0: off)
     // kernel timing (lvs_profile_*): event pairs recorded around launches
     bool profiling = false;
@@ -52,12 +53,13 @@ inline hipEvent_t take_event(Context* C) {
 
 // Profile ids (lvs_profile_read): 0 sums the blind-rotation forms, which are
 // recorded as 3 (eight-wave workgroup, one per CU), 4 (four-wave workgroups,
-// two per CU) and 5 (sixteen-wave workgroup, one per CU).
+// two per CU), 5 (sixteen-wave workgroup, one per CU) and 6 (eight-wave
+// workgroups, two per CU).
 constexpr int kProfBlindRotate = 0, kProfKeySwitch = 1, kProfGraph = 2, kProfBrLatency = 3, kProfBrThroughput = 4,
-              kProfBrW16 = 5;
+              kProfBrW16 = 5, kProfBrPair = 6;
 
 inline int br_profile_id(const Context* C, int B) {
-    if (B > C->latency_form_max) return kProfBrThroughput;
+    if (B > C->latency_form_max) return C->throughput_waves == 8 ? kProfBrPair : kProfBrThroughput;
     return C->latency_waves == 16 ? kProfBrW16 : kProfBrLatency;
 }
 

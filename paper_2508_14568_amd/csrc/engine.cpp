@@ -170,7 +170,8 @@ struct Engine : Handle {
                 if (e == hipSuccess) {
                     what = "blind rotation";
                     e = launch_blind_rotate_jobs(d_jobs, B, d_part, C->luts, C->bsk, C->tables, C->br_grid,
-                                                 C->latency_form_max, C->latency_waves, stream);
+                                                 C->latency_form_max, C->latency_waves, stream, 0,
+                                                 C->throughput_waves);
                 }
             }
             if (e == hipSuccess) {

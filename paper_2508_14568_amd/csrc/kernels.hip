@@ -865,6 +865,281 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
     }
 }
 
+// -------------------------------- blind rotation, two eight-wave groups per CU
+
+// The eight-wave form with one LDS buffer instead of two, so that two
+// workgroups (two bootstraps) share a CU: 16 waves per CU, 4 per SIMD, and
+// one bootstrap's barrier and LDS waits are filled by the other's
+// arithmetic.  Registers are held to 128 per thread (no key or twiddle
+// prefetch across phases); every coefficient lives at its padded LDS
+// position, so that each wave's transposes write exactly the words it has
+// just read and one buffer serves every phase.  Six barriers per CMux:
+// accumulator copy -> digits; digits read -> first stage written (the
+// copy and the first-stage outputs share the buffer); first stage ->
+// transform; the forward transpose; the inverse transpose; inverse outputs
+// -> CRT.  Transform positions, key layout and results are those of the
+// eight-wave form.
+constexpr size_t kPairLds = sizeof(uint32_t) * kPrimes * 2 * kPoly              // X
+                            + sizeof(uint32_t) * (kSmallWords + 1)              // switched mask and body
+                            + sizeof(uint2) * 2 * kPrimes * kLatTwu;            // uniform-stage twiddles
+
+__global__ void __launch_bounds__(kLatThreads, 4) blind_rotate_pair_kernel(BrArgs A) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint32_t* X = reinterpret_cast<uint32_t*>(lds);      // [kPrimes][2][kPoly], padded positions
+    uint32_t* abar = X + kPrimes * 2 * kPoly;            // [n+1]
+    uint2* twu = reinterpret_cast<uint2*>(abar + kSmallWords + 1);   // [2][kPrimes][kLatTwu]
+    // the accumulator copy: low words in prime 0's regions, high words in
+    // prime 1's, at the padded positions of the writing thread's coefficients
+    uint32_t* acc_lo = X;
+    uint32_t* acc_hi = X + 2 * kPoly;
+
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int r = wave >> 1;          // prime
+    const int g = wave & 1;           // element half
+    const int e0 = kLatE * g;
+    const int lane = tid & 63;
+    const int h = lane >> 5;
+    const int lh = lane & 31;
+    const uint32_t p = pick(A.crt.p, r);
+    const uint32_t mont = pick(A.crt.mont, r);
+    const uint32_t q = pick(A.crt.red, r);
+    const uint2* fw = A.tw.fwd + size_t(r) * kN;
+    const uint2* iw = A.tw.inv + size_t(r) * kN;
+    uint32_t* const scr = X + (r * 2 + h) * kPoly;
+    uint2 wfirst[kPrimes], wlast[kPrimes];
+#pragma unroll
+    for (int w = 0; w < kPrimes; ++w) {
+        wfirst[w] = A.tw.fwd[size_t(w) * kN + 1];
+        wlast[w] = A.tw.inv[size_t(w) * kN + 1];
+    }
+    for (int t = tid; t < 2 * kPrimes * kLatTwu; t += kLatThreads) {
+        const int dir = t / (kPrimes * kLatTwu), pr = (t / kLatTwu) % kPrimes, idx = t % kLatTwu;
+        twu[t] = (dir ? A.tw.inv : A.tw.fwd)[size_t(pr) * kN + idx];
+    }
+    const uint2* const twf = twu + r * kLatTwu;
+    const uint2* const twi = twu + (kPrimes + r) * kLatTwu;
+    // element el of the wave's half at pad(lh + 32 (e0 + el)) = lh + 32 e0 + e0 / 2 + 32 el + el / 2
+    // (coefficient order) and at pad(64 lh + e0 + el) = 65 lh + e0 + el (transform order)
+    uint32_t* const col = scr + lh + 32 * e0 + (e0 >> 1);
+    uint32_t* const row = scr + 65 * lh + e0;
+
+    for (int b = blockIdx.x; b < A.B; b += gridDim.x) {
+        const Job& J = A.jobs[b];
+        for (int c = tid; c < kSmallWords; c += kLatThreads) {
+            uint64_t v = 0;
+            for (int sp = 0; sp < A.nsplit; ++sp) v += A.part[(size_t(sp) * A.B + b) * kSmallWords + c];
+            if (c == kSmallN) v += job_word(J, kN) + J.delta;
+            abar[c] = uint32_t((((v >> 51) + 1) >> 1) & (2 * kN - 1));
+        }
+        __syncthreads();
+        const int lut = min(int(J.lut), LVS_LUT_SLOTS - 1);
+        const uint64_t* tp = A.luts + size_t(lut) * kN;
+        const uint32_t bbar = abar[kSmallN];
+        uint64_t acc[kLatAcc];
+#pragma unroll
+        for (int k = 0; k < kLatAcc; ++k) {
+            const uint32_t c = uint32_t(lat_coef(tid, k));
+            const uint32_t src = (c + bbar) & (2 * kN - 1);
+            const uint64_t v = tp[src & (kN - 1)];
+            acc[k] = lat_poly(k) ? ((src < uint32_t(kN)) ? v : uint64_t(0) - v) : uint64_t(0);
+        }
+        const uint4* const K0 = reinterpret_cast<const uint4*>(A.bsk) + (size_t(r) * 2 + h) * (kN / 2) + lh + 16 * e0;
+        constexpr size_t kKeyStep = size_t(kPrimes) * 2 * (kN / 2);   // uint4 per CMux
+
+        for (int i = 0; i < kSmallN; ++i) {
+            const uint32_t a = abar[i];
+#pragma unroll
+            for (int k = 0; k < kLatAcc; ++k) {
+                const int at = lat_poly(k) * kPoly + int(pad(uint32_t(lat_coef(tid, k))));
+                acc_lo[at] = uint32_t(acc[k]);
+                acc_hi[at] = uint32_t(acc[k] >> 32);
+            }
+            __syncthreads();
+            // digits of X^a ACC - ACC, d + 2^22 for the balanced 23-bit digit d
+            uint32_t u[kLatAcc];
+#pragma unroll
+            for (int k = 0; k < kLatAcc; ++k) {
+                const uint32_t c = uint32_t(lat_coef(tid, k));
+                const uint32_t src = (c - a) & (2 * kN - 1);
+                const int at = lat_poly(k) * kPoly + int(pad(src & (kN - 1)));
+                uint64_t rr = uint64_t(acc_lo[at]) | (uint64_t(acc_hi[at]) << 32);
+                if (src >= uint32_t(kN)) rr = uint64_t(0) - rr;
+                const uint64_t t = rr - acc[k];
+                u[k] = ((((uint32_t(t >> 40) + 1) >> 1) & 0x7FFFFFu) + 0x400000u) & 0x7FFFFFu;
+            }
+            __syncthreads();
+            // the first forward stage of every prime on the pairs (c, c + 1024)
+#pragma unroll
+            for (int k = 0; k < kLatAcc; k += 2) {
+                const int at = lat_poly(k) * kPoly + int(pad(uint32_t(lat_coef(tid, k))));
+#pragma unroll
+                for (int w = 0; w < kPrimes; ++w) {
+                    const uint32_t pw = A.crt.p[w];
+                    const uint32_t lo = u[k] + (pw - (1u << 22)), hi = u[k + 1] + (pw - (1u << 22));
+                    const uint32_t s = __umulhi(hi, wfirst[w].y) * pw - hi * wfirst[w].x;
+                    X[w * 2 * kPoly + at] = lo - s;
+                    X[w * 2 * kPoly + at + kN / 2 + kN / 128] = lo + 2 * pw + s;   // pad(c + 1024)
+                }
+            }
+            __syncthreads();
+            uint32_t x[kLatE];
+#pragma unroll
+            for (int el = 0; el < kLatE; ++el) x[el] = col[32 * el + (el >> 1)];
+            fwd_stage_lds<1, kLatE>(x, twf, p, e0);
+            fwd_stage_lds<2, kLatE>(x, twf, p, e0);
+            fwd_stage_lds<3, kLatE>(x, twf, p, e0);
+            fwd_stage_lds<4, kLatE>(x, twf, p, e0);
+            fwd_stage_lds<5, kLatE>(x, twf, p, e0);
+            // transpose through the words this wave has just read
+#pragma unroll
+            for (int el = 0; el < kLatE; ++el) col[32 * el + (el >> 1)] = x[el];
+            __syncthreads();
+#pragma unroll
+            for (int el = 0; el < kLatE; ++el) x[el] = row[el];
+            asm volatile("" ::: "memory");   // keep each stage's twiddle loads in its stage
+            {
+                FwdTw<6, kLatE> t6;
+                load_fwd_tw(t6, fw, lh, e0);
+                fwd_stage_tw(x, t6, p);
+            }
+            asm volatile("" ::: "memory");   // keep each stage's twiddle loads in its stage
+            {
+                FwdTw<7, kLatE> t7;
+                load_fwd_tw(t7, fw, lh, e0);
+                fwd_stage_tw(x, t7, p);
+            }
+            asm volatile("" ::: "memory");   // keep each stage's twiddle loads in its stage
+            {
+                FwdTw<8, kLatE> t8;
+                load_fwd_tw(t8, fw, lh, e0);
+                fwd_stage_tw(x, t8, p);
+            }
+            asm volatile("" ::: "memory");   // keep each stage's twiddle loads in its stage
+            {
+                FwdTw<9, kLatE> t9;
+                load_fwd_tw(t9, fw, lh, e0);
+                fwd_stage_tw(x, t9, p);
+            }
+            asm volatile("" ::: "memory");   // keep each stage's twiddle loads in its stage
+            {
+                FwdTw<10, kLatE> t10;
+                load_fwd_tw(t10, fw, lh, e0);
+                fwd_stage_tw(x, t10, p);
+            }
+            // products with the GGSW rows (own digit first, as in the key), the
+            // key loaded in four parts of 16 registers
+            {
+                const uint4* K = K0 + size_t(i) * kKeyStep;
+#pragma unroll
+                for (int part = 0; part < 4; ++part) {
+                    asm volatile("" ::: "memory");
+                    uint4 kq[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) kq[j] = K[(part * 4 + j) * 32];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int el = (part * 4 + j) * 2;
+#pragma unroll
+                        for (int o = 0; o < 2; ++o) {
+                            const uint32_t own = x[el + o];
+                            const uint32_t other = swap_halves(own, lane);
+                            x[el + o] = redc(uint64_t(own) * (o ? kq[j].z : kq[j].x) +
+                                                 uint64_t(other) * (o ? kq[j].w : kq[j].y),
+                                             p, mont);
+                        }
+                    }
+                }
+            }
+            asm volatile("" ::: "memory");
+            {
+                InvTw<0, kLatE> u0;
+                load_inv_tw(u0, iw, lh, e0);
+                inv_stage_tw(x, u0, p, q);
+            }
+            asm volatile("" ::: "memory");
+            {
+                InvTw<1, kLatE> u1;
+                load_inv_tw(u1, iw, lh, e0);
+                inv_stage_tw(x, u1, p, q);
+            }
+            asm volatile("" ::: "memory");
+            {
+                InvTw<2, kLatE> u2;
+                load_inv_tw(u2, iw, lh, e0);
+                inv_stage_tw(x, u2, p, q);
+            }
+            asm volatile("" ::: "memory");
+            {
+                InvTw<3, kLatE> u3;
+                load_inv_tw(u3, iw, lh, e0);
+                inv_stage_tw(x, u3, p, q);
+            }
+            asm volatile("" ::: "memory");
+            {
+                InvTw<4, kLatE> u4;
+                load_inv_tw(u4, iw, lh, e0);
+                inv_stage_tw(x, u4, p, q);
+            }
+            // inverse transpose through the words this wave read after the forward one
+#pragma unroll
+            for (int el = 0; el < kLatE; ++el) row[el] = x[el];
+            __syncthreads();
+#pragma unroll
+            for (int el = 0; el < kLatE; ++el) x[el] = col[32 * el + (el >> 1)];
+            inv_stage_lds<5, kLatE>(x, twi, p, q, e0);
+            inv_stage_lds<6, kLatE>(x, twi, p, q, e0);
+            inv_stage_lds<7, kLatE>(x, twi, p, q, e0);
+            inv_stage_lds<8, kLatE>(x, twi, p, q, e0);
+            inv_stage_lds<9, kLatE>(x, twi, p, q, e0);
+#pragma unroll
+            for (int el = 0; el < kLatE; ++el) col[32 * el + (el >> 1)] = x[el];
+            __syncthreads();
+            // last inverse stage (coefficients c and c + 1024), then the CRT
+#pragma unroll
+            for (int k = 0; k < kLatAcc; k += 2) {
+                const int at = lat_poly(k) * kPoly + int(pad(uint32_t(lat_coef(tid, k))));
+                uint32_t rlo[kPrimes], rhi[kPrimes];
+#pragma unroll
+                for (int w = 0; w < kPrimes; ++w) {
+                    const uint32_t pw = A.crt.p[w];
+                    const uint32_t v0 = X[w * 2 * kPoly + at];
+                    const uint32_t v1 = X[w * 2 * kPoly + at + kN / 2 + kN / 128];
+                    rlo[w] = v0 + v1;                                        // below 16 p_w
+                    rhi[w] = mul_shoup(v0 + 8 * pw - v1, wlast[w].x, wlast[w].y, pw);
+                }
+                acc[k] += crt_lift(rlo, A.crt);
+                acc[k + 1] += crt_lift(rhi, A.crt);
+            }
+        }
+        // sample extraction of coefficient 0, then the job's output rule (the
+        // copy overwrites only words its own thread read in the CRT step)
+#pragma unroll
+        for (int k = 0; k < kLatAcc; ++k) {
+            const int at = lat_poly(k) * kPoly + int(pad(uint32_t(lat_coef(tid, k))));
+            acc_lo[at] = uint32_t(acc[k]);
+            acc_hi[at] = uint32_t(acc[k] >> 32);
+        }
+        __syncthreads();
+        for (int t = tid; t < kCtWords; t += kLatThreads) {
+            const uint32_t c = (t == 0) ? 0u : (t < kN) ? uint32_t(kN - t) : 0u;
+            const int at = (t == kN) ? kPoly + int(pad(0)) : int(pad(c));
+            const uint64_t m = uint64_t(acc_lo[at]) | (uint64_t(acc_hi[at]) << 32);
+            const uint64_t v = (t > 0 && t < kN) ? uint64_t(0) - m : m;
+            const uint64_t s0 = J.sub[0] ? J.sub[0][t] : 0;
+            const uint64_t s1 = J.sub[1] ? J.sub[1][t] : 0;
+            const uint64_t c0 = (t == kN) ? J.sub_delta[0] : 0;
+            const uint64_t c1 = (t == kN) ? J.sub_delta[1] : 0;
+            const uint64_t o0 = v - s0 - c0, o1 = v - s1 - c1;
+            if (J.dst[0]) J.dst[0][t] = o0;
+            if (J.dst[1]) J.dst[1][t] = o1;
+            if (J.dst[2]) J.dst[2][t] = v;
+            if (J.dst[3]) J.dst[3][t] = J.copy_of ? o1 : o0;
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------ blind rotation, sixteen-wave form
 
 // One workgroup of 16 wavefronts per bootstrap (four per prime), one per CU,
@@ -1385,12 +1660,15 @@ hipError_t prepare_kernels() {
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(dev::blind_rotate_w16_kernel),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(dev::kW16Lds));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(dev::blind_rotate_pair_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(dev::kPairLds));
     return e;
 }
 
 hipError_t launch_blind_rotate_jobs(const Job* jobs, int B, const uint64_t* part, const uint64_t* luts,
                                     const uint32_t* bsk, const DevTables& t, int grid, int latency_form_max,
-                                    int latency_waves, hipStream_t st, int nsplit) {
+                                    int latency_waves, hipStream_t st, int nsplit, int throughput_waves) {
     if (B <= 0) return hipSuccess;
     if (nsplit < 0 || nsplit > 64 || (nsplit & (nsplit - 1))) return hipErrorInvalidValue;
     dev::BrArgs A{};
@@ -1407,6 +1685,8 @@ hipError_t launch_blind_rotate_jobs(const Job* jobs, int B, const uint64_t* part
         hipLaunchKernelGGL(dev::blind_rotate_w16_kernel, dim3(grid), dim3(dev::kW16Threads), dev::kW16Lds, st, A);
     else if (B <= latency_form_max)
         hipLaunchKernelGGL(dev::blind_rotate_latency_kernel, dim3(grid), dim3(dev::kLatThreads), dev::kLatLds, st, A);
+    else if (throughput_waves == 8)
+        hipLaunchKernelGGL(dev::blind_rotate_pair_kernel, dim3(grid), dim3(dev::kLatThreads), dev::kPairLds, st, A);
     else
         hipLaunchKernelGGL(dev::blind_rotate_kernel, dim3(grid), dim3(dev::kBrThreads), dev::kBrLds, st, A);
     return hipGetLastError();

@@ -48,10 +48,11 @@ hipError_t launch_keyswitch_jobs(const Job* jobs, int B, const uint64_t* ksk, ui
                                  int nsplit = 0);
 // Batches of at most latency_form_max bootstraps take the one-workgroup-per-CU
 // form of the blind rotation (latency_waves 8 or 16 wavefronts), larger ones
-// the two-per-CU form.
+// a two-per-CU form (throughput_waves 8: the eight-wave form with one LDS
+// buffer; 4: the four-wave form).
 hipError_t launch_blind_rotate_jobs(const Job* jobs, int B, const uint64_t* part, const uint64_t* luts,
                                     const uint32_t* bsk, const DevTables& t, int grid, int latency_form_max,
-                                    int latency_waves, hipStream_t st, int nsplit = 0);
+                                    int latency_waves, hipStream_t st, int nsplit = 0, int throughput_waves = 8);
 hipError_t prepare_kernels();
 // Records the address of the no-allocation entry point's device array on
 // `device`, which must be current (static_pbs.hip); once per device.

@@ -712,12 +712,16 @@ hipError_t upload_plan(Plan& P, uint8_t*& ws, hipStream_t st) {
 }
 
 namespace {
-hipError_t launch_steps(Context* C, const Plan& P, hipStream_t st, bool timed) {
-    for (const auto& f : P.fills) {
-        hipError_t e = launch_trivial(f.first, int(f.second), 1, st);
-        if (e != hipSuccess) return e;
-    }
-    for (const auto& s : P.steps) {
+hipError_t launch_steps(Context* C, const Plan& P, hipStream_t st, bool timed, size_t first = 0,
+                        size_t count = SIZE_MAX, bool fills = true) {
+    if (fills)
+        for (const auto& f : P.fills) {
+            hipError_t e = launch_trivial(f.first, int(f.second), 1, st);
+            if (e != hipSuccess) return e;
+        }
+    const size_t last = std::min(P.steps.size(), count > P.steps.size() ? P.steps.size() : first + count);
+    for (size_t x = first; x < last; ++x) {
+        const PlanStep& s = P.steps[x];
         if (s.sum >= 0) {
             const SumOp& o = P.sums[size_t(s.sum)];
             hipError_t e = launch_group_sum(o.in, o.out, o.items, o.cnt, o.groups, o.group, C->cus, st);
@@ -734,13 +738,23 @@ hipError_t launch_steps(Context* C, const Plan& P, hipStream_t st, bool timed) {
         {
             TimedLaunch t(C, timed ? br_profile_id(C, B) : -1, uint64_t(B));
             hipError_t e = launch_blind_rotate_jobs(P.d_jobs + s.off, B, P.d_part, C->luts, C->bsk, C->tables,
-                                                    C->br_grid, C->latency_form_max, C->latency_waves, st);
+                                                    C->br_grid, C->latency_form_max, C->latency_waves, st, 0,
+                                                    C->throughput_waves);
             if (e != hipSuccess) return e;
         }
     }
     return hipSuccess;
 }
 }  // namespace
+
+hipError_t run_plan_steps(Context* C, const Plan& P, size_t first, size_t count) {
+    if (first == 0)
+        for (const auto& f : P.fills) {
+            hipError_t e = launch_trivial(f.first, int(f.second), 1, C->stream);
+            if (e != hipSuccess) return e;
+        }
+    return launch_steps(C, P, C->stream, true, first, count, false);
+}
 
 hipError_t run_plan(Context* C, const Plan& P) {
     if (P.graph) {

@@ -174,6 +174,10 @@ hipError_t upload_plan(Plan& P, uint8_t*& ws, hipStream_t st);
 // Enqueues every step (or the captured graph).
 hipError_t run_plan(Context* C, const Plan& P);
 
+// Enqueues steps first .. first + count - 1 (never the graph); the plan's
+// Enc(1) fills run first when first is 0.
+hipError_t run_plan_steps(Context* C, const Plan& P, size_t first, size_t count);
+
 // Captures the plan's launches into a graph executable.
 hipError_t capture_plan(Context* C, Plan& P);
 

@@ -147,7 +147,7 @@ int lvs_pbs_batch_static(lvs_context* ctx, const uint64_t* d_in, const uint8_t* 
     if (e == hipSuccess) {
         TimedLaunch t(C, br_profile_id(C, nB), uint64_t(nB));
         e = launch_blind_rotate_jobs(a.jobs, nB, part, C->luts, C->bsk, C->tables, C->br_grid, C->latency_form_max,
-                                     C->latency_waves, C->stream, ns);
+                                     C->latency_waves, C->stream, ns, C->throughput_waves);
     }
     if (e != hipSuccess) return fail(LVS_E_DEVICE, std::string("lvs_pbs_batch_static: ") + hipGetErrorString(e));
     return LVS_OK;

@@ -1,8 +1,8 @@
 // Launch-shape tuning of the blind rotation.
 //
-// The blind rotation has three forms (one eight-wave or one sixteen-wave
-// workgroup per CU, or two four-wave workgroups per CU) and an optional
-// persistent grid.  Which is faster depends on how a batch fills the device,
+// The blind rotation has four forms (one eight-wave or one sixteen-wave
+// workgroup per CU; two eight-wave or two four-wave workgroups per CU) and an
+// optional persistent grid.  Which is faster depends on how a batch fills the device,
 // so the autotuner times every form, and a persistent grid, on batches around
 // the CU count and keeps the fastest shape per batch size.  Its inputs are zero
 // ciphertexts: the work of a bootstrap does not depend on the values.
@@ -67,6 +67,7 @@ int lvs_context_get_tuning(const lvs_context* ctx, lvs_tuning* out) {
     out->br_grid = C->br_grid;
     out->latency_form_max = C->latency_form_max;
     out->latency_waves = C->latency_waves;
+    out->throughput_waves = C->throughput_waves;
     return LVS_OK;
 }
 
@@ -76,9 +77,12 @@ int lvs_context_set_tuning(lvs_context* ctx, const lvs_tuning* t) {
     if (t->br_grid < 0 || t->latency_form_max < 0) TUNE_FAIL(LVS_E_INVAL, "lvs_context_set_tuning: negative value");
     if (t->latency_waves != 0 && t->latency_waves != 8 && t->latency_waves != 16)
         TUNE_FAIL(LVS_E_INVAL, "lvs_context_set_tuning: latency_waves must be 8 or 16");
+    if (t->throughput_waves != 0 && t->throughput_waves != 4 && t->throughput_waves != 8)
+        TUNE_FAIL(LVS_E_INVAL, "lvs_context_set_tuning: throughput_waves must be 4 or 8");
     C->br_grid = t->br_grid;
     C->latency_form_max = t->latency_form_max;
     C->latency_waves = t->latency_waves ? t->latency_waves : 8;
+    C->throughput_waves = t->throughput_waves ? t->throughput_waves : 8;
     return LVS_OK;
 }
 
@@ -118,18 +122,26 @@ int lvs_autotune(lvs_context* ctx, size_t max_batch, void* d_work, size_t work_b
         uint8_t* w = ws;
         err = upload_plan(P, w, st);
         if (err == hipSuccess) err = launch_keyswitch_jobs(P.d_jobs, B, C->ksk, P.d_part, st);
-        std::vector<Candidate> cands{{1, B}, {3, B}, {2, B}};
-        if (B >= 2 * cus) cands.push_back({2, 2 * cus});
+        // forms: 1 / 3 one eight- / sixteen-wave workgroup per CU, 2 / 4 two
+        // four- / eight-wave workgroups per CU
+        std::vector<Candidate> cands{{1, B}, {3, B}, {2, B}, {4, B}};
+        if (B >= 2 * cus) {
+            cands.push_back({2, 2 * cus});
+            cands.push_back({4, 2 * cus});
+        }
         for (const Candidate& c : cands) {
             if (err != hipSuccess) break;
-            const int lf = c.form == 2 ? 0 : INT_MAX;
+            const bool two = c.form == 2 || c.form == 4;
+            const int lf = two ? 0 : INT_MAX;
             const int waves = c.form == 3 ? 16 : 8;
+            const int tw = c.form == 2 ? 4 : 8;
             // one launch to warm caches, then two timed
-            err = launch_blind_rotate_jobs(P.d_jobs, B, P.d_part, C->luts, C->bsk, C->tables, c.grid, lf, waves, st);
+            err = launch_blind_rotate_jobs(P.d_jobs, B, P.d_part, C->luts, C->bsk, C->tables, c.grid, lf, waves, st, 0,
+                                           tw);
             if (err == hipSuccess) err = hipEventRecord(e0, st);
             for (int r = 0; r < 2 && err == hipSuccess; ++r)
                 err = launch_blind_rotate_jobs(P.d_jobs, B, P.d_part, C->luts, C->bsk, C->tables, c.grid, lf, waves,
-                                               st);
+                                               st, 0, tw);
             if (err == hipSuccess) err = hipEventRecord(e1, st);
             if (err == hipSuccess) err = hipEventSynchronize(e1);
             float ms = 0;
@@ -147,35 +159,41 @@ int lvs_autotune(lvs_context* ctx, size_t max_batch, void* d_work, size_t work_b
             if (r.batch == B && r.form == form && r.grid == grid) return r.ms;
         return -1.0;
     };
-    // the one-per-CU form with the smaller total time over the batches tried,
-    // then that form while it is at least as fast as the two-per-CU form, in
-    // increasing batch order; if it is at every size tried, it takes every size
+    // the one-per-CU form and the two-per-CU form with the smaller total
+    // time over the batches tried, then the one-per-CU form until the
+    // two-per-CU form is more than 1% faster, in increasing batch order (if it
+    // never is, the one-per-CU form takes every size)
     lvs_tuning t{};
     const std::vector<int> tried_b = tune_batches(cus, max_batch);
-    double t8 = 0, t16 = 0;
+    double t8 = 0, t16 = 0, t4x2 = 0, t8x2 = 0;
     for (int B : tried_b) {
         t8 += time_of(B, 1, B);
         t16 += time_of(B, 3, B);
+        t4x2 += time_of(B, 2, B);
+        t8x2 += time_of(B, 4, B);
     }
     const int lat = t16 < t8 ? 3 : 1;
+    const int thr = t4x2 < t8x2 ? 2 : 4;
     t.latency_waves = lat == 3 ? 16 : 8;
+    t.throughput_waves = thr == 2 ? 4 : 8;
     t.latency_form_max = 0;
     for (size_t k = 0; k < tried_b.size(); ++k) {
         const int B = tried_b[k];
-        if (time_of(B, lat, B) > time_of(B, 2, B)) break;
+        if (time_of(B, lat, B) > 1.01 * time_of(B, thr, B)) break;
         t.latency_form_max = (k + 1 == tried_b.size()) ? INT_MAX : B;
     }
     // a persistent grid only if it wins by more than 1% at every batch that tried it
     bool tried = false, wins = true;
     for (const auto& r : res)
-        if (r.grid != r.batch) {
+        if (r.grid != r.batch && r.form == thr) {
             tried = true;
-            wins = wins && r.ms < 0.99 * time_of(r.batch, 2, r.batch);
+            wins = wins && r.ms < 0.99 * time_of(r.batch, thr, r.batch);
         }
     t.br_grid = (tried && wins) ? 2 * cus : 0;
     C->br_grid = t.br_grid;
     C->latency_form_max = t.latency_form_max;
     C->latency_waves = t.latency_waves;
+    C->throughput_waves = t.throughput_waves;
     if (best) *best = t;
     if (n_samples) *n_samples = res.size();
     for (size_t k = 0; k < res.size() && samples && k < max_samples; ++k)

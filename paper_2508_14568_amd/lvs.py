@@ -102,6 +102,8 @@ _SIGS = {
     "lvs_context_get_refresh": (I32, [VP, ctypes.POINTER(SZ)]),
     "lvs_plan_run": (I32, [VP]),
     "lvs_plan_info": (I32, [VP, ctypes.POINTER(SZ), ctypes.POINTER(SZ), ctypes.POINTER(SZ)]),
+    "lvs_plan_run_steps": (I32, [VP, SZ, SZ]),
+    "lvs_plan_step_bootstraps": (I32, [VP, VP, SZ]),
     "lvs_server_fixed_bytes": (SZ, [SZ]),
     "lvs_server_request_bytes": (SZ, [VP, VP, SZ, SZ, SZ]),
     "lvs_server_create": (I32, [VP, VP, VP, SZ, VP, SZ, SZ, VP, SZ, ctypes.POINTER(VP)]),
@@ -304,10 +306,11 @@ def to_host(t) -> np.ndarray:
 class Context(_Handle):
     """A device context; keeps its torch arena alive."""
 
-    def __init__(self, ptr, arena, device):
+    def __init__(self, ptr, arena, device, stream_handle=0):
         super().__init__(ptr)
         self.arena = arena
         self.device = device
+        self.stream_handle = stream_handle      # the HIP stream the context enqueues on
 
 
 def lvs_context_bytes(params: lvs_params) -> int:
@@ -324,11 +327,12 @@ def lvs_context_create(sk, params: lvs_params, device=0, stream=None) -> Context
     st = stream if stream is not None else torch.cuda.current_stream(dev)
     out = VP()
     _check(lib().lvs_context_create(sk, dev.index or 0, VP(st.cuda_stream), _dptr(arena), nbytes, ctypes.byref(out)))
-    return Context(out, arena, dev)
+    return Context(out, arena, dev, st.cuda_stream)
 
 
 def lvs_context_set_stream(ctx: Context, stream):
     _check(lib().lvs_context_set_stream(ctx, VP(stream.cuda_stream)))
+    ctx.stream_handle = stream.cuda_stream
 
 
 def lvs_context_set_lut(ctx: Context, slot: int, f16):
@@ -723,6 +727,17 @@ def lvs_plan_run(plan: Plan):
     _check(lib().lvs_plan_run(plan))
 
 
+def lvs_plan_run_steps(plan: Plan, first: int, count: int):
+    _check(lib().lvs_plan_run_steps(plan, first, count))
+
+
+def lvs_plan_step_bootstraps(plan: Plan):
+    steps = lvs_plan_info(plan)[0]
+    out = (SZ * max(1, steps))()
+    _check(lib().lvs_plan_step_bootstraps(plan, out, steps))
+    return [int(out[k]) for k in range(steps)]
+
+
 def lvs_plan_info(plan: Plan):
     st, pb, mx = SZ(), SZ(), SZ()
     _check(lib().lvs_plan_info(plan, ctypes.byref(st), ctypes.byref(pb), ctypes.byref(mx)))
@@ -887,7 +902,8 @@ def lvs_engine_stats(eng: Engine):
 # ------------------------------------------------------------------ tuning
 
 class lvs_tuning(ctypes.Structure):
-    _fields_ = [("br_grid", ctypes.c_int32), ("latency_form_max", ctypes.c_int32), ("latency_waves", ctypes.c_int32)]
+    _fields_ = [("br_grid", ctypes.c_int32), ("latency_form_max", ctypes.c_int32), ("latency_waves", ctypes.c_int32),
+                ("throughput_waves", ctypes.c_int32)]
 
 
 class lvs_tune_sample(ctypes.Structure):
@@ -898,11 +914,13 @@ class lvs_tune_sample(ctypes.Structure):
 def lvs_context_get_tuning(ctx: Context) -> dict:
     t = lvs_tuning()
     _check(lib().lvs_context_get_tuning(ctx, ctypes.byref(t)))
-    return {"br_grid": t.br_grid, "latency_form_max": t.latency_form_max, "latency_waves": t.latency_waves}
+    return {"br_grid": t.br_grid, "latency_form_max": t.latency_form_max, "latency_waves": t.latency_waves,
+            "throughput_waves": t.throughput_waves}
 
 
 def lvs_context_set_tuning(ctx: Context, tuning: dict):
-    t = lvs_tuning(int(tuning["br_grid"]), int(tuning["latency_form_max"]), int(tuning.get("latency_waves", 8)))
+    t = lvs_tuning(int(tuning["br_grid"]), int(tuning["latency_form_max"]), int(tuning.get("latency_waves", 8)),
+                   int(tuning.get("throughput_waves", 8)))
     _check(lib().lvs_context_set_tuning(ctx, ctypes.byref(t)))
 
 
@@ -921,7 +939,7 @@ def lvs_autotune(ctx: Context, max_batch: int, d_work=None):
                               ctypes.byref(best), samples, 64, ctypes.byref(n)))
     rows = [{"batch": x.batch, "form": x.form, "grid": x.grid, "ms": round(x.ms, 4)} for x in samples[:n.value]]
     return {"br_grid": best.br_grid, "latency_form_max": best.latency_form_max,
-            "latency_waves": best.latency_waves}, rows
+            "latency_waves": best.latency_waves, "throughput_waves": best.throughput_waves}, rows
 
 
 def _tuning_key(ctx: Context) -> str:
@@ -968,12 +986,13 @@ def autotune(ctx: Context, max_batch: int = None, cache: str = None) -> dict:
 
 # ------------------------------------------------------------ measurement
 
-KERNEL_BLIND_ROTATE = 0              # both forms
+KERNEL_BLIND_ROTATE = 0              # every form
 KERNEL_KEYSWITCH = 1
 KERNEL_GRAPH = 2
 KERNEL_BLIND_ROTATE_LATENCY = 3      # eight-wave form, one workgroup per CU
 KERNEL_BLIND_ROTATE_THROUGHPUT = 4   # four-wave form, two workgroups per CU
 KERNEL_BLIND_ROTATE_W16 = 5          # sixteen-wave form, one workgroup per CU
+KERNEL_BLIND_ROTATE_PAIR = 6         # eight-wave form, two workgroups per CU
 
 
 def lvs_microbench_modmul(ctx: Context, iters: int = 4096):

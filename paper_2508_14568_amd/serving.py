@@ -45,5 +45,9 @@ def run(srv, queries_ct, arrivals, on_result=None):
 
 
 def percentiles(lat, ps=(50, 99)):
+    """Latency percentiles with the number of samples they rest on (with few
+    samples a high percentile is close to the maximum)."""
     a = np.asarray([x for x in lat if x is not None], dtype=float)
-    return {f"p{p}": float(np.percentile(a, p)) for p in ps}
+    out = {f"p{p}": float(np.percentile(a, p)) for p in ps}
+    out["samples"] = int(a.size)
+    return out

@@ -13,12 +13,20 @@ from oracle import tfhe as T
 pytestmark = pytest.mark.gpu
 
 SHAPES = [
-    {"br_grid": 0, "latency_form_max": 1 << 30, "latency_waves": 8},   # eight-wave form, one workgroup per bootstrap
-    {"br_grid": 0, "latency_form_max": 0, "latency_waves": 8},         # four-wave form, two per CU
-    {"br_grid": 7, "latency_form_max": 0, "latency_waves": 8},         # persistent four-wave form, 7 workgroups loop
-    {"br_grid": 5, "latency_form_max": 1 << 30, "latency_waves": 8},   # persistent eight-wave form
-    {"br_grid": 0, "latency_form_max": 1 << 30, "latency_waves": 16},   # sixteen-wave form
-    {"br_grid": 3, "latency_form_max": 1 << 30, "latency_waves": 16},   # persistent sixteen-wave form
+    # eight-wave form, one workgroup per bootstrap
+    {"br_grid": 0, "latency_form_max": 1 << 30, "latency_waves": 8, "throughput_waves": 8},
+    # eight-wave form with one LDS buffer, two per CU
+    {"br_grid": 0, "latency_form_max": 0, "latency_waves": 8, "throughput_waves": 8},
+    # the same with a persistent grid of 7 workgroups that loop over the batch
+    {"br_grid": 7, "latency_form_max": 0, "latency_waves": 8, "throughput_waves": 8},
+    # four-wave form, two per CU, and persistent
+    {"br_grid": 0, "latency_form_max": 0, "latency_waves": 8, "throughput_waves": 4},
+    {"br_grid": 7, "latency_form_max": 0, "latency_waves": 8, "throughput_waves": 4},
+    # persistent eight-wave form
+    {"br_grid": 5, "latency_form_max": 1 << 30, "latency_waves": 8, "throughput_waves": 8},
+    # sixteen-wave form, and persistent
+    {"br_grid": 0, "latency_form_max": 1 << 30, "latency_waves": 16, "throughput_waves": 8},
+    {"br_grid": 3, "latency_form_max": 1 << 30, "latency_waves": 16, "throughput_waves": 8},
 ]
 
 
@@ -53,23 +61,31 @@ def test_every_shape_bit_identical(gpu, okeys):
         assert_same_ct(outs[0][b], ref[b], f"b={b}")
 
 
-def test_sixteen_wave_form_bit_exact(gpu, okeys):
-    """The sixteen-wave form on all 32 inputs of Table table_lutrelu and on an
-    ASCII edit distance: every ciphertext bit-exact with the oracle."""
+FORMS = {
+    "sixteen_wave": {"br_grid": 0, "latency_form_max": 1 << 30, "latency_waves": 16, "throughput_waves": 8},
+    "eight_wave_two_per_cu": {"br_grid": 0, "latency_form_max": 0, "latency_waves": 8, "throughput_waves": 8},
+}
+
+
+@pytest.mark.parametrize("form", sorted(FORMS))
+def test_form_bit_exact(gpu, okeys, form):
+    """The sixteen-wave form and the eight-wave form with two workgroups per
+    CU on all 32 inputs of Table table_lutrelu and on an ASCII edit
+    distance: every ciphertext bit-exact with the oracle."""
     from oracle import leuvenshtein as OL
     g = gpu
     L, torch = g.L, g.torch
     saved = L.lvs_context_get_tuning(g.ctx)
     try:
-        L.lvs_context_set_tuning(g.ctx, {"br_grid": 0, "latency_form_max": 1 << 30, "latency_waves": 16})
-        say("sixteen-wave: table1 exhaustive")
+        L.lvs_context_set_tuning(g.ctx, FORMS[form])
+        say(form, "table1 exhaustive")
         L.lvs_context_set_lut(g.ctx, L.LVS_LUT_USER, P.LUT_X_MINUS_4)
         cts = np.stack([L.lvs_lwe_encrypt(g.ck, x, 501, x) for x in range(32)])
         out = run_pbs(g, cts, L.LVS_LUT_USER)
         ref = okeys.pbs_batch(cts, T.test_polynomial(P.LUT_X_MINUS_4, 2048)[None, :], 0)
         for x in range(32):
             assert_same_ct(out[x], ref[x], f"x={x}")
-        say("sixteen-wave: kitten / sitting")
+        say(form, "kitten / sitting")
         a, b = b"kitten", b"sitting"
         A = L.lvs_encrypt_string(g.ck, a, L.LVS_ENC_ASCII7, 1001)
         B = L.lvs_encrypt_string(g.ck, b, L.LVS_ENC_ASCII7, 1002)
@@ -95,6 +111,9 @@ def test_set_tuning_rejects_negative(gpu):
     with pytest.raises(L.LvsError) as e:
         L.lvs_context_set_tuning(gpu.ctx, {"br_grid": 0, "latency_form_max": 0, "latency_waves": 12})
     assert e.value.code == -1
+    with pytest.raises(L.LvsError) as e:
+        L.lvs_context_set_tuning(gpu.ctx, {"br_grid": 0, "latency_form_max": 0, "throughput_waves": 6})
+    assert e.value.code == -1
 
 
 def test_autotune_and_cache(gpu, tmp_path):
@@ -111,7 +130,8 @@ def test_autotune_and_cache(gpu, tmp_path):
         assert t["br_grid"] in (0, 2 * cus)
         assert 0 <= t["latency_form_max"] <= 512 or t["latency_form_max"] == 2 ** 31 - 1
         forms = {(r["batch"], r["form"]) for r in first["samples"]}
-        assert (cus, 1) in forms and (cus, 2) in forms
+        assert {(cus, 1), (cus, 2), (cus, 3), (cus, 4)} <= forms
+        assert t["throughput_waves"] in (4, 8) and t["latency_waves"] in (8, 16)
         assert all(r["ms"] > 0 for r in first["samples"])
         assert L.lvs_context_get_tuning(g.ctx) == t
         with open(path) as f:
