@@ -324,7 +324,8 @@ def W_codes(s):
     return W.dna_codes(s)
 
 
-def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos, progress=False, arena_gb=4, max_step=1024):
+def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos, progress=False, arena_gb=4, max_step=1024,
+                  poisson_seed=6, query_offset=0):
     """The serving workload on the first n_names of its 1024 cleartext server
     names: n_sat queries submitted at once (saturated queries/s), then
     n_poisson queries per load factor rho arriving as a Poisson process at
@@ -333,7 +334,9 @@ def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos, progress=False, a
     import numpy as np
     import workloads as W
     from paper_2508_14568_amd import serving as S
-    server, queries = W.serving(n_queries=1 + n_sat + n_poisson * len(rhos))
+    # the workload's query stream, from query_offset on (a later run draws later queries)
+    server, queries = W.serving(n_queries=query_offset + 1 + n_sat + n_poisson * len(rhos))
+    queries = queries[query_offset:]
     names = server[:n_names]
     alpha = W.alphabet_of(names)
     cts = [L.lvs_encrypt_string(ck, q, L.LVS_ENC_ASCII7, 40000 + k) for k, q in enumerate(queries)]
@@ -372,13 +375,15 @@ def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos, progress=False, a
     base = 1 + n_sat
     for r, rho in enumerate(rhos if n_poisson > 0 else []):
         idx = range(base + r * n_poisson, base + (r + 1) * n_poisson)
-        arr = W.poisson_arrivals(6 + r, rho * sat_qps, n_poisson)
+        arr = W.poisson_arrivals(poisson_seed + r, rho * sat_qps, n_poisson)
         note(f"serving: Poisson arrivals at rho={rho}, {n_poisson} queries")
         st0, pbs0 = L.lvs_server_stats(srv)
         lat, wall, _ = S.run(srv, [cts[k] for k in idx], list(arr),
                              on_result=lambda k, o, b=idx.start: check(b + k, o))
         st1, pbs1 = L.lvs_server_stats(srv)
         res["poisson"].append({"rho": rho, "queries": n_poisson, "rate_per_s": round(rho * sat_qps, 4),
+                               "arrival_seed": poisson_seed + r, "query_offset": query_offset,
+                               "latencies_s": [round(x, 3) for x in lat],
                                "seconds": round(wall, 3), "pbs_per_s": round((pbs1 - pbs0) / wall, 1),
                                **{k: round(v, 3) for k, v in S.percentiles(lat).items()},
                                "mean": round(float(np.mean(lat)), 3)})
@@ -563,6 +568,8 @@ def main():
                     help="bootstraps per engine step at most (admitted requests beyond it wait a step)")
     ap.add_argument("--poisson-queries", type=int, default=0, help="queries per load factor")
     ap.add_argument("--rho", type=str, default="0.8", help="comma-separated load factors")
+    ap.add_argument("--poisson-seed", type=int, default=6, help="seed of the first load factor's arrivals")
+    ap.add_argument("--query-offset", type=int, default=0, help="first query of the serving workload's stream")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--band-queries", type=int, default=0, help="the band modes on this many batched pairs")
     ap.add_argument("--band-ell", type=int, default=4, help="half-width of the approximate band")
@@ -571,6 +578,7 @@ def main():
     ap.add_argument("--tuning", type=str, default=None,
                     help="launch shape as JSON (lvs_tuning fields) instead of the autotuner's")
     ap.add_argument("--no-microbench", action="store_true")
+    ap.add_argument("--serving-only", action="store_true", help="only the serving block (latency studies)")
     ap.add_argument("--timed-only", action="store_true",
                     help="only the warm-up and timed plan steps (for profiling their launches)")
     ap.add_argument("--full-configs", action="store_true",
@@ -601,6 +609,13 @@ def main():
     elif not args.no_autotune:
         note("autotune")
         tuning = L.autotune(ctx)
+    if args.serving_only:
+        res = serving_block(L, ck, ctx, args.serving_names, args.serving_queries, args.poisson_queries,
+                            [float(x) for x in args.rho.split(",") if x], max_step=args.serving_max_step,
+                            progress=args.serving_progress, arena_gb=32 if args.serving_names > 256 else 4,
+                            poisson_seed=args.poisson_seed, query_offset=args.query_offset)
+        print(json.dumps({"serving": res, "tuning": tuning and tuning["tuning"]}), flush=True)
+        return
     if args.full_configs:
         res = full_configs(L, ck, ctx, args.full_serving_queries, args.full_poisson_queries)
         print(json.dumps({"full_configs": res, "tuning": tuning and tuning["tuning"]}), flush=True)
@@ -658,7 +673,8 @@ def main():
         line["serving"] = serving_block(L, ck, ctx, args.serving_names, args.serving_queries,
                                         args.poisson_queries, [float(x) for x in args.rho.split(",") if x],
                                         max_step=args.serving_max_step, progress=args.serving_progress,
-                                        arena_gb=32 if args.serving_names > 256 else 4)
+                                        arena_gb=32 if args.serving_names > 256 else 4,
+                                        poisson_seed=args.poisson_seed, query_offset=args.query_offset)
     if args.band_queries > 0:
         line["band"] = band_block(L, ck, ctx, args.band_queries, args.band_ell)
     if args.wide:

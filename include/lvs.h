@@ -217,24 +217,29 @@ int lvs_sync(lvs_context* ctx);
  * four waves per prime, first and last three transform stages in the digit
  * and CRT steps).  throughput_waves picks the two-per-CU form: 8 (the
  * eight-wave form with one LDS buffer and at most 128 registers per thread)
- * or 4 (256 threads, one wave per prime).  A new context starts at
- * {0, INT32_MAX, 8, 8}.  Plans captured as graphs keep the shape they were
+ * or 4 (256 threads, one wave per prime).  ks_tile: job inputs per
+ * key-switch workgroup, each key-switching key row read once per tile.  A new
+ * context starts at {0, INT32_MAX, 8, 8, 8}.  Plans captured as graphs keep the shape they were
  * captured with. */
 typedef struct lvs_tuning {
     int32_t br_grid;
     int32_t latency_form_max;
     int32_t latency_waves;      /* 8 or 16: wavefronts per bootstrap of the one-per-CU form (0 = 8) */
     int32_t throughput_waves;   /* 8 or 4: wavefronts per bootstrap of the two-per-CU form (0 = 8) */
+    int32_t ks_tile;            /* 4, 8 or 16: ciphertexts per key-switch workgroup (0 = 8) */
 } lvs_tuning;
 
 int lvs_context_get_tuning(const lvs_context* ctx, lvs_tuning* out);
-/* Rejects negative values, latency_waves other than 0, 8, 16 and
- * throughput_waves other than 0, 4, 8 (LVS_E_INVAL). */
+/* Rejects negative values, latency_waves other than 0, 8, 16,
+ * throughput_waves other than 0, 4, 8 and ks_tile other than 0, 4, 8, 16
+ * (LVS_E_INVAL). */
 int lvs_context_set_tuning(lvs_context* ctx, const lvs_tuning* t);
 
-/* One timing of the autotuner: mean duration (ms) of a blind-rotation launch
- * of `batch` bootstraps in `form` (1: eight-wave, 2: four-wave, 3:
- * sixteen-wave) with `grid` workgroups. */
+/* One timing of the autotuner: mean duration (ms) of a launch over `batch`
+ * bootstraps: the blind rotation in `form` 1 to 4 (1: eight-wave, one
+ * workgroup per CU; 2: four-wave, two per CU; 3: sixteen-wave, one per CU;
+ * 4: eight-wave with one LDS buffer, two per CU) with `grid` workgroups, or
+ * the key switch (form 5) with tiles of `grid` ciphertexts. */
 typedef struct lvs_tune_sample {
     int32_t batch;
     int32_t form;
@@ -252,7 +257,9 @@ size_t lvs_autotune_workspace_bytes(size_t max_batch);
  * ciphertexts, installs the fastest shape in the context (of each kind the
  * form with the smaller total time; the one-per-CU form up to the batch
  * before the first one at which the two-per-CU form is more than 1% faster)
- * and returns it in *best.  Up to max_samples timings go to samples (may be NULL); *n_samples
+ * and returns it in *best; the key switch is timed at tiles of 4, 8 and 16
+ * on the same batches and the tile with the smallest total time is
+ * installed.  Up to max_samples timings go to samples (may be NULL); *n_samples
  * (may be NULL) receives how many were taken.  Synchronous; uses the
  * context's stream.  Errors: LVS_E_INVAL, LVS_E_NOMEM_DEVICE (workspace too
  * small), LVS_E_DEVICE. */

@@ -28,6 +28,7 @@ struct Context : Handle {
     int latency_form_max = 0;     // batches up to this size take the one-workgroup-per-CU form
     int latency_waves = 8;        // that form's wavefronts per bootstrap: 8 or 16
     int throughput_waves = 8;     // larger batches: two workgroups per CU of 8 (or 4) wavefronts
+    int ks_tile = 8;              // key switch: ciphertexts per workgroup (4, 8 or 16)
     size_t refresh_every = LVS_REFRESH_DEFAULT;   // noise-refresh interval in anti-diagonals (0: off)
     // kernel timing (lvs_profile_*): event pairs recorded around launches
     bool profiling = false;

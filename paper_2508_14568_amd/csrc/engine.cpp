@@ -165,13 +165,14 @@ struct Engine : Handle {
                 e = hipMemcpyAsync(d_jobs, jobs.data(), sizeof(Job) * jobs.size(), hipMemcpyHostToDevice, stream);
                 if (e == hipSuccess) {
                     what = "key switch";
-                    e = launch_keyswitch_jobs(d_jobs, B, C->ksk, d_part, stream);
+                    e = launch_keyswitch_jobs(d_jobs, B, C->ksk, d_part, stream, keyswitch_splits(B, C->ks_tile),
+                                              C->ks_tile);
                 }
                 if (e == hipSuccess) {
                     what = "blind rotation";
                     e = launch_blind_rotate_jobs(d_jobs, B, d_part, C->luts, C->bsk, C->tables, C->br_grid,
-                                                 C->latency_form_max, C->latency_waves, stream, 0,
-                                                 C->throughput_waves);
+                                                 C->latency_form_max, C->latency_waves, stream,
+                                                 keyswitch_splits(B, C->ks_tile), C->throughput_waves);
                 }
             }
             if (e == hipSuccess) {

@@ -318,7 +318,6 @@ __device__ __forceinline__ uint64_t crt_lift(const uint32_t (&y)[kPrimes], const
 
 // ------------------------------------------------------------ key switch
 
-constexpr int kKsTile = 8;                       // ciphertexts per workgroup
 constexpr int kKsSub = 128;                      // input coefficients per LDS round
 constexpr int kKsCols = (kSmallWords + 255) / 256;
 
@@ -348,18 +347,23 @@ __device__ __forceinline__ void ks_load_row(uint64_t (&k)[kKsCols], const uint64
     for (int cs = 0; cs < kKsCols; ++cs) k[cs] = row[min(tid + 256 * cs, kSmallWords - 1)];
 }
 
-// The products of one row with the tile's biased digits (dp: 8 bytes, one
-// per ciphertext): sum (d + 4) k = sum (d + 4) k_lo + 2^32 sum (d + 4) k_hi
-// (mod 2^64), the first sum kept in 64 bits (a 32 x 32 + 64 multiply-add per
-// product), the second in 32 bits; ksum collects the rows for the bias.
-__device__ __forceinline__ void ks_row_products(uint64_t dp, const uint64_t (&k)[kKsCols],
-                                                uint64_t (&acc_lo)[kKsTile][kKsCols],
-                                                uint32_t (&acc_hi)[kKsTile][kKsCols], uint64_t (&ksum)[kKsCols]) {
+// The products of one row with the tile's biased digits (dp: one byte per
+// ciphertext, T of them): sum (d + 4) k = sum (d + 4) k_lo + 2^32 sum (d + 4)
+// k_hi (mod 2^64), the first sum kept in 64 bits (a 32 x 32 + 64
+// multiply-add per product), the second in 32 bits; ksum collects the rows
+// for the bias.
+template <int T>
+__device__ __forceinline__ void ks_row_products(const uint64_t* dp, const uint64_t (&k)[kKsCols],
+                                                uint64_t (&acc_lo)[T][kKsCols], uint32_t (&acc_hi)[T][kKsCols],
+                                                uint64_t (&ksum)[kKsCols]) {
 #pragma unroll
     for (int cs = 0; cs < kKsCols; ++cs) ksum[cs] += k[cs];
+    uint64_t w[(T + 7) / 8];
 #pragma unroll
-    for (int bb = 0; bb < kKsTile; ++bb) {
-        const uint32_t d = uint32_t(dp >> (8 * bb)) & 0xFFu;
+    for (int q = 0; q < (T + 7) / 8; ++q) w[q] = dp[q];
+#pragma unroll
+    for (int bb = 0; bb < T; ++bb) {
+        const uint32_t d = uint32_t(w[bb >> 3] >> (8 * (bb & 7))) & 0xFFu;
 #pragma unroll
         for (int cs = 0; cs < kKsCols; ++cs) {
             acc_lo[bb][cs] += uint64_t(d) * uint32_t(k[cs]);
@@ -368,30 +372,34 @@ __device__ __forceinline__ void ks_row_products(uint64_t dp, const uint64_t (&k)
     }
 }
 
+// Tiles of T job inputs x all n+1 output columns per workgroup: each KSK row
+// is read once per tile and multiplied with the tile's T digits.
+template <int T>
 __global__ void __launch_bounds__(256) keyswitch_jobs_kernel(const Job* __restrict__ jobs, int B,
                                                              const uint64_t* __restrict__ ksk,
                                                              uint64_t* __restrict__ part, int chunk, int sub) {
-    // 8 bytes per row, one per tile ciphertext: the balanced digit d in
-    // [-4, 4) stored as d + 4.  The products then take unsigned 32 x 64-bit
-    // multiply-adds, and the bias comes off once per split:
-    // sum (d + 4) k - 4 sum k = sum d k (mod 2^64).
-    __shared__ uint64_t digits[kKsSub * kKsLevel];
+    // one byte per row and tile ciphertext (rows padded to whole 8-byte
+    // words): the balanced digit d in [-4, 4) stored as d + 4.  The products
+    // then take unsigned 32 x 64-bit multiply-adds, and the bias comes off
+    // once per split: sum (d + 4) k - 4 sum k = sum d k (mod 2^64).
+    constexpr int kWords = (T + 7) / 8;
+    __shared__ uint64_t digits[kKsSub * kKsLevel * kWords];
     const int tid = threadIdx.x;
-    const int b0 = blockIdx.x * kKsTile;
+    const int b0 = blockIdx.x * T;
     const int split = blockIdx.y;
     uint8_t* dig8 = reinterpret_cast<uint8_t*>(digits);
-    uint64_t acc_lo[kKsTile][kKsCols];
-    uint32_t acc_hi[kKsTile][kKsCols];
+    uint64_t acc_lo[T][kKsCols];
+    uint32_t acc_hi[T][kKsCols];
     uint64_t ksum[kKsCols];
 #pragma unroll
     for (int cs = 0; cs < kKsCols; ++cs) ksum[cs] = 0;
 #pragma unroll
-    for (int bb = 0; bb < kKsTile; ++bb)
+    for (int bb = 0; bb < T; ++bb)
 #pragma unroll
         for (int cs = 0; cs < kKsCols; ++cs) acc_lo[bb][cs] = acc_hi[bb][cs] = 0;
     for (int j0 = split * chunk; j0 < (split + 1) * chunk; j0 += sub) {
         __syncthreads();
-        for (int idx = tid; idx < kKsTile * sub; idx += 256) {
+        for (int idx = tid; idx < T * sub; idx += 256) {
             const int bb = idx / sub, jj = idx % sub;
             uint64_t c = 0;
             if (b0 + bb < B) c = job_word(jobs[b0 + bb], j0 + jj);
@@ -401,7 +409,7 @@ __global__ void __launch_bounds__(256) keyswitch_jobs_kernel(const Job* __restri
                 int d = int(r & 7u);
                 r >>= 3;
                 if (d >= 4) { d -= 8; r += 1; }
-                dig8[(jj * kKsLevel + lev) * 8 + bb] = uint8_t(d + 4);
+                dig8[(jj * kKsLevel + lev) * 8 * kWords + bb] = uint8_t(d + 4);
             }
         }
         __syncthreads();
@@ -409,11 +417,11 @@ __global__ void __launch_bounds__(256) keyswitch_jobs_kernel(const Job* __restri
         for (int rr = 0; rr < sub * kKsLevel; ++rr) {
             uint64_t k[kKsCols];
             ks_load_row(k, rows + size_t(rr) * kSmallWords, tid);
-            ks_row_products(digits[rr], k, acc_lo, acc_hi, ksum);
+            ks_row_products<T>(digits + rr * kWords, k, acc_lo, acc_hi, ksum);
         }
     }
 #pragma unroll
-    for (int bb = 0; bb < kKsTile; ++bb) {
+    for (int bb = 0; bb < T; ++bb) {
         if (b0 + bb >= B) break;
 #pragma unroll
         for (int cs = 0; cs < kKsCols; ++cs) {
@@ -1619,35 +1627,42 @@ hipError_t launch_fill_u64(uint64_t* p, size_t count, uint64_t v, hipStream_t st
     return hipGetLastError();
 }
 
-int keyswitch_splits(int B) {
+int keyswitch_splits(int B, int tile) {
     // enough workgroups to fill the chip: tiles x splits >= 1024, at most 64
-    // splits of 32 input coefficients
-    const int tiles = (B + dev::kKsTile - 1) / dev::kKsTile;
+    // splits of 32 input coefficients, and at most kKsPartRows partial rows
+    const int tiles = (B + tile - 1) / tile;
     int s = 1;
     while (s < 64 && tiles * s < 1024) s *= 2;
+    while (s > 1 && size_t(s) * size_t(B) > kKsPartRows) s /= 2;
     return s;
 }
 
 size_t keyswitch_part_words(int B) {
     // A smaller batch can take more splits than a larger one, so the buffer
-    // must hold the largest splits(b) * b over every b <= B.  splits(b) * b
-    // stays below 2 * 1024 * kKsTile once b has that many ciphertexts.
-    size_t most = 0;
-    const int top = std::min(B, 2 * 1024 * dev::kKsTile);
-    for (int b = 1; b <= top; ++b) most = std::max(most, size_t(keyswitch_splits(b)) * size_t(b));
-    most = std::max(most, size_t(keyswitch_splits(B)) * size_t(B));
+    // must hold the largest splits(b) * b over every b <= B and every tile;
+    // past kKsPartRows ciphertexts a batch takes one split.
+    size_t most = size_t(std::max(B, 1));
+    const int top = std::min<int>(B, int(kKsPartRows));
+    for (int tile : {4, 8, 16})
+        for (int b = 1; b <= top; ++b) most = std::max(most, size_t(keyswitch_splits(b, tile)) * size_t(b));
     return most * kSmallWords;
 }
 
 hipError_t launch_keyswitch_jobs(const Job* jobs, int B, const uint64_t* ksk, uint64_t* part, hipStream_t st,
-                                 int nsplit) {
+                                 int nsplit, int tile) {
     if (B <= 0) return hipSuccess;
     if (nsplit < 0 || nsplit > 64 || (nsplit & (nsplit - 1))) return hipErrorInvalidValue;
-    const int ns = nsplit ? nsplit : keyswitch_splits(B);
-    dim3 grid((B + dev::kKsTile - 1) / dev::kKsTile, ns);
+    if (tile != 4 && tile != 8 && tile != 16) return hipErrorInvalidValue;
+    const int ns = nsplit ? nsplit : keyswitch_splits(B, tile);
+    dim3 grid((B + tile - 1) / tile, ns);
     const int chunk = kN / ns;   // input coefficients per split, a power of two
-    hipLaunchKernelGGL(dev::keyswitch_jobs_kernel, grid, dim3(256), 0, st, jobs, B, ksk, part, chunk,
-                       std::min(chunk, dev::kKsSub));
+    const int sub = std::min(chunk, dev::kKsSub);
+    if (tile == 4)
+        hipLaunchKernelGGL(dev::keyswitch_jobs_kernel<4>, grid, dim3(256), 0, st, jobs, B, ksk, part, chunk, sub);
+    else if (tile == 8)
+        hipLaunchKernelGGL(dev::keyswitch_jobs_kernel<8>, grid, dim3(256), 0, st, jobs, B, ksk, part, chunk, sub);
+    else
+        hipLaunchKernelGGL(dev::keyswitch_jobs_kernel<16>, grid, dim3(256), 0, st, jobs, B, ksk, part, chunk, sub);
     return hipGetLastError();
 }
 

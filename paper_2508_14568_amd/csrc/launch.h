@@ -38,14 +38,19 @@ struct DevTables {
 };
 
 hipError_t launch_fill_u64(uint64_t* p, size_t count, uint64_t v, hipStream_t st);
-// Key switch of B job inputs into partial sums part[split][B][n+1]; returns
-// the number of splits used (they are summed by the blind rotation).
-int keyswitch_splits(int B);
+// Key switch of B job inputs in tiles of `tile` ciphertexts per workgroup (4,
+// 8 or 16) into partial sums part[split][B][n+1]; keyswitch_splits gives the
+// number of splits of the input coefficients (the blind rotation sums them),
+// at most kKsPartRows / B (rounded down to a power of two) when B > 1, so
+// that keyswitch_part_words(B) words hold the partials of any batch up to B
+// at any tile.
+constexpr size_t kKsPartRows = 16384;
+int keyswitch_splits(int B, int tile = 8);
 size_t keyswitch_part_words(int B);
-// nsplit > 0 overrides keyswitch_splits(B) (a power of two, at most 64); the
-// blind rotation that sums the partials must be given the same count.
+// nsplit > 0 overrides keyswitch_splits(B, tile) (a power of two, at most
+// 64); the blind rotation that sums the partials must be given the same count.
 hipError_t launch_keyswitch_jobs(const Job* jobs, int B, const uint64_t* ksk, uint64_t* part, hipStream_t st,
-                                 int nsplit = 0);
+                                 int nsplit = 0, int tile = 8);
 // Batches of at most latency_form_max bootstraps take the one-workgroup-per-CU
 // form of the blind rotation (latency_waves 8 or 16 wavefronts), larger ones
 // a two-per-CU form (throughput_waves 8: the eight-wave form with one LDS

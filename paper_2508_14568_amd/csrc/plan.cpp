@@ -730,15 +730,16 @@ hipError_t launch_steps(Context* C, const Plan& P, hipStream_t st, bool timed, s
         }
         if (!s.count) continue;
         const int B = int(s.count);
+        const int ns = keyswitch_splits(B, C->ks_tile);
         {
             TimedLaunch t(C, timed ? kProfKeySwitch : -1, uint64_t(B));
-            hipError_t e = launch_keyswitch_jobs(P.d_jobs + s.off, B, C->ksk, P.d_part, st);
+            hipError_t e = launch_keyswitch_jobs(P.d_jobs + s.off, B, C->ksk, P.d_part, st, ns, C->ks_tile);
             if (e != hipSuccess) return e;
         }
         {
             TimedLaunch t(C, timed ? br_profile_id(C, B) : -1, uint64_t(B));
             hipError_t e = launch_blind_rotate_jobs(P.d_jobs + s.off, B, P.d_part, C->luts, C->bsk, C->tables,
-                                                    C->br_grid, C->latency_form_max, C->latency_waves, st, 0,
+                                                    C->br_grid, C->latency_form_max, C->latency_waves, st, ns,
                                                     C->throughput_waves);
             if (e != hipSuccess) return e;
         }

@@ -474,13 +474,14 @@ int lvs_server_step(lvs_server* srv, size_t* active, size_t* queued, size_t* ste
                                C->stream));
         {
             TimedLaunch t(C, kProfKeySwitch, uint64_t(B));
-            SRV_HIP(launch_keyswitch_jobs(S->d_jobs, B, C->ksk, S->d_part, C->stream));
+            SRV_HIP(launch_keyswitch_jobs(S->d_jobs, B, C->ksk, S->d_part, C->stream, keyswitch_splits(B, C->ks_tile),
+                                          C->ks_tile));
         }
         {
             TimedLaunch t(C, br_profile_id(C, B), uint64_t(B));
             SRV_HIP(launch_blind_rotate_jobs(S->d_jobs, B, S->d_part, C->luts, C->bsk, C->tables, C->br_grid,
-                                             C->latency_form_max, C->latency_waves, C->stream, 0,
-                                             C->throughput_waves));
+                                             C->latency_form_max, C->latency_waves, C->stream,
+                                             keyswitch_splits(B, C->ks_tile), C->throughput_waves));
         }
         SRV_HIP(hipStreamSynchronize(C->stream));   // the job list is reused by the next step
         S->steps++;

@@ -65,8 +65,8 @@ __global__ void __launch_bounds__(256) static_jobs_kernel(StaticJobsArgs a) {
 
 // Largest power-of-two split count up to the launcher's own choice whose
 // partial sums fit the array's rows.
-int static_splits(int B) {
-    int s = keyswitch_splits(B);
+int static_splits(int B, int tile) {
+    int s = keyswitch_splits(B, tile);
     while (s > 1 && size_t(s) * size_t(B) > kPartRows) s /= 2;
     return s;
 }
@@ -135,14 +135,14 @@ int lvs_pbs_batch_static(lvs_context* ctx, const uint64_t* d_in, const uint8_t* 
     a.per_ct = lut_ids ? 1u : 0u;
     uint64_t* part = reinterpret_cast<uint64_t*>(base + kJobArea);
     const int nB = int(B);
-    const int ns = static_splits(nB);
+    const int ns = static_splits(nB, C->ks_tile);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(static_jobs_kernel, dim3((nB + 255) / 256), dim3(256), 0, C->stream, a);
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
         TimedLaunch t(C, kProfKeySwitch, uint64_t(nB));
-        e = launch_keyswitch_jobs(a.jobs, nB, C->ksk, part, C->stream, ns);
+        e = launch_keyswitch_jobs(a.jobs, nB, C->ksk, part, C->stream, ns, C->ks_tile);
     }
     if (e == hipSuccess) {
         TimedLaunch t(C, br_profile_id(C, nB), uint64_t(nB));

@@ -68,6 +68,7 @@ int lvs_context_get_tuning(const lvs_context* ctx, lvs_tuning* out) {
     out->latency_form_max = C->latency_form_max;
     out->latency_waves = C->latency_waves;
     out->throughput_waves = C->throughput_waves;
+    out->ks_tile = C->ks_tile;
     return LVS_OK;
 }
 
@@ -79,10 +80,13 @@ int lvs_context_set_tuning(lvs_context* ctx, const lvs_tuning* t) {
         TUNE_FAIL(LVS_E_INVAL, "lvs_context_set_tuning: latency_waves must be 8 or 16");
     if (t->throughput_waves != 0 && t->throughput_waves != 4 && t->throughput_waves != 8)
         TUNE_FAIL(LVS_E_INVAL, "lvs_context_set_tuning: throughput_waves must be 4 or 8");
+    if (t->ks_tile != 0 && t->ks_tile != 4 && t->ks_tile != 8 && t->ks_tile != 16)
+        TUNE_FAIL(LVS_E_INVAL, "lvs_context_set_tuning: ks_tile must be 4, 8 or 16");
     C->br_grid = t->br_grid;
     C->latency_form_max = t->latency_form_max;
     C->latency_waves = t->latency_waves ? t->latency_waves : 8;
     C->throughput_waves = t->throughput_waves ? t->throughput_waves : 8;
+    C->ks_tile = t->ks_tile ? t->ks_tile : 8;
     return LVS_OK;
 }
 
@@ -148,6 +152,20 @@ int lvs_autotune(lvs_context* ctx, size_t max_batch, void* d_work, size_t work_b
             if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
             if (err == hipSuccess) res.push_back({B, c.form, c.grid, double(ms) / 2});
         }
+        // the key switch at each tile size (form 5, grid = the tile)
+        for (int tile : {4, 8, 16}) {
+            if (err != hipSuccess) break;
+            const int ns = keyswitch_splits(B, tile);
+            err = launch_keyswitch_jobs(P.d_jobs, B, C->ksk, P.d_part, st, ns, tile);
+            if (err == hipSuccess) err = hipEventRecord(e0, st);
+            for (int r = 0; r < 2 && err == hipSuccess; ++r)
+                err = launch_keyswitch_jobs(P.d_jobs, B, C->ksk, P.d_part, st, ns, tile);
+            if (err == hipSuccess) err = hipEventRecord(e1, st);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
+            float ms = 0;
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+            if (err == hipSuccess) res.push_back({B, 5, tile, double(ms) / 2});
+        }
         if (err != hipSuccess) break;
     }
     (void)hipEventDestroy(e0);   // a failed measurement is reported below
@@ -190,6 +208,18 @@ int lvs_autotune(lvs_context* ctx, size_t max_batch, void* d_work, size_t work_b
             wins = wins && r.ms < 0.99 * time_of(r.batch, thr, r.batch);
         }
     t.br_grid = (tried && wins) ? 2 * cus : 0;
+    // the key-switch tile with the smallest total time over the batches tried
+    double best_ks = -1;
+    t.ks_tile = 8;
+    for (int tile : {4, 8, 16}) {
+        double tot = 0;
+        for (int B : tried_b) tot += time_of(B, 5, tile);
+        if (best_ks < 0 || tot < best_ks) {
+            best_ks = tot;
+            t.ks_tile = tile;
+        }
+    }
+    C->ks_tile = t.ks_tile;
     C->br_grid = t.br_grid;
     C->latency_form_max = t.latency_form_max;
     C->latency_waves = t.latency_waves;

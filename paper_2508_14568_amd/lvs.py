@@ -903,7 +903,7 @@ def lvs_engine_stats(eng: Engine):
 
 class lvs_tuning(ctypes.Structure):
     _fields_ = [("br_grid", ctypes.c_int32), ("latency_form_max", ctypes.c_int32), ("latency_waves", ctypes.c_int32),
-                ("throughput_waves", ctypes.c_int32)]
+                ("throughput_waves", ctypes.c_int32), ("ks_tile", ctypes.c_int32)]
 
 
 class lvs_tune_sample(ctypes.Structure):
@@ -915,12 +915,12 @@ def lvs_context_get_tuning(ctx: Context) -> dict:
     t = lvs_tuning()
     _check(lib().lvs_context_get_tuning(ctx, ctypes.byref(t)))
     return {"br_grid": t.br_grid, "latency_form_max": t.latency_form_max, "latency_waves": t.latency_waves,
-            "throughput_waves": t.throughput_waves}
+            "throughput_waves": t.throughput_waves, "ks_tile": t.ks_tile}
 
 
 def lvs_context_set_tuning(ctx: Context, tuning: dict):
     t = lvs_tuning(int(tuning["br_grid"]), int(tuning["latency_form_max"]), int(tuning.get("latency_waves", 8)),
-                   int(tuning.get("throughput_waves", 8)))
+                   int(tuning.get("throughput_waves", 8)), int(tuning.get("ks_tile", 8)))
     _check(lib().lvs_context_set_tuning(ctx, ctypes.byref(t)))
 
 
@@ -939,7 +939,8 @@ def lvs_autotune(ctx: Context, max_batch: int, d_work=None):
                               ctypes.byref(best), samples, 64, ctypes.byref(n)))
     rows = [{"batch": x.batch, "form": x.form, "grid": x.grid, "ms": round(x.ms, 4)} for x in samples[:n.value]]
     return {"br_grid": best.br_grid, "latency_form_max": best.latency_form_max,
-            "latency_waves": best.latency_waves, "throughput_waves": best.throughput_waves}, rows
+            "latency_waves": best.latency_waves, "throughput_waves": best.throughput_waves,
+            "ks_tile": best.ks_tile}, rows
 
 
 def _tuning_key(ctx: Context) -> str:

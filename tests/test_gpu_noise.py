@@ -96,3 +96,19 @@ def test_key_noise_dna_256(gpu):
     assert 0.75 < fit_lo < 1.33 and 0.75 < fit_hi < 1.33
     assert 4.0 < hi / lo < 12.0
     assert worst < 2.0 ** 57                # half the decoding threshold (a box is 2^59 wide)
+    # Section 3.1 asks the noise to stay below the decoding threshold with a
+    # small failure probability: a value is lost when the key's error plus the
+    # key switch's and the modulus switch's (computed from the parameters:
+    # 2048 x 5 balanced base-8 digits, mean square 5.5, times the key
+    # switching key's noise; the rounding of the input to 15 bits; the
+    # rounding of 742 mask words and the body to multiples of 2^52) passes
+    # 2^58.  With the measured key errors the two-sided Gaussian tail gives
+    # the failure probability of one bootstrap at both ends of the wavefront.
+    from math import erfc, log2, sqrt
+    sig_ksk = float(L.lvs_params_default().lwe_noise_q64)
+    var_kms = 2048 * 5 * 5.5 * sig_ksk ** 2 + 2048 * 0.5 * 2.0 ** 98 / 12 + 372 * 2.0 ** 104 / 12
+    p_lo = erfc(2.0 ** 58 / sqrt(lo ** 2 + var_kms) / sqrt(2))
+    p_hi = erfc(2.0 ** 58 / sqrt(hi ** 2 + var_kms) / sqrt(2))
+    say(f"key switch + modulus switch error 2^{0.5 * log2(var_kms):.2f}; failure probability per bootstrap "
+        f"2^{log2(p_lo):.1f} (min(i,j) <= 8), 2^{log2(p_hi):.1f} (>= 192, refresh off)")
+    assert p_lo < 2.0 ** -38 and p_hi < 2.0 ** -29

@@ -14,19 +14,19 @@ pytestmark = pytest.mark.gpu
 
 SHAPES = [
     # eight-wave form, one workgroup per bootstrap
-    {"br_grid": 0, "latency_form_max": 1 << 30, "latency_waves": 8, "throughput_waves": 8},
-    # eight-wave form with one LDS buffer, two per CU
-    {"br_grid": 0, "latency_form_max": 0, "latency_waves": 8, "throughput_waves": 8},
-    # the same with a persistent grid of 7 workgroups that loop over the batch
-    {"br_grid": 7, "latency_form_max": 0, "latency_waves": 8, "throughput_waves": 8},
+    {"br_grid": 0, "latency_form_max": 1 << 30, "latency_waves": 8, "throughput_waves": 8, "ks_tile": 8},
+    # eight-wave form with one LDS buffer, two per CU; key switch in tiles of 4
+    {"br_grid": 0, "latency_form_max": 0, "latency_waves": 8, "throughput_waves": 8, "ks_tile": 4},
+    # the same with a persistent grid of 7 workgroups that loop over the batch; tiles of 16
+    {"br_grid": 7, "latency_form_max": 0, "latency_waves": 8, "throughput_waves": 8, "ks_tile": 16},
     # four-wave form, two per CU, and persistent
-    {"br_grid": 0, "latency_form_max": 0, "latency_waves": 8, "throughput_waves": 4},
-    {"br_grid": 7, "latency_form_max": 0, "latency_waves": 8, "throughput_waves": 4},
+    {"br_grid": 0, "latency_form_max": 0, "latency_waves": 8, "throughput_waves": 4, "ks_tile": 8},
+    {"br_grid": 7, "latency_form_max": 0, "latency_waves": 8, "throughput_waves": 4, "ks_tile": 16},
     # persistent eight-wave form
-    {"br_grid": 5, "latency_form_max": 1 << 30, "latency_waves": 8, "throughput_waves": 8},
+    {"br_grid": 5, "latency_form_max": 1 << 30, "latency_waves": 8, "throughput_waves": 8, "ks_tile": 4},
     # sixteen-wave form, and persistent
-    {"br_grid": 0, "latency_form_max": 1 << 30, "latency_waves": 16, "throughput_waves": 8},
-    {"br_grid": 3, "latency_form_max": 1 << 30, "latency_waves": 16, "throughput_waves": 8},
+    {"br_grid": 0, "latency_form_max": 1 << 30, "latency_waves": 16, "throughput_waves": 8, "ks_tile": 8},
+    {"br_grid": 3, "latency_form_max": 1 << 30, "latency_waves": 16, "throughput_waves": 8, "ks_tile": 8},
 ]
 
 
@@ -62,8 +62,10 @@ def test_every_shape_bit_identical(gpu, okeys):
 
 
 FORMS = {
-    "sixteen_wave": {"br_grid": 0, "latency_form_max": 1 << 30, "latency_waves": 16, "throughput_waves": 8},
-    "eight_wave_two_per_cu": {"br_grid": 0, "latency_form_max": 0, "latency_waves": 8, "throughput_waves": 8},
+    "sixteen_wave": {"br_grid": 0, "latency_form_max": 1 << 30, "latency_waves": 16, "throughput_waves": 8,
+                     "ks_tile": 16},
+    "eight_wave_two_per_cu": {"br_grid": 0, "latency_form_max": 0, "latency_waves": 8, "throughput_waves": 8,
+                              "ks_tile": 4},
 }
 
 
@@ -114,6 +116,9 @@ def test_set_tuning_rejects_negative(gpu):
     with pytest.raises(L.LvsError) as e:
         L.lvs_context_set_tuning(gpu.ctx, {"br_grid": 0, "latency_form_max": 0, "throughput_waves": 6})
     assert e.value.code == -1
+    with pytest.raises(L.LvsError) as e:
+        L.lvs_context_set_tuning(gpu.ctx, {"br_grid": 0, "latency_form_max": 0, "ks_tile": 5})
+    assert e.value.code == -1
 
 
 def test_autotune_and_cache(gpu, tmp_path):
@@ -130,8 +135,9 @@ def test_autotune_and_cache(gpu, tmp_path):
         assert t["br_grid"] in (0, 2 * cus)
         assert 0 <= t["latency_form_max"] <= 512 or t["latency_form_max"] == 2 ** 31 - 1
         forms = {(r["batch"], r["form"]) for r in first["samples"]}
-        assert {(cus, 1), (cus, 2), (cus, 3), (cus, 4)} <= forms
-        assert t["throughput_waves"] in (4, 8) and t["latency_waves"] in (8, 16)
+        assert {(cus, 1), (cus, 2), (cus, 3), (cus, 4), (cus, 5)} <= forms
+        assert {r["grid"] for r in first["samples"] if r["form"] == 5} == {4, 8, 16}
+        assert t["throughput_waves"] in (4, 8) and t["latency_waves"] in (8, 16) and t["ks_tile"] in (4, 8, 16)
         assert all(r["ms"] > 0 for r in first["samples"])
         assert L.lvs_context_get_tuning(g.ctx) == t
         with open(path) as f:
