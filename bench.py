@@ -325,7 +325,7 @@ def W_codes(s):
 
 
 def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos, progress=False, arena_gb=4, max_step=1024,
-                  poisson_seed=6, query_offset=0):
+                  poisson_seed=6, query_offset=0, arrival_rate=None, stream=None):
     """The serving workload on the first n_names of its 1024 cleartext server
     names: n_sat queries submitted at once (saturated queries/s), then
     n_poisson queries per load factor rho arriving as a Poisson process at
@@ -345,7 +345,7 @@ def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos, progress=False, a
     srv = L.lvs_server_create(ctx, names, alpha, L.lvs_server_fixed_bytes(max_step) + per * cap + 4096,
                               max_step=max_step)
 
-    def check(k, out):
+    def check(k, out, lat=None):
         q, row = queries[k], 0
         for nm in names:
             if L.lvs_decrypt_distance(ck, out[row:row + len(nm)], len(q)) != levenshtein(q, nm):
@@ -353,35 +353,45 @@ def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos, progress=False, a
             row += len(nm)
         if progress:
             note(f"serving: query {k} done")
+        if stream and lat is not None:        # each Poisson query as it finishes
+            with open(stream, "a") as f:
+                f.write(json.dumps({"query": query_offset + k, "latency_s": round(lat, 4)}) + "\n")
 
-    S.run(srv, cts[:1], [0.0], on_result=check)            # warm-up
-    st0, pbs0 = L.lvs_server_stats(srv)
-    note(f"serving: {n_names} names, saturated run of {n_sat} queries")
-    lat, wall, _ = S.run(srv, cts[1:1 + n_sat], [0.0] * n_sat, on_result=lambda k, o: check(1 + k, o))
-    st1, pbs1 = L.lvs_server_stats(srv)
-    sat_qps = n_sat / wall
+    S.run(srv, cts[:1], [0.0], on_result=lambda k, o, t: check(k, o))            # warm-up
     res = {
         "workload": f"serving: first {n_names} of 1024 cleartext names (lengths lognormal, mean 15), "
                     f"alphabet {len(alpha)} letters, encrypted queries of the same length law",
         "names": n_names, "alphabet": len(alpha), "max_requests_resident": cap, "max_step": max_step,
-        "request_bytes": per,
-        "saturated": {"queries": n_sat, "seconds": round(wall, 3), "queries_per_s": round(sat_qps, 4),
-                      "pbs_per_s": round((pbs1 - pbs0) / wall, 1), "steps": st1 - st0,
-                      "pbs_per_query": round((pbs1 - pbs0) / n_sat, 1),
-                      **{k: round(v, 3) for k, v in S.percentiles(lat).items()}},
-        "latency_note": "seconds from submission to results on the host; with few samples p99 is the maximum",
-        "poisson": [],
+        "request_bytes": per, "poisson": [],
     }
+    sat_qps = None
+    if n_sat > 0:
+        st0, pbs0 = L.lvs_server_stats(srv)
+        note(f"serving: {n_names} names, saturated run of {n_sat} queries")
+        lat, wall, _ = S.run(srv, cts[1:1 + n_sat], [0.0] * n_sat, on_result=lambda k, o, t: check(1 + k, o))
+        st1, pbs1 = L.lvs_server_stats(srv)
+        sat_qps = n_sat / wall
+        res["saturated"] = {"queries": n_sat, "seconds": round(wall, 3), "queries_per_s": round(sat_qps, 4),
+                            "pbs_per_s": round((pbs1 - pbs0) / wall, 1), "steps": st1 - st0,
+                            "pbs_per_query": round((pbs1 - pbs0) / n_sat, 1),
+                            **{k: round(v, 3) for k, v in S.percentiles(lat).items()}}
+        res["latency_note"] = "seconds from submission to results on the host; with few samples p99 is the maximum"
     base = 1 + n_sat
     for r, rho in enumerate(rhos if n_poisson > 0 else []):
         idx = range(base + r * n_poisson, base + (r + 1) * n_poisson)
-        arr = W.poisson_arrivals(poisson_seed + r, rho * sat_qps, n_poisson)
-        note(f"serving: Poisson arrivals at rho={rho}, {n_poisson} queries")
+        rate = arrival_rate if arrival_rate else rho * sat_qps
+        arr = W.poisson_arrivals(poisson_seed + r, rate, n_poisson)
+        note(f"serving: Poisson arrivals at {rate:.4f} queries/s (rho={rho}), {n_poisson} queries")
         st0, pbs0 = L.lvs_server_stats(srv)
+        if stream:
+            with open(stream, "a") as f:
+                f.write(json.dumps({"names": n_names, "rate_per_s": round(rate, 5), "rho": rho,
+                                    "arrival_seed": poisson_seed + r, "queries": n_poisson,
+                                    "first_query": query_offset + idx.start, "max_step": max_step}) + "\n")
         lat, wall, _ = S.run(srv, [cts[k] for k in idx], list(arr),
-                             on_result=lambda k, o, b=idx.start: check(b + k, o))
+                             on_result=lambda k, o, t, b=idx.start: check(b + k, o, t))
         st1, pbs1 = L.lvs_server_stats(srv)
-        res["poisson"].append({"rho": rho, "queries": n_poisson, "rate_per_s": round(rho * sat_qps, 4),
+        res["poisson"].append({"rho": rho, "queries": n_poisson, "rate_per_s": round(rate, 4),
                                "arrival_seed": poisson_seed + r, "query_offset": query_offset,
                                "latencies_s": [round(x, 3) for x in lat],
                                "seconds": round(wall, 3), "pbs_per_s": round((pbs1 - pbs0) / wall, 1),
@@ -570,6 +580,10 @@ def main():
     ap.add_argument("--rho", type=str, default="0.8", help="comma-separated load factors")
     ap.add_argument("--poisson-seed", type=int, default=6, help="seed of the first load factor's arrivals")
     ap.add_argument("--query-offset", type=int, default=0, help="first query of the serving workload's stream")
+    ap.add_argument("--arrival-rate", type=float, default=None,
+                    help="Poisson arrival rate in queries/s (default: rho x the saturated rate)")
+    ap.add_argument("--serving-stream", type=str, default=None,
+                    help="file that receives one JSON line per finished Poisson query")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--band-queries", type=int, default=0, help="the band modes on this many batched pairs")
     ap.add_argument("--band-ell", type=int, default=4, help="half-width of the approximate band")
@@ -613,7 +627,8 @@ def main():
         res = serving_block(L, ck, ctx, args.serving_names, args.serving_queries, args.poisson_queries,
                             [float(x) for x in args.rho.split(",") if x], max_step=args.serving_max_step,
                             progress=args.serving_progress, arena_gb=32 if args.serving_names > 256 else 4,
-                            poisson_seed=args.poisson_seed, query_offset=args.query_offset)
+                            poisson_seed=args.poisson_seed, query_offset=args.query_offset,
+                            arrival_rate=args.arrival_rate, stream=args.serving_stream)
         print(json.dumps({"serving": res, "tuning": tuning and tuning["tuning"]}), flush=True)
         return
     if args.full_configs:

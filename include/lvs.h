@@ -579,7 +579,9 @@ int lvs_plan_step_bootstraps(const lvs_plan* plan, size_t* counts, size_t n);
  * reports the query done; then its results are complete in d_h_last (d_path
  * for a banded query).  d_trace, d_eq1 and d_eq9 must be NULL.  Host buffers
  * (alphabet, b_clear) are read during lvs_submit.  The context's refresh
- * interval at submission applies. */
+ * interval at submission applies; its launch shape (lvs_context_set_tuning)
+ * must not change while an engine runs, and engines are released before
+ * their context. */
 typedef struct lvs_engine lvs_engine;
 
 /* Job list and key-switch partials for at most max_step bootstraps per step. */

@@ -15,8 +15,9 @@ from . import lvs as L
 def run(srv, queries_ct, arrivals, on_result=None):
     """queries_ct: list of encrypted queries ([m][2][N+1] arrays, [m][c][N+1]
     chunk ciphertexts on a wide server); arrivals:
-    non-decreasing arrival times in seconds.  Returns (latencies in seconds,
-    wall seconds, results)."""
+    non-decreasing arrival times in seconds; on_result(k, rows, latency) is
+    called as each query finishes.  Returns (latencies in seconds, wall
+    seconds, results)."""
     order = np.argsort(np.asarray(arrivals, dtype=float), kind="stable")
     t0 = time.perf_counter()
     nxt = 0
@@ -40,7 +41,7 @@ def run(srv, queries_ct, arrivals, on_result=None):
                 lat[k] = time.perf_counter() - t0 - arrivals[k]
                 results[k] = out
                 if on_result:
-                    on_result(k, out)
+                    on_result(k, out, lat[k])
     return lat, time.perf_counter() - t0, results
 
 
