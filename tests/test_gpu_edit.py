@@ -162,8 +162,25 @@ def test_dna_256_alignment(gpu):
     refresh = g.L.lvs_context_get_refresh(g.ctx)
     assert refresh == meta["refresh_every"], refresh
     sa, sb = W.dna_codes(a), W.dna_codes(b)
-    A, B, eq9, tr, h = gpu_run(g, sa, sb, OL.ENC_DNA2)
+    L, torch = g.L, g.torch
     m, n = len(a), len(b)
+    # the plain path's own plan (one query: the plan lvs_edit_distance builds,
+    # equality inside the wavefront, refresh after anti-diagonal 256) keeping
+    # every eq9 and M
+    A = L.lvs_encrypt_string(g.ck, sa, L.LVS_ENC_DNA2, SEED_A)
+    B = L.lvs_encrypt_string(g.ck, sb, L.LVS_ENC_DNA2, SEED_B)
+    d_eq9 = torch.zeros(m * n * L.CT_WORDS, dtype=torch.int64, device=g.dev)
+    d_tr = torch.zeros_like(d_eq9)
+    item = {"d_a": L.to_device(A, g.dev), "m": m, "d_b": L.to_device(B, g.dev), "n": n,
+            "d_h_last": torch.zeros(n * L.CT_WORDS, dtype=torch.int64, device=g.dev), "d_eq9": d_eq9, "d_trace": d_tr}
+    plan = L.lvs_plan_create(g.ctx, [item], L.LVS_ENC_DNA2)
+    L.lvs_plan_run(plan)
+    torch.cuda.synchronize()
+    del plan
+    eq9 = L.to_host(d_eq9).reshape(m, n, L.CT_WORDS)
+    tr = L.to_host(d_tr).reshape(m, n, L.CT_WORDS)
+    h = L.to_host(item["d_h_last"]).reshape(n, L.CT_WORDS)
+    assert (gpu_one_shot(g, A, m, B, n, OL.ENC_DNA2) == h).all()      # bench.py's call
     assert g.L.lvs_decrypt_distance(g.ck, h, m) == P.edit_distance(a, b) == meta["distance"]
     bad_eq = [i for i in range(m) if row_digest(eq9[i]) != meta["eq9_row_sha256"][i]]
     bad_m = [i for i in range(m) if row_digest(tr[i]) != meta["M_row_sha256"][i]]

@@ -148,3 +148,37 @@ def test_engine_refusals(gpu):
         L.lvs_poll(eng, 12345)
     assert L.lvs_engine_stats(eng)[2:] == (0, 0)
     del eng
+
+
+def test_engine_dna_with_refresh(gpu):
+    """DNA queries with a short refresh interval (R = 4: refresh steps inside
+    every query's plan), an empty string among them: each equal to its lone
+    lvs_edit_distance under the same interval."""
+    g = gpu
+    L, torch = g.L, g.torch
+    Wd = L.CT_WORDS
+    rng = np.random.default_rng(8501)
+    pairs = [(W.random_dna(rng, 9), W.random_dna(rng, 13)), (W.random_dna(rng, 17), W.random_dna(rng, 6)),
+             (b"", W.random_dna(rng, 5)), (W.random_dna(rng, 12), W.random_dna(rng, 12))]
+    saved = L.lvs_context_get_refresh(g.ctx)
+    L.lvs_context_set_refresh(g.ctx, 4)
+    try:
+        cts = [(L.lvs_encrypt_string(g.ck, W.dna_codes(a), L.LVS_ENC_DNA2, 8600 + 2 * k),
+                L.lvs_encrypt_string(g.ck, W.dna_codes(b), L.LVS_ENC_DNA2, 8601 + 2 * k))
+               for k, (a, b) in enumerate(pairs)]
+        items = [{"d_a": L.to_device(A, g.dev) if len(a) else None, "m": len(a), "d_b": L.to_device(B, g.dev),
+                  "n": len(b), "d_h_last": torch.zeros(len(b) * Wd, dtype=torch.int64, device=g.dev)}
+                 for (a, b), (A, B) in zip(pairs, cts)]
+        per = max(L.lvs_engine_query_bytes(it, L.LVS_ENC_DNA2) for it in items)
+        say("engine: DNA, refresh every 4 anti-diagonals")
+        eng = L.lvs_engine_create(g.ctx, L.LVS_ENC_DNA2, L.lvs_engine_fixed_bytes(512) + 4 * per, max_step=512)
+        wait_all(L, eng, L.lvs_submit(eng, items))
+        del eng
+        for k, ((a, b), (A, B), it) in enumerate(zip(pairs, cts, items)):
+            h = L.to_host(it["d_h_last"]).reshape(len(b), Wd)
+            if len(a):
+                ref = lone_full(g, A, len(a), B, len(b), L.LVS_ENC_DNA2)
+                assert np.array_equal(h, ref), k
+            assert L.lvs_decrypt_distance(g.ck, h, len(a)) == P.edit_distance(a, b), k
+    finally:
+        L.lvs_context_set_refresh(g.ctx, saved)

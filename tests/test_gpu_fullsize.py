@@ -174,7 +174,7 @@ def test_serving_sampled_queries_against_1024_names(gpu):
     qidx, nidx = W.serving_sample()
     alpha = W.alphabet_of(server)
     assert meta["alphabet"] == alpha.decode() and [q["query"] for q in meta["queries"]] == qidx
-    max_step = 8192
+    max_step = 1024                  # the step cap bench.py serves with
     per = sum(L.lvs_server_request_bytes(server, len(alpha), len(queries[qi])) for qi in qidx)
     say("full size: serving, 1024 names, queries", qidx)
     srv = L.lvs_server_create(g.ctx, server, alpha, L.lvs_server_fixed_bytes(max_step) + per + 4096,
