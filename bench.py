@@ -376,6 +376,13 @@ def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos, progress=False, a
                             "pbs_per_query": round((pbs1 - pbs0) / n_sat, 1),
                             **{k: round(v, 3) for k, v in S.percentiles(lat).items()}}
         res["latency_note"] = "seconds from submission to results on the host; with few samples p99 is the maximum"
+        # the workload's own query mix (first 200 queries of its stream): mean bootstraps per query and the
+        # saturated query rate the measured bootstrap rate gives for that mix
+        _, mix = W.serving(n_queries=200)
+        tot = sum(len(nm) for nm in names)
+        mean_pbs = float(np.mean([2 * len(alpha) * len(q) + len(q) * tot for q in mix]))
+        res["saturated"]["workload_mean_pbs_per_query"] = round(mean_pbs, 1)
+        res["saturated"]["workload_queries_per_s"] = round(res["saturated"]["pbs_per_s"] / mean_pbs, 4)
     base = 1 + n_sat
     for r, rho in enumerate(rhos if n_poisson > 0 else []):
         idx = range(base + r * n_poisson, base + (r + 1) * n_poisson)
