@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 
 #include "launch.h"
 #include "lvs_internal.h"
@@ -218,22 +219,91 @@ __device__ __forceinline__ void load_inv_tw(InvTw<U, NE>& t, const uint2* w, int
 #pragma unroll
     for (int k = 0; k < (NE >> sh); ++k) t.v[k] = wb[k];
 }
-template <int U, int NE>
-__device__ __forceinline__ void inv_stage_tw(uint32_t (&x)[NE], const InvTw<U, NE>& t, uint32_t p, uint32_t q) {
-    constexpr int half = 1 << U;
-    constexpr int since = (U <= 3) ? U : U - 4;
-    constexpr bool reduce = (U == 3);
-    const uint32_t bound = (2 * p) << since;
-    constexpr int sh = U + 1;
-#pragma unroll
-    for (int el = 0; el < NE; ++el) {
-        if (el & half) continue;
-        const uint2 tw = t.v[el >> sh];
-        const uint32_t a = x[el], b = x[el + half];
-        const uint32_t sum = a + b;
-        x[el] = reduce ? reduce2p(sum, q, p) : sum;
-        x[el + half] = mul_shoup(a + bound - b, tw.x, tw.y, p);
+// Sign and offset plan of the in-lane inverse stages of the eight-wave forms.
+// A butterfly needs one instruction for its sum and one for the input of its
+// product when either its b element arrives negated (register -b: sum a - b,
+// product input a + b + B) or its a element arrives with an offset B, a
+// multiple of p no smaller than b's bound (product input a - b, sum
+// a + b + c for any wanted offset c).  The plan arranges one of the two for
+// every butterfly of the transform:
+//  * row stages 0..4 (element bit j at stage j): the products enter stage 0
+//    with the a elements offset by 2p (added to their Montgomery product's
+//    high word); along the chain of sums of sums (elements whose low j bits
+//    are zero, up to the reduction after stage 3) the sums add the next
+//    stage's bound to their a elements in the same add3; every other output
+//    is produced negated where the next stage takes it as b (products as
+//    q p - x w instead of x w - q p, sums as b - a);
+//  * stage 4 ends the row segment with the values of the wave holding the
+//    position's bit 5 set negated, so that column stage 5 (bit 5, elements
+//    0..4 of the column layout) starts with its b elements negated and every
+//    column stage keeps them so; stage 9 likewise negates the half with bit
+//    10 set, which the CRT step's last stage takes as b.
+// The integers that reach the Shoup products, the reductions and the CRT are
+// those of plain butterflies (a + b and a - b + B), so the bounds above hold
+// unchanged.
+template <int J, int RED, bool CHAIN>
+struct InvPlan {
+    static constexpr bool chain(int j, int el) { return CHAIN && j <= RED && (el & ((1 << j) - 1)) == 0; }
+    // 1: b negated; 2: a offset by B
+    static constexpr int mode(int el) { return chain(J, el) ? 2 : 1; }
+    static constexpr bool next_b(int e) { return (e >> (J + 1)) & 1; }
+};
+
+// One butterfly of the plan: B and Bn are the bounds (multiples of p) of this
+// stage and the next, q = floor(2^32 / p); NEG: the segment's last stage
+// negates its outputs.
+template <int J, int RED, bool CHAIN, bool NEG, int EL>
+__device__ __forceinline__ void inv_bfly_plan(uint32_t& xa, uint32_t& xb, uint2 tw, uint32_t p, uint32_t q,
+                                              uint32_t B, uint32_t Bn) {
+    using Pl = InvPlan<J, RED, CHAIN>;
+    constexpr int m = Pl::mode(EL);
+    const uint32_t a = xa, b = xb;
+    const uint32_t x = (m == 1) ? a + b + B : a - b;     // product input: the plain a - b + B
+    if constexpr (J == RED) {
+        // the plain sum, reduced below 2p
+        const uint32_t sum = (m == 1) ? a - b : a + b - B;
+        const uint32_t qq = __umulhi(sum, q) * p;
+        xa = Pl::next_b(EL) ? qq - sum : sum - qq;
+    } else if constexpr (J == 4) {
+        static_assert(m == 1, "the last stage of a segment follows its reduction");
+        xa = NEG ? b - a : a - b;
+    } else if constexpr (Pl::chain(J + 1, EL)) {
+        static_assert(m == 2, "chain sums come from chain pairs");
+        const uint32_t c = Pl::next_b(EL) ? 0u : Bn;
+        xa = a + b + (c - B);
+    } else {
+        static_assert(m == 1, "other sums come from pairs with b negated");
+        xa = Pl::next_b(EL) ? b - a : a - b;
     }
+    const uint32_t qd = __umulhi(x, tw.y);
+    constexpr bool neg_d = (J == 4) ? NEG : Pl::next_b(EL + (1 << J));
+    xb = neg_d ? qd * p - x * tw.x : x * tw.x - qd * p;
+}
+
+// The butterfly of element EL if EL is the a element of its pair (bit J clear);
+// its twiddle is tws[EL >> sh].
+template <int J, int RED, bool CHAIN, bool NEG, int EL, int NE>
+__device__ __forceinline__ void inv_elem_plan(uint32_t (&x)[NE], const uint2* tws, int sh, uint32_t p, uint32_t q,
+                                              uint32_t B, uint32_t Bn) {
+    if constexpr (!((EL >> J) & 1))
+        inv_bfly_plan<J, RED, CHAIN, NEG, EL>(x[EL], x[EL + (1 << J)], tws[EL >> sh], p, q, B, Bn);
+}
+template <int J, int RED, bool CHAIN, bool NEG, int NE, int... E>
+__device__ __forceinline__ void inv_stage_plan(uint32_t (&x)[NE], const uint2* tws, int sh, uint32_t p, uint32_t q,
+                                               uint32_t B, uint32_t Bn, std::integer_sequence<int, E...>) {
+    (inv_elem_plan<J, RED, CHAIN, NEG, E>(x, tws, sh, p, q, B, Bn), ...);
+}
+
+// Row stages 0..4 of the plan (NEG: stage 4 of the wave whose positions have
+// bit 5 set).
+template <bool NEG = false, int U, int NE>
+__device__ __forceinline__ void inv_stage_tw(uint32_t (&x)[NE], const InvTw<U, NE>& t, uint32_t p, uint32_t q) {
+    static_assert(NE == 32, "the sign plan covers 32 elements per lane");
+    static_assert(U == 4 || !NEG, "only the segment's last stage negates");
+    constexpr int since = (U <= 3) ? U : U - 4;
+    constexpr int since_next = (U + 1 <= 3) ? U + 1 : U - 3;
+    inv_stage_plan<U, 3, true, NEG>(x, t.v, U + 1, p, q, (2 * p) << since, (2 * p) << since_next,
+                                    std::make_integer_sequence<int, NE>{});
 }
 
 // The stages with wave-uniform twiddles (forward S < 6, inverse U >= 5) read
@@ -258,24 +328,18 @@ __device__ __forceinline__ void fwd_stage_lds(uint32_t (&x)[NE], const uint2* tl
         x[el + half] = a + two_p + s;
     }
 }
-template <int U, int NE>
+// Column stages 5..9 of the plan (NEG: stage 9 of the wave whose positions
+// have bit 10 set).
+template <int U, int NE, bool NEG = false>
 __device__ __forceinline__ void inv_stage_lds(uint32_t (&x)[NE], const uint2* tl, uint32_t p, uint32_t q, int e0) {
     static_assert(U >= 5 && U < 10, "wave-uniform stages only");
-    constexpr int half = 1 << (U - 5);
+    static_assert(NE == 32, "the sign plan covers 32 elements per lane");
+    static_assert(U == 9 || !NEG, "only the segment's last stage negates");
     constexpr int since = (U <= 7) ? U - 4 : U - 8;
-    constexpr bool reduce = (U == 7);
-    const uint32_t bound = (2 * p) << since;
+    constexpr int since_next = (U + 1 <= 7) ? U - 3 : U - 7;
     constexpr int sh = U - 4;
-    const uint2* wb = tl + (1 << (10 - U)) + (e0 >> sh);
-#pragma unroll
-    for (int el = 0; el < NE; ++el) {
-        if (el & half) continue;
-        const uint2 tw = wb[el >> sh];
-        const uint32_t a = x[el], b = x[el + half];
-        const uint32_t sum = a + b;
-        x[el] = reduce ? reduce2p(sum, q, p) : sum;
-        x[el + half] = mul_shoup(a + bound - b, tw.x, tw.y, p);
-    }
+    inv_stage_plan<U - 5, 2, false, NEG>(x, tl + (1 << (10 - U)) + (e0 >> sh), sh, p, q, (2 * p) << since,
+                                         (2 * p) << since_next, std::make_integer_sequence<int, NE>{});
 }
 
 __device__ __forceinline__ void ntt_inverse(uint32_t (&x)[kEh], uint32_t* scr, const uint2* w, uint32_t p, uint32_t q,
@@ -301,19 +365,31 @@ __device__ __forceinline__ void ntt_inverse(uint32_t (&x)[kEh], uint32_t* scr, c
 }
 
 // Explicit CRT.  y_i (any representative below 2^30) of X (Q/p_i)^{-1} mod
-// p_i for a signed integer |X| <= 2^97 < Q / 2^6.9 -> X mod 2^64.  As
+// p_i for a signed integer |X| <= 2^97 < Q / 2^6.9 -> acc + X mod 2^64.  As
 // integers sum_i y_i (Q/p_i) = X + K Q with K = sum_i y_i / p_i - X / Q, so K
-// is the integer nearest sum y_i / p_i (within 2^-6.9 of it); the fixed-point
-// sum of y_i floor(2^57 / p_i) is within 2^-25 of that sum, so rounding it
-// gives K exactly, and X = sum y_i (Q/p_i) - K Q mod 2^64.
-__device__ __forceinline__ uint64_t crt_lift(const uint32_t (&y)[kPrimes], const CrtConsts& C) {
-    uint64_t s = uint64_t(1) << 56, x = 0;
+// is the integer nearest sum y_i / p_i (within 2^-6.9 of it).
+//
+// K in 32-bit words: with G_i = floor(2^56 / p_i), floor(y_i G_i / 2^32) is
+// y_i / p_i in units of 2^-24, low by less than 1 + y_i / 2^32 < 1.25 units,
+// so the sum s of the four is below sum y_i / p_i by less than 5 units
+// (2^-21.7) and (s + 2^23) >> 24 rounds to K; s < 2^30.1 (p_i > 2^25.9).
+// X mod 2^64 = sum y_i (Q/p_i mod 2^64) - K Q: the 32x32-bit products with
+// the low words are chained into acc by 64-bit multiply-adds, the products
+// with the high words only add their low words at bit 32.
+__device__ __forceinline__ uint64_t crt_add(uint64_t acc, const uint32_t (&y)[kPrimes], const CrtConsts& C) {
+    uint32_t s = 1u << 23, h = 0;
+    uint64_t r = acc;
 #pragma unroll
     for (int i = 0; i < kPrimes; ++i) {
-        s += uint64_t(y[i]) * C.g[i];
-        x += uint64_t(y[i]) * C.m[i];
+        s += __umulhi(y[i], C.g[i] >> 1);
+        r += uint64_t(y[i]) * uint32_t(C.m[i]);
+        h += y[i] * uint32_t(C.m[i] >> 32);
     }
-    return x - (s >> 57) * C.Q;
+    const uint32_t K = s >> 24;
+    const uint64_t nQ = uint64_t(0) - C.Q;
+    r += uint64_t(K) * uint32_t(nQ);
+    h += K * uint32_t(nQ >> 32);
+    return r + (uint64_t(h) << 32);
 }
 
 // ------------------------------------------------------------ key switch
@@ -570,7 +646,7 @@ __global__ void __launch_bounds__(kBrThreads, 2) blind_rotate_kernel(BrArgs A) {
                 uint32_t r[kPrimes];
 #pragma unroll
                 for (int w = 0; w < kPrimes; ++w) r[w] = region[w * 2 * kPoly + at];
-                acc[k] += crt_lift(r, A.crt);
+                acc[k] = crt_add(acc[k], r, A.crt);
             }
         }
         // sample extraction of coefficient 0, then the job's output rule
@@ -650,6 +726,7 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
     const uint32_t p = pick(A.crt.p, r);
     const uint32_t mont = pick(A.crt.mont, r);
     const uint32_t q = pick(A.crt.red, r);
+    const uint64_t off2p = uint64_t(2 * p) << 32;     // offset of the inverse transform's first a elements
     const uint2* fw = A.tw.fwd + size_t(r) * kN;
     const uint2* iw = A.tw.inv + size_t(r) * kN;
     uint32_t* scrF = F + (r * 2 + h) * kPoly;
@@ -786,7 +863,9 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
                 for (int o = 0; o < 2; ++o) {
                     const uint32_t own = x[el + o];
                     const uint32_t other = swap_halves(own, lane);
-                    x[el + o] = redc(uint64_t(own) * (o ? kq.z : kq.x) + uint64_t(other) * (o ? kq.w : kq.y), p, mont);
+                    // the a elements of inverse stage 0 (even) take the plan's offset 2p
+                    const uint64_t t0 = (o ? uint64_t(0) : off2p) + uint64_t(own) * (o ? kq.z : kq.x);
+                    x[el + o] = redc(t0 + uint64_t(other) * (o ? kq.w : kq.y), p, mont);
                 }
             }
             // twiddles of inverse stages 0..4
@@ -806,7 +885,8 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
             inv_stage_tw(x, u1, p, q);
             inv_stage_tw(x, u2, p, q);
             inv_stage_tw(x, u3, p, q);
-            inv_stage_tw(x, u4, p, q);
+            if (g) inv_stage_tw<true>(x, u4, p, q);
+            else inv_stage_tw(x, u4, p, q);
             uint32_t* const rowI = scrF + 65 * lh + e0;
             uint32_t* const colI = scrF + lh + 32 * e0 + (e0 >> 1);
 #pragma unroll
@@ -818,7 +898,8 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
             inv_stage_lds<6, kLatE>(x, twi, p, q, e0);
             inv_stage_lds<7, kLatE>(x, twi, p, q, e0);
             inv_stage_lds<8, kLatE>(x, twi, p, q, e0);
-            inv_stage_lds<9, kLatE>(x, twi, p, q, e0);
+            if (g) inv_stage_lds<9, kLatE, true>(x, twi, p, q, e0);
+            else inv_stage_lds<9, kLatE>(x, twi, p, q, e0);
             uint32_t* const nat = scrI + lh + 32 * e0;
 #pragma unroll
             for (int el = 0; el < kLatE; ++el) nat[32 * el] = x[el];
@@ -840,11 +921,12 @@ __global__ void __launch_bounds__(kLatThreads, 1) blind_rotate_latency_kernel(Br
                     const uint32_t pw = A.crt.p[w];
                     const uint32_t u0 = I[w * 2 * kPoly + at];
                     const uint32_t u1 = I[w * 2 * kPoly + at + kN / 2];
-                    rlo[w] = u0 + u1;                                        // below 16 p_w
-                    rhi[w] = mul_shoup(u0 + 8 * pw - u1, wlast[w].x, wlast[w].y, pw);
+                    // u1 arrives negated (the plan's stage 9)
+                    rlo[w] = u0 - u1;                                        // below 16 p_w
+                    rhi[w] = mul_shoup(u0 + u1 + 8 * pw, wlast[w].x, wlast[w].y, pw);
                 }
-                acc[k] += crt_lift(rlo, A.crt);
-                acc[k + 1] += crt_lift(rhi, A.crt);
+                acc[k] = crt_add(acc[k], rlo, A.crt);
+                acc[k + 1] = crt_add(acc[k + 1], rhi, A.crt);
             }
         }
         // sample extraction of coefficient 0, then the job's output rule
@@ -912,6 +994,7 @@ __global__ void __launch_bounds__(kLatThreads, 4) blind_rotate_pair_kernel(BrArg
     const uint32_t p = pick(A.crt.p, r);
     const uint32_t mont = pick(A.crt.mont, r);
     const uint32_t q = pick(A.crt.red, r);
+    const uint64_t off2p = uint64_t(2 * p) << 32;     // offset of the inverse transform's first a elements
     const uint2* fw = A.tw.fwd + size_t(r) * kN;
     const uint2* iw = A.tw.inv + size_t(r) * kN;
     uint32_t* const scr = X + (r * 2 + h) * kPoly;
@@ -1052,9 +1135,9 @@ __global__ void __launch_bounds__(kLatThreads, 4) blind_rotate_pair_kernel(BrArg
                         for (int o = 0; o < 2; ++o) {
                             const uint32_t own = x[el + o];
                             const uint32_t other = swap_halves(own, lane);
-                            x[el + o] = redc(uint64_t(own) * (o ? kq[j].z : kq[j].x) +
-                                                 uint64_t(other) * (o ? kq[j].w : kq[j].y),
-                                             p, mont);
+                            // the a elements of inverse stage 0 (even) take the plan's offset 2p
+                            const uint64_t t0 = (o ? uint64_t(0) : off2p) + uint64_t(own) * (o ? kq[j].z : kq[j].x);
+                            x[el + o] = redc(t0 + uint64_t(other) * (o ? kq[j].w : kq[j].y), p, mont);
                         }
                     }
                 }
@@ -1087,7 +1170,8 @@ __global__ void __launch_bounds__(kLatThreads, 4) blind_rotate_pair_kernel(BrArg
             {
                 InvTw<4, kLatE> u4;
                 load_inv_tw(u4, iw, lh, e0);
-                inv_stage_tw(x, u4, p, q);
+                if (g) inv_stage_tw<true>(x, u4, p, q);
+            else inv_stage_tw(x, u4, p, q);
             }
             // inverse transpose through the words this wave read after the forward one
 #pragma unroll
@@ -1099,7 +1183,8 @@ __global__ void __launch_bounds__(kLatThreads, 4) blind_rotate_pair_kernel(BrArg
             inv_stage_lds<6, kLatE>(x, twi, p, q, e0);
             inv_stage_lds<7, kLatE>(x, twi, p, q, e0);
             inv_stage_lds<8, kLatE>(x, twi, p, q, e0);
-            inv_stage_lds<9, kLatE>(x, twi, p, q, e0);
+            if (g) inv_stage_lds<9, kLatE, true>(x, twi, p, q, e0);
+            else inv_stage_lds<9, kLatE>(x, twi, p, q, e0);
 #pragma unroll
             for (int el = 0; el < kLatE; ++el) col[32 * el + (el >> 1)] = x[el];
             __syncthreads();
@@ -1113,11 +1198,12 @@ __global__ void __launch_bounds__(kLatThreads, 4) blind_rotate_pair_kernel(BrArg
                     const uint32_t pw = A.crt.p[w];
                     const uint32_t v0 = X[w * 2 * kPoly + at];
                     const uint32_t v1 = X[w * 2 * kPoly + at + kN / 2 + kN / 128];
-                    rlo[w] = v0 + v1;                                        // below 16 p_w
-                    rhi[w] = mul_shoup(v0 + 8 * pw - v1, wlast[w].x, wlast[w].y, pw);
+                    // v1 arrives negated (the plan's stage 9)
+                    rlo[w] = v0 - v1;                                        // below 16 p_w
+                    rhi[w] = mul_shoup(v0 + v1 + 8 * pw, wlast[w].x, wlast[w].y, pw);
                 }
-                acc[k] += crt_lift(rlo, A.crt);
-                acc[k + 1] += crt_lift(rhi, A.crt);
+                acc[k] = crt_add(acc[k], rlo, A.crt);
+                acc[k + 1] = crt_add(acc[k + 1], rhi, A.crt);
             }
         }
         // sample extraction of coefficient 0, then the job's output rule (the
@@ -1449,7 +1535,7 @@ __global__ void __launch_bounds__(kW16Threads, 1) blind_rotate_w16_kernel(BrArgs
                 res[1] = sel(ppm, recv[1], y[1][k]);
                 res[2] = sel(ppm, y[0][k + 4], recv[0]);
                 res[3] = sel(ppm, y[1][k + 4], recv[1]);
-                acc[k] += crt_lift(res, A.crt);
+                acc[k] = crt_add(acc[k], res, A.crt);
             }
         }
         // sample extraction of coefficient 0, then the job's output rule

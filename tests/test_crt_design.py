@@ -4,14 +4,18 @@ with |X| <= N * 2^22 * 2^63 = 2^96 (a balanced 23-bit digit times a 64-bit
 key word, summed over N = 2048 terms); the kernel holds X as residues y_i of
 X (Q/p_i)^-1 mod p_i, each any representative below 2^30 (the inverse
 transform leaves them unreduced), for the four largest primes p_i < 2^26
-with p_i = 1 mod 2N, and lifts X mod 2^64 as
+with p_i = 1 mod 2N, and adds X mod 2^64 to the accumulator as
 
-    X = sum y_i (Q/p_i) - K Q  (mod 2^64),  K = (2^56 + sum y_i floor(2^57/p_i)) >> 57,
+    acc + sum y_i (Q/p_i) - K Q  (mod 2^64),
+    K = (2^23 + sum floor(y_i floor(2^56/p_i) / 2^32)) >> 24  (32-bit words),
 
-i.e. K is the integer nearest sum y_i / p_i from a 57-bit fixed-point sum.
-This checks that reading against exact integer arithmetic at random X, at
-+-2^97 and near every point where sum y_i / p_i is half an integer away from
-K, for residues at both ends of their range."""
+i.e. K is the integer nearest sum y_i / p_i from a 24-bit fixed-point sum of
+32-bit high products; the 64-bit sum takes the products with the low words of
+Q/p_i and -Q as 64-bit multiply-adds and those with the high words as 32-bit
+low products added at bit 32.  This checks that reading against exact integer
+arithmetic at random X, at +-2^97 and near every point where sum y_i / p_i is
+half an integer away from K, for residues at both ends of their range, with
+every 32-bit intermediate asserted below 2^32."""
 import random
 
 N = 2048
@@ -57,14 +61,22 @@ C = [pow(Q // p, -1, p) for p in P]
 MASK = (1 << 64) - 1
 
 
-def lift(y):
-    """The kernel's formula, in 64-bit wrapping arithmetic."""
-    s = (1 << 56)
-    x = 0
+def lift(y, acc=0):
+    """The kernel's formula, in 32- and 64-bit wrapping arithmetic: acc + X mod 2^64."""
+    s = 1 << 23
+    h = 0
+    r = acc
     for yi, gi, mi in zip(y, G, M):
-        s += yi * gi
-        x = (x + yi * (mi & MASK)) & MASK
-    return (x - (s >> 57) * (Q & MASK)) & MASK
+        assert 0 <= yi < (1 << 30)
+        s += (yi * (gi >> 1)) >> 32                # __umulhi(y_i, floor(2^56 / p_i))
+        assert s < (1 << 32)
+        r = (r + yi * (mi & 0xFFFFFFFF)) & MASK    # 64-bit multiply-add, low word of Q/p_i
+        h = (h + yi * ((mi & MASK) >> 32)) & 0xFFFFFFFF
+    k = s >> 24
+    nq = (-Q) & MASK
+    r = (r + k * (nq & 0xFFFFFFFF)) & MASK
+    h = (h + k * (nq >> 32)) & 0xFFFFFFFF
+    return (r + (h << 32)) & MASK
 
 
 def residues(X, rng, pick):
@@ -81,6 +93,8 @@ def residues(X, rng, pick):
 
 def test_primes_and_range():
     assert all(p < (1 << 26) and p % (2 * N) == 1 for p in P)
+    assert min(P) > 2 ** 25.9                   # sum y_i / p_i < 64.1, so the 24-bit sum stays below 2^31
+    assert all(g >> 1 == (1 << 56) // p for g, p in zip(G, P))
     assert len(set(P)) == 4
     assert Q / (1 << 97) > 2 ** 6.9             # |X| <= 2^97 keeps X / Q within 2^-6.9 of 0
     # the bound of X: a balanced digit |d| <= 2^22 times |key word| <= 2^63, N terms
@@ -95,6 +109,8 @@ def test_lift_exact_at_random_and_extreme_values():
     for X in xs:
         for pick in ("low", "high", "random"):
             assert lift(residues(X, rng, pick)) == X & MASK, (X, pick)
+            acc = rng.getrandbits(64)
+            assert lift(residues(X, rng, pick), acc) == (acc + X) & MASK, (X, pick)
 
 
 def test_lift_exact_where_the_rounding_is_tightest():

@@ -4,7 +4,13 @@ transform (Cooley-Tukey with the psi^brv table, natural order in,
 bit-reversed out, a butterfly adding at most 2p, never reduced), Montgomery
 products with the key transform scaled by N^-1 (Q/p)^-1 2^32, the lazy
 inverse transform (Gentleman-Sande, reduced to below 2p after stages 3 and 7,
-the last stage feeding the CRT unreduced), then the explicit CRT.  Every
+the last stage feeding the CRT unreduced), then the explicit CRT.  The
+eight-wave forms run the in-lane inverse stages with a sign and offset plan
+(products negated, sums formed as b - a or with the next stage's bound added
+where the next stage takes them so, so that a butterfly's sum and product
+input take one instruction each); it is simulated in lockstep with the plain
+inverse transform and must feed every Shoup product, every reduction and the
+CRT the very same integers.  Every
 intermediate value is checked against the bounds the kernel relies on (below
 2^31, subtrahends below the added bound, Montgomery inputs below p 2^32),
 and the result against the exact negacyclic product mod 2^64, at random
@@ -89,6 +95,16 @@ def redc(T, p):
     return r
 
 
+def redc_offset(T, p):
+    """Montgomery reduction of an input offset by 2p at its high word (below 4p)."""
+    assert T < p * (1 << 32) + (2 * p << 32)
+    mont = (-pow(p, -1, 1 << 32)) % (1 << 32)
+    m = (T & M32) * mont & M32
+    r = (T + m * p) >> 32
+    assert r < 4 * p
+    return r
+
+
 def inverse_lazy_then_crt_inputs(x, p):
     """Stages 0..9 with the kernel's bounds, then the last stage as the CRT
     step forms it: (u0 + u1, Shoup(u0 + 8p - u1)) for positions c, c + N/2."""
@@ -120,8 +136,94 @@ def inverse_lazy_then_crt_inputs(x, p):
     return lo + hi
 
 
-def external_product_sim(d0, d1, k0, k1):
-    """X = d0 * k0 + d1 * k1 (negacyclic) mod 2^64 through the kernel's path."""
+def plan_mode(J, RED, chain0, el):
+    """The plan's pairs at stage J of a five-stage segment (element bit J): 1 b
+    negated, 2 a offset by the stage's bound (along the chain of sums of sums
+    of the row segment, up to its reduction)."""
+    chain = chain0 and J <= RED and (el & ((1 << J) - 1)) == 0
+    return 2 if chain else 1
+
+
+def plan_chain(J, RED, chain0, el):
+    return chain0 and J <= RED and (el & ((1 << J) - 1)) == 0
+
+
+def inverse_plan_then_crt_inputs(x, reg, p):
+    """Stages 0..9 as the eight-wave forms run them, from the products x and
+    the registers reg the products leave (x + 2p at even positions): in-lane
+    segments of five stages (positions' bits 0..4 and 5..9, reductions at the
+    segments' stages 3 and 2), the registers wrapping mod 2^32; stage 4
+    negates the positions with bit 5 set and stage 9 those with bit 10 set
+    (the waves holding them).  Runs the plain butterflies alongside and
+    asserts that the Shoup and reduction inputs are identical and every
+    register is the plain value or its negation plus a multiple of p; the
+    CRT step's last stage takes u0 - u1 and u0 + u1 + 8p."""
+    x = list(x)
+    reg = list(reg)
+    inv = TABLES[p][1]
+    q = (1 << 32) // p
+    for U in range(LOG_N - 1):
+        t, m = 1 << U, N >> (U + 1)
+        base, RED, chain0 = (0, 3, True) if U < 5 else (5, 2, False)
+        J = U - base
+        since = U if U <= 3 else (U - 4 if U <= 7 else U - 8)
+        since_n = (U + 1) if U + 1 <= 3 else ((U - 3) if U + 1 <= 7 else U - 7)
+        B, Bn = (2 * p) << since, (2 * p) << since_n
+
+        def next_b(pos):
+            if J == 4:
+                return (pos >> (base + 5)) & 1           # the negated half: bit 5 (row), bit 10 (column)
+            return (pos >> (base + J + 1)) & 1
+
+        for i in range(m):
+            w = inv[m + i]
+            for j in range(2 * i * t, 2 * i * t + t):
+                el = (j >> base) & 31
+                a, b = x[j], x[j + t]
+                ra, rb = reg[j], reg[j + t]
+                md = plan_mode(J, RED, chain0, el)
+                xin = (ra + rb + B if md == 1 else ra - rb) & M32
+                assert xin == a + B - b                     # the plain product input, exactly
+                s_plain = a + b
+                if U in (3, 7):
+                    sm = (ra - rb if md == 1 else ra + rb - B) & M32
+                    assert sm == s_plain < (1 << 32)         # the plain reduction input
+                    qq = ((sm * q) >> 32) * p
+                    s_plain = s_plain - ((s_plain * q) >> 32) * p
+                    rs = (qq - sm) if next_b(j) else (sm - qq)
+                elif J == 4:
+                    assert md == 1
+                    rs = (rb - ra) if next_b(j) else (ra - rb)
+                elif plan_chain(J + 1, RED, chain0, el):
+                    assert md == 2
+                    c = 0 if next_b(j) else Bn
+                    rs = ra + rb + c - B
+                else:
+                    assert md == 1
+                    rs = (rb - ra) if next_b(j) else (ra - rb)
+                d_plain = shoup(xin, w, p)
+                ws = (w << 32) // p
+                qd = (xin * ws) >> 32
+                rd = (qd * p - xin * w) if next_b(j + t) else (xin * w - qd * p)
+                x[j], x[j + t] = s_plain, d_plain
+                reg[j], reg[j + t] = rs & M32, rd & M32
+                for r, v in ((reg[j], s_plain), (reg[j + t], d_plain)):
+                    assert any((sg * v + c * p - r) % (1 << 32) == 0 for sg in (1, -1) for c in range(-32, 33))
+        if U == 4:
+            assert all(reg[k] == (x[k] if not (k >> 5) & 1 else (-x[k]) & M32) for k in range(N))
+        if U == 9:
+            assert all(reg[k] == (x[k] if not (k >> 10) & 1 else (-x[k]) & M32) for k in range(N))
+    w = inv[1]
+    lo, hi = [0] * (N // 2), [0] * (N // 2)
+    for c in range(N // 2):
+        u0, u1 = reg[c], reg[c + N // 2]
+        lo[c], hi[c] = (u0 - u1) & M32, shoup((u0 + u1 + 8 * p) & M32, w, p)
+    return lo + hi
+
+
+def external_product_sim(d0, d1, k0, k1, planned=False):
+    """X = d0 * k0 + d1 * k1 (negacyclic) mod 2^64 through the kernel's path
+    (planned: the eight-wave forms' inverse stages)."""
     res = []
     for p, c in zip(P, C):
         scale = pow(N, -1, p) * c * (1 << 32) % p
@@ -130,7 +232,15 @@ def external_product_sim(d0, d1, k0, k1):
         K0 = [v * scale % p for v in forward_exact(k0, p)]
         K1 = [v * scale % p for v in forward_exact(k1, p)]
         prod = [redc(a * ka + b * kb, p) for a, b, ka, kb in zip(x0, x1, K0, K1)]
-        res.append(inverse_lazy_then_crt_inputs(prod, p))
+        plain = inverse_lazy_then_crt_inputs(prod, p)
+        if planned:
+            # even positions (the a elements of inverse stage 0) add 2p at the
+            # high word of the Montgomery input, which leaves its low word alone
+            reg = [redc_offset(a * ka + b * kb + (0 if k & 1 else (2 * p) << 32), p) if not k & 1 else prod[k]
+                   for k, (a, b, ka, kb) in enumerate(zip(x0, x1, K0, K1))]
+            assert all(reg[k] == prod[k] + (0 if k & 1 else 2 * p) for k in range(N))
+            assert inverse_plan_then_crt_inputs(prod, reg, p) == plain
+        res.append(plain)
     return np.array([lift([r[i] for r in res]) for i in range(N)], dtype=np.uint64)
 
 
@@ -145,8 +255,9 @@ def negacyclic_mod64(d, k):
     return out
 
 
+@pytest.mark.parametrize("planned", [False, True], ids=["plain", "planned"])
 @pytest.mark.parametrize("case", ["random", "extreme_neg", "extreme_mixed"])
-def test_external_product_matches_exact(case):
+def test_external_product_matches_exact(case, planned):
     rng = np.random.default_rng({"random": 1, "extreme_neg": 2, "extreme_mixed": 3}[case])
     lo_d, hi_d = -(1 << 22), (1 << 22) - 1
     if case == "random":
@@ -162,6 +273,6 @@ def test_external_product_matches_exact(case):
         d1 = [lo_d if rng.random() < 0.5 else hi_d for _ in range(N)]
         k0 = [-(1 << 63) if rng.random() < 0.5 else (1 << 63) - 1 for _ in range(N)]
         k1 = [-(1 << 63) if rng.random() < 0.5 else (1 << 63) - 1 for _ in range(N)]
-    got = external_product_sim(d0, d1, k0, k1)
+    got = external_product_sim(d0, d1, k0, k1, planned)
     want = negacyclic_mod64(d0, k0) + negacyclic_mod64(d1, k1)
     assert (got == want).all()
