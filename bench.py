@@ -29,6 +29,7 @@ import hashlib
 import json
 import os
 import sys
+import statistics
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -292,9 +293,10 @@ def batched_headline(L, ck, ctx, warmup, steps, plain_sample, only_timed=False):
     return head, full, plain
 
 
-def plain_config(L, ck, ctx, a, b, enc, seed, reps=1):
+def plain_config(L, ck, ctx, a, b, enc, seed, reps=5):
     """One pair through the plain per-diagonal path, after a warm-up run:
-    bootstraps per second over reps runs and the checked distance."""
+    bootstraps per second at the median of reps timed runs (each its own
+    interval), the fastest and slowest run, and the checked distance."""
     import torch
     dev = ctx.device
     sa, sb = (W_codes(a), W_codes(b)) if enc == L.LVS_ENC_DNA2 else (a, b)
@@ -304,11 +306,13 @@ def plain_config(L, ck, ctx, a, b, enc, seed, reps=1):
     work = L.device_buffer(L.lvs_edit_distance_workspace_bytes(len(a), len(b), enc), dev)
     L.lvs_edit_distance(ctx, dA, len(a), dB, len(b), enc, d_h, work)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    times = []
     for _ in range(reps):
+        t0 = time.perf_counter()
         L.lvs_edit_distance(ctx, dA, len(a), dB, len(b), enc, d_h, work)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    dt = statistics.median(times)
     d = L.lvs_decrypt_distance(ck, L.to_host(d_h).reshape(len(b), L.CT_WORDS), len(a))
     if d != levenshtein(a, b):
         raise SystemExit("plain config: wrong distance")
@@ -316,7 +320,8 @@ def plain_config(L, ck, ctx, a, b, enc, seed, reps=1):
     R = L.lvs_context_get_refresh(ctx)
     pbs = per_cell * len(a) * len(b) + refresh_pbs(len(a), len(b), R)
     return {"m": len(a), "n": len(b), "pbs": pbs, "seconds": round(dt, 4), "pbs_per_s": round(pbs / dt, 1),
-            "cells_per_s": round(len(a) * len(b) / dt, 1), "distance": d, "runs": reps, "refresh_every": R}
+            "cells_per_s": round(len(a) * len(b) / dt, 1), "distance": d, "runs": reps,
+            "seconds_min": round(min(times), 4), "seconds_max": round(max(times), 4), "refresh_every": R}
 
 
 def W_codes(s):
@@ -684,11 +689,11 @@ def main():
     # the other configurations
     note("configs: dna 256 x 256, tiny dna, plain 32 x 32")
     a, b = W.dna_align()
-    line["dna_align_256x256"] = plain_config(L, ck, ctx, a, b, L.LVS_ENC_DNA2, 70001)
+    line["dna_align_256x256"] = plain_config(L, ck, ctx, a, b, L.LVS_ENC_DNA2, 70001, reps=3)
     a, b = W.tiny_dna()
     line["tiny_dna_6x6"] = plain_config(L, ck, ctx, a, b, L.LVS_ENC_DNA2, 70011, reps=5)
     a, b = W.plain_ascii()
-    line["plain_ascii_32x32"] = plain_config(L, ck, ctx, a, b, L.LVS_ENC_ASCII7, 1001, reps=3)
+    line["plain_ascii_32x32"] = plain_config(L, ck, ctx, a, b, L.LVS_ENC_ASCII7, 1001, reps=5)
     line["plain_same_queries"]["vs_plain_32x32_pbs_per_s"] = round(
         full["pbs_per_s"] / line["plain_ascii_32x32"]["pbs_per_s"], 2)
     if not args.no_serving and args.serving_names > 0:
