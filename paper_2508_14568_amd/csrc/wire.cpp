@@ -11,6 +11,7 @@
 // Payloads: client key = the small key's n bits then the GLWE key's N bits,
 // one byte each; server key = the bootstrapping key's words then the key
 // switching key's words; ciphertexts = count x (N+1) words.
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <string>
@@ -202,6 +203,10 @@ int lvs_export(int kind, const void* obj, size_t count, uint8_t* buf, size_t* le
         fill = fill_server;
         count = 0;
     } else if (kind == LVS_WIRE_CIPHERTEXTS) {
+        if (count > (SIZE_MAX - kHeader - kTrailer) / (8 * size_t(kCtWords))) {
+            set_error("lvs_export: too many ciphertexts for one record");
+            return LVS_E_INVAL;
+        }
         lvs_params_default(&p);
         span = CtSpan{static_cast<const uint64_t*>(obj), count * size_t(kCtWords)};
         payload = 8 * span.words;
@@ -252,8 +257,14 @@ int lvs_import_key(const uint8_t* buf, size_t len, int* kind, void** out) {
         }
         k->kind = kClientKey;
         k->p = p;
-        k->s.assign(r.payload, r.payload + p.n_lwe);
-        k->S.assign(r.payload + p.n_lwe, r.payload + p.n_lwe + p.poly_N);
+        try {
+            k->s.assign(r.payload, r.payload + p.n_lwe);
+            k->S.assign(r.payload + p.n_lwe, r.payload + p.n_lwe + p.poly_N);
+        } catch (const std::bad_alloc&) {
+            delete k;
+            set_error("lvs_import_key: out of host memory");
+            return LVS_E_NOMEM_HOST;
+        }
         *kind = LVS_WIRE_CLIENT_KEY;
         *out = k;
         return LVS_OK;
@@ -270,10 +281,16 @@ int lvs_import_key(const uint8_t* buf, size_t len, int* kind, void** out) {
         }
         k->kind = kServerKey;
         k->p = p;
+        try {
+            k->bsk.resize(bsk_words(p));
+            k->ksk.resize(ksk_words(p));
+        } catch (const std::bad_alloc&) {
+            delete k;
+            set_error("lvs_import_key: out of host memory");
+            return LVS_E_NOMEM_HOST;
+        }
         Reader rd{r.payload, r.payload + r.payload_bytes};
-        k->bsk.resize(bsk_words(p));
         for (auto& v : k->bsk) v = rd.u64();
-        k->ksk.resize(ksk_words(p));
         for (auto& v : k->ksk) v = rd.u64();
         *kind = LVS_WIRE_SERVER_KEY;
         *out = k;

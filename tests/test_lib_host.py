@@ -289,3 +289,15 @@ def test_wire_rejects_malformed(L, both_keys):
         L.lvs_export(9, ck)
     with pytest.raises(L.LvsError, match="not a server key"):
         L.lvs_export(L.LVS_WIRE_SERVER_KEY, ck)
+
+
+def test_wire_export_rejects_oversized_count(L):
+    """A ciphertext count whose record size would not fit in size_t is an
+    error, not a wrapped length (the size query passes no buffer)."""
+    import ctypes
+    n = ctypes.c_size_t()
+    dummy = (ctypes.c_uint64 * 1)()
+    rc = L.lib().lvs_export(L.LVS_WIRE_CIPHERTEXTS, dummy, ctypes.c_size_t(2 ** 64 // (8 * L.CT_WORDS) + 1), None,
+                            ctypes.byref(n))
+    assert rc == -1
+    assert "too many ciphertexts" in L.lib().lvs_last_error().decode()
