@@ -13,8 +13,11 @@ namespace lvs {
 // First-fit allocator over a byte range of the arena (offsets, 256-aligned).
 class Pool {
 public:
+    // The range is used in whole 256-byte units, so that a request of at most
+    // total() bytes always fits an empty pool.
     void init(size_t bytes) {
         free_.clear();
+        bytes &= ~size_t(255);
         if (bytes) free_[0] = bytes;
         total_ = bytes;
     }
