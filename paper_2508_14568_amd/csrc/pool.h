@@ -6,8 +6,6 @@
 #include <iterator>
 #include <map>
 
-#include "plan.h"
-
 namespace lvs {
 
 // First-fit allocator over a byte range of the arena (offsets, 256-aligned).
@@ -22,7 +20,7 @@ public:
         total_ = bytes;
     }
     bool alloc(size_t bytes, size_t* off) {
-        bytes = align256(bytes);
+        bytes = unit(bytes);
         for (auto it = free_.begin(); it != free_.end(); ++it) {
             if (it->second < bytes) continue;
             *off = it->first;
@@ -35,7 +33,7 @@ public:
         return false;
     }
     void release(size_t off, size_t bytes) {
-        bytes = align256(bytes);
+        bytes = unit(bytes);
         auto it = free_.emplace(off, bytes).first;
         auto nx = std::next(it);
         if (nx != free_.end() && it->first + it->second == nx->first) {
@@ -53,6 +51,7 @@ public:
     size_t total() const { return total_; }
 
 private:
+    static size_t unit(size_t x) { return (x + 255) & ~size_t(255); }
     std::map<size_t, size_t> free_;
     size_t total_ = 0;
 };
