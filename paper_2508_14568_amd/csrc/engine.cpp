@@ -97,10 +97,6 @@ struct Engine : Handle {
 
     void run() {
         std::vector<Job> jobs;
-        struct Take {
-            EngineRequest* r;
-            size_t count;
-        };
         std::unique_lock<std::mutex> lk(mu);
         if (hipSetDevice(C->device) != hipSuccess) {
             fail(hipErrorInvalidDevice, "hipSetDevice");
@@ -109,6 +105,27 @@ struct Engine : Handle {
         for (;;) {
             cv.wait(lk, [&] { return stop || (error == LVS_OK && has_work()); });
             if (stop) return;
+            try {
+                step(lk, jobs);
+            } catch (const std::exception& ex) {
+                // host allocation while admitting or gathering: the engine
+                // stops with a sticky error instead of ending the process
+                if (!lk.owns_lock()) lk.lock();
+                error = LVS_E_NOMEM_HOST;
+                error_msg = std::string("lvs engine: ") + ex.what();
+                for (EngineRequest* r : active) r->done = true;
+                cv.notify_all();
+            }
+        }
+    }
+
+    // One engine step (called with mu held; returns with it held).
+    void step(std::unique_lock<std::mutex>& lk, std::vector<Job>& jobs) {
+        struct Take {
+            EngineRequest* r;
+            size_t count;
+        };
+        {
             // admission in arrival order while the request's state fits
             std::vector<EngineRequest*> fresh;
             while (!queue.empty()) {
@@ -183,7 +200,7 @@ struct Engine : Handle {
             if (e != hipSuccess) {
                 fail(e, what);
                 cv.notify_all();
-                continue;
+                return;
             }
             for (EngineRequest* r : fresh) {
                 r->filled = true;
