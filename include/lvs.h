@@ -605,7 +605,9 @@ int lvs_submit(lvs_engine* eng, const lvs_query* q, size_t nq, uint64_t* tickets
 
 /* *done = 1 once the query's results are complete (wait != 0 blocks until
  * then); a done ticket is released and its pool space returns to the engine.
- * An error of the worker's device work is returned by every later call. */
+ * An error of the worker (LVS_E_DEVICE for its device work, LVS_E_NOMEM_HOST
+ * for host memory while admitting a query) stops the engine and is returned
+ * by every later lvs_submit and lvs_poll. */
 int lvs_poll(lvs_engine* eng, uint64_t ticket, int wait, int* done);
 
 /* Engine steps and bootstraps run so far, queries running and queued (any
