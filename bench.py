@@ -334,7 +334,8 @@ def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos, progress=False, a
     """The serving workload on the first n_names of its 1024 cleartext server
     names: n_sat queries submitted at once (saturated queries/s), then
     n_poisson queries per load factor rho arriving as a Poisson process at
-    rho x the saturated rate (p50/p99 latency from arrival to results on the
+    rho x the saturated rate for their own mix (the saturated run's bootstrap
+    rate over their mean bootstraps per query; p50/p99 latency from arrival to results on the
     host).  Every query's distances to every name are checked."""
     import numpy as np
     import workloads as W
@@ -389,9 +390,16 @@ def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos, progress=False, a
         res["saturated"]["workload_mean_pbs_per_query"] = round(mean_pbs, 1)
         res["saturated"]["workload_queries_per_s"] = round(res["saturated"]["pbs_per_s"] / mean_pbs, 4)
     base = 1 + n_sat
+    tot = sum(len(nm) for nm in names)
     for r, rho in enumerate(rhos if n_poisson > 0 else []):
         idx = range(base + r * n_poisson, base + (r + 1) * n_poisson)
-        rate = arrival_rate if arrival_rate else rho * sat_qps
+        # load rho for the queries that will arrive: the measured bootstrap rate
+        # over their own mean bootstraps per query (the saturated run's queries
+        # are a different, smaller sample of the length law)
+        mean_r = float(np.mean([2 * len(alpha) * len(queries[k]) + len(queries[k]) * tot for k in idx]))
+        if not arrival_rate and sat_qps is None:
+            raise SystemExit("serving: Poisson arrivals need a saturated run or --arrival-rate")
+        rate = arrival_rate if arrival_rate else rho * res["saturated"]["pbs_per_s"] / mean_r
         arr = W.poisson_arrivals(poisson_seed + r, rate, n_poisson)
         note(f"serving: Poisson arrivals at {rate:.4f} queries/s (rho={rho}), {n_poisson} queries")
         st0, pbs0 = L.lvs_server_stats(srv)
@@ -404,6 +412,7 @@ def serving_block(L, ck, ctx, n_names, n_sat, n_poisson, rhos, progress=False, a
                              on_result=lambda k, o, t, b=idx.start: check(b + k, o, t))
         st1, pbs1 = L.lvs_server_stats(srv)
         res["poisson"].append({"rho": rho, "queries": n_poisson, "rate_per_s": round(rate, 4),
+                               "mean_pbs_per_query": round(mean_r, 1),
                                "arrival_seed": poisson_seed + r, "query_offset": query_offset,
                                "latencies_s": [round(x, 3) for x in lat],
                                "seconds": round(wall, 3), "pbs_per_s": round((pbs1 - pbs0) / wall, 1),
