@@ -49,7 +49,7 @@ def okeys_kara():
 
 
 def oracle_threads():
-    """Host threads for live oracle runs (the GPU machine grants 16 per GPU)."""
+    """Host threads for live oracle runs: the host cores, at most 16 (the CPU share of one GPU)."""
     import os
     return max(1, min(16, os.cpu_count() or 1))
 
