@@ -234,10 +234,11 @@ __device__ __forceinline__ void load_inv_tw(InvTw<U, NE>& t, const uint2* w, int
 //    is produced negated where the next stage takes it as b (products as
 //    q p - x w instead of x w - q p, sums as b - a);
 //  * stage 4 ends the row segment with the values of the wave holding the
-//    position's bit 5 set negated, so that column stage 5 (bit 5, elements
-//    0..4 of the column layout) starts with its b elements negated and every
-//    column stage keeps them so; stage 9 likewise negates the half with bit
-//    10 set, which the CRT step's last stage takes as b.
+//    positions with bit 5 set negated, so that column stage 5 (position bit
+//    5, element bit 0 of the column layout) starts with its b elements
+//    negated and every column stage keeps them so; stage 9 likewise negates
+//    the half with position bit 10 set, which the CRT step's last stage takes
+//    as b.
 // The integers that reach the Shoup products, the reductions and the CRT are
 // those of plain butterflies (a + b and a - b + B), so the bounds above hold
 // unchanged.
